@@ -1,0 +1,580 @@
+/*
+ * FP64 CPU oracle for point-cloud SBR -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously-correct reference for what the GPU path computes.  Only the test
+ * suite, the smoke check and the bench's CPU-baseline leg may load this library; the product
+ * path never does.  It shares no code, header or constant with the HIP library.
+ *
+ * The method being checked: points carrying normals are treated as oriented disks ("splats"),
+ * a screen of central rays is shot at them along the incident direction, rays bounce off PEC
+ * disks by geometric optics, and the physical-optics aperture integral of each ray's last
+ * facet is summed into the far field.  Definitions followed, by section of the paper:
+ *   - ray field and PEC reflection: Sec. II-A, Eq. (1)-(4);
+ *   - PO facet integral with central rays only: Sec. II-B, Eq. (5)-(13);
+ *   - total SBR field over rays, last bounce, image-method path length: Sec. II-C, Eq. (14);
+ *   - ray-tube nearest-point depth (Top-K with K unbounded): Sec. III-A, Algorithm 1;
+ *   - bounce loop with a minimum travel distance eps for secondary rays: Sec. III-B,
+ *     Algorithm 3 and the paragraph after Eq. (23).
+ * Readings where the paper is silent (screen placement, tie-breaks, grazing threshold, the
+ * parallelogram area, sinc convention) are stated at each function.
+ *
+ * Everything is double precision; libm sin/cos.  No blocking or reordering beyond what the
+ * definitions state, except the optional uniform grid (or_scene_build_grid) which visits a
+ * superset of the disks a ray can hit in ray order and returns the bitwise-identical first hit.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define OR_C0 299792458.0
+#define OR_GRAZE 1e-6
+#define OR_PI 3.14159265358979323846
+
+typedef struct { double x, y, z; } v3;
+
+static inline v3 mk(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static inline v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static inline v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static inline v3 scl(v3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static inline double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static inline v3 cross(v3 a, v3 b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static inline double len(v3 a) { return sqrt(dot(a, a)); }
+static inline v3 unit(v3 a) { return scl(a, 1.0 / len(a)); }
+static inline v3 ld(const double* p) { return mk(p[0], p[1], p[2]); }
+static inline void st(double* p, v3 a) { p[0] = a.x; p[1] = a.y; p[2] = a.z; }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Scene: disks (centre, unit normal, radius, material) plus optional uniform grid.            */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    double* xyz;
+    double* nrm;
+    double* rad;
+    uint8_t* mat;
+    double c[3];   /* bounding-box centre */
+    double R;      /* max over disks of |x_i - c| + r_i */
+    /* grid (c.8): CSR lists of disk ids per cell */
+    int G;
+    double lo[3], h;
+    int64_t* cell_start; /* G^3 + 1 */
+    int32_t* cell_ids;
+} or_scene;
+
+/* Returns NULL and *err != 0 on invalid input: non-finite position, zero/non-finite normal,
+ * non-positive radius or a material other than 0 (PEC) / 1 (absorber). */
+void* or_scene_new(int64_t n, const double* xyz, const double* nrm, const double* rad,
+                   const uint8_t* mat, int* err) {
+    *err = 0;
+    if (n <= 0) { *err = 1; return NULL; }
+    or_scene* s = (or_scene*)calloc(1, sizeof(or_scene));
+    s->n = n;
+    s->xyz = (double*)malloc(sizeof(double) * 3 * n);
+    s->nrm = (double*)malloc(sizeof(double) * 3 * n);
+    s->rad = (double*)malloc(sizeof(double) * n);
+    s->mat = (uint8_t*)malloc(n);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < n; i++) {
+        v3 x = ld(xyz + 3 * i), nn = ld(nrm + 3 * i);
+        double l = len(nn);
+        if (!isfinite(x.x) || !isfinite(x.y) || !isfinite(x.z) || !(l > 0) || !isfinite(l) ||
+            !(rad[i] > 0) || !isfinite(rad[i]) || (mat && mat[i] > 1)) {
+            *err = 1;
+        }
+        st(s->xyz + 3 * i, x);
+        st(s->nrm + 3 * i, scl(nn, 1.0 / l));
+        s->rad[i] = rad[i];
+        s->mat[i] = mat ? mat[i] : 0;
+        for (int a = 0; a < 3; a++) {
+            double v = (&x.x)[a];
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    }
+    if (*err) {
+        free(s->xyz); free(s->nrm); free(s->rad); free(s->mat); free(s);
+        return NULL;
+    }
+    for (int a = 0; a < 3; a++) s->c[a] = 0.5 * (lo[a] + hi[a]);
+    double R = 0;
+    v3 c = ld(s->c);
+    for (int64_t i = 0; i < n; i++) {
+        double r = len(sub(ld(s->xyz + 3 * i), c)) + s->rad[i];
+        if (r > R) R = r;
+    }
+    s->R = R;
+    return s;
+}
+
+void or_scene_free(void* p) {
+    or_scene* s = (or_scene*)p;
+    if (!s) return;
+    free(s->xyz); free(s->nrm); free(s->rad); free(s->mat);
+    free(s->cell_start); free(s->cell_ids);
+    free(s);
+}
+
+void or_scene_frame(const void* p, double* c, double* R) {
+    const or_scene* s = (const or_scene*)p;
+    c[0] = s->c[0]; c[1] = s->c[1]; c[2] = s->c[2];
+    *R = s->R;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Screen (Algorithm 1, RayTubeInitialization).  Reading: the screen is a square of side 2R   */
+/* centred on the scene, placed R before the centre along the propagation direction k, pixel  */
+/* pitch 2R/max(W,H); u = normalise(z x k) (x if k is within 1e-9 of +-z), v = k x u.          */
+/* ------------------------------------------------------------------------------------------ */
+
+void or_screen(const void* p, const double* kin, int W, int H, double* o00, double* du,
+               double* dv) {
+    const or_scene* s = (const or_scene*)p;
+    v3 k = unit(ld(kin));
+    v3 u = fabs(k.z) > 1.0 - 1e-9 ? mk(1, 0, 0) : unit(cross(mk(0, 0, 1), k));
+    v3 v = cross(k, u);
+    double pitch = 2.0 * s->R / (double)(W > H ? W : H);
+    v3 c = ld(s->c);
+    /* centre of pixel (0,0): c - R k + (0.5 - W/2) pitch u + (0.5 - H/2) pitch v */
+    v3 o = add(sub(c, scl(k, s->R)),
+               add(scl(u, (0.5 - 0.5 * W) * pitch), scl(v, (0.5 - 0.5 * H) * pitch)));
+    st(o00, o);
+    st(du, scl(u, pitch));
+    st(dv, scl(v, pitch));
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Ray-disk test.  Reading: disks are two-sided; |n.k| < 1e-6 is a miss (grazing); the hit     */
+/* must satisfy t > tmin; the boundary |q - x|^2 <= r^2 is inclusive.                          */
+/* ------------------------------------------------------------------------------------------ */
+
+static inline int disk_hit(const or_scene* s, int64_t i, v3 o, v3 k, double tmin, double* t) {
+    v3 n = ld(s->nrm + 3 * i), x = ld(s->xyz + 3 * i);
+    double den = dot(n, k);
+    if (fabs(den) < OR_GRAZE) return 0;
+    double tt = dot(n, sub(x, o)) / den;
+    if (!(tt > tmin)) return 0;
+    v3 q = sub(add(o, scl(k, tt)), x);
+    if (dot(q, q) <= s->rad[i] * s->rad[i]) { *t = tt; return 1; }
+    return 0;
+}
+
+static int64_t first_hit_brute(const or_scene* s, v3 o, v3 k, double tmin, double* tbest,
+                               int64_t* ntests) {
+    int64_t best = -1;
+    double bt = INFINITY, t;
+    for (int64_t i = 0; i < s->n; i++) {
+        if (disk_hit(s, i, o, k, tmin, &t) && t < bt) { bt = t; best = i; }
+    }
+    *ntests += s->n;
+    *tbest = bt;
+    return best;
+}
+
+/* Uniform grid (c.8).  Each disk is listed in every cell its inflated bounding cube touches. */
+int or_scene_build_grid(void* p, int G) {
+    or_scene* s = (or_scene*)p;
+    if (G < 1) G = 1;
+    double rmax = 0;
+    for (int64_t i = 0; i < s->n; i++) if (s->rad[i] > rmax) rmax = s->rad[i];
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; a++) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int64_t i = 0; i < s->n; i++)
+        for (int a = 0; a < 3; a++) {
+            double v = s->xyz[3 * i + a];
+            if (v - s->rad[i] < lo[a]) lo[a] = v - s->rad[i];
+            if (v + s->rad[i] > hi[a]) hi[a] = v + s->rad[i];
+        }
+    double ext = 0;
+    for (int a = 0; a < 3; a++) if (hi[a] - lo[a] > ext) ext = hi[a] - lo[a];
+    double pad = 1e-6 * ext + 1e-12;
+    for (int a = 0; a < 3; a++) { s->lo[a] = lo[a] - pad; }
+    s->h = (ext + 2 * pad) / G;
+    s->G = G;
+    int64_t nc = (int64_t)G * G * G;
+    free(s->cell_start); free(s->cell_ids);
+    s->cell_start = (int64_t*)calloc(nc + 1, sizeof(int64_t));
+    double e = 1e-9 * ext;
+    for (int pass = 0; pass < 2; pass++) {
+        int64_t* cursor = NULL;
+        if (pass == 1) {
+            for (int64_t c = 0; c < nc; c++) s->cell_start[c + 1] += s->cell_start[c];
+            s->cell_ids = (int32_t*)malloc(sizeof(int32_t) * (s->cell_start[nc] + 1));
+            cursor = (int64_t*)malloc(sizeof(int64_t) * nc);
+            memcpy(cursor, s->cell_start, sizeof(int64_t) * nc);
+        }
+        for (int64_t i = 0; i < s->n; i++) {
+            int c0[3], c1[3];
+            for (int a = 0; a < 3; a++) {
+                double v = s->xyz[3 * i + a];
+                int q0 = (int)floor((v - s->rad[i] - e - s->lo[a]) / s->h);
+                int q1 = (int)floor((v + s->rad[i] + e - s->lo[a]) / s->h);
+                c0[a] = q0 < 0 ? 0 : (q0 >= G ? G - 1 : q0);
+                c1[a] = q1 < 0 ? 0 : (q1 >= G ? G - 1 : q1);
+            }
+            for (int z = c0[2]; z <= c1[2]; z++)
+                for (int y = c0[1]; y <= c1[1]; y++)
+                    for (int x = c0[0]; x <= c1[0]; x++) {
+                        int64_t c = ((int64_t)z * G + y) * G + x;
+                        if (pass == 0) s->cell_start[c + 1]++;
+                        else s->cell_ids[cursor[c]++] = (int32_t)i;
+                    }
+        }
+        free(cursor);
+    }
+    return 0;
+}
+
+/* Amanatides-Woo traversal; a candidate is accepted once its t lies within the current cell. */
+static int64_t first_hit_grid(const or_scene* s, v3 o, v3 k, double tmin, double* tbest,
+                              int64_t* ntests) {
+    int G = s->G;
+    double t0 = tmin > 0 ? tmin : 0, t1 = INFINITY;
+    double oo[3] = {o.x, o.y, o.z}, kk[3] = {k.x, k.y, k.z};
+    double hi[3];
+    for (int a = 0; a < 3; a++) hi[a] = s->lo[a] + G * s->h;
+    for (int a = 0; a < 3; a++) {
+        if (kk[a] == 0.0) {
+            if (oo[a] < s->lo[a] || oo[a] > hi[a]) { *tbest = INFINITY; return -1; }
+        } else {
+            double ta = (s->lo[a] - oo[a]) / kk[a], tb = (hi[a] - oo[a]) / kk[a];
+            if (ta > tb) { double tt = ta; ta = tb; tb = tt; }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        }
+    }
+    if (t0 > t1) { *tbest = INFINITY; return -1; }
+    int cell[3], step[3];
+    double tmax[3], tdel[3];
+    for (int a = 0; a < 3; a++) {
+        double pa = oo[a] + t0 * kk[a];
+        int q = (int)floor((pa - s->lo[a]) / s->h);
+        cell[a] = q < 0 ? 0 : (q >= G ? G - 1 : q);
+        if (kk[a] > 0) {
+            step[a] = 1;
+            tmax[a] = (s->lo[a] + (cell[a] + 1) * s->h - oo[a]) / kk[a];
+            tdel[a] = s->h / kk[a];
+        } else if (kk[a] < 0) {
+            step[a] = -1;
+            tmax[a] = (s->lo[a] + cell[a] * s->h - oo[a]) / kk[a];
+            tdel[a] = -s->h / kk[a];
+        } else {
+            step[a] = 0;
+            tmax[a] = INFINITY;
+            tdel[a] = INFINITY;
+        }
+    }
+    int64_t best = -1;
+    double bt = INFINITY, t;
+    for (;;) {
+        int64_t c = ((int64_t)cell[2] * G + cell[1]) * G + cell[0];
+        for (int64_t j = s->cell_start[c]; j < s->cell_start[c + 1]; j++) {
+            int64_t i = s->cell_ids[j];
+            (*ntests)++;
+            if (disk_hit(s, i, o, k, tmin, &t) && (t < bt || (t == bt && i < best))) {
+                bt = t;
+                best = i;
+            }
+        }
+        int a = (tmax[0] < tmax[1]) ? (tmax[0] < tmax[2] ? 0 : 2) : (tmax[1] < tmax[2] ? 1 : 2);
+        double texit = tmax[a];
+        if (best >= 0 && bt <= texit) break;
+        cell[a] += step[a];
+        if (cell[a] < 0 || cell[a] >= G) break;
+        tmax[a] += tdel[a];
+    }
+    *tbest = bt;
+    return best;
+}
+
+static int64_t first_hit(const or_scene* s, v3 o, v3 k, double tmin, int use_grid,
+                         double* t, int64_t* ntests) {
+    if (use_grid && s->cell_start) return first_hit_grid(s, o, k, tmin, t, ntests);
+    return first_hit_brute(s, o, k, tmin, t, ntests);
+}
+
+int64_t or_first_hit(const void* p, const double* o, const double* k, double tmin, int use_grid,
+                     double* t) {
+    int64_t nt = 0;
+    return first_hit((const or_scene*)p, ld(o), unit(ld(k)), tmin, use_grid, t, &nt);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Primary geometric frame buffer with disks (c.4): first hit with tmin = 0 at every pixel;   */
+/* normal oriented against the ray (two-sided splats, "oriented normal map").                 */
+/* ------------------------------------------------------------------------------------------ */
+
+void or_render_disk(const void* p, const double* kin, int W, int H, int use_grid, double* depth,
+                    int64_t* idx, double* nrm, uint8_t* mask) {
+    const or_scene* s = (const or_scene*)p;
+    double o00[3], du[3], dv[3];
+    or_screen(p, kin, W, H, o00, du, dv);
+    v3 k = unit(ld(kin));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < H; j++) {
+        int64_t nt = 0;
+        for (int i = 0; i < W; i++) {
+            v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
+            double t;
+            int64_t h = first_hit(s, o, k, 0.0, use_grid, &t, &nt);
+            int64_t q = (int64_t)j * W + i;
+            if (h >= 0) {
+                v3 n = ld(s->nrm + 3 * h);
+                if (dot(n, k) > 0) n = scl(n, -1.0);
+                depth[q] = t; idx[q] = h; mask[q] = 1;
+                if (nrm) st(nrm + 3 * q, n);
+            } else {
+                depth[q] = INFINITY; idx[q] = -1; mask[q] = 0;
+                if (nrm) st(nrm + 3 * q, mk(0, 0, 0));
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Coarse depth by ray tubes (Algorithm 1 with K unbounded, c.5): a point is a candidate iff   */
+/* its distance to the central ray is below delta and it lies in front of the screen; the     */
+/* depth is the along-ray distance of the nearest candidate (ties: smallest index).           */
+/* ------------------------------------------------------------------------------------------ */
+
+void or_render_tube(const void* p, const double* kin, int W, int H, double delta, double* depth,
+                    int64_t* idx) {
+    const or_scene* s = (const or_scene*)p;
+    double o00[3], du[3], dv[3];
+    or_screen(p, kin, W, H, o00, du, dv);
+    v3 k = unit(ld(kin));
+    double d2 = delta * delta;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < H; j++) {
+        for (int i = 0; i < W; i++) {
+            v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
+            double bt = INFINITY;
+            int64_t best = -1;
+            for (int64_t m = 0; m < s->n; m++) {
+                v3 w = sub(ld(s->xyz + 3 * m), o);
+                double tc = dot(w, k);
+                if (!(tc > 0)) continue;
+                v3 c = cross(w, k);
+                if (dot(c, c) < d2 && tc < bt) { bt = tc; best = m; }
+            }
+            int64_t q = (int64_t)j * W + i;
+            depth[q] = bt;
+            idx[q] = best;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Bounce recursion for one central ray (c.6).                                                  */
+/* Record per bounce b (22 doubles): x(3) hit point, n(3) oriented normal, kin(3) incoming     */
+/* direction, Eth(3) and Eph(3) incoming field for the two incident polarisations, u(3), v(3) */
+/* incoming tube vectors, d path length to x by the image method.                              */
+/* ------------------------------------------------------------------------------------------ */
+
+#define REC 22
+
+/* polarisation basis (theta-hat, phi-hat) of a direction s (spherical angles of s) */
+static void pol_basis(v3 s, v3* th, v3* ph) {
+    double theta = acos(s.z > 1 ? 1 : (s.z < -1 ? -1 : s.z));
+    double phi = atan2(s.y, s.x);
+    *th = mk(cos(theta) * cos(phi), cos(theta) * sin(phi), -sin(theta));
+    *ph = mk(-sin(phi), cos(phi), 0);
+}
+
+static int trace_ray(const or_scene* s, v3 o, v3 k0, v3 u0, v3 v0, int max_b, double eps,
+                     int use_grid, double* rec, int64_t* hit_idx, int64_t* ntests) {
+    v3 th, ph;
+    pol_basis(scl(k0, -1.0), &th, &ph);
+    v3 k = k0, Et = th, Ep = ph, u = u0, v = v0;
+    double d = dot(k0, o);
+    int M = 0;
+    for (int b = 1; b <= max_b; b++) {
+        double t;
+        int64_t h = first_hit(s, o, k, b == 1 ? 0.0 : eps, use_grid, &t, ntests);
+        if (h < 0) break;
+        if (s->mat[h] != 0) break; /* absorber: the ray ends, nothing recorded */
+        v3 x = add(o, scl(k, t));
+        v3 n = ld(s->nrm + 3 * h);
+        if (dot(n, k) > 0) n = scl(n, -1.0);
+        double* r = rec + (int64_t)(b - 1) * REC;
+        st(r + 0, x); st(r + 3, n); st(r + 6, k); st(r + 9, Et); st(r + 12, Ep);
+        st(r + 15, u); st(r + 18, v); r[21] = d + t;
+        if (hit_idx) hit_idx[b - 1] = h;
+        /* Eq. (4) for k and the tube vectors; Eq. (2)-(3) with Gamma_p = +1, Gamma_v = -1,
+         * which for a PEC plane is E_r = 2 (n.E) n - E. */
+        k = sub(k, scl(n, 2 * dot(n, k)));
+        Et = sub(scl(n, 2 * dot(n, Et)), Et);
+        Ep = sub(scl(n, 2 * dot(n, Ep)), Ep);
+        u = sub(u, scl(n, 2 * dot(n, u)));
+        v = sub(v, scl(n, 2 * dot(n, v)));
+        d += t;
+        o = x;
+        M = b;
+    }
+    return M;
+}
+
+/* Eq. (2)-(3) written as the paper states them: decompose into perpendicular/parallel parts
+ * with e_v = k x n / |k x n|, e_p = e_v x k, apply Gamma, recombine. Exposed for the pin that
+ * checks it against the vector form used in trace_ray. Requires k not parallel to n. */
+void or_reflect_field_decomposed(const double* kin, const double* nin, const double* Ein,
+                                 double* Eout, double* kout) {
+    v3 k = unit(ld(kin)), n = unit(ld(nin)), E = ld(Ein);
+    v3 kr = sub(k, scl(n, 2 * dot(n, k)));
+    v3 ev = unit(cross(k, n));
+    v3 epi = unit(cross(ev, k));
+    v3 epr = unit(cross(ev, kr));
+    double Ep = dot(E, epi), Ev = dot(E, ev);
+    double Gp = 1.0, Gv = -1.0;
+    st(Eout, add(scl(epr, Gp * Ep), scl(ev, Gv * Ev)));
+    st(kout, kr);
+}
+
+void or_reflect_field_vector(const double* kin, const double* nin, const double* Ein,
+                             double* Eout, double* kout) {
+    v3 k = unit(ld(kin)), n = unit(ld(nin)), E = ld(Ein);
+    st(kout, sub(k, scl(n, 2 * dot(n, k))));
+    st(Eout, sub(scl(n, 2 * dot(n, E)), E));
+}
+
+void or_pol_basis(const double* s, double* th, double* ph) {
+    v3 a, b;
+    pol_basis(unit(ld(s)), &a, &b);
+    st(th, a);
+    st(ph, b);
+}
+
+int or_trace_pixels(const void* p, const double* kin, int W, int H, int64_t n_pix,
+                    const int64_t* pix, int max_b, double eps, int use_grid, int32_t* n_bounce,
+                    double* rec, int64_t* hit_idx) {
+    const or_scene* s = (const or_scene*)p;
+    double o00[3], du[3], dv[3];
+    or_screen(p, kin, W, H, o00, du, dv);
+    v3 k = unit(ld(kin));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t m = 0; m < n_pix; m++) {
+        int64_t q = pix[m];
+        int i = (int)(q % W), j = (int)(q / W);
+        v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
+        int64_t nt = 0;
+        n_bounce[m] = trace_ray(s, o, k, ld(du), ld(dv), max_b, eps, use_grid,
+                                rec + m * (int64_t)max_b * REC,
+                                hit_idx ? hit_idx + m * (int64_t)max_b : NULL, &nt);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Field of one facet record toward k_s at wavenumber k (Eq. (11)-(14)).                       */
+/* Readings: the parallelogram area is |u' x v'| (the paper's U'V' equals it when u' and v'   */
+/* are perpendicular); sinc(x) = sin(x)/x; h = k_in x E_in with |E_i| = 1 so eta_0 cancels;    */
+/* time convention exp(+jwt), incident phase exp(-j k.r) about the global origin.              */
+/* Adds  -(j k / 2 pi) * psi * area * S * V * exp(-j k (d - k_s . x))  projected on (th, ph)  */
+/* of k_s for both transmit polarisations: acc[rx][tx][re,im].                                 */
+/* ------------------------------------------------------------------------------------------ */
+
+static inline double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+static void facet_field(const double* r, v3 ks, double kw, v3 rth, v3 rph, double psi,
+                        double acc[2][2][2]) {
+    v3 x = ld(r + 0), n = ld(r + 3), ki = ld(r + 6), u = ld(r + 15), v = ld(r + 18);
+    double d = r[21];
+    double nk = dot(n, ki);
+    v3 up = sub(u, scl(ki, dot(n, u) / nk));   /* Eq. (12) */
+    v3 vp = sub(v, scl(ki, dot(n, v) / nk));   /* Eq. (13) */
+    double area = len(cross(up, vp));
+    v3 q = scl(sub(ki, ks), kw);
+    double S = sinc(0.5 * dot(q, up)) * sinc(0.5 * dot(q, vp));
+    double phase = kw * (d - dot(ks, x));
+    double a0 = psi * area * S * kw / (2 * OR_PI);
+    /* -(j) * exp(-j phase) = -sin(phase) - j cos(phase) */
+    double cre = -a0 * sin(phase), cim = -a0 * cos(phase);
+    for (int tx = 0; tx < 2; tx++) {
+        v3 E = ld(r + (tx == 0 ? 9 : 12));
+        v3 hh = cross(ki, E);
+        v3 V = cross(cross(cross(n, hh), ks), ks);
+        double vp_[2] = {dot(V, rth), dot(V, rph)};
+        for (int rx = 0; rx < 2; rx++) {
+            acc[rx][tx][0] += vp_[rx] * cre;
+            acc[rx][tx][1] += vp_[rx] * cim;
+        }
+    }
+}
+
+/* Full solve (c.6 + c.7): E[inc][obs][freq][rx][tx][re,im].  obs_dir == NULL means monostatic
+ * (k_s = -k_inc).  contrib 0 = last bounce only (Eq. (14)), 1 = every bounce.
+ * Visibility psi of a radiating facet: the ray from x toward k_s with tmin = eps hits nothing.
+ * Summation order: pixels row by row; rows summed in order (independent of thread count).
+ * stats[0] += ray-disk tests, stats[1] += rays traced (queries), stats[2] += radiating facets. */
+int or_solve(const void* p, int n_inc, const double* inc_dir, int n_obs, const double* obs_dir,
+             int n_freq, const double* freq, int W, int H, int max_b, double eps, int contrib,
+             int use_grid, double* E, double* stats) {
+    const or_scene* s = (const or_scene*)p;
+    int mono = obs_dir == NULL;
+    int no = mono ? 1 : n_obs;
+    size_t per_row = (size_t)no * n_freq * 8;
+    double* rows = (double*)malloc(sizeof(double) * per_row * H);
+    int64_t tests = 0, queries = 0, facets = 0;
+    for (int ia = 0; ia < n_inc; ia++) {
+        double o00[3], du[3], dv[3];
+        or_screen(p, inc_dir + 3 * ia, W, H, o00, du, dv);
+        v3 k0 = unit(ld(inc_dir + 3 * ia));
+        memset(rows, 0, sizeof(double) * per_row * H);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : tests, queries, facets)
+        for (int j = 0; j < H; j++) {
+            double* rec = (double*)malloc(sizeof(double) * REC * max_b);
+            double* racc = rows + per_row * j;
+            int64_t nt = 0, nq = 0, nf = 0;
+            for (int i = 0; i < W; i++) {
+                v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
+                int M = trace_ray(s, o, k0, ld(du), ld(dv), max_b, eps, use_grid, rec, NULL, &nt);
+                nq += M + (M < max_b ? 1 : 0);
+                if (M == 0) continue;
+                int b0 = contrib == 1 ? 1 : M;
+                for (int io = 0; io < no; io++) {
+                    v3 ks = mono ? scl(k0, -1.0) : unit(ld(obs_dir + 3 * io));
+                    v3 rth, rph;
+                    pol_basis(ks, &rth, &rph);
+                    for (int b = b0; b <= M; b++) {
+                        const double* r = rec + (int64_t)(b - 1) * REC;
+                        double tv;
+                        int64_t blk = first_hit(s, ld(r), ks, eps, use_grid, &tv, &nt);
+                        nq++;
+                        nf++;
+                        double psi = blk >= 0 ? 0.0 : 1.0;
+                        if (psi == 0.0) continue;
+                        for (int f = 0; f < n_freq; f++) {
+                            double kw = 2 * OR_PI * freq[f] / OR_C0;
+                            double acc[2][2][2] = {{{0}}};
+                            facet_field(r, ks, kw, rth, rph, psi, acc);
+                            double* a = racc + ((size_t)io * n_freq + f) * 8;
+                            for (int t = 0; t < 8; t++) a[t] += (&acc[0][0][0])[t];
+                        }
+                    }
+                }
+            }
+            free(rec);
+            tests += nt;
+            queries += nq;
+            facets += nf;
+        }
+        double* out = E + (size_t)ia * per_row;
+        memset(out, 0, sizeof(double) * per_row);
+        for (int j = 0; j < H; j++)
+            for (size_t t = 0; t < per_row; t++) out[t] += rows[per_row * j + t];
+    }
+    free(rows);
+    if (stats) {
+        stats[0] += (double)tests;
+        stats[1] += (double)queries;
+        stats[2] += (double)facets;
+    }
+    return 0;
+}
+
+int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_num_threads(int n) { omp_set_num_threads(n); }

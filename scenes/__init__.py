@@ -1,0 +1,355 @@
+"""Seeded synthetic scenes and sweep definitions shared by the oracle, the tests and the bench.
+
+This module only produces *inputs*: point positions, unit normals, splat radii, material flags,
+incidence directions, frequencies and the scalar knobs of a run.  It holds none of the method's
+arithmetic (no screens, no intersections, no fields), so the oracle and the HIP path can both
+consume it without sharing any computation.
+
+The paper's own workloads are meshes from a public model repository sampled into 10k-50k point
+clouds, scaled to 20 m and simulated at 500 MHz with a ray spacing of a tenth of a wavelength
+(Sec. IV-A).  Those meshes are not available here; the seeded analytic scenes below stand in for
+them with the same structure (point-sampled PEC surfaces with exact normals, uniform area
+density, optional Gaussian position noise) at electrically larger sizes.
+
+All random numbers come from NumPy's PCG64 with the stated seed.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+C0 = 299_792_458.0  # speed of light in vacuum, m/s
+
+MAT_PEC = 0
+MAT_ABSORBER = 1
+
+
+@dataclass
+class Scene:
+    """A point-sampled surface: positions (n,3) f64, unit normals (n,3) f64, radius, material."""
+
+    xyz: np.ndarray
+    nrm: np.ndarray
+    radius: float | np.ndarray
+    material: np.ndarray
+    name: str = ""
+    noise_sigma: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def radius_array(self) -> np.ndarray:
+        if np.isscalar(self.radius):
+            return np.full(self.n, float(self.radius))
+        return np.asarray(self.radius, dtype=np.float64)
+
+
+@dataclass
+class Sweep:
+    """What to solve on a scene: incidence propagation directions, frequencies and knobs."""
+
+    inc_dir: np.ndarray          # (n_inc, 3) unit propagation directions of the incident wave
+    freq_hz: np.ndarray          # (n_freq,)
+    screen: int                  # square ray screen, pixels per side
+    max_bounces: int
+    eps: float                   # minimum travel distance of secondary rays (m)
+    view_res: int                # resolution of the aggregation views
+    view_dirs: np.ndarray | None = None  # None -> the six axis views
+    obs_dir: np.ndarray | None = None    # None -> monostatic
+    az_deg: np.ndarray | None = None
+    el_deg: float = 0.0
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def azimuth_sweep(az_deg, el_deg: float) -> np.ndarray:
+    """Propagation directions of plane waves arriving FROM azimuth az at elevation el."""
+    az = np.radians(np.asarray(az_deg, dtype=np.float64))
+    el = math.radians(el_deg)
+    src = np.stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az),
+                    np.full_like(az, np.sin(el))], axis=1)
+    return -src
+
+
+def random_unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
+    g = rng.standard_normal((n, 3))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def _random_rotation(rng: np.random.Generator) -> np.ndarray:
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+# ---------------------------------------------------------------------------------------------
+# Dihedral: two square plates meeting at a right angle (the small case the oracle finishes).
+# ---------------------------------------------------------------------------------------------
+
+def dihedral(seed: int = 1, n_side: int = 100, size: float = 0.3, jitter: float = 0.2,
+             radius_factor: float = 1.5) -> Scene:
+    """Plate A on y=0 (normal +y, x in [0,size]), plate B on x=0 (normal +x, y in [0,size]);
+    both span z in [-size/2, size/2].  Each plate is an n_side x n_side cell-centred grid with
+    uniform in-plane jitter of +-jitter*spacing.  Splat radius = radius_factor * spacing."""
+    rng = _rng(seed)
+    s = size / n_side
+    g = (np.arange(n_side) + 0.5) * s
+    a, b = np.meshgrid(g, g - size / 2, indexing="ij")
+    a = a.ravel()
+    b = b.ravel()
+    n = a.size
+    ja = rng.uniform(-jitter * s, jitter * s, n)
+    jb = rng.uniform(-jitter * s, jitter * s, n)
+    plate_a = np.stack([a + ja, np.zeros(n), b + jb], axis=1)
+    ja = rng.uniform(-jitter * s, jitter * s, n)
+    jb = rng.uniform(-jitter * s, jitter * s, n)
+    plate_b = np.stack([np.zeros(n), a + ja, b + jb], axis=1)
+    xyz = np.concatenate([plate_a, plate_b])
+    nrm = np.concatenate([np.tile([0.0, 1.0, 0.0], (n, 1)), np.tile([1.0, 0.0, 0.0], (n, 1))])
+    return Scene(xyz=xyz, nrm=nrm, radius=radius_factor * s, material=np.zeros(2 * n, np.uint8),
+                 name="dihedral", meta=dict(size=size, spacing=s, n_side=n_side))
+
+
+def plate(seed: int = 1, n_side: int = 100, size: float = 0.3, jitter: float = 0.2,
+          radius_factor: float = 1.5) -> Scene:
+    """A single square plate on x=0 with normal +x (plate B of the dihedral, alone)."""
+    d = dihedral(seed, n_side, size, jitter, radius_factor)
+    n = n_side * n_side
+    return Scene(xyz=d.xyz[n:].copy(), nrm=d.nrm[n:].copy(), radius=d.radius,
+                 material=np.zeros(n, np.uint8), name="plate", meta=d.meta)
+
+
+# ---------------------------------------------------------------------------------------------
+# Analytic primitives for the composite scene.
+# ---------------------------------------------------------------------------------------------
+
+def _box_sample(rng, dims, m):
+    a, b, c = dims
+    areas = np.array([b * c, b * c, a * c, a * c, a * b, a * b])
+    face = rng.choice(6, size=m, p=areas / areas.sum())
+    u = rng.uniform(-0.5, 0.5, m)
+    v = rng.uniform(-0.5, 0.5, m)
+    p = np.zeros((m, 3))
+    nrm = np.zeros((m, 3))
+    for f in range(6):
+        sel = face == f
+        axis, sign = f // 2, (1.0 if f % 2 == 0 else -1.0)
+        o1, o2 = [ax for ax in range(3) if ax != axis]
+        p[sel, axis] = sign * dims[axis] / 2
+        p[sel, o1] = u[sel] * dims[o1]
+        p[sel, o2] = v[sel] * dims[o2]
+        nrm[sel, axis] = sign
+    return p, nrm, float(areas.sum())
+
+
+def _cylinder_sample(rng, r, h, m):
+    a_lat = 2 * math.pi * r * h
+    a_cap = math.pi * r * r
+    areas = np.array([a_lat, a_cap, a_cap])
+    part = rng.choice(3, size=m, p=areas / areas.sum())
+    p = np.zeros((m, 3))
+    nrm = np.zeros((m, 3))
+    lat = part == 0
+    phi = rng.uniform(0, 2 * math.pi, lat.sum())
+    p[lat, 0] = r * np.cos(phi)
+    p[lat, 1] = r * np.sin(phi)
+    p[lat, 2] = rng.uniform(-h / 2, h / 2, lat.sum())
+    nrm[lat, 0] = np.cos(phi)
+    nrm[lat, 1] = np.sin(phi)
+    for k, sign in ((1, 1.0), (2, -1.0)):
+        sel = part == k
+        rr = r * np.sqrt(rng.uniform(0, 1, sel.sum()))
+        ph = rng.uniform(0, 2 * math.pi, sel.sum())
+        p[sel, 0] = rr * np.cos(ph)
+        p[sel, 1] = rr * np.sin(ph)
+        p[sel, 2] = sign * h / 2
+        nrm[sel, 2] = sign
+    return p, nrm, float(areas.sum())
+
+
+def _sphere_sample(rng, r, m):
+    d = random_unit_vectors(rng, m)
+    return r * d, d.copy(), 4 * math.pi * r * r
+
+
+def _plate_sample(rng, a, b, m):
+    p = np.zeros((m, 3))
+    p[:, 0] = rng.uniform(-a / 2, a / 2, m)
+    p[:, 1] = rng.uniform(-b / 2, b / 2, m)
+    nrm = np.zeros((m, 3))
+    nrm[:, 2] = 1.0
+    return p, nrm, a * b
+
+
+def _split_counts(n_total: int, areas: np.ndarray) -> np.ndarray:
+    share = n_total * areas / areas.sum()
+    counts = np.floor(share).astype(np.int64)
+    rem = n_total - counts.sum()
+    order = np.argsort(-(share - counts), kind="stable")
+    counts[order[:rem]] += 1
+    return counts
+
+
+def composite(seed: int = 2, n_points: int = 2_000_000, noise_sigma: float | None = None,
+              n_prims: int = 12, slab=(6.0, 6.0, 2.0), radius_factor: float = 1.5) -> Scene:
+    """Twelve primitives cycling box / capped cylinder / sphere / two-sided plate, each with a
+    random orientation, centres in a slab with bounding-sphere rejection (no overlap; a
+    primitive that cannot be placed after 2000 tries is shrunk by 0.85 and tried again).
+    Points are split between primitives by area (uniform density); positions get isotropic
+    Gaussian noise of sigma (default: a fiftieth of the wavelength at 12 GHz); normals are the
+    exact analytic normals at the unperturbed sample.  radius = radius_factor*sqrt(area/N)."""
+    rng = _rng(seed)
+    if noise_sigma is None:
+        noise_sigma = C0 / 12e9 / 50
+    kinds = ["box", "cylinder", "sphere", "plate"]
+    prims = []
+    for i in range(n_prims):
+        kind = kinds[i % 4]
+        if kind == "box":
+            params = rng.uniform(0.2, 2.0, 3)
+        elif kind == "cylinder":
+            params = np.array([rng.uniform(0.1, 1.0), rng.uniform(0.2, 2.0)])
+        elif kind == "sphere":
+            params = np.array([rng.uniform(0.1, 1.0)])
+        else:
+            params = rng.uniform(0.2, 2.0, 2)
+        rot = _random_rotation(rng)
+        prims.append([kind, params, rot, None])
+
+    def bound(kind, p):
+        if kind == "box":
+            return 0.5 * float(np.linalg.norm(p))
+        if kind == "cylinder":
+            return float(math.hypot(p[0], p[1] / 2))
+        if kind == "sphere":
+            return float(p[0])
+        return 0.5 * float(math.hypot(p[0], p[1]))
+
+    placed = []
+    half = np.array(slab) / 2
+    for pr in prims:
+        while True:
+            rb = bound(pr[0], pr[1])
+            ok = False
+            for _ in range(2000):
+                c = rng.uniform(-half, half)
+                if all(np.linalg.norm(c - c2) > rb + r2 for c2, r2 in placed):
+                    ok = True
+                    break
+            if ok:
+                pr[3] = c
+                placed.append((c, rb))
+                break
+            pr[1] = pr[1] * 0.85
+
+    areas = []
+    for kind, p, _, _ in prims:
+        if kind == "box":
+            a, b, c = p
+            areas.append(2 * (a * b + b * c + a * c))
+        elif kind == "cylinder":
+            areas.append(2 * math.pi * p[0] * p[1] + 2 * math.pi * p[0] ** 2)
+        elif kind == "sphere":
+            areas.append(4 * math.pi * p[0] ** 2)
+        else:
+            areas.append(p[0] * p[1])
+    areas = np.array(areas)
+    counts = _split_counts(n_points, areas)
+    xs, ns = [], []
+    for (kind, p, rot, c), m in zip(prims, counts):
+        if kind == "box":
+            pts, nr, _ = _box_sample(rng, p, m)
+        elif kind == "cylinder":
+            pts, nr, _ = _cylinder_sample(rng, p[0], p[1], m)
+        elif kind == "sphere":
+            pts, nr, _ = _sphere_sample(rng, p[0], m)
+        else:
+            pts, nr, _ = _plate_sample(rng, p[0], p[1], m)
+        xs.append(pts @ rot.T + c)
+        ns.append(nr @ rot.T)
+    xyz = np.concatenate(xs)
+    nrm = np.concatenate(ns)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    if noise_sigma > 0:
+        xyz = xyz + rng.normal(0.0, noise_sigma, xyz.shape)
+    radius = radius_factor * math.sqrt(areas.sum() / n_points)
+    meta = dict(prims=[(k, np.asarray(p).tolist(), np.asarray(c).tolist()) for k, p, _, c in prims],
+                area=float(areas.sum()))
+    return Scene(xyz=xyz, nrm=nrm, radius=radius, material=np.zeros(n_points, np.uint8),
+                 name="composite", noise_sigma=noise_sigma, meta=meta)
+
+
+def sphere(seed: int = 3, n_points: int = 4_000_000, a: float = 4.0,
+           noise_sigma: float | None = None, radius_factor: float = 1.5) -> Scene:
+    """Points uniform on a sphere of radius a (normalised Gaussians), radial normals, Gaussian
+    position noise (default: a fiftieth of the wavelength at 24 GHz)."""
+    rng = _rng(seed)
+    if noise_sigma is None:
+        noise_sigma = C0 / 24e9 / 50
+    d = random_unit_vectors(rng, n_points)
+    xyz = a * d
+    if noise_sigma > 0:
+        xyz = xyz + rng.normal(0.0, noise_sigma, xyz.shape)
+    radius = radius_factor * math.sqrt(4 * math.pi * a * a / n_points)
+    return Scene(xyz=xyz, nrm=d, radius=radius, material=np.zeros(n_points, np.uint8),
+                 name="sphere", noise_sigma=noise_sigma, meta=dict(a=a))
+
+
+def random_disks(seed: int, n: int, extent: float = 1.0, r_lo: float = 0.05,
+                 r_hi: float = 0.2, absorber_frac: float = 0.0) -> Scene:
+    """Tiny random clouds for exhaustive tests: centres uniform in a cube, random normals,
+    per-point radii, optionally some absorbers."""
+    rng = _rng(seed)
+    xyz = rng.uniform(-extent / 2, extent / 2, (n, 3))
+    nrm = random_unit_vectors(rng, n)
+    radius = rng.uniform(r_lo, r_hi, n)
+    mat = (rng.uniform(0, 1, n) < absorber_frac).astype(np.uint8)
+    return Scene(xyz=xyz, nrm=nrm, radius=radius, material=mat, name="random_disks")
+
+
+# ---------------------------------------------------------------------------------------------
+# The five workloads.
+# ---------------------------------------------------------------------------------------------
+
+def workload_dihedral() -> tuple[Scene, Sweep]:
+    """Dihedral of two 0.3 m plates, 256^2 screen, 10 GHz, <=2 bounces, azimuth 0..90 deg."""
+    sc = dihedral(seed=1)
+    az = np.arange(0, 91, dtype=np.float64)
+    sw = Sweep(inc_dir=azimuth_sweep(az, 0.0), freq_hz=np.array([10e9]), screen=256,
+               max_bounces=2, eps=0.5 * float(sc.radius), view_res=256, az_deg=az, el_deg=0.0)
+    return sc, sw
+
+
+def workload_composite(n_points: int = 2_000_000, n_az: int = 360, screen: int = 1024,
+                       n_freq: int = 64, max_bounces: int = 4, seed: int = 2) -> tuple[Scene, Sweep]:
+    """Twelve-primitive composite, 1024^2 screen and views, 64 freqs 2-12 GHz, 360 azimuths at
+    30 deg elevation, <=4 bounces."""
+    sc = composite(seed=seed, n_points=n_points)
+    az = np.arange(n_az, dtype=np.float64) * (360.0 / n_az)
+    eps = max(0.5 * float(sc.radius), 6.0 * sc.noise_sigma)
+    sw = Sweep(inc_dir=azimuth_sweep(az, 30.0), freq_hz=np.linspace(2e9, 12e9, n_freq),
+               screen=screen, max_bounces=max_bounces, eps=eps, view_res=screen,
+               az_deg=az, el_deg=30.0)
+    return sc, sw
+
+
+def workload_sphere(n_points: int = 4_000_000, n_az: int = 360, screen: int = 1024,
+                    n_freq: int = 64) -> tuple[Scene, Sweep]:
+    """Sphere r=4 m, 64 freqs 2-24 GHz (ka up to ~2000), 360 azimuths at 0 deg elevation."""
+    sc = sphere(seed=3, n_points=n_points)
+    az = np.arange(n_az, dtype=np.float64) * (360.0 / n_az)
+    eps = max(0.5 * float(sc.radius), 6.0 * sc.noise_sigma)
+    sw = Sweep(inc_dir=azimuth_sweep(az, 0.0), freq_hz=np.linspace(2e9, 24e9, n_freq),
+               screen=screen, max_bounces=4, eps=eps, view_res=screen, az_deg=az, el_deg=0.0)
+    return sc, sw
