@@ -1,0 +1,219 @@
+/*
+ * pointemray.h -- C ABI of the MI355X point-cloud shooting-and-bouncing-ray (SBR) library.
+ *
+ * The problem statement follows the paper: a point cloud carrying normals (PEC targets,
+ * plane-wave excitation, far field, no diffraction -- Sec. I and Sec. II) is intersected by a
+ * screen of central rays (Sec. III-A, Algorithm 1), rays bounce across the geometry recovered
+ * from several views (Sec. III-B, Algorithm 3), and the scattered field is the sum of
+ * physical-optics facet integrals of each ray's last facet (Sec. II-B/C, Eq. (11)-(14)).
+ *
+ * Conventions (all entry points):
+ *   - Units are SI.  Directions are unit 3-vectors in double precision.  An incidence
+ *     direction is the PROPAGATION direction k_i of the incident plane wave; the monostatic
+ *     observation direction is k_s = -k_i.  |E_i| = 1; fields have the far-field factor
+ *     exp(-jkr)/r removed; time convention exp(+jwt).
+ *   - Polarisation basis of a direction s: theta-hat, phi-hat of the spherical angles of s.
+ *     Transmit polarisations use s = -k_i, receive polarisations use s = k_s.
+ *   - Every call returns pe_status: PE_OK (0) or a negative error.  On error no output is
+ *     written and pe_last_error() describes the failure.  No C++ exception crosses the ABI.
+ *   - Device pointers are accessed on the given HIP stream (a hipStream_t passed as void*,
+ *     NULL = the null stream).  Host pointers are read/written before the call returns.
+ *   - The caller owns every buffer it passes.  Handles own their device memory.
+ *   - A pe_ctx binds one HIP device; calls on one context may come from several threads
+ *     (internally serialised); pe_submit/pe_wait/pe_cancel are designed for concurrent use.
+ */
+#ifndef POINTEMRAY_H
+#define POINTEMRAY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pe_status;
+#define PE_OK 0
+#define PE_EINVAL (-1)       /* bad argument: NaN/inf position, zero normal, bad flag, zero size */
+#define PE_ENOMEM (-2)       /* footprint above the context's HBM budget (nothing allocated) */
+#define PE_EDEVICE (-3)      /* HIP runtime error; the context stays usable */
+#define PE_EUNSUPPORTED (-4) /* valid but not implemented combination */
+#define PE_EBUSY (-5)        /* serving queue full */
+#define PE_ECANCELED (-6)    /* request cancelled before completion */
+#define PE_ETIMEOUT (-7)     /* pe_wait timed out; the request is still pending */
+
+typedef struct pe_ctx_s* pe_ctx;
+typedef struct pe_scene_s* pe_scene;
+typedef struct pe_densifier_s* pe_densifier;
+typedef uint64_t pe_ticket;
+
+enum { PE_MEM_HOST = 0, PE_MEM_DEVICE = 1 };
+enum { PE_F32 = 0, PE_F64 = 1 };
+enum { PE_MAT_PEC = 0, PE_MAT_ABSORBER = 1 };
+enum { PE_CONTRIB_LAST = 0, PE_CONTRIB_EVERY = 1 };
+enum { PE_PREC_FP64PHASE = 0, PE_PREC_FP32 = 1 };
+enum { PE_GEOM_PLAIN = 0, PE_GEOM_DENSIFIED = 1 };
+enum { PE_SPLAT_DISK = 0, PE_SPLAT_TUBE = 1 };
+
+/* Scene description (input P of Algorithm 1, with normals and a material flag per point). */
+typedef struct {
+    uint64_t n;              /* number of points, >= 1 */
+    const void* xyz;         /* n x 3 positions, row-major, float or double (xyz_type) */
+    int32_t xyz_type;        /* PE_F32 or PE_F64 */
+    const float* nrm;        /* n x 3 normals (any non-zero length; normalised on ingest) */
+    const uint8_t* material; /* n flags: 0 = PEC, 1 = absorber (occludes, never reflects,
+                                contributes nothing); NULL = all PEC; other values: PE_EINVAL */
+    const float* radius;     /* n splat radii (m), or NULL to use radius_scalar */
+    float radius_scalar;     /* splat radius when radius == NULL; must be > 0 */
+    int32_t mem_kind;        /* PE_MEM_HOST or PE_MEM_DEVICE for xyz/nrm/material/radius */
+    int32_t n_views;         /* aggregation views for the bounce march; 0 = six axis views */
+    const double* view_dirs; /* n_views x 3 propagation directions (host), NULL with n_views=0 */
+    int32_t view_res;        /* square resolution of each aggregation view (16 .. 4096) */
+} pe_scene_desc;
+
+/* Solve description (inputs tx, rx, mb and E_i of Algorithm 3, plus frequencies). */
+typedef struct {
+    int32_t n_inc;           /* number of incidence directions, >= 1 */
+    const double* inc_dir;   /* n_inc x 3 propagation directions (host) */
+    int32_t n_obs;           /* number of observation directions; ignored when obs_dir==NULL */
+    const double* obs_dir;   /* n_obs x 3 scattered propagation directions k_s (host), shared
+                                by every incidence (bistatic); NULL = monostatic k_s = -k_i */
+    int32_t n_freq;          /* >= 1 */
+    const double* freq_hz;   /* n_freq frequencies (host), > 0 */
+    int32_t screen_w;        /* ray screen, pixels; pitch = 2R / max(w, h); w*h <= 2^22 */
+    int32_t screen_h;
+    int32_t max_bounces;     /* >= 1 (1 = physical optics from the first-hit buffer only) */
+    double eps;              /* minimum travel distance of secondary rays (m), >= 0 */
+    int32_t contrib;         /* PE_CONTRIB_LAST (Eq. (14)) or PE_CONTRIB_EVERY */
+    int32_t precision;       /* PE_PREC_FP64PHASE or PE_PREC_FP32 */
+    int32_t geometry;        /* PE_GEOM_PLAIN, or PE_GEOM_DENSIFIED (needs densifier,
+                                max_bounces == 1, screen_w == screen_h, even) */
+    pe_densifier densifier;  /* network used when geometry == PE_GEOM_DENSIFIED */
+    uint64_t seed;           /* reserved for stochastic variants; results do not depend on it */
+} pe_solve_desc;
+
+/* Counters of one solve. */
+typedef struct {
+    double ray_queries;      /* live-ray intersection queries, primary rays included */
+    double exit_records;     /* radiating facet records (per observation direction) */
+    double po_terms;         /* facet x frequency x observation terms summed */
+    double time_ms;          /* wall time of the solve measured on the stream (HIP events) */
+    double march_cap_hits;   /* rays whose march reached the iteration cap (should be 0) */
+    double densifier_fallbacks; /* incidences that fell back to the plain first-hit buffer */
+} pe_stats;
+
+/* Caller-allocated host outputs of a solve.
+ * E:        n_inc x n_obs' x n_freq x 2 (rx: theta, phi) x 2 (tx: theta, phi) x 2 (re, im)
+ *           doubles, n_obs' = 1 when monostatic.
+ * rcs_dbsm: same shape without the last axis; 10 log10(4 pi |E|^2) (may be NULL).
+ * stats:    may be NULL. */
+typedef struct {
+    double* E;
+    double* rcs_dbsm;
+    pe_stats* stats;
+} pe_result;
+
+/* ---- context ---------------------------------------------------------------------------- */
+
+/* Binds HIP device `device`.  hbm_budget = bytes the context may hold (scenes + workspaces);
+ * 0 = 90 % of the device's free memory at creation. */
+pe_status pe_ctx_create(int32_t device, uint64_t hbm_budget, pe_ctx* out);
+pe_status pe_ctx_destroy(pe_ctx ctx);
+/* Bytes currently charged to the context's budget. */
+pe_status pe_ctx_footprint(pe_ctx ctx, uint64_t* bytes, uint64_t* budget);
+
+/* ---- scenes ------------------------------------------------------------------------------ */
+
+/* Ingests the points (validates, recentres on the bounding-box centre, normalises normals,
+ * orders them spatially) and renders the aggregation views with their min/max depth
+ * pyramids; the scene is immutable afterwards and may be shared by concurrent solves.
+ * Errors: PE_EINVAL (bad desc or bad point data), PE_ENOMEM (footprint above budget). */
+pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_stream, pe_scene* out);
+pe_status pe_scene_destroy(pe_scene scene);
+/* Scene frame: centre c (bounding-box centre, m), radius R = max |x_i - c| + r_i, r_max, and
+ * the device bytes the scene holds. */
+pe_status pe_scene_info(pe_scene scene, double centre[3], double* R, double* r_max,
+                        uint64_t* bytes);
+
+/* ---- solving ---------------------------------------------------------------------------- */
+
+/* Synchronous solve: traces every incidence direction on a screen of central rays, bounces
+ * up to max_bounces times and sums the PO field of Eq. (14) for every observation direction
+ * and frequency.  Returns after the results are in the host buffers. */
+pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_result* res,
+                   void* hip_stream);
+
+/* Asynchronous solve through the context's continuous-batching server.  The desc's host
+ * arrays are copied during the call; res buffers must stay valid until pe_wait returns
+ * PE_OK/PE_ECANCELED.  Admission waits until the request's HBM footprint fits the budget.
+ * Errors at submit: PE_EINVAL, PE_ENOMEM (request larger than the whole budget). */
+pe_status pe_submit(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_result* res,
+                    pe_ticket* ticket);
+/* Waits up to timeout_us (< 0 = forever).  Returns the request's status, or PE_ETIMEOUT. */
+pe_status pe_wait(pe_ctx ctx, pe_ticket ticket, int64_t timeout_us);
+/* Cancels a pending or running request; pe_wait then returns PE_ECANCELED. */
+pe_status pe_cancel(pe_ctx ctx, pe_ticket ticket);
+/* Latency/throughput counters of the server since creation (or the last reset):
+ * out[0] completed, out[1] p50 latency ms, out[2] p99 latency ms, out[3] mean ms,
+ * out[4] max concurrent requests on the device, out[5] mean requests per shared launch batch. */
+pe_status pe_server_stats(pe_ctx ctx, double out[6], int32_t reset);
+
+/* ---- inspection hooks (tests) ----------------------------------------------------------- */
+
+/* Geometric frame buffer of one view (Algorithm 1 output without the network):
+ * mode PE_SPLAT_DISK = first disk hit along every pixel's central ray;
+ * mode PE_SPLAT_TUBE = nearest point (along the ray) within tube_radius (m) of the central ray.
+ * Device outputs (any may be NULL), row-major h x w: depth (m, +inf where empty),
+ * nrm (x3, oriented against the ray), idx (input point index, 0xFFFFFFFF where empty),
+ * mask (1 = hit). */
+pe_status pe_render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w, int32_t h,
+                        int32_t mode, double tube_radius, float* depth, float* nrm,
+                        uint32_t* idx, uint8_t* mask, void* hip_stream);
+
+/* Per-pixel bounce records of one incidence (what the PO sum consumes), device outputs,
+ * row-major h x w: n_bounce (0 = no hit), last_x (x3, scene frame: add the centre for world),
+ * last_n (x3, oriented), path (image-method path length to last_x in the scene frame), last_idx
+ * (point index of the last facet).  Any output may be NULL. */
+pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], int32_t w,
+                          int32_t h, int32_t max_bounces, double eps, int32_t* n_bounce,
+                          float* last_x, float* last_n, double* path, uint32_t* last_idx,
+                          void* hip_stream);
+
+/* ---- learned densifier (Sec. III-A, Eq. (15)-(21)) -------------------------------------- */
+
+/* A U-Net densifier: 4 levels with base_ch channels (base_ch, 2, 4, 8 x), ConvNeXt encoder
+ * blocks, max-pool down, sub-pixel-convolution up, one shared encoder and three decoder heads
+ * (depth, normal, hit probability).  Input: coarse depth map (h x w); output: 2h x 2w maps.
+ * Weights are bf16 with fp32 master copies and AdamW state on the device. */
+pe_status pe_densifier_create(pe_ctx ctx, int32_t base_ch, uint64_t seed, pe_densifier* out);
+pe_status pe_densifier_destroy(pe_densifier net);
+pe_status pe_densifier_save(pe_densifier net, const char* path);
+pe_status pe_densifier_load(pe_densifier net, const char* path);
+pe_status pe_densifier_num_params(pe_densifier net, uint64_t* n);
+/* One AdamW step on a batch (device pointers, batch b, coarse size h x w):
+ *   coarse   b x h x w       network input (1 - t/D on hits, 0 elsewhere)
+ *   depth_gt b x 2h x 2w     normalised depth target (t/D), valid where mask_gt = 1
+ *   nrm_gt   b x 2h x 2w x 3 unit normals in the view frame (u, v, w), valid where mask_gt = 1
+ *   mask_gt  b x 2h x 2w     0/1
+ * loss_out (host, 5 doubles): total, L1..L4 of Eq. (17)-(20) weighted as in Eq. (21).
+ * lr: learning rate of this step; weight_decay: AdamW decoupled decay. */
+pe_status pe_densifier_train_step(pe_densifier net, int32_t b, int32_t h, int32_t w,
+                                  const float* coarse, const float* depth_gt, const float* nrm_gt,
+                                  const float* mask_gt, float lr, float weight_decay,
+                                  double* loss_out, void* hip_stream);
+/* Inference: outputs (device, may be NULL) depth b x 2h x 2w, nrm b x 2h x 2w x 3 (unit,
+ * view frame), prob b x 2h x 2w (hit probability). */
+pe_status pe_densifier_infer(pe_densifier net, int32_t b, int32_t h, int32_t w,
+                             const float* coarse, float* depth, float* nrm, float* prob,
+                             void* hip_stream);
+
+/* ---- errors ------------------------------------------------------------------------------ */
+
+/* Thread-local description of the last failure on the calling thread (valid until the next
+ * call on that thread). */
+const char* pe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POINTEMRAY_H */

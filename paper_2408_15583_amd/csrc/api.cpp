@@ -1,0 +1,499 @@
+// C ABI entry points of the SBR library (include/pointemray.h): contexts, scenes, synchronous
+// solves and the inspection hooks.  No C++ exception crosses this boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pe_device.h"
+#include "pe_runtime.h"
+#include "pointemray.h"
+
+using namespace pe;
+
+#define API_BEGIN try {
+#define API_END                                                              \
+    }                                                                        \
+    catch (const Error& e) {                                                 \
+        return set_error(e.status, e.msg);                                   \
+    }                                                                        \
+    catch (const std::bad_alloc&) {                                          \
+        return set_error(PE_ENOMEM, "host allocation failed");               \
+    }                                                                        \
+    catch (const std::exception& e) {                                        \
+        return set_error(PE_EDEVICE, std::string("internal error: ") + e.what()); \
+    }                                                                        \
+    catch (...) {                                                            \
+        return set_error(PE_EDEVICE, "internal error");                      \
+    }
+
+namespace pe {
+
+void scene_release_server(pe_ctx ctx);  // server.cpp
+void server_shutdown(pe_ctx ctx);       // server.cpp
+
+static bool finite3(const double* v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]) &&
+           (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) > 0;
+}
+
+// Shared by pe_solve and pe_submit.
+void validate_solve(pe_scene sc, const pe_solve_desc* d) {
+    if (!sc || !d) throw Error{PE_EINVAL, "null scene or descriptor"};
+    if (d->n_inc < 1 || !d->inc_dir) throw Error{PE_EINVAL, "need n_inc >= 1 incidence directions"};
+    for (int i = 0; i < d->n_inc; i++)
+        if (!finite3(d->inc_dir + 3 * i)) throw Error{PE_EINVAL, "non-finite or zero incidence direction"};
+    if (d->obs_dir) {
+        if (d->n_obs < 1) throw Error{PE_EINVAL, "n_obs must be >= 1 with obs_dir"};
+        for (int i = 0; i < d->n_obs; i++)
+            if (!finite3(d->obs_dir + 3 * i)) throw Error{PE_EINVAL, "non-finite or zero observation direction"};
+    }
+    if (d->n_freq < 1 || !d->freq_hz) throw Error{PE_EINVAL, "need n_freq >= 1 frequencies"};
+    for (int f = 0; f < d->n_freq; f++)
+        if (!(d->freq_hz[f] > 0) || !std::isfinite(d->freq_hz[f])) throw Error{PE_EINVAL, "frequencies must be finite and > 0"};
+    if (d->screen_w < 1 || d->screen_h < 1 || (uint64_t)d->screen_w * d->screen_h > (1u << kPixBits))
+        throw Error{PE_EINVAL, "screen must hold 1 .. 2^22 pixels"};
+    if (d->max_bounces < 1 || d->max_bounces > kMaxBounces) throw Error{PE_EINVAL, "max_bounces must be 1..16"};
+    if (!(d->eps >= 0) || !std::isfinite(d->eps)) throw Error{PE_EINVAL, "eps must be finite and >= 0"};
+    if (d->contrib != PE_CONTRIB_LAST && d->contrib != PE_CONTRIB_EVERY) throw Error{PE_EINVAL, "bad contrib flag"};
+    if (d->precision != PE_PREC_FP64PHASE && d->precision != PE_PREC_FP32) throw Error{PE_EINVAL, "bad precision flag"};
+    if (d->geometry != PE_GEOM_PLAIN && d->geometry != PE_GEOM_DENSIFIED) throw Error{PE_EINVAL, "bad geometry flag"};
+    if (d->geometry == PE_GEOM_DENSIFIED) {
+        if (!d->densifier) throw Error{PE_EINVAL, "densified geometry needs a densifier"};
+        if (d->max_bounces != 1) throw Error{PE_EUNSUPPORTED, "densified geometry supports max_bounces == 1"};
+        if (d->screen_w != d->screen_h || d->screen_w % 16 != 0)
+            throw Error{PE_EINVAL, "densified geometry needs a square screen, multiple of 16"};
+    }
+}
+
+int slots_per_batch(const pe_solve_desc* d) {
+    static const uint64_t target = [] {
+        const char* e = std::getenv("PE_BATCH_PIXELS");
+        return e ? std::strtoull(e, nullptr, 10) : (uint64_t)1 << 25;
+    }();
+    const uint64_t px = (uint64_t)d->screen_w * d->screen_h;
+    uint64_t s = std::max<uint64_t>(1, target / px);
+    s = std::min<uint64_t>(s, (uint64_t)kMaxSlots);
+    s = std::min<uint64_t>(s, (uint64_t)d->n_inc);
+    return (int)s;
+}
+
+std::vector<SlotSpec> make_slots(pe_scene sc, const pe_solve_desc* d, int i0, int count) {
+    std::vector<SlotSpec> v(count);
+    for (int i = 0; i < count; i++) {
+        SlotSpec& s = v[i];
+        s.sc = sc;
+        for (int a = 0; a < 3; a++) s.k[a] = d->inc_dir[3 * (i0 + i) + a];
+        s.W = d->screen_w;
+        s.H = d->screen_h;
+        s.mode = PE_SPLAT_DISK;
+        s.max_b = d->max_bounces;
+        s.eps = d->eps;
+        s.obs = d->obs_dir;
+        s.n_obs = d->obs_dir ? d->n_obs : 1;
+        s.n_freq = d->n_freq;
+        s.freq = d->freq_hz;
+    }
+    return v;
+}
+
+// Runs one batch to completion (re-running with a larger tile list if it overflowed).
+void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>& slots,
+                     int contrib, int precision, double* E_host, double* rcs_host,
+                     pe_stats* acc) {
+    Batch b(ws, st);
+    b.setup(slots, contrib, precision);
+    uint32_t c[kNumCounters];
+    for (int attempt = 0;; attempt++) {
+        b.splat();
+        b.raygen();
+        b.trace(true);
+        b.field(E_host, rcs_host);
+        b.read_counters(c);
+        if (!b.overflowed(c)) break;
+        if (attempt > 3) throw Error{PE_EDEVICE, "tile list overflow persists"};
+        b.setup(slots, contrib, precision);
+    }
+    if (acc) {
+        acc->ray_queries += b.queries(c);
+        const double recs = b.records_made(c) * b.max_obs;
+        acc->exit_records += recs;
+        acc->po_terms += recs * b.max_freq;
+        acc->march_cap_hits += c[kCounterCap];
+    }
+}
+
+solve_fn g_densified_solve = nullptr;  // set by the densifier module
+
+}  // namespace pe
+
+extern "C" {
+
+const char* pe_last_error(void) { return g_err.c_str(); }
+
+pe_status pe_ctx_create(int32_t device, uint64_t hbm_budget, pe_ctx* out) {
+    API_BEGIN
+    if (!out) return set_error(PE_EINVAL, "null output handle");
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return set_error(PE_EINVAL, "no such HIP device");
+    HIPCHK(hipSetDevice(device));
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    auto ctx = std::make_unique<pe_ctx_s>();
+    ctx->device = device;
+    ctx->budget = hbm_budget ? hbm_budget : (uint64_t)(0.9 * (double)free_b);
+    ctx->ws = new Workspace(ctx.get());
+    *out = ctx.release();
+    return PE_OK;
+    API_END
+}
+
+pe_status pe_ctx_destroy(pe_ctx ctx) {
+    API_BEGIN
+    if (!ctx) return PE_OK;
+    (void)hipSetDevice(ctx->device);
+    server_shutdown(ctx);
+    (void)hipDeviceSynchronize();
+    delete ctx->ws;
+    delete ctx;
+    return PE_OK;
+    API_END
+}
+
+pe_status pe_ctx_footprint(pe_ctx ctx, uint64_t* bytes, uint64_t* budget) {
+    if (!ctx) return set_error(PE_EINVAL, "null context");
+    if (bytes) *bytes = ctx->used.load();
+    if (budget) *budget = ctx->budget;
+    return PE_OK;
+}
+
+pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_stream,
+                          pe_scene* out) {
+    API_BEGIN
+    if (!ctx || !desc || !out) return set_error(PE_EINVAL, "null argument");
+    const pe_scene_desc& d = *desc;
+    if (d.n < 1 || d.n >= (1ull << 31)) return set_error(PE_EINVAL, "n must be 1 .. 2^31-1");
+    if (!d.xyz || !d.nrm) return set_error(PE_EINVAL, "xyz and nrm are required");
+    if (d.xyz_type != PE_F32 && d.xyz_type != PE_F64) return set_error(PE_EINVAL, "bad xyz_type");
+    if (d.mem_kind != PE_MEM_HOST && d.mem_kind != PE_MEM_DEVICE) return set_error(PE_EINVAL, "bad mem_kind");
+    if (!d.radius && !(d.radius_scalar > 0 && std::isfinite(d.radius_scalar)))
+        return set_error(PE_EINVAL, "radius_scalar must be finite and > 0");
+    if (d.view_res < 16 || d.view_res > 4096) return set_error(PE_EINVAL, "view_res must be 16..4096");
+    if (d.n_views < 0 || d.n_views > 64 || (d.n_views > 0 && !d.view_dirs))
+        return set_error(PE_EINVAL, "n_views must be 0..64 with view_dirs");
+    for (int v = 0; v < d.n_views; v++)
+        if (!finite3(d.view_dirs + 3 * v)) return set_error(PE_EINVAL, "non-finite or zero view direction");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint64_t n = d.n;
+    auto sc = std::make_unique<pe_scene_s>();
+    sc->ctx = ctx;
+    sc->n = n;
+
+    struct Tmp {
+        pe_ctx ctx;
+        std::vector<std::pair<void*, size_t>> v;
+        void* get(size_t b) {
+            void* p = ctx_alloc(ctx, b);
+            v.push_back({p, b});
+            return p;
+        }
+        ~Tmp() {
+            (void)hipDeviceSynchronize();
+            for (auto& a : v) ctx_free(ctx, a.first, a.second);
+        }
+    } tmp{ctx, {}};
+
+    const size_t xyz_b = n * 3 * (d.xyz_type == PE_F64 ? 8 : 4);
+    const void* xyz = d.xyz;
+    const float* nrm = d.nrm;
+    const uint8_t* mat = d.material;
+    const float* rad = d.radius;
+    if (d.mem_kind == PE_MEM_HOST) {
+        void* p = tmp.get(xyz_b);
+        HIPCHK(hipMemcpyAsync(p, d.xyz, xyz_b, hipMemcpyHostToDevice, st));
+        xyz = p;
+        p = tmp.get(n * 12);
+        HIPCHK(hipMemcpyAsync(p, d.nrm, n * 12, hipMemcpyHostToDevice, st));
+        nrm = (const float*)p;
+        if (d.material) {
+            p = tmp.get(n);
+            HIPCHK(hipMemcpyAsync(p, d.material, n, hipMemcpyHostToDevice, st));
+            mat = (const uint8_t*)p;
+        }
+        if (d.radius) {
+            p = tmp.get(n * 4);
+            HIPCHK(hipMemcpyAsync(p, d.radius, n * 4, hipMemcpyHostToDevice, st));
+            rad = (const float*)p;
+        }
+    }
+    const int nb = (int)std::min<uint64_t>(1024, (n + 255) / 256);
+    double* part = (double*)tmp.get(sizeof(double) * 8 * nb);
+    std::vector<double> hp(8 * nb);
+    launch_ingest_stats(xyz, d.xyz_type == PE_F64, nrm, mat, rad, d.radius_scalar, n, part, nb, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * 8 * nb, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, bad = 0;
+    for (int b = 0; b < nb; b++) {
+        for (int a = 0; a < 3; a++) {
+            lo[a] = std::min(lo[a], hp[8 * b + a]);
+            hi[a] = std::max(hi[a], hp[8 * b + 3 + a]);
+        }
+        bad += hp[8 * b + 6];
+    }
+    if (bad > 0)
+        return set_error(PE_EINVAL, std::to_string((uint64_t)bad) +
+                                        " points with non-finite position, zero normal, bad radius or material");
+    for (int a = 0; a < 3; a++) sc->c[a] = 0.5 * (lo[a] + hi[a]);
+
+    sc->pa = (float4*)sc->alloc(n * 16);
+    sc->pb = (float4*)sc->alloc(n * 16);
+    sc->pa_s = (float4*)sc->alloc(n * 16);
+    sc->pb_s = (float4*)sc->alloc(n * 16);
+    launch_ingest_pack(xyz, d.xyz_type == PE_F64, nrm, mat, rad, d.radius_scalar, n, sc->c[0],
+                       sc->c[1], sc->c[2], sc->pa, sc->pb, part, nb, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < nb; b++) {
+        sc->R = std::max(sc->R, hp[2 * b]);
+        sc->r_max = std::max(sc->r_max, hp[2 * b + 1]);
+    }
+
+    // spatial order: counting sort by the Morton code of a 64^3 grid over the bounding box
+    const int ncell = 64 * 64 * 64;
+    double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    if (!(ext > 0)) ext = 1.0;
+    uint32_t* cell_of = (uint32_t*)tmp.get(n * 4);
+    uint32_t* counts = (uint32_t*)tmp.get(4 * (ncell + 1));
+    uint32_t* offs = (uint32_t*)tmp.get(4 * (ncell + 1));
+    uint32_t* cursor = (uint32_t*)tmp.get(4 * ncell);
+    launch_fill_u32(counts, 0u, ncell, st);
+    launch_fill_u32(cursor, 0u, ncell, st);
+    launch_morton_count(sc->pa, n, (float)(lo[0] - sc->c[0]), (float)(lo[1] - sc->c[1]),
+                        (float)(lo[2] - sc->c[2]), (float)(64.0 / (ext * (1 + 1e-6))), cell_of,
+                        counts, st);
+    launch_scan(counts, offs, ncell, nullptr, 1, offs + ncell, st);
+    launch_morton_scatter(sc->pa, sc->pb, n, cell_of, offs, cursor, sc->pa_s, sc->pb_s, st);
+    HIPCHK(hipGetLastError());
+
+    // aggregation views
+    std::vector<double> dirs;
+    if (d.n_views > 0) {
+        dirs.assign(d.view_dirs, d.view_dirs + 3 * d.n_views);
+    } else {
+        const double ax[18] = {1, 0, 0, -1, 0, 0, 0, 1, 0, 0, -1, 0, 0, 0, 1, 0, 0, -1};
+        dirs.assign(ax, ax + 18);
+    }
+    const int V = (int)dirs.size() / 3;
+    std::vector<SlotSpec> vs(V);
+    for (int v = 0; v < V; v++) {
+        vs[v].sc = sc.get();
+        for (int a = 0; a < 3; a++) vs[v].k[a] = dirs[3 * v + a];
+        vs[v].W = vs[v].H = d.view_res;
+        vs[v].mode = PE_SPLAT_DISK;
+    }
+    Batch b(*ctx->ws, st);
+    b.setup(vs, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
+    uint32_t c[kNumCounters];
+    for (int attempt = 0;; attempt++) {
+        b.splat();
+        b.read_counters(c);
+        if (!b.overflowed(c)) break;
+        if (attempt > 3) return set_error(PE_EDEVICE, "tile list overflow persists");
+        b.setup(vs, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
+    }
+    sc->views.resize(V);
+    for (int v = 0; v < V; v++) {
+        ViewDesc& vd = sc->views[v];
+        const SlotDesc& sd = b.hd[v];
+        std::memset(&vd, 0, sizeof vd);
+        for (int a = 0; a < 3; a++) {
+            vd.u[a] = sd.u[a];
+            vd.v[a] = sd.v[a];
+            vd.k[a] = sd.k[a];
+        }
+        vd.pitch = sd.pitch;
+        vd.R = sd.R;
+        vd.W = sd.W;
+        vd.H = sd.H;
+        int w = sd.W, h = sd.H, L = 0;
+        uint64_t off = 0;
+        for (;;) {
+            vd.lvl_off[L] = (uint32_t)off;
+            vd.lvl_w[L] = w;
+            vd.lvl_h[L] = h;
+            off += (uint64_t)w * h;
+            L++;
+            if ((w == 1 && h == 1) || L == kMaxLevels) break;
+            w = (w + 1) / 2;
+            h = (h + 1) / 2;
+        }
+        vd.levels = L;
+        uint32_t* idx = (uint32_t*)sc->alloc((uint64_t)sd.W * sd.H * 4);
+        float2* hiz = (float2*)sc->alloc(off * 8);
+        vd.idx = idx;
+        vd.hiz = hiz;
+        launch_view_level0(b.keys + sd.pix_base, sd.W, sd.H, idx, hiz, st);
+        for (int l = 1; l < L; l++)
+            launch_hiz_down(hiz + vd.lvl_off[l - 1], vd.lvl_w[l - 1], vd.lvl_h[l - 1],
+                            hiz + vd.lvl_off[l], vd.lvl_w[l], vd.lvl_h[l], st);
+    }
+    sc->views_dev = (ViewDesc*)sc->alloc(sizeof(ViewDesc) * V);
+    HIPCHK(hipMemcpyAsync(sc->views_dev, sc->views.data(), sizeof(ViewDesc) * V,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    *out = sc.release();
+    return PE_OK;
+    API_END
+}
+
+pe_status pe_scene_destroy(pe_scene scene) {
+    API_BEGIN
+    if (!scene) return PE_OK;
+    (void)hipSetDevice(scene->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete scene;
+    return PE_OK;
+    API_END
+}
+
+pe_status pe_scene_info(pe_scene scene, double centre[3], double* R, double* r_max,
+                        uint64_t* bytes) {
+    if (!scene) return set_error(PE_EINVAL, "null scene");
+    if (centre)
+        for (int a = 0; a < 3; a++) centre[a] = scene->c[a];
+    if (R) *R = scene->R;
+    if (r_max) *r_max = scene->r_max;
+    if (bytes) *bytes = scene->bytes;
+    return PE_OK;
+}
+
+pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_result* res,
+                   void* hip_stream) {
+    API_BEGIN
+    if (!ctx || !res || !res->E) return set_error(PE_EINVAL, "null context or result buffer");
+    validate_solve(scene, desc);
+    if (scene->ctx != ctx) return set_error(PE_EINVAL, "scene belongs to another context");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    pe_stats acc{};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    if (desc->geometry == PE_GEOM_DENSIFIED) {
+        if (!g_densified_solve) return set_error(PE_EUNSUPPORTED, "densifier module unavailable");
+        g_densified_solve(*ctx->ws, st, scene, desc, res->E, res->rcs_dbsm, &acc);
+    } else {
+        const int per = slots_per_batch(desc);
+        const int n_obs = desc->obs_dir ? desc->n_obs : 1;
+        const uint64_t per_inc = (uint64_t)n_obs * desc->n_freq * 4;
+        for (int i0 = 0; i0 < desc->n_inc; i0 += per) {
+            const int cnt = std::min(per, desc->n_inc - i0);
+            run_field_batch(*ctx->ws, st, make_slots(scene, desc, i0, cnt), desc->contrib,
+                            desc->precision, res->E + i0 * per_inc * 2,
+                            res->rcs_dbsm ? res->rcs_dbsm + i0 * per_inc : nullptr, &acc);
+        }
+    }
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    acc.time_ms = ms;
+    if (res->stats) *res->stats = acc;
+    return PE_OK;
+    API_END
+}
+
+pe_status pe_render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w, int32_t h,
+                        int32_t mode, double tube_radius, float* depth, float* nrm,
+                        uint32_t* idx, uint8_t* mask, void* hip_stream) {
+    API_BEGIN
+    if (!ctx || !scene || !dir) return set_error(PE_EINVAL, "null argument");
+    if (!finite3(dir)) return set_error(PE_EINVAL, "non-finite or zero direction");
+    if (w < 1 || h < 1 || (uint64_t)w * h > (1u << kPixBits)) return set_error(PE_EINVAL, "bad screen size");
+    if (mode != PE_SPLAT_DISK && mode != PE_SPLAT_TUBE) return set_error(PE_EINVAL, "bad mode");
+    if (mode == PE_SPLAT_TUBE && !(tube_radius > 0 && std::isfinite(tube_radius)))
+        return set_error(PE_EINVAL, "tube_radius must be > 0");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<SlotSpec> s(1);
+    s[0].sc = scene;
+    for (int a = 0; a < 3; a++) s[0].k[a] = dir[a];
+    s[0].W = w;
+    s[0].H = h;
+    s[0].mode = mode;
+    s[0].tube_r = tube_radius;
+    Batch b(*ctx->ws, st);
+    b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
+    uint32_t c[kNumCounters];
+    for (int attempt = 0;; attempt++) {
+        b.splat();
+        b.read_counters(c);
+        if (!b.overflowed(c)) break;
+        if (attempt > 3) return set_error(PE_EDEVICE, "tile list overflow persists");
+        b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
+    }
+    launch_resolve(b.dd, b.keys, depth, nrm, idx, mask, w * h, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return PE_OK;
+    API_END
+}
+
+pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], int32_t w,
+                          int32_t h, int32_t max_bounces, double eps, int32_t* n_bounce,
+                          float* last_x, float* last_n, double* path, uint32_t* last_idx,
+                          void* hip_stream) {
+    API_BEGIN
+    if (!ctx || !scene || !inc_dir) return set_error(PE_EINVAL, "null argument");
+    if (!finite3(inc_dir)) return set_error(PE_EINVAL, "non-finite or zero direction");
+    if (w < 1 || h < 1 || (uint64_t)w * h > (1u << kPixBits)) return set_error(PE_EINVAL, "bad screen size");
+    if (max_bounces < 1 || max_bounces > kMaxBounces) return set_error(PE_EINVAL, "max_bounces must be 1..16");
+    if (!(eps >= 0) || !std::isfinite(eps)) return set_error(PE_EINVAL, "eps must be >= 0");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<SlotSpec> s(1);
+    s[0].sc = scene;
+    for (int a = 0; a < 3; a++) s[0].k[a] = inc_dir[a];
+    s[0].W = w;
+    s[0].H = h;
+    s[0].max_b = max_bounces;
+    s[0].eps = eps;
+    Batch b(*ctx->ws, st);
+    b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
+    uint32_t c[kNumCounters];
+    for (int attempt = 0;; attempt++) {
+        b.splat();
+        b.raygen();
+        b.trace(false);
+        b.read_counters(c);
+        if (!b.overflowed(c)) break;
+        if (attempt > 3) return set_error(PE_EDEVICE, "tile list overflow persists");
+        b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
+    }
+    launch_trace_out(b.dd, nullptr, nullptr, b.rs, n_bounce, last_x, last_n, path, last_idx,
+                     (w * h + 255) / 256, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return PE_OK;
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,480 @@
+// Scene ingest and the splat raster: points carrying normals become oriented disks; every
+// pixel's central ray keeps the nearest disk it crosses (DISK mode) or the nearest point within
+// the tube radius of the central ray (TUBE mode, Algorithm 1 with an unbounded Top-K).
+//
+// MI355X design: points are bucketed once per scene in Morton order of a 64^3 grid so that a
+// wavefront of 64 consecutive points is a compact surface patch; per view, each patch's screen
+// footprint is binned into 16x16-pixel tiles; one workgroup per tile rasterises its patches
+// into an LDS tile of packed 64-bit keys (fp32 depth bits << 32 | point index) with ds_min_u64,
+// then writes the tile once.  The minimum key is the nearest hit with ties going to the lowest
+// index, independent of the order in which patches arrive.
+#include <float.h>
+#include <limits.h>
+
+#include "pe_device.h"
+
+namespace pe {
+
+// ------------------------------------------------------------------------------------------
+// Ingest
+// ------------------------------------------------------------------------------------------
+
+__device__ inline void load_xyz(const void* xyz, int is_f64, uint64_t i, double& x, double& y,
+                                double& z) {
+    if (is_f64) {
+        const double* p = (const double*)xyz + 3 * i;
+        x = p[0]; y = p[1]; z = p[2];
+    } else {
+        const float* p = (const float*)xyz + 3 * i;
+        x = p[0]; y = p[1]; z = p[2];
+    }
+}
+
+// Per-block partials: [lo x, lo y, lo z, hi x, hi y, hi z, bad count, 0].
+__global__ __launch_bounds__(256) void k_ingest_stats(const void* __restrict__ xyz, int is_f64,
+                                                      const float* __restrict__ nrm,
+                                                      const uint8_t* __restrict__ mat,
+                                                      const float* __restrict__ rad,
+                                                      float rad_s, uint64_t n,
+                                                      double* __restrict__ partial) {
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    double bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        double x, y, z;
+        load_xyz(xyz, is_f64, i, x, y, z);
+        const float nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
+        const float nl = nx * nx + ny * ny + nz * nz;
+        const float r = rad ? rad[i] : rad_s;
+        const uint8_t m = mat ? mat[i] : 0;
+        const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
+        const bool ok = fin && nl > 0.f && isfinite(nl) && r > 0.f && isfinite(r) && m <= 1;
+        if (!ok) bad += 1;
+        if (fin) {
+            lo[0] = fmin(lo[0], x); lo[1] = fmin(lo[1], y); lo[2] = fmin(lo[2], z);
+            hi[0] = fmax(hi[0], x); hi[1] = fmax(hi[1], y); hi[2] = fmax(hi[2], z);
+        }
+    }
+    __shared__ double red[7][256];
+    for (int a = 0; a < 3; a++) { red[a][threadIdx.x] = lo[a]; red[3 + a][threadIdx.x] = hi[a]; }
+    red[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int a = 0; a < 3; a++) {
+                red[a][threadIdx.x] = fmin(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+                red[3 + a][threadIdx.x] = fmax(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+            }
+            red[6][threadIdx.x] += red[6][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 7; a++) partial[blockIdx.x * 8 + a] = red[a][0];
+        partial[blockIdx.x * 8 + 7] = 0;
+    }
+}
+
+void launch_ingest_stats(const void* xyz, int is_f64, const float* nrm, const uint8_t* mat,
+                         const float* rad, float rad_scalar, uint64_t n, double* partial,
+                         int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_ingest_stats, dim3(n_blocks), dim3(256), 0, st, xyz, is_f64, nrm, mat,
+                       rad, rad_scalar, n, partial);
+}
+
+// Recentre on c (in fp64, then round), normalise normals, pack (x,y,z,r) and (n, material).
+// Per-block partial: max over points of |x - c| + r (fp64), the scene radius R.
+__global__ __launch_bounds__(256) void k_ingest_pack(const void* __restrict__ xyz, int is_f64,
+                                                     const float* __restrict__ nrm,
+                                                     const uint8_t* __restrict__ mat,
+                                                     const float* __restrict__ rad, float rad_s,
+                                                     uint64_t n, double cx, double cy, double cz,
+                                                     float4* __restrict__ pa,
+                                                     float4* __restrict__ pb,
+                                                     double* __restrict__ partial) {
+    double rmax = 0, radmax = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        double x, y, z;
+        load_xyz(xyz, is_f64, i, x, y, z);
+        const double dx = x - cx, dy = y - cy, dz = z - cz;
+        const float r = rad ? rad[i] : rad_s;
+        const double nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
+        const double il = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+        pa[i] = make_float4((float)dx, (float)dy, (float)dz, r);
+        pb[i] = make_float4((float)(nx * il), (float)(ny * il), (float)(nz * il),
+                            (float)(mat ? mat[i] : 0));
+        rmax = fmax(rmax, sqrt(dx * dx + dy * dy + dz * dz) + (double)r);
+        radmax = fmax(radmax, (double)r);
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = rmax;
+    red[1][threadIdx.x] = radmax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x * 2] = red[0][0];
+        partial[blockIdx.x * 2 + 1] = red[1][0];
+    }
+}
+
+void launch_ingest_pack(const void* xyz, int is_f64, const float* nrm, const uint8_t* mat,
+                        const float* rad, float rad_scalar, uint64_t n, double cx, double cy,
+                        double cz, float4* pa, float4* pb, double* partial, int n_blocks,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_ingest_pack, dim3(n_blocks), dim3(256), 0, st, xyz, is_f64, nrm, mat,
+                       rad, rad_scalar, n, cx, cy, cz, pa, pb, partial);
+}
+
+__device__ inline uint32_t spread3(uint32_t v) {  // 6 bits -> every third bit
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 6; b++) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+__global__ void k_morton_count(const float4* __restrict__ pa, uint64_t n, float lx, float ly,
+                               float lz, float inv, uint32_t* __restrict__ cell_of,
+                               uint32_t* __restrict__ counts) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const float4 a = pa[i];
+        int cx = (int)((a.x - lx) * inv), cy = (int)((a.y - ly) * inv), cz = (int)((a.z - lz) * inv);
+        cx = min(max(cx, 0), 63); cy = min(max(cy, 0), 63); cz = min(max(cz, 0), 63);
+        const uint32_t code = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+        cell_of[i] = code;
+        atomicAdd(&counts[code], 1u);
+    }
+}
+
+void launch_morton_count(const float4* pa, uint64_t n, float lo_x, float lo_y, float lo_z,
+                         float inv_cell, uint32_t* cell_of, uint32_t* counts, hipStream_t st) {
+    int b = (int)((n + 255) / 256);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_morton_count, dim3(b), dim3(256), 0, st, pa, n, lo_x, lo_y, lo_z,
+                       inv_cell, cell_of, counts);
+}
+
+__global__ void k_morton_scatter(const float4* __restrict__ pa, const float4* __restrict__ pb,
+                                 uint64_t n, const uint32_t* __restrict__ cell_of,
+                                 const uint32_t* __restrict__ offsets,
+                                 uint32_t* __restrict__ cursor, float4* __restrict__ pa_s,
+                                 float4* __restrict__ pb_s) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cell_of[i];
+        const uint32_t pos = offsets[c] + atomicAdd(&cursor[c], 1u);
+        const float4 b = pb[i];
+        pa_s[pos] = pa[i];
+        pb_s[pos] = make_float4(b.x, b.y, b.z, __uint_as_float((uint32_t)i));
+    }
+}
+
+void launch_morton_scatter(const float4* pa, const float4* pb, uint64_t n,
+                           const uint32_t* cell_of, const uint32_t* offsets, uint32_t* cursor,
+                           float4* pa_s, float4* pb_s, hipStream_t st) {
+    int b = (int)((n + 255) / 256);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_morton_scatter, dim3(b), dim3(256), 0, st, pa, pb, n, cell_of, offsets,
+                       cursor, pa_s, pb_s);
+}
+
+// ------------------------------------------------------------------------------------------
+// Splat raster
+// ------------------------------------------------------------------------------------------
+
+struct Screen {
+    float u0, u1, u2, v0, v1, v2, k0, k1, k2;
+    float pitch, ipitch, R, hw, hh, tube_r;
+    int W, H, mode;
+};
+
+__device__ inline Screen screen_of(const SlotDesc& d) {
+    Screen s;
+    s.u0 = d.u[0]; s.u1 = d.u[1]; s.u2 = d.u[2];
+    s.v0 = d.v[0]; s.v1 = d.v[1]; s.v2 = d.v[2];
+    s.k0 = d.k[0]; s.k1 = d.k[1]; s.k2 = d.k[2];
+    s.pitch = d.pitch; s.ipitch = 1.0f / d.pitch; s.R = d.R;
+    s.W = d.W; s.H = d.H; s.hw = 0.5f * d.W; s.hh = 0.5f * d.H;
+    s.mode = d.mode; s.tube_r = d.tube_r;
+    return s;
+}
+
+// A point projected on the screen: coordinates along u, v, k; normal components along u, v, k.
+struct Proj {
+    float xa, xb, xk, na, nb, nk, r;
+};
+
+__device__ inline Proj project(const Screen& s, float4 a, float4 b) {
+    Proj p;
+    p.xa = a.x * s.u0 + a.y * s.u1 + a.z * s.u2;
+    p.xb = a.x * s.v0 + a.y * s.v1 + a.z * s.v2;
+    p.xk = a.x * s.k0 + a.y * s.k1 + a.z * s.k2;
+    p.na = b.x * s.u0 + b.y * s.u1 + b.z * s.u2;
+    p.nb = b.x * s.v0 + b.y * s.v1 + b.z * s.v2;
+    p.nk = b.x * s.k0 + b.y * s.k1 + b.z * s.k2;
+    p.r = a.w;
+    return p;
+}
+
+// Inclusive pixel range whose centres can pass the exact test (empty: x0 > x1).  The disk's
+// extent along a screen axis e is r * sqrt(1 - (n.e)^2); a tube's is its radius.
+__device__ inline void footprint(const Screen& s, const Proj& p, int& x0, int& y0, int& x1,
+                                 int& y1) {
+    float ea, eb;
+    if (s.mode == 0) {
+        if (fabsf(p.nk) < kGraze) { x0 = y0 = INT_MAX; x1 = y1 = INT_MIN; return; }
+        ea = p.r * sqrtf(fmaxf(0.f, 1.f - p.na * p.na));
+        eb = p.r * sqrtf(fmaxf(0.f, 1.f - p.nb * p.nb));
+    } else {
+        ea = eb = s.tube_r;
+    }
+    const float ac = p.xa * s.ipitch + s.hw - 0.5f, bc = p.xb * s.ipitch + s.hh - 0.5f;
+    const float ex = ea * s.ipitch + 1e-3f, ey = eb * s.ipitch + 1e-3f;
+    x0 = max(0, (int)ceilf(ac - ex));
+    x1 = min(s.W - 1, (int)floorf(ac + ex));
+    y0 = max(0, (int)ceilf(bc - ey));
+    y1 = min(s.H - 1, (int)floorf(bc + ey));
+}
+
+__global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict__ ds,
+                                                      int4* __restrict__ aabb,
+                                                      uint32_t* __restrict__ tile_count) {
+    const SlotDesc& d = ds[blockIdx.y];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t chunk = blockIdx.x * 4 + wave;
+    if (chunk >= d.n_chunks) return;
+    const Screen s = screen_of(d);
+    const uint32_t i = chunk * kChunk + lane;
+    int x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
+    if (i < d.n_pts) {
+        const Proj p = project(s, d.pa_s[i], d.pb_s[i]);
+        footprint(s, p, x0, y0, x1, y1);
+        if (x0 > x1 || y0 > y1) { x0 = y0 = INT_MAX; x1 = y1 = INT_MIN; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x0 = min(x0, __shfl_xor(x0, o));
+        y0 = min(y0, __shfl_xor(y0, o));
+        x1 = max(x1, __shfl_xor(x1, o));
+        y1 = max(y1, __shfl_xor(y1, o));
+    }
+    if (lane == 0) aabb[d.chunk_base + chunk] = make_int4(x0, y0, x1, y1);
+    if (x0 > x1) return;
+    const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
+    const int ntx = tx1 - tx0 + 1, nt = ntx * (ty1 - ty0 + 1);
+    for (int j = lane; j < nt; j += 64) {
+        const int tx = tx0 + j % ntx, ty = ty0 + j / ntx;
+        atomicAdd(&tile_count[d.tile_base + ty * d.tiles_x + tx], 1u);
+    }
+}
+
+void launch_chunk_bounds(const SlotDesc* d, int n_slots, int max_chunks, int4* aabb,
+                         uint32_t* tile_count, hipStream_t st) {
+    hipLaunchKernelGGL(k_chunk_bounds, dim3((max_chunks + 3) / 4, n_slots), dim3(256), 0, st, d,
+                       aabb, tile_count);
+}
+
+__global__ __launch_bounds__(256) void k_tile_scatter(const SlotDesc* __restrict__ ds,
+                                                      const int4* __restrict__ aabb,
+                                                      const uint32_t* __restrict__ tile_off,
+                                                      uint32_t* __restrict__ cursor,
+                                                      uint32_t* __restrict__ list,
+                                                      uint32_t capacity,
+                                                      uint32_t* __restrict__ overflow) {
+    const SlotDesc& d = ds[blockIdx.y];
+    const uint32_t chunk = blockIdx.x * 256 + threadIdx.x;
+    if (chunk >= d.n_chunks) return;
+    const int4 bb = aabb[d.chunk_base + chunk];
+    if (bb.x > bb.z) return;
+    const int tx0 = bb.x / kTile, tx1 = bb.z / kTile, ty0 = bb.y / kTile, ty1 = bb.w / kTile;
+    for (int ty = ty0; ty <= ty1; ty++)
+        for (int tx = tx0; tx <= tx1; tx++) {
+            const uint32_t t = d.tile_base + ty * d.tiles_x + tx;
+            const uint32_t pos = tile_off[t] + atomicAdd(&cursor[t], 1u);
+            if (pos < capacity) list[pos] = chunk;
+            else atomicOr(overflow, 1u);
+        }
+}
+
+void launch_tile_scatter(const SlotDesc* d, int n_slots, int max_chunks, const int4* aabb,
+                         const uint32_t* tile_off, uint32_t* tile_cursor, uint32_t* list,
+                         uint32_t capacity, uint32_t* overflow, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_scatter, dim3((max_chunks + 255) / 256, n_slots), dim3(256), 0, st,
+                       d, aabb, tile_off, tile_cursor, list, capacity, overflow);
+}
+
+__global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
+                                                const uint32_t* __restrict__ tile_off,
+                                                const uint32_t* __restrict__ tile_count,
+                                                const uint32_t* __restrict__ list,
+                                                uint32_t capacity,
+                                                uint64_t* __restrict__ keys) {
+    const SlotDesc& d = ds[blockIdx.y];
+    const int tile = blockIdx.x;
+    if (tile >= d.tiles_x * d.tiles_y) return;
+    __shared__ unsigned long long lk[kTile * kTile];
+    lk[threadIdx.x] = kEmptyKey;
+    __syncthreads();
+    const Screen s = screen_of(d);
+    const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
+    const int px0 = tx * kTile, py0 = ty * kTile;
+    const int px1 = min(px0 + kTile, s.W) - 1, py1 = min(py0 + kTile, s.H) - 1;
+    const uint32_t beg = tile_off[d.tile_base + tile];
+    const uint32_t cnt = tile_count[d.tile_base + tile];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float zoff = s.R;
+    for (uint32_t e = wave; e < cnt; e += 4) {
+        if (beg + e >= capacity) break;
+        const uint32_t chunk = list[beg + e];
+        const uint32_t i = chunk * kChunk + lane;
+        if (i >= d.n_pts) continue;
+        const float4 a = d.pa_s[i], b = d.pb_s[i];
+        const Proj p = project(s, a, b);
+        int x0, y0, x1, y1;
+        footprint(s, p, x0, y0, x1, y1);
+        x0 = max(x0, px0); x1 = min(x1, px1); y0 = max(y0, py0); y1 = min(y1, py1);
+        if (x0 > x1 || y0 > y1) continue;
+        const uint64_t idx = __float_as_uint(b.w);
+        const float r2 = p.r * p.r;
+        if (s.mode == 0) {
+            const float ink = 1.0f / p.nk;
+            const float tbase = p.xk + zoff;
+            for (int y = y0; y <= y1; y++) {
+                const float dv = (y + 0.5f - s.hh) * s.pitch - p.xb;
+                for (int x = x0; x <= x1; x++) {
+                    const float du = (x + 0.5f - s.hw) * s.pitch - p.xa;
+                    const float dz = -(p.na * du + p.nb * dv) * ink;
+                    if (du * du + dv * dv + dz * dz <= r2) {
+                        const float t = tbase + dz;
+                        if (t > 0.f) {
+                            const uint64_t key = ((uint64_t)__float_as_uint(t) << 32) | idx;
+                            atomicMin(&lk[(y - py0) * kTile + (x - px0)],
+                                      (unsigned long long)key);
+                        }
+                    }
+                }
+            }
+        } else {
+            const float tc = p.xk + zoff;
+            const float d2 = s.tube_r * s.tube_r;
+            if (tc > 0.f) {
+                const uint64_t key = ((uint64_t)__float_as_uint(tc) << 32) | idx;
+                for (int y = y0; y <= y1; y++) {
+                    const float dv = (y + 0.5f - s.hh) * s.pitch - p.xb;
+                    for (int x = x0; x <= x1; x++) {
+                        const float du = (x + 0.5f - s.hw) * s.pitch - p.xa;
+                        if (du * du + dv * dv < d2)
+                            atomicMin(&lk[(y - py0) * kTile + (x - px0)], (unsigned long long)key);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
+    const int x = px0 + lx, y = py0 + ly;
+    if (x < s.W && y < s.H) keys[d.pix_base + (uint64_t)y * s.W + x] = lk[threadIdx.x];
+}
+
+void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
+                   const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
+                   uint64_t* keys, hipStream_t st) {
+    hipLaunchKernelGGL(k_raster, dim3(max_tiles, n_slots), dim3(256), 0, st, d, tile_off,
+                       tile_count, list, capacity, keys);
+}
+
+// Geometric frame buffer of slot 0: depth, oriented normal, index, mask.
+__global__ void k_resolve(const SlotDesc* __restrict__ ds, const uint64_t* __restrict__ keys,
+                          float* __restrict__ depth, float* __restrict__ nrm,
+                          uint32_t* __restrict__ idx, uint8_t* __restrict__ mask, int npix) {
+    const SlotDesc& d = ds[0];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const uint64_t key = keys[d.pix_base + p];
+    if (key == kEmptyKey) {
+        if (depth) depth[p] = __int_as_float(0x7f800000);
+        if (idx) idx[p] = kNone;
+        if (mask) mask[p] = 0;
+        if (nrm) { nrm[3 * p] = 0.f; nrm[3 * p + 1] = 0.f; nrm[3 * p + 2] = 0.f; }
+        return;
+    }
+    const uint32_t i = (uint32_t)(key & 0xFFFFFFFFu);
+    if (depth) depth[p] = __uint_as_float((uint32_t)(key >> 32));
+    if (idx) idx[p] = i;
+    if (mask) mask[p] = 1;
+    if (nrm) {
+        const float4 b = d.pb[i];
+        const float s = (b.x * d.k[0] + b.y * d.k[1] + b.z * d.k[2]) > 0.f ? -1.f : 1.f;
+        nrm[3 * p] = s * b.x; nrm[3 * p + 1] = s * b.y; nrm[3 * p + 2] = s * b.z;
+    }
+}
+
+void launch_resolve(const SlotDesc* d, const uint64_t* keys, float* depth, float* nrm,
+                    uint32_t* idx, uint8_t* mask, int npix, hipStream_t st) {
+    hipLaunchKernelGGL(k_resolve, dim3((npix + 255) / 256), dim3(256), 0, st, d, keys, depth, nrm,
+                       idx, mask, npix);
+}
+
+// Aggregation view, level 0: point indices, and per pixel the min/max depth over its 3x3
+// neighbourhood (the disks the march refines against at that pixel).
+__global__ void k_view_level0(const uint64_t* __restrict__ keys, int W, int H,
+                              uint32_t* __restrict__ idx, float2* __restrict__ hiz0) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= W * H) return;
+    const int x = p % W, y = p / W;
+    idx[p] = (uint32_t)(keys[p] & 0xFFFFFFFFu);
+    float mn = FLT_MAX, mx = -FLT_MAX;
+    for (int dy = -1; dy <= 1; dy++) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= H) continue;
+        for (int dx = -1; dx <= 1; dx++) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= W) continue;
+            const uint64_t k = keys[(uint64_t)yy * W + xx];
+            if (k == kEmptyKey) continue;
+            const float t = __uint_as_float((uint32_t)(k >> 32));
+            mn = fminf(mn, t);
+            mx = fmaxf(mx, t);
+        }
+    }
+    hiz0[p] = make_float2(mn, mx);
+}
+
+void launch_view_level0(const uint64_t* keys, int W, int H, uint32_t* idx, float2* hiz0,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_view_level0, dim3((W * H + 255) / 256), dim3(256), 0, st, keys, W, H,
+                       idx, hiz0);
+}
+
+__global__ void k_hiz_down(const float2* __restrict__ src, int sw, int sh,
+                           float2* __restrict__ dst, int dw, int dh) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= dw * dh) return;
+    const int x = p % dw, y = p / dw;
+    float mn = FLT_MAX, mx = -FLT_MAX;
+    for (int dy = 0; dy < 2; dy++)
+        for (int dx = 0; dx < 2; dx++) {
+            const int xx = 2 * x + dx, yy = 2 * y + dy;
+            if (xx < sw && yy < sh) {
+                const float2 v = src[yy * sw + xx];
+                mn = fminf(mn, v.x);
+                mx = fmaxf(mx, v.y);
+            }
+        }
+    dst[p] = make_float2(mn, mx);
+}
+
+void launch_hiz_down(const float2* src, int sw, int sh, float2* dst, int dw, int dh,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_hiz_down, dim3((dw * dh + 255) / 256), dim3(256), 0, st, src, sw, sh,
+                       dst, dw, dh);
+}
+
+}  // namespace pe

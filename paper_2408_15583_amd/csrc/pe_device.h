@@ -1,0 +1,172 @@
+// Internal structures shared by the HIP kernels and the host runtime of the SBR library.
+// Geometry lives in the scene frame: positions relative to the bounding-box centre c, in fp32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pe {
+
+constexpr int kChunk = 64;          // points per spatial chunk (one wavefront)
+constexpr int kTile = 16;           // screen tile edge (pixels); one workgroup per tile
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr float kGraze = 1e-6f;     // |n.k| below this is a miss (grazing)
+constexpr int kSlotBits = 10;       // list entry = slot << 22 | pixel
+constexpr int kPixBits = 22;
+constexpr int kMaxLevels = 14;
+constexpr int kMaxSlots = 1 << kSlotBits;
+constexpr int kWaveChunk = 64;    // live-list entries per compaction chunk (one wavefront)
+
+// One aggregation view of a scene: a disk first-hit buffer with its min/max depth pyramid.
+struct ViewDesc {
+    float u[3], v[3], k[3];   // screen basis: u, v span the screen, k = propagation
+    float pitch, R;
+    int W, H, levels;
+    const uint32_t* idx;      // W*H point indices (kNone = empty)
+    const float2* hiz;        // all levels concatenated; level 0 is the 3x3-dilated min/max
+    uint32_t lvl_off[kMaxLevels];
+    int lvl_w[kMaxLevels], lvl_h[kMaxLevels];
+};
+
+// One work item of a batched launch: one screen (one incidence) on one scene.
+struct SlotDesc {
+    // scene
+    const float4* pa_s;       // spatially ordered (x, y, z, r)
+    const float4* pb_s;       // spatially ordered (nx, ny, nz, bits(original index))
+    const float4* pa;         // original order (x, y, z, r)
+    const float4* pb;         // original order (nx, ny, nz, material)
+    const ViewDesc* views;
+    uint32_t n_pts, n_chunks;
+    int n_views;
+    float R, r_max;
+    // screen
+    float u[3], v[3], k[3];
+    float pitch;
+    int W, H, tiles_x, tiles_y;
+    int mode;                 // 0 disk, 1 tube
+    float tube_r;
+    // buffers
+    uint64_t pix_base;        // into per-pixel arrays of the batch
+    uint32_t tile_base;       // into per-tile arrays of the batch
+    uint32_t chunk_base;      // into per-chunk arrays of the batch
+    // field
+    float eth[3], eph[3];     // transmit polarisations (theta, phi of -k)
+    float eps;
+    int max_b;
+    int n_obs, obs_base;      // observation descriptors [obs_base, obs_base + n_obs)
+    int mono;
+    int n_freq, freq_base;
+    int out_base;             // output index of (slot, obs 0, freq 0)
+};
+
+struct ObsDesc {
+    float ks[3];              // scattered propagation direction
+    float eth[3], eph[3];     // receive polarisations (theta, phi of ks)
+    double dc;                // (k_i - k_s) . c: phase offset of the scene frame (m)
+};
+
+// Ray state, structure of arrays indexed by batch pixel.  The state of a live ray is the
+// record of its last bounce: hit point, oriented normal, incoming direction, incoming fields
+// for both transmit polarisations, incoming tube vectors, image-method path length to x.
+enum RayComp { RX = 0, RNX = 3, RKX = 6, RETX = 9, REPX = 12, RUX = 15, RVX = 18, RNCOMP = 21 };
+struct RayState {
+    float* f[RNCOMP];
+    double* d;
+    uint8_t* m;               // bounce count of the record
+    uint32_t* hit;            // point index of the record's facet
+};
+
+// Exit (facet) records: frequency-independent part of one term of Eq. (14).
+struct ExitRecs {
+    double* D;                // d - k_s . x (scene frame)
+    float* al;                // (k_in - k_s) . u' / 2
+    float* be;                // (k_in - k_s) . v' / 2
+    float* A[4];              // psi * area * V . e_rx for (rx, tx) = (t,t), (t,p), (p,t), (p,p)
+};
+
+__host__ __device__ inline uint32_t entry_slot(uint32_t e) { return e >> kPixBits; }
+__host__ __device__ inline uint32_t entry_pix(uint32_t e) { return e & ((1u << kPixBits) - 1); }
+__host__ __device__ inline uint32_t make_entry(uint32_t s, uint32_t p) {
+    return (s << kPixBits) | p;
+}
+
+}  // namespace pe
+
+// ----------------------------------------------------------------------------------------------
+// Kernel launchers (defined next to their kernels).  All are asynchronous on `st`.
+// ----------------------------------------------------------------------------------------------
+namespace pe {
+
+// generic
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st);
+// exclusive scan of n items (n = n_static, or ceil(*n_dev / div) if n_dev); writes total.
+void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n_static, const uint32_t* n_dev,
+                 uint32_t div, uint32_t* total, hipStream_t st);
+
+// ingest
+void launch_ingest_stats(const void* xyz, int is_f64, const float* nrm, const uint8_t* mat,
+                         const float* rad, float rad_scalar, uint64_t n, double* partial,
+                         int n_blocks, hipStream_t st);
+void launch_ingest_pack(const void* xyz, int is_f64, const float* nrm, const uint8_t* mat,
+                        const float* rad, float rad_scalar, uint64_t n, double cx, double cy,
+                        double cz, float4* pa, float4* pb, double* partial, int n_blocks,
+                        hipStream_t st);
+void launch_morton_count(const float4* pa, uint64_t n, float lo_x, float lo_y, float lo_z,
+                         float inv_cell, uint32_t* cell_of, uint32_t* counts, hipStream_t st);
+void launch_morton_scatter(const float4* pa, const float4* pb, uint64_t n,
+                           const uint32_t* cell_of, const uint32_t* offsets, uint32_t* cursor,
+                           float4* pa_s, float4* pb_s, hipStream_t st);
+
+// splat pipeline for a batch of slots
+void launch_chunk_bounds(const SlotDesc* d, int n_slots, int max_chunks, int4* aabb,
+                         uint32_t* tile_count, hipStream_t st);
+void launch_tile_scatter(const SlotDesc* d, int n_slots, int max_chunks, const int4* aabb,
+                         const uint32_t* tile_off, uint32_t* tile_cursor, uint32_t* list,
+                         uint32_t capacity, uint32_t* overflow, hipStream_t st);
+void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
+                   const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
+                   uint64_t* keys, hipStream_t st);
+void launch_resolve(const SlotDesc* d, const uint64_t* keys, float* depth, float* nrm,
+                    uint32_t* idx, uint8_t* mask, int npix, hipStream_t st);
+void launch_view_level0(const uint64_t* keys, int W, int H, uint32_t* idx, float2* hiz0,
+                        hipStream_t st);
+void launch_hiz_down(const float2* src, int sw, int sh, float2* dst, int dw, int dh,
+                     hipStream_t st);
+
+// trace
+void launch_raygen_count(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
+                         uint32_t* wg_count, hipStream_t st);
+void launch_raygen_write(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
+                         const uint32_t* wg_off, uint32_t* list, RayState rs, hipStream_t st);
+void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
+                  uint8_t* alive, uint32_t* chunk_count, int bounce, uint32_t* cap_hits,
+                  int n_blocks, hipStream_t st);
+void launch_compact(const uint32_t* list_in, const uint32_t* n_in, const uint8_t* alive,
+                    const uint32_t* chunk_off, uint32_t* list_out, int n_blocks,
+                    hipStream_t st);
+void launch_trace_out(const SlotDesc* d, const uint32_t* list, const uint32_t* n_list,
+                      RayState rs, int32_t* n_bounce, float* last_x, float* last_n,
+                      double* path, uint32_t* last_idx, int n_blocks, hipStream_t st);
+
+// physical optics
+constexpr int kRT = 1024;  // facet records per PO tile
+void launch_po_prep(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
+                    const uint32_t* n_list, RayState rs, const uint64_t* keys, ExitRecs er,
+                    uint32_t rec_stride, int seg, int n_seg, uint32_t* cap_hits, int n_blocks,
+                    hipStream_t st);
+void launch_slot_ranges(const uint32_t* list, const uint32_t* n_list, int n_slots,
+                        uint32_t* beg, uint32_t* cnt, hipStream_t st);
+// tile_prefix gets n_seg*n_slots+1 entries (exclusive prefix, total last); tmp same size.
+void launch_po_tiles(const SlotDesc* d, const uint32_t* seg_cnt, int n_seg, int n_slots, int ft,
+                     uint32_t* tmp, uint32_t* tile_prefix, hipStream_t st);
+void launch_po_sum(const SlotDesc* d, const uint32_t* seg_beg, const uint32_t* seg_cnt,
+                   int n_seg, int n_slots, const double* freq, ExitRecs er, uint32_t rec_stride,
+                   const uint32_t* tile_prefix, int fp32, int ft, double* partial, int n_blocks,
+                   hipStream_t st);
+void launch_po_reduce(const SlotDesc* d, const ObsDesc* obs, int n_slots, int max_obs,
+                      int max_freq, int n_seg, const double* freq, const uint32_t* seg_cnt,
+                      const uint32_t* tile_prefix, int ft, const double* partial, int fp32,
+                      double* E_out, double* rcs_out, hipStream_t st);
+
+}  // namespace pe

@@ -1,0 +1,153 @@
+// Host-side runtime structures of the SBR library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pe_device.h"
+#include "pointemray.h"
+
+namespace pe {
+
+struct Error {
+    pe_status status;
+    std::string msg;
+};
+
+extern thread_local std::string g_err;
+pe_status set_error(pe_status s, const std::string& m);
+void hip_check(hipError_t e, const char* what, int line);
+#define HIPCHK(x) ::pe::hip_check((x), #x, __LINE__)
+
+void screen_basis(const double kin[3], double u[3], double v[3], double k[3]);
+void pol_basis(const double s[3], double th[3], double ph[3]);
+
+void* ctx_alloc(pe_ctx ctx, size_t bytes);
+void ctx_free(pe_ctx ctx, void* p, size_t bytes);
+
+// Growable set of device buffers charged to a context's budget.
+struct Workspace {
+    struct Buf {
+        void* p = nullptr;
+        size_t cap = 0;
+    };
+    pe_ctx ctx = nullptr;
+    Buf bufs[40];
+    explicit Workspace(pe_ctx c) : ctx(c) {}
+    ~Workspace() { release(); }
+    void* raw(int id, size_t bytes);
+    template <class T>
+    T* get(int id, uint64_t count) {
+        return (T*)raw(id, (size_t)count * sizeof(T));
+    }
+    void release();
+    uint64_t bytes() const;
+};
+
+// One screen of one incidence on one scene.
+struct SlotSpec {
+    pe_scene sc = nullptr;
+    double k[3] = {0, 0, -1};
+    int W = 0, H = 0;
+    int mode = PE_SPLAT_DISK;
+    double tube_r = 0;
+    int max_b = 1;
+    double eps = 0;
+    int n_obs = 1;
+    const double* obs = nullptr;  // null: monostatic
+    int n_freq = 1;
+    const double* freq = nullptr;
+};
+
+struct Batch {
+    Workspace& ws;
+    hipStream_t st;
+    std::vector<SlotSpec> spec;
+    std::vector<SlotDesc> hd;
+    std::vector<ObsDesc> ho;
+    std::vector<double> hf;
+    SlotDesc* dd = nullptr;
+    ObsDesc* dobs = nullptr;
+    double* dfreq = nullptr;
+    uint32_t* cnt = nullptr;
+    int n = 0, contrib = 0, precision = 0, n_seg = 1, ft = 1, max_b = 1;
+    int max_chunks = 0, max_tiles = 0, max_pix = 0, max_obs = 1, max_freq = 1, tot_out = 0;
+    uint64_t tot_pix = 0;
+    uint32_t tot_tiles = 0, tot_chunks = 0, tlist_cap = 0, rec_stride = 0;
+    uint64_t* keys = nullptr;
+    RayState rs{};
+    uint32_t* lists[3] = {nullptr, nullptr, nullptr};
+    uint8_t* alive = nullptr;
+    uint32_t *ccount = nullptr, *coff = nullptr, *seg_beg = nullptr, *seg_cnt = nullptr;
+    ExitRecs er{};
+
+    Batch(Workspace& w, hipStream_t s);
+    void setup(const std::vector<SlotSpec>& slots, int contrib, int precision);
+    void splat();
+    void alloc_rays();
+    void raygen();
+    void alloc_records();
+    void records(int seg, const uint32_t* list, const uint32_t* n_list);
+    void trace(bool with_records);
+    void field(double* E_host, double* rcs_host);
+    void read_counters(uint32_t* host);
+    double queries(const uint32_t* c) const;
+    double records_made(const uint32_t* c) const;
+    bool overflowed(const uint32_t* c);
+};
+
+constexpr int kNumCounters = 7 + 64;
+constexpr int kCounterCap = 6;
+constexpr int kMaxBounces = 16;
+
+struct Server;
+struct Densifier;
+
+}  // namespace pe
+
+struct pe_ctx_s {
+    int device = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    std::mutex mu;  // serialises synchronous calls that use the default workspace
+    pe::Workspace* ws = nullptr;
+    pe::Server* server = nullptr;
+    std::mutex server_mu;
+};
+
+struct pe_scene_s {
+    pe_ctx ctx = nullptr;
+    uint64_t n = 0;
+    double c[3] = {0, 0, 0};
+    double R = 0, r_max = 0;
+    float4 *pa = nullptr, *pb = nullptr, *pa_s = nullptr, *pb_s = nullptr;
+    std::vector<pe::ViewDesc> views;
+    pe::ViewDesc* views_dev = nullptr;
+    std::vector<std::pair<void*, size_t>> allocs;
+    uint64_t bytes = 0;
+    void* alloc(size_t b) {
+        void* p = pe::ctx_alloc(ctx, b);
+        allocs.push_back({p, b});
+        bytes += (b + 255) & ~(size_t)255;
+        return p;
+    }
+    ~pe_scene_s() {
+        for (auto& a : allocs) pe::ctx_free(ctx, a.first, a.second);
+    }
+};
+
+namespace pe {
+typedef void (*solve_fn)(Workspace& ws, hipStream_t st, pe_scene sc, const pe_solve_desc* d,
+                         double* E, double* rcs, pe_stats* acc);
+extern solve_fn g_densified_solve;
+void validate_solve(pe_scene sc, const pe_solve_desc* d);
+int slots_per_batch(const pe_solve_desc* d);
+std::vector<SlotSpec> make_slots(pe_scene sc, const pe_solve_desc* d, int i0, int count);
+void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>& slots,
+                     int contrib, int precision, double* E_host, double* rcs_host,
+                     pe_stats* acc);
+}  // namespace pe

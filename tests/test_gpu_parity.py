@@ -1,0 +1,324 @@
+"""GPU path vs the FP64 CPU oracle, element by element, on seeded inputs (needs a HIP device).
+
+Tolerances (stated by the task's parity bar):
+  - hit masks agree on >= 99.9 % of the pixels hit by either side;
+  - depth |dt| <= 1e-5 * D (D = 2R, the screen width) where both hit;
+  - RCS within 0.1 dB at every (angle, freq, pol) where the oracle's sigma is within 30 dB of
+    that curve's peak over angles.
+Index parity is not required on coplanar ties (fp32 vs fp64 can pick different disks of equal
+depth); depth and normal are.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+DB_TOL = 0.1
+DYN = 30.0
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    import paper_2408_15583_amd as pe_mod
+    assert torch.cuda.is_available()
+    return pe_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(pe):
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def dihedral(ctx, pe):
+    sc = scenes.dihedral()
+    s = pe.Scene.from_scene(ctx, sc, view_res=256)
+    o = oracle.OracleScene(sc, grid=64)
+    yield sc, s, o
+    s.close()
+
+
+def rcs_parity(r_gpu, r_or, tol=DB_TOL, dyn=DYN, floor=60.0):
+    """r_*: [angle, obs, freq, rx, tx] dBsm.  Compare where the oracle is within dyn dB of
+    the curve's peak over angles (per obs, freq, rx, tx).  Channels that physical optics makes
+    identically zero (e.g. single-bounce cross-polarisation, 10 log10 of a rounding residue)
+    have no meaningful curve: values more than `floor` dB below the global peak are excluded
+    here and bounded separately in linear field by xpol_bound."""
+    peak = r_or.max(axis=0, keepdims=True)
+    sel = (r_or >= peak - dyn) & (r_or >= r_or.max() - floor)
+    err = np.abs(r_gpu - r_or)[sel]
+    return float(err.max()) if err.size else 0.0, int(sel.sum())
+
+
+def xpol_bound(E_gpu, E_or, rel=1e-3):
+    """|E_gpu - E_or| <= rel * max|E_or| on every channel (covers the zero channels)."""
+    return float(np.abs(E_gpu - E_or).max() / np.abs(E_or).max()) <= rel
+
+
+def mask_agreement(mg, mo):
+    union = (mg | mo).sum()
+    diff = (mg ^ mo).sum()
+    return 1.0 - diff / max(union, 1), diff
+
+
+DIRS = [scenes.azimuth_sweep([a], e)[0] for a, e in [(0, 0), (30, 0), (45, 0), (77, 0), (20, 25),
+                                                       (135, -40)]] + \
+       [np.array(v, float) for v in ([1, 0, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1])]
+
+
+@pytest.mark.parametrize("di", range(len(DIRS)))
+def test_render_disk_dihedral(pe, ctx, dihedral, di):
+    sc, s, o = dihedral
+    k = DIRS[di]
+    W = 128
+    g = pe.render_gfb(ctx, s, k, W, W)
+    dg = g["depth"].cpu().numpy()
+    mg = g["mask"].cpu().numpy().astype(bool)
+    ng = g["nrm"].cpu().numpy()
+    do, io, no, mo = o.render_disk(k, W, W)
+    mo = mo.astype(bool)
+    agree, diff = mask_agreement(mg, mo)
+    assert agree >= 0.999, (agree, diff)
+    both = mg & mo
+    _, R = o.frame()
+    if both.any():
+        assert np.abs(dg[both] - do[both]).max() <= 1e-5 * 2 * R
+        assert np.all(np.einsum("ijk,ijk->ij", ng, no)[both] > 0.9999)
+    else:
+        assert not mg.any() and not mo.any()  # edge-on view of both plates
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_render_disk_random_clouds(pe, ctx, seed):
+    sc = scenes.random_disks(100 + seed, 300, extent=1.0, r_lo=0.02, r_hi=0.1, absorber_frac=0.1)
+    s = pe.Scene.from_scene(ctx, sc, view_res=64)
+    o = oracle.OracleScene(sc)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        k = rng.standard_normal(3)
+        k /= np.linalg.norm(k)
+        g = pe.render_gfb(ctx, s, k, 96, 96)
+        do, io, no, mo = o.render_disk(k, 96, 96)
+        mg = g["mask"].cpu().numpy().astype(bool)
+        agree, diff = mask_agreement(mg, mo.astype(bool))
+        assert agree >= 0.999, (agree, diff)
+        both = mg & mo.astype(bool)
+        ig = g["idx"].cpu().numpy().astype(np.int64)
+        # random disks have no coplanar ties: the index must match where both hit
+        assert (ig[both] == io[both]).mean() >= 0.999
+        dg = g["depth"].cpu().numpy()
+        _, R = o.frame()
+        assert np.abs(dg[both] - do[both]).max() <= 1e-5 * 2 * R
+    s.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_render_tube(pe, ctx, seed):
+    """Ray-tube coarse depth (Algorithm 1, unbounded K): nearest point within delta of the
+    central ray."""
+    sc = scenes.random_disks(200 + seed, 2000, extent=1.0)
+    s = pe.Scene.from_scene(ctx, sc, view_res=32)
+    o = oracle.OracleScene(sc)
+    k = np.array([0.2, 0.3, -0.93])
+    k /= np.linalg.norm(k)
+    W = 64
+    _, R = o.frame()
+    delta = 1.5 * 2 * R / W
+    g = pe.render_gfb(ctx, s, k, W, W, mode="tube", tube_radius=delta)
+    do, io = o.render_tube(k, W, W, delta)
+    mg = g["mask"].cpu().numpy().astype(bool)
+    mo = io >= 0
+    agree, diff = mask_agreement(mg, mo)
+    assert agree >= 0.999, (agree, diff)
+    both = mg & mo
+    ig = g["idx"].cpu().numpy().astype(np.int64)
+    assert (ig[both] == io[both]).mean() >= 0.999
+    dg = g["depth"].cpu().numpy()
+    assert np.abs(dg[both] - do[both]).max() <= 1e-5 * 2 * R
+    s.close()
+
+
+@pytest.mark.parametrize("az", [20.0, 45.0, 70.0])
+def test_trace_dihedral(pe, ctx, dihedral, az):
+    """Per-pixel bounce records after two bounces agree with the oracle's recursion."""
+    sc, s, o = dihedral
+    k = scenes.azimuth_sweep([az], 0.0)[0]
+    W = 128
+    eps = 0.5 * sc.radius
+    g = pe.trace_pixels(ctx, s, k, W, W, 2, eps)
+    nb_g = g["n_bounce"].cpu().numpy().ravel()
+    nb_o, rec, _ = o.trace_pixels(k, W, W, np.arange(W * W), 2, eps)
+    agree = (nb_g == nb_o).mean()
+    assert agree >= 0.995, agree
+    c, R = o.frame()
+    same = (nb_g == nb_o) & (nb_o > 0)
+    xg = g["last_x"].cpu().numpy().reshape(-1, 3)[same] + c
+    xo = rec[same, nb_o[same] - 1, 0:3]
+    assert np.abs(xg - xo).max() <= 1e-4 * 2 * R
+    pg = g["path"].cpu().numpy().ravel()[same]
+    # scene-frame path + k.c is the global image-method path
+    po = rec[same, nb_o[same] - 1, 21] - float(np.dot(k, c))
+    assert np.abs(pg - po).max() <= 1e-4 * 2 * R
+
+
+def test_solve_dihedral_rcs(pe, ctx, dihedral):
+    sc, s, o = dihedral
+    az = np.arange(0, 91, 6, dtype=float)
+    inc = scenes.azimuth_sweep(az, 0.0)
+    eps = 0.5 * sc.radius
+    E, rcs, st = pe.solve(ctx, s, inc, [10e9], 128, max_bounces=2, eps=eps)
+    Eo, _ = o.solve(inc, [10e9], 128, 128, 2, eps)
+    ro = oracle.rcs_dbsm(Eo)
+    err, n = rcs_parity(rcs, ro)
+    assert n > 0
+    assert err <= DB_TOL, err
+    assert np.abs(E[..., 0, 1]).max() <= 1e-4 * np.abs(E).max()
+    assert st["march_cap_hits"] == 0
+    # the library's dBsm equals 10 log10(4 pi |E|^2) of its own field
+    assert np.allclose(rcs, oracle.rcs_dbsm(E), atol=1e-9, equal_nan=True)
+
+
+def test_solve_deterministic(pe, ctx, dihedral):
+    sc, s, o = dihedral
+    inc = scenes.azimuth_sweep([15.0, 45.0], 0.0)
+    a = pe.solve(ctx, s, inc, [9e9, 10e9], 128, max_bounces=2, eps=0.5 * sc.radius)[0]
+    b = pe.solve(ctx, s, inc, [9e9, 10e9], 128, max_bounces=2, eps=0.5 * sc.radius)[0]
+    assert np.array_equal(a, b)
+
+
+def test_frequency_independence(pe, ctx, dihedral):
+    sc, s, o = dihedral
+    inc = scenes.azimuth_sweep([30.0], 0.0)
+    fr = [8e9, 10e9, 12.5e9]
+    E = pe.solve(ctx, s, inc, fr, 128, max_bounces=2, eps=0.5 * sc.radius)[0]
+    for i, f in enumerate(fr):
+        Ei = pe.solve(ctx, s, inc, [f], 128, max_bounces=2, eps=0.5 * sc.radius)[0]
+        assert np.array_equal(E[:, :, i], Ei[:, :, 0])
+
+
+def test_batch_independence(pe, ctx, dihedral):
+    """A result does not depend on which other incidences share its batch."""
+    sc, s, o = dihedral
+    inc = scenes.azimuth_sweep(np.arange(0, 90, 10.0), 0.0)
+    E = pe.solve(ctx, s, inc, [10e9], 96, max_bounces=2, eps=0.5 * sc.radius)[0]
+    for i in (0, 4, 8):
+        Ei = pe.solve(ctx, s, inc[i:i + 1], [10e9], 96, max_bounces=2, eps=0.5 * sc.radius)[0]
+        assert np.array_equal(E[i], Ei[0])
+
+
+@pytest.mark.parametrize("az", [0.0, 2.5, 7.0, 13.0])
+def test_plate_exact_pattern(pe, ctx, az):
+    """The exact plate pattern (whole pixel facets) within 0.01 dB on the GPU."""
+    sc = scenes.plate(jitter=0.0)
+    s = pe.Scene.from_scene(ctx, sc, view_res=64)
+    o = oracle.OracleScene(sc)
+    inc = scenes.azimuth_sweep([az], 0.0)
+    E, rcs, _ = pe.solve(ctx, s, inc, [10e9], 40, max_bounces=1, eps=0.5 * sc.radius)
+    Eo, _ = o.solve(inc, [10e9], 40, 40, 1, 0.5 * sc.radius)
+    ro = oracle.rcs_dbsm(Eo)
+    for p in range(2):
+        assert abs(rcs[0, 0, 0, p, p] - ro[0, 0, 0, p, p]) < 0.01
+        assert abs(E[0, 0, 0, p, 1 - p]) <= 1e-5 * abs(E[0, 0, 0, p, p])
+    s.close()
+
+
+def test_sphere_single_bounce(pe, ctx):
+    """Large sphere, PO: GPU vs oracle (0.1 dB) and vs pi a^2 [...] (oracle's pin bounds)."""
+    a = 0.5
+    sc = scenes.sphere(seed=5, n_points=400_000, a=a, noise_sigma=0.0)
+    s = pe.Scene.from_scene(ctx, sc, view_res=128)
+    o = oracle.OracleScene(sc, grid=160)
+    inc = scenes.azimuth_sweep([0.0, 33.0, 71.0, 200.0], 10.0)
+    fr = [10e9, 20e9]
+    E, rcs, _ = pe.solve(ctx, s, inc, fr, 400, max_bounces=1, eps=0.5 * sc.radius)
+    Eo, _ = o.solve(inc, fr, 400, 400, 1, 0.5 * sc.radius)
+    ro = oracle.rcs_dbsm(Eo)
+    for p in range(2):
+        assert np.abs(rcs[..., p, p] - ro[..., p, p]).max() < DB_TOL
+    s.close()
+
+
+def test_every_mode(pe, ctx, dihedral):
+    sc, s, o = dihedral
+    inc = scenes.azimuth_sweep([20.0, 45.0], 0.0)
+    eps = 0.5 * sc.radius
+    E, rcs, _ = pe.solve(ctx, s, inc, [10e9], 128, max_bounces=2, eps=eps, contrib="every")
+    Eo, _ = o.solve(inc, [10e9], 128, 128, 2, eps, contrib="every")
+    ro = oracle.rcs_dbsm(Eo)
+    for p in range(2):
+        assert np.abs(rcs[..., p, p] - ro[..., p, p]).max() < DB_TOL
+
+
+def test_bistatic_plate(pe, ctx):
+    sc = scenes.plate()
+    s = pe.Scene.from_scene(ctx, sc, view_res=128)
+    o = oracle.OracleScene(sc)
+    inc = scenes.azimuth_sweep([10.0, 25.0], 0.0)
+    obs = -scenes.azimuth_sweep([-10.0, -5.0, 0.0, 3.0], 0.0)
+    E, rcs, _ = pe.solve(ctx, s, inc, [10e9], 96, max_bounces=1, eps=0.5 * sc.radius,
+                         obs_dir=obs)
+    Eo, _ = o.solve(inc, [10e9], 96, 96, 1, 0.5 * sc.radius, obs_dir=obs)
+    ro = oracle.rcs_dbsm(Eo)
+    err, n = rcs_parity(rcs, ro)
+    assert n > 0 and err < DB_TOL, err
+    assert np.abs(E[..., 0, 1]).max() <= 1e-4 * np.abs(E).max()
+    s.close()
+
+
+def test_absorber(pe, ctx):
+    """Absorbing points occlude and never radiate."""
+    sc = scenes.random_disks(7, 400, extent=1.0, r_lo=0.03, r_hi=0.1, absorber_frac=0.3)
+    s = pe.Scene.from_scene(ctx, sc, view_res=64)
+    o = oracle.OracleScene(sc)
+    inc = scenes.azimuth_sweep([0.0, 40.0, 95.0], 20.0)
+    E, rcs, _ = pe.solve(ctx, s, inc, [3e9], 64, max_bounces=1, eps=1e-3)
+    Eo, _ = o.solve(inc, [3e9], 64, 64, 1, 1e-3)
+    ro = oracle.rcs_dbsm(Eo)
+    for p in range(2):
+        assert np.abs(rcs[..., p, p] - ro[..., p, p]).max() < DB_TOL
+    s.close()
+
+
+def test_invalid_inputs(pe, ctx):
+    from paper_2408_15583_amd import _native
+    bad = scenes.random_disks(1, 10)
+    xyz = bad.xyz.copy()
+    xyz[3, 1] = np.nan
+    with pytest.raises(pe.PEError) as e:
+        pe.Scene(ctx, xyz, bad.nrm, 0.1)
+    assert e.value.status == _native.PE_EINVAL
+    nrm = bad.nrm.copy()
+    nrm[2] = 0
+    with pytest.raises(pe.PEError):
+        pe.Scene(ctx, bad.xyz, nrm, 0.1)
+    mat = np.zeros(10, np.uint8)
+    mat[0] = 9
+    with pytest.raises(pe.PEError):
+        pe.Scene(ctx, bad.xyz, bad.nrm, 0.1, mat)
+    s = pe.Scene(ctx, bad.xyz, bad.nrm, 0.1, view_res=32)
+    with pytest.raises(pe.PEError):
+        pe.solve(ctx, s, [[0, 0, 0]], [1e9], 32)
+    with pytest.raises(pe.PEError):
+        pe.solve(ctx, s, [[0, 0, 1]], [-1e9], 32)
+    with pytest.raises(pe.PEError):
+        pe.solve(ctx, s, [[0, 0, 1]], [1e9], 32, max_bounces=0)
+    s.close()
+
+
+def test_budget_enomem(pe):
+    from paper_2408_15583_amd import _native
+    c = pe.Context(0, budget=1 << 20)
+    sc = scenes.random_disks(2, 100_000)
+    with pytest.raises(pe.PEError) as e:
+        pe.Scene(c, sc.xyz, sc.nrm, 0.01, view_res=256)
+    assert e.value.status == _native.PE_ENOMEM
+    assert c.footprint()[0] == 0
+    c.close()
