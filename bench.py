@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain SBR hot path on one MI355X.
+
+Workload (default): the twelve-primitive composite scene sampled to 2,000,000 points, six
+1024^2 aggregation views, a 1024^2 ray screen, 360 monostatic azimuths at 30 deg elevation,
+64 frequencies from 2 to 12 GHz, up to 4 bounces.  One step = one pass of the whole path on
+that input: scene ingest (recentre, normalise, spatial order), the six view buffers with their
+min/max pyramids, then for every azimuth the first-hit splat, ray generation, bounce march,
+visibility, facet records and the PO sum over all frequencies.  Inputs (points, normals) are
+resident in device memory before the timed region.
+
+Prints one JSON line: value = ray-bounces/s (live-ray intersection queries, primary rays
+included, per second of step wall time); extra fields give RCS samples/s, the dominant
+kernel's roofline (HIP events on its launch stream, over the timed steps) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# fp32 vector issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 4 (wave64 over 4 cycles... =
+# 128 lanes/clk/CU) x 2.4 GHz = 78.6 T lane-ops/s (157.3 TFLOP/s counting an FMA as two).
+FP32_LANE_OPS = 256 * 128 * 2.4e9
+
+
+def kernel_models(workload):
+    """Algorithmic work per launch of each kernel, from the workload's sizes.
+    Returns {kernel: (bound, unit, work_fn(stats) -> amount per launch)}."""
+    return {}
+
+
+def po_slots_per_term():
+    """Issue slots (fp32 lane-op equivalents) one PO term needs: fp64 ops count twice (half
+    rate), transcendentals four times (quarter rate)."""
+    fp64 = 1 + 2 + 1 + 8 + 8      # D*rev, floor+sub, cvt f64->f32, 8 cvt f32->f64, 8 adds
+    fp32 = 2 + 2 * 5 + 2 + 4 + 8  # k*al, k*be, two sinc (mul, rcp, mul, cmp, sel), S, 2pi*rf, 8 mul
+    trans = 4                     # sin, cos, two sinc sines
+    return 2 * fp64 + fp32 + 4 * trans
+
+
+def cpu_baseline(sc, sw, sample_px, seed=11):
+    """FP64 oracle (brute force over all disks) tracing a fixed seeded sample of the
+    workload's pixel rays for one azimuth; returns ray-bounces/s on the host."""
+    import numpy as np
+    import oracle
+    o = oracle.OracleScene(sc)
+    rng = np.random.default_rng(seed)
+    pix = rng.choice(sw.screen * sw.screen, size=sample_px, replace=False)
+    t0 = time.perf_counter()
+    nb, _, _ = o.trace_pixels(sw.inc_dir[0], sw.screen, sw.screen, pix, sw.max_bounces, sw.eps,
+                              grid=0)
+    dt = time.perf_counter() - t0
+    q = float(np.sum(nb + (nb < sw.max_bounces)))
+    return dict(value=q / dt, unit="ray-bounces/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{sample_px} seeded pixel rays of azimuth 0 at {sw.screen}^2, "
+                       f"<= {sw.max_bounces} bounces, brute force over all {sc.n} disks "
+                       f"({q:.0f} queries in {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--points", type=int, default=2_000_000)
+    ap.add_argument("--screen", type=int, default=1024)
+    ap.add_argument("--n-az", type=int, default=360)
+    ap.add_argument("--n-freq", type=int, default=64)
+    ap.add_argument("--bounces", type=int, default=4)
+    ap.add_argument("--precision", default="fp64phase", choices=["fp64phase", "fp32"])
+    ap.add_argument("--cpu-sample", type=int, default=3000,
+                    help="pixel rays traced by the CPU oracle (0 = skip)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path shards by "
+              "incidence angle with no exchange, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2408_15583_amd as pe
+    import scenes
+
+    if args.copy_calib:
+        n = (1 << 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+
+    t_gen = time.perf_counter()
+    sc, sw = scenes.workload_composite(n_points=args.points, n_az=args.n_az, screen=args.screen,
+                                       n_freq=args.n_freq, max_bounces=args.bounces)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] scene generated: {sc.n} points, radius {sc.radius*1e3:.2f} mm, "
+          f"eps {sw.eps*1e3:.2f} mm ({t_gen:.1f} s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda")
+    xyz = torch.from_numpy(np.ascontiguousarray(sc.xyz)).to(dev)
+    nrm = torch.from_numpy(np.ascontiguousarray(sc.nrm, dtype=np.float32)).to(dev)
+    torch.cuda.synchronize()
+    ctx = pe.Context(0)
+
+    def step():
+        s = pe.Scene(ctx, xyz, nrm, sc.radius, view_res=sw.view_res)
+        E, rcs, st = pe.solve(ctx, s, sw.inc_dir, sw.freq_hz, sw.screen,
+                              max_bounces=sw.max_bounces, eps=sw.eps, precision=args.precision)
+        s.close()
+        return E, rcs, st
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ctx.kernel_stats(reset=True)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    queries = 0.0
+    terms = 0.0
+    last = None
+    for i in range(args.steps):
+        last = step()
+        queries += last[2]["ray_queries"]
+        terms += last[2]["po_terms"]
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    ks = ctx.kernel_stats(reset=True)
+    dt = t1 - t0
+    ms_step = 1e3 * dt / args.steps
+    E, rcs, st = last
+    finite = np.isfinite(rcs[..., 0, 0]).all() and np.isfinite(rcs[..., 1, 1]).all()
+
+    # dominant kernel and its roofline
+    dom = max(ks.items(), key=lambda kv: kv[1][0])
+    name, (tot_ms, launches) = dom
+    avg_ms = tot_ms / max(launches, 1)
+    if name == "po_sum":
+        per_launch_terms = terms / launches
+        achieved = per_launch_terms * po_slots_per_term() / (avg_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP32_LANE_OPS / 1e12,
+                    unit="T lane-op/s", frac=achieved / (FP32_LANE_OPS / 1e12), traffic=None,
+                    kernel=name, avg_launch_ms=avg_ms, launches=launches,
+                    work_per_launch=f"{per_launch_terms:.4g} terms x {po_slots_per_term()} "
+                                    "fp32-equivalent issue slots")
+    elif name == "raster":
+        per_launch = (32.0 * sc.n + 8.0 * sw.screen * sw.screen) * (launches and
+                                                                    (sw.n_inc_per_launch
+                                                                     if hasattr(sw, "n_inc_per_launch") else 1))
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None, kernel=name,
+                    avg_launch_ms=avg_ms, launches=launches)
+    else:
+        roof = dict(bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s", frac=None,
+                    traffic=None, kernel=name, avg_launch_ms=avg_ms, launches=launches)
+
+    out = {
+        "metric": "ray-bounces/s + RCS samples/s at <=0.1 dB error; p50/p99 solve latency",
+        "value": queries / dt,
+        "unit": "ray-bounces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f32+f64phase",
+        "data": "synthetic",
+        "config": {"workload": f"composite 12 primitives, {sc.n} points, {sw.screen}^2 screen, "
+                               f"6 views at {sw.view_res}^2, {len(sw.inc_dir)} azimuths at 30 deg "
+                               f"elevation, {len(sw.freq_hz)} freqs 2-12 GHz, <= {sw.max_bounces} "
+                               "bounces, monostatic"},
+        "rcs_samples_per_s": len(sw.inc_dir) * len(sw.freq_hz) * args.steps / dt,
+        "ray_queries_per_step": queries / args.steps,
+        "po_terms_per_step": terms / args.steps,
+        "march_cap_hits": st["march_cap_hits"],
+        "rcs_finite": bool(finite),
+        "roofline": roof,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in sorted(ks.items(),
+                                                                        key=lambda kv: -kv[1][0])},
+    }
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(sc, sw, args.cpu_sample)
+    else:
+        out["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -122,6 +122,15 @@ pe_status pe_ctx_destroy(pe_ctx ctx);
 /* Bytes currently charged to the context's budget. */
 pe_status pe_ctx_footprint(pe_ctx ctx, uint64_t* bytes, uint64_t* budget);
 
+/* Per-kernel timing: while enabled, every kernel the pipeline launches is bracketed by HIP
+ * events recorded on its own launch stream; elapsed times accumulate per kernel name. */
+pe_status pe_ctx_set_profiling(pe_ctx ctx, int32_t enable);
+/* Copies up to `cap` entries (kernel name, total ms, launch count) into the caller's arrays
+ * (names point to library-owned strings valid for the process lifetime); *n = number of
+ * kernels recorded (may exceed cap).  reset != 0 clears the table afterwards. */
+pe_status pe_ctx_kernel_stats(pe_ctx ctx, int32_t cap, const char** names, double* total_ms,
+                              uint64_t* launches, int32_t* n, int32_t reset);
+
 /* ---- scenes ------------------------------------------------------------------------------ */
 
 /* Ingests the points (validates, recentres on the bounding-box centre, normalises normals,

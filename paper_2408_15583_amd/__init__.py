@@ -47,6 +47,20 @@ class Context:
         check(lib().pe_ctx_footprint(self.h, ctypes.byref(used), ctypes.byref(bud)))
         return used.value, bud.value
 
+    def set_profiling(self, enable: bool = True):
+        check(lib().pe_ctx_set_profiling(self.h, 1 if enable else 0))
+
+    def kernel_stats(self, reset: bool = False):
+        """{kernel: (total_ms, launches)} recorded with HIP events while profiling is on."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int32()
+        check(lib().pe_ctx_kernel_stats(self.h, cap, names, ms, cnt, ctypes.byref(n),
+                                        1 if reset else 0))
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(n.value, cap))}
+
     def close(self):
         if self.h:
             check(lib().pe_ctx_destroy(self.h))

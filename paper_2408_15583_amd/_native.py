@@ -75,6 +75,9 @@ _SIGS = {
     "pe_ctx_create": [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(pe_ctx)],
     "pe_ctx_destroy": [pe_ctx],
     "pe_ctx_footprint": [pe_ctx, c_u64_p, c_u64_p],
+    "pe_ctx_set_profiling": [pe_ctx, ctypes.c_int32],
+    "pe_ctx_kernel_stats": [pe_ctx, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), c_double_p,
+                            c_u64_p, c_i32_p, ctypes.c_int32],
     "pe_scene_create": [pe_ctx, ctypes.POINTER(pe_scene_desc), ctypes.c_void_p,
                         ctypes.POINTER(pe_scene)],
     "pe_scene_destroy": [pe_scene],

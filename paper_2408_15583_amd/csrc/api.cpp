@@ -174,6 +174,34 @@ pe_status pe_ctx_footprint(pe_ctx ctx, uint64_t* bytes, uint64_t* budget) {
     return PE_OK;
 }
 
+pe_status pe_ctx_set_profiling(pe_ctx ctx, int32_t enable) {
+    if (!ctx) return set_error(PE_EINVAL, "null context");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->profile = enable != 0;
+    return PE_OK;
+}
+
+pe_status pe_ctx_kernel_stats(pe_ctx ctx, int32_t cap, const char** names, double* total_ms,
+                              uint64_t* launches, int32_t* n, int32_t reset) {
+    if (!ctx || !n) return set_error(PE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    static std::map<std::string, const char*> interned;
+    int32_t i = 0;
+    for (const auto& kv : ctx->ktab) {
+        if (i < cap) {
+            auto it = interned.find(kv.first);
+            if (it == interned.end()) it = interned.emplace(kv.first, strdup(kv.first.c_str())).first;
+            if (names) names[i] = it->second;
+            if (total_ms) total_ms[i] = kv.second.first;
+            if (launches) launches[i] = kv.second.second;
+        }
+        i++;
+    }
+    *n = i;
+    if (reset) ctx->ktab.clear();
+    return PE_OK;
+}
+
 pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_stream,
                           pe_scene* out) {
     API_BEGIN

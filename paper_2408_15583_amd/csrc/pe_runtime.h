@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -98,6 +99,21 @@ struct Batch {
     double queries(const uint32_t* c) const;
     double records_made(const uint32_t* c) const;
     bool overflowed(const uint32_t* c);
+    struct Pending {
+        const char* name;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Pending> pend;
+    hipEvent_t pend_begin = nullptr;
+    void prof_begin();
+    void prof_end(const char* name);
+    void prof_flush();
+    ~Batch() {
+        try {
+            prof_flush();
+        } catch (...) {
+        }
+    }
 };
 
 constexpr int kNumCounters = 7 + 64;
@@ -117,6 +133,9 @@ struct pe_ctx_s {
     pe::Workspace* ws = nullptr;
     pe::Server* server = nullptr;
     std::mutex server_mu;
+    bool profile = false;
+    std::mutex prof_mu;
+    std::map<std::string, std::pair<double, uint64_t>> ktab;  // kernel -> (total ms, launches)
 };
 
 struct pe_scene_s {

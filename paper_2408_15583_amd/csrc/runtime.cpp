@@ -290,11 +290,19 @@ void Batch::splat() {
     keys = ws.get<uint64_t>(B_KEYS, tot_pix);
     launch_fill_u32(tcount, 0u, tot_tiles, st);
     launch_fill_u32(tcursor, 0u, tot_tiles, st);
+    prof_begin();
     launch_chunk_bounds(dd, n, max_chunks, aabb, tcount, st);
+    prof_end("chunk_bounds");
+    prof_begin();
     launch_scan(tcount, toff, tot_tiles, nullptr, 1, cnt + C_TILES, st);
+    prof_end("tile_scan");
+    prof_begin();
     launch_tile_scatter(dd, n, max_chunks, aabb, toff, tcursor, tlist, tlist_cap,
                         cnt + C_OVERFLOW, st);
+    prof_end("tile_scatter");
+    prof_begin();
     launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, st);
+    prof_end("raster");
     HIPCHK(hipGetLastError());
 }
 
@@ -319,9 +327,15 @@ void Batch::raygen() {
     const int gx = (max_pix + 255) / 256;
     uint32_t* wgc = ws.get<uint32_t>(B_WGC, (uint64_t)gx * n + 1);
     uint32_t* wgo = ws.get<uint32_t>(B_WGO, (uint64_t)gx * n + 1);
+    prof_begin();
     launch_raygen_count(dd, n, max_pix, keys, wgc, st);
+    prof_end("raygen_count");
+    prof_begin();
     launch_scan(wgc, wgo, (uint32_t)(gx * n), nullptr, 1, cnt + C_N0, st);
+    prof_end("raygen_scan");
+    prof_begin();
     launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, st);
+    prof_end("raygen_write");
     HIPCHK(hipGetLastError());
 }
 
@@ -338,10 +352,14 @@ void Batch::alloc_records() {
 }
 
 void Batch::records(int seg, const uint32_t* list, const uint32_t* n_list) {
+    prof_begin();
     launch_po_prep(dd, dobs, list, n_list, rs, keys, er, rec_stride, seg, n_seg, cnt + C_CAP,
                    persistent_blocks(), st);
+    prof_end("po_prep");
+    prof_begin();
     launch_slot_ranges(list, n_list, n, seg_beg + (uint64_t)seg * n, seg_cnt + (uint64_t)seg * n,
                        st);
+    prof_end("slot_ranges");
 }
 
 // Bounces 2..max_b.  For LAST the first-hit list is kept intact: every ray's state ends as its
@@ -354,9 +372,15 @@ void Batch::trace(bool with_records) {
     for (int b = 2; b <= max_b; b++) {
         uint32_t* out = lists[b % 2 == 0 ? 1 : 2];
         uint32_t* nout = cnt + (b % 2 == 0 ? C_N1 : C_N2);
+        prof_begin();
         launch_march(dd, cur, ncur, rs, alive, ccount, b, cnt + C_CAP, persistent_blocks(), st);
+        prof_end("march");
+        prof_begin();
         launch_scan(ccount, coff, 0, ncur, kWaveChunk, nout, st);
+        prof_end("compact_scan");
+        prof_begin();
         launch_compact(cur, ncur, alive, coff, out, persistent_blocks(), st);
+        prof_end("compact");
         HIPCHK(hipMemcpyAsync(cnt + C_BOUNCE0 + b, ncur, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(cnt + C_BOUNCE0 + 32 + b, nout, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
         if (with_records && contrib == PE_CONTRIB_EVERY) records(b - 1, out, nout);
@@ -375,11 +399,17 @@ void Batch::field(double* E_host, double* rcs_host) {
     double* part = ws.get<double>(B_PART, max_tiles_po * ft * 8);
     double* Eo = ws.get<double>(B_EOUT, (uint64_t)tot_out * 8);
     double* Ro = ws.get<double>(B_ROUT, (uint64_t)tot_out * 4);
+    prof_begin();
     launch_po_tiles(dd, seg_cnt, n_seg, n, ft, ttmp, tpre, st);
+    prof_end("po_tiles");
+    prof_begin();
     launch_po_sum(dd, seg_beg, seg_cnt, n_seg, n, dfreq, er, rec_stride, tpre,
                   precision == PE_PREC_FP32, ft, part, persistent_blocks(), st);
+    prof_end("po_sum");
+    prof_begin();
     launch_po_reduce(dd, dobs, n, max_obs, max_freq, n_seg, dfreq, seg_cnt, tpre, ft, part,
                      precision == PE_PREC_FP32, Eo, Ro, st);
+    prof_end("po_reduce");
     HIPCHK(hipGetLastError());
     if (E_host) HIPCHK(hipMemcpyAsync(E_host, Eo, sizeof(double) * 8 * tot_out, hipMemcpyDeviceToHost, st));
     if (rcs_host) HIPCHK(hipMemcpyAsync(rcs_host, Ro, sizeof(double) * 4 * tot_out, hipMemcpyDeviceToHost, st));
@@ -388,6 +418,40 @@ void Batch::field(double* E_host, double* rcs_host) {
 void Batch::read_counters(uint32_t* host) {
     HIPCHK(hipMemcpyAsync(host, cnt, sizeof(uint32_t) * C_NCOUNT, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    prof_flush();
+}
+
+// Per-kernel HIP-event timers on the launch stream (enabled per context).
+void Batch::prof_begin() {
+    if (!ws.ctx->profile) return;
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(e, st));
+    pend_begin = e;
+}
+
+void Batch::prof_end(const char* name) {
+    if (!ws.ctx->profile) return;
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(e, st));
+    pend.push_back({name, pend_begin, e});
+}
+
+void Batch::prof_flush() {
+    if (pend.empty()) return;
+    std::lock_guard<std::mutex> lk(ws.ctx->prof_mu);
+    for (auto& p : pend) {
+        float ms = 0;
+        HIPCHK(hipEventSynchronize(p.e1));
+        HIPCHK(hipEventElapsedTime(&ms, p.e0, p.e1));
+        auto& slot = ws.ctx->ktab[p.name];
+        slot.first += ms;
+        slot.second += 1;
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    pend.clear();
 }
 
 double Batch::queries(const uint32_t* c) const {
