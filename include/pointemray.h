@@ -100,6 +100,8 @@ typedef struct {
     double time_ms;          /* wall time of the solve measured on the stream (HIP events) */
     double march_cap_hits;   /* rays whose march reached the iteration cap (should be 0) */
     double densifier_fallbacks; /* incidences that fell back to the plain first-hit buffer */
+    double march_rays;       /* live rays processed by the bounce march (all bounces) */
+    double march_hits;       /* of which found a PEC facet and continued */
 } pe_stats;
 
 /* Caller-allocated host outputs of a solve.

@@ -63,7 +63,8 @@ class pe_solve_desc(ctypes.Structure):
 class pe_stats(ctypes.Structure):
     _fields_ = [("ray_queries", ctypes.c_double), ("exit_records", ctypes.c_double),
                 ("po_terms", ctypes.c_double), ("time_ms", ctypes.c_double),
-                ("march_cap_hits", ctypes.c_double), ("densifier_fallbacks", ctypes.c_double)]
+                ("march_cap_hits", ctypes.c_double), ("densifier_fallbacks", ctypes.c_double),
+                ("march_rays", ctypes.c_double), ("march_hits", ctypes.c_double)]
 
 
 class pe_result(ctypes.Structure):

@@ -126,6 +126,8 @@ void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>&
         acc->exit_records += recs;
         acc->po_terms += recs * b.max_freq;
         acc->march_cap_hits += c[kCounterCap];
+        acc->march_rays += b.march_rays(c);
+        acc->march_hits += b.march_hits(c);
     }
 }
 
@@ -354,27 +356,23 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
         vd.R = sd.R;
         vd.W = sd.W;
         vd.H = sd.H;
-        int w = sd.W, h = sd.H, L = 0;
-        uint64_t off = 0;
-        for (;;) {
-            vd.lvl_off[L] = (uint32_t)off;
-            vd.lvl_w[L] = w;
-            vd.lvl_h[L] = h;
-            off += (uint64_t)w * h;
-            L++;
-            if ((w == 1 && h == 1) || L == kMaxLevels) break;
-            w = (w + 1) / 2;
-            h = (h + 1) / 2;
+        int P = 1, lp = 0;
+        while (P < std::max(sd.W, sd.H)) {
+            P <<= 1;
+            lp++;
         }
-        vd.levels = L;
-        uint32_t* idx = (uint32_t*)sc->alloc((uint64_t)sd.W * sd.H * 4);
-        float2* hiz = (float2*)sc->alloc(off * 8);
-        vd.idx = idx;
+        vd.P = P;
+        vd.lp = lp;
+        vd.levels = lp + 1;
+        const uint64_t total = hiz_offset(P, lp) + 1;
+        float4* pix = (float4*)sc->alloc((uint64_t)sd.W * sd.H * 32);
+        float2* hiz = (float2*)sc->alloc(total * 8);
+        float2* ext = (float2*)tmp.get((uint64_t)sd.W * sd.H * 8);
+        vd.pix = pix;
         vd.hiz = hiz;
-        launch_view_level0(b.keys + sd.pix_base, sd.W, sd.H, idx, hiz, st);
-        for (int l = 1; l < L; l++)
-            launch_hiz_down(hiz + vd.lvl_off[l - 1], vd.lvl_w[l - 1], vd.lvl_h[l - 1],
-                            hiz + vd.lvl_off[l], vd.lvl_w[l], vd.lvl_h[l], st);
+        launch_view_level0(b.dd, v, b.keys, sd.W, sd.H, P, pix, ext, hiz, st);
+        for (int l = 1; l <= lp; l++)
+            launch_hiz_down(hiz + hiz_offset(P, l - 1), P >> (l - 1), hiz + hiz_offset(P, l), st);
     }
     sc->views_dev = (ViewDesc*)sc->alloc(sizeof(ViewDesc) * V);
     HIPCHK(hipMemcpyAsync(sc->views_dev, sc->views.data(), sizeof(ViewDesc) * V,

@@ -422,59 +422,78 @@ void launch_resolve(const SlotDesc* d, const uint64_t* keys, float* depth, float
                        idx, mask, npix);
 }
 
-// Aggregation view, level 0: point indices, and per pixel the min/max depth over its 3x3
-// neighbourhood (the disks the march refines against at that pixel).
-__global__ void k_view_level0(const uint64_t* __restrict__ keys, int W, int H,
-                              uint32_t* __restrict__ idx, float2* __restrict__ hiz0) {
+// Aggregation view, level 0.  Pass 1: each pixel stores its front-most disk inline (so the
+// march's 3x3 refinement reads contiguous rows) and that disk's depth extent along the view,
+// centre depth +- r sqrt(1 - (n.k)^2).  Pass 2: the pyramid base (P x P) holds the min/max of
+// those extents over each pixel's 3x3 neighbourhood; texels outside the screen are empty
+// (min = +max float, max = -max float).
+__global__ void k_view_pix(const SlotDesc* __restrict__ ds, int slot,
+                           const uint64_t* __restrict__ keys, float4* __restrict__ pix,
+                           float2* __restrict__ ext) {
+    const SlotDesc& d = ds[slot];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= W * H) return;
-    const int x = p % W, y = p / W;
-    idx[p] = (uint32_t)(keys[p] & 0xFFFFFFFFu);
+    if (p >= d.W * d.H) return;
+    const uint64_t key = keys[d.pix_base + p];
+    if (key == kEmptyKey) {
+        pix[2 * p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        pix[2 * p + 1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNone));
+        ext[p] = make_float2(FLT_MAX, -FLT_MAX);
+        return;
+    }
+    const uint32_t i = (uint32_t)(key & 0xFFFFFFFFu);
+    const float4 a = d.pa[i], b = d.pb[i];
+    pix[2 * p] = a;
+    pix[2 * p + 1] = make_float4(b.x, b.y, b.z, __uint_as_float(i));
+    const float tc = a.x * d.k[0] + a.y * d.k[1] + a.z * d.k[2] + d.R;
+    const float nk = b.x * d.k[0] + b.y * d.k[1] + b.z * d.k[2];
+    const float e = a.w * sqrtf(fmaxf(0.f, 1.f - nk * nk));
+    ext[p] = make_float2(tc - e, tc + e);
+}
+
+__global__ void k_view_dilate(const float2* __restrict__ ext, int W, int H, int P,
+                              float2* __restrict__ hiz0) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P * P) return;
+    const int x = p % P, y = p / P;
     float mn = FLT_MAX, mx = -FLT_MAX;
-    for (int dy = -1; dy <= 1; dy++) {
-        const int yy = y + dy;
-        if (yy < 0 || yy >= H) continue;
-        for (int dx = -1; dx <= 1; dx++) {
-            const int xx = x + dx;
-            if (xx < 0 || xx >= W) continue;
-            const uint64_t k = keys[(uint64_t)yy * W + xx];
-            if (k == kEmptyKey) continue;
-            const float t = __uint_as_float((uint32_t)(k >> 32));
-            mn = fminf(mn, t);
-            mx = fmaxf(mx, t);
+    if (x < W && y < H) {
+        for (int dy = -1; dy <= 1; dy++) {
+            const int yy = y + dy;
+            if (yy < 0 || yy >= H) continue;
+            for (int dx = -1; dx <= 1; dx++) {
+                const int xx = x + dx;
+                if (xx < 0 || xx >= W) continue;
+                const float2 v = ext[yy * W + xx];
+                mn = fminf(mn, v.x);
+                mx = fmaxf(mx, v.y);
+            }
         }
     }
     hiz0[p] = make_float2(mn, mx);
 }
 
-void launch_view_level0(const uint64_t* keys, int W, int H, uint32_t* idx, float2* hiz0,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_view_level0, dim3((W * H + 255) / 256), dim3(256), 0, st, keys, W, H,
-                       idx, hiz0);
+void launch_view_level0(const SlotDesc* d, int slot, const uint64_t* keys, int W, int H, int P,
+                        float4* pix, float2* ext, float2* hiz0, hipStream_t st) {
+    hipLaunchKernelGGL(k_view_pix, dim3((W * H + 255) / 256), dim3(256), 0, st, d, slot, keys,
+                       pix, ext);
+    hipLaunchKernelGGL(k_view_dilate, dim3((P * P + 255) / 256), dim3(256), 0, st,
+                       (const float2*)ext, W, H, P, hiz0);
 }
 
-__global__ void k_hiz_down(const float2* __restrict__ src, int sw, int sh,
-                           float2* __restrict__ dst, int dw, int dh) {
+__global__ void k_hiz_down(const float2* __restrict__ src, int sp, float2* __restrict__ dst) {
+    const int dp = sp >> 1;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= dw * dh) return;
-    const int x = p % dw, y = p / dw;
-    float mn = FLT_MAX, mx = -FLT_MAX;
-    for (int dy = 0; dy < 2; dy++)
-        for (int dx = 0; dx < 2; dx++) {
-            const int xx = 2 * x + dx, yy = 2 * y + dy;
-            if (xx < sw && yy < sh) {
-                const float2 v = src[yy * sw + xx];
-                mn = fminf(mn, v.x);
-                mx = fmaxf(mx, v.y);
-            }
-        }
-    dst[p] = make_float2(mn, mx);
+    if (p >= dp * dp) return;
+    const int x = p % dp, y = p / dp;
+    const float2 a = src[(2 * y) * sp + 2 * x], b = src[(2 * y) * sp + 2 * x + 1];
+    const float2 c = src[(2 * y + 1) * sp + 2 * x], d = src[(2 * y + 1) * sp + 2 * x + 1];
+    dst[p] = make_float2(fminf(fminf(a.x, b.x), fminf(c.x, d.x)),
+                         fmaxf(fmaxf(a.y, b.y), fmaxf(c.y, d.y)));
 }
 
-void launch_hiz_down(const float2* src, int sw, int sh, float2* dst, int dw, int dh,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(k_hiz_down, dim3((dw * dh + 255) / 256), dim3(256), 0, st, src, sw, sh,
-                       dst, dw, dh);
+void launch_hiz_down(const float2* src, int sp, float2* dst, hipStream_t st) {
+    const int dp = sp >> 1;
+    hipLaunchKernelGGL(k_hiz_down, dim3((dp * dp + 255) / 256), dim3(256), 0, st, src, sp, dst);
 }
 
 }  // namespace pe

@@ -154,13 +154,19 @@ __device__ inline void slab(float a0, float da, float lo, float hi, float& s0, f
     s1 = fminf(s1, tb);
 }
 
-__device__ void march_view(const ViewDesc& V, const float4* __restrict__ pa,
-                           const float4* __restrict__ pb, f3 x, f3 k, float tmin, float smax,
-                           float margin, float& best_t, uint32_t& best_i, uint32_t* cap_hits) {
+// March of one ray through one aggregation view's pyramid.  A level-0 texel is a candidate
+// when the ray's depth over the pixel, widened by one pixel of travel (the 3x3 refinement
+// reaches one pixel around), meets the texel's [min, max] of stored disk extents; the disks of
+// the 3x3 block are then intersected exactly, skipping those already tested in the previous
+// block.
+__device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
+                           float& best_t, uint32_t& best_i, uint32_t* cap_hits) {
     const float ip = 1.f / V.pitch;
     const f3 vu = mk3(V.u[0], V.u[1], V.u[2]), vv = mk3(V.v[0], V.v[1], V.v[2]);
     const f3 vk = mk3(V.k[0], V.k[1], V.k[2]);
-    const int W = V.W, H = V.H;
+    const int W = V.W, H = V.H, P = V.P;
+    const float2* __restrict__ hiz = V.hiz;
+    const float4* __restrict__ pix = V.pix;
     const float a0 = dot(x, vu) * ip + 0.5f * W, b0 = dot(x, vv) * ip + 0.5f * H;
     const float z0 = dot(x, vk) + V.R;
     const float da = dot(k, vu) * ip, db = dot(k, vv) * ip, dz = dot(k, vk);
@@ -169,11 +175,14 @@ __device__ void march_view(const ViewDesc& V, const float4* __restrict__ pa,
     slab(b0, db, 0.f, (float)H, s_lo, s_hi);
     if (!(s_lo <= s_hi)) return;
     const float ida = da != 0.f ? 1.f / da : 0.f, idb = db != 0.f ? 1.f / db : 0.f;
+    const float lat = fmaxf(fabsf(da), fabsf(db));
+    const float zpad = (lat > 0.f ? fabsf(dz) / lat : 0.f) + tol;  // depth change per pixel
     float s = s_lo;
     int ix = min(max((int)floorf(a0 + s * da), 0), W - 1);
     int iy = min(max((int)floorf(b0 + s * db), 0), H - 1);
+    int px_prev = -1000, py_prev = -1000;
     int level = 0;
-    const int lmax = V.levels - 1;
+    const int lmax = V.lp;
     const int cap = 4 * (W + H) * (lmax + 1) + 64;
     for (int it = 0;; it++) {
         if (it > cap) {
@@ -187,8 +196,8 @@ __device__ void march_view(const ViewDesc& V, const float4* __restrict__ pa,
         const float sy = db > 0.f ? (yh - b0) * idb : (db < 0.f ? (yl - b0) * idb : FLT_MAX);
         const float se = fminf(fminf(sx, sy), s_hi);
         const float za = z0 + s * dz, zb = z0 + se * dz;
-        const float2 h = V.hiz[V.lvl_off[level] + cy * V.lvl_w[level] + cx];
-        const bool ov = fmaxf(za, zb) + margin >= h.x && fminf(za, zb) - margin <= h.y;
+        const float2 h = hiz[hiz_offset(P, level) + cy * (P >> level) + cx];
+        const bool ov = fmaxf(za, zb) + zpad >= h.x && fminf(za, zb) - zpad <= h.y;
         if (ov && level > 0) {
             level--;
             continue;
@@ -200,16 +209,20 @@ __device__ void march_view(const ViewDesc& V, const float4* __restrict__ pa,
                 for (int dx = -1; dx <= 1; dx++) {
                     const int px = ix + dx;
                     if (px < 0 || px >= W) continue;
-                    const uint32_t i = V.idx[py * W + px];
+                    if (abs(px - px_prev) <= 1 && abs(py - py_prev) <= 1) continue;
+                    const float4 pb = pix[2 * (py * W + px) + 1];
+                    const uint32_t i = __float_as_uint(pb.w);
                     if (i == kNone) continue;
                     float t;
-                    if (disk_test(pa[i], pb[i], x, k, tmin, t) &&
+                    if (disk_test(pix[2 * (py * W + px)], pb, x, k, tmin, t) &&
                         (t < best_t || (t == best_t && i < best_i))) {
                         best_t = t;
                         best_i = i;
                     }
                 }
             }
+            px_prev = ix;
+            py_prev = iy;
             s_hi = fminf(s_hi, best_t);
         }
         if (se >= s_hi) break;
@@ -232,30 +245,40 @@ __device__ inline float sphere_exit(f3 x, f3 k, float R) {
     return -b + sqrtf(fmaxf(b * b - c, 0.f));
 }
 
-// Nearest hit of the ray (x, k) beyond tmin over all aggregation views of the slot's scene.
-__device__ inline void march_all(const SlotDesc& d, f3 x, f3 k, float tmin, float& best_t,
-                                 uint32_t& best_i, uint32_t* cap_hits) {
-    const float margin = 2.f * d.r_max + 1e-5f * d.R;
-    const float smax = sphere_exit(x, k, d.R * 1.0001f) + 2.f * d.r_max;
-    for (int v = 0; v < d.n_views; v++)
-        march_view(d.views[v], d.pa, d.pb, x, k, tmin, smax, margin, best_t, best_i, cap_hits);
+// fp32 tolerance of depth comparisons in the march (scene-size relative).
+__device__ inline float march_tol(const SlotDesc& d) { return 4e-6f * d.R; }
+__device__ inline float march_smax(const SlotDesc& d, f3 x, f3 k) {
+    return sphere_exit(x, k, d.R * 1.0001f) + 2.f * d.r_max;
 }
 
-// One bounce for one live ray: march from the last record along its reflected direction;
-// on a PEC hit the record advances to the new facet, otherwise the ray stops (its state keeps
-// the last record, which is what radiates under Eq. (14)).
-__device__ bool bounce_one(const SlotDesc* __restrict__ ds, uint32_t entry, const RayState& rs,
-                           int bounce, uint32_t* cap_hits) {
-    const SlotDesc& d = ds[entry_slot(entry)];
-    if (bounce > d.max_b) return false;
-    const uint64_t g = d.pix_base + entry_pix(entry);
-    const f3 x = ld3(rs, RX, g), n = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
-    f3 k = mirror(kin, n);
-    k = k * rsqrtf(dot(k, k));
-    float best_t = FLT_MAX;
-    uint32_t best_i = kNone;
-    march_all(d, x, k, d.eps, best_t, best_i, cap_hits);
+// Nearest hit of the ray (x, k) beyond tmin over all aggregation views, one lane (used for the
+// visibility of bistatic facets).
+__device__ inline void march_all(const SlotDesc& d, f3 x, f3 k, float tmin, float& best_t,
+                                 uint32_t& best_i, uint32_t* cap_hits) {
+    const float tol = march_tol(d);
+    const float smax = march_smax(d, x, k);
+    for (int v = 0; v < d.n_views; v++)
+        march_view(d.views[v], x, k, tmin, smax, tol, best_t, best_i, cap_hits);
+}
+
+__device__ inline uint64_t pack_hit(float t, uint32_t i) {
+    return ((uint64_t)__float_as_uint(t) << 32) | i;
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Applies the bounce found for one live ray: on a PEC hit the record advances to the new facet
+// (Eq. (2)-(4) at the old facet's normal, path += t), otherwise the ray stops and keeps its
+// last record, which is what radiates under Eq. (14).
+__device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, f3 x, f3 n, f3 k,
+                             uint64_t key, int bounce) {
+    const uint32_t best_i = (uint32_t)(key & 0xFFFFFFFFu);
     if (best_i == kNone) return false;
+    const float best_t = __uint_as_float((uint32_t)(key >> 32));
     const float4 b = d.pb[best_i];
     if (b.w != 0.f) return false;
     f3 nn = mk3(b.x, b.y, b.z);
@@ -274,16 +297,70 @@ __device__ bool bounce_one(const SlotDesc* __restrict__ ds, uint32_t entry, cons
     return true;
 }
 
-// Persistent and barrier-free: wavefront w of the grid handles 64-entry chunks w, w + W, w + 2W,
-// ... of the live list (W = wavefronts in the grid).  The chunk index is a scalar (uniform) loop
-// variable, so every lane of a wavefront runs the same iterations and the ballot that counts a
-// chunk's survivors sees the whole wavefront.
-__global__ __launch_bounds__(256) void k_march(const SlotDesc* __restrict__ ds,
+// One bounce for the live list.  Eight lanes cooperate on one ray: lane v of the group marches
+// views v, v + 8, ... of the ray's scene, the nearest hit (packed t|index, so ties go to the
+// lowest index) is reduced across the group with shuffles, and the group's first lane applies
+// it.  The loop over groups of 8 rays is strided by wavefront with a scalar index, so all lanes
+// of a wavefront run the same iterations (no barriers, no lane-divergent trip counts).
+__global__ __launch_bounds__(256, 6) void k_march(const SlotDesc* __restrict__ ds,
                                                const uint32_t* __restrict__ list,
                                                const uint32_t* __restrict__ n_live, RayState rs,
-                                               uint8_t* __restrict__ alive,
-                                               uint32_t* __restrict__ chunk_count, int bounce,
+                                               uint8_t* __restrict__ alive, int bounce,
                                                uint32_t* __restrict__ cap_hits) {
+    const uint32_t n = *n_live;
+    const uint32_t n_groups = (n + 7) / 8;
+    const int lane = threadIdx.x & 63;
+    const int member = lane & 7;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const uint32_t nw = gridDim.x * 4;
+    for (uint32_t c = wid; c < n_groups; c += nw) {
+        const uint32_t e = c * 8 + (lane >> 3);
+        uint64_t key = ~0ull;
+        uint64_t g = 0;
+        const SlotDesc* dp = nullptr;
+        f3 x = mk3(0.f, 0.f, 0.f), n3 = x, k = x;
+        bool run = false;
+        if (e < n) {
+            const uint32_t entry = list[e];
+            dp = &ds[entry_slot(entry)];
+            g = dp->pix_base + entry_pix(entry);
+            run = bounce <= dp->max_b;
+            if (run) {
+                x = ld3(rs, RX, g);
+                n3 = ld3(rs, RNX, g);
+                const f3 kin = ld3(rs, RKX, g);
+                k = mirror(kin, n3);
+                k = k * rsqrtf(dot(k, k));
+                const float tol = march_tol(*dp), smax = march_smax(*dp, x, k);
+                for (int v = member; v < dp->n_views; v += 8) {
+                    float bt = FLT_MAX;
+                    uint32_t bi = kNone;
+                    march_view(dp->views[v], x, k, dp->eps, smax, tol, bt, bi, cap_hits);
+                    const uint64_t kk = pack_hit(bt, bi);
+                    key = kk < key ? kk : key;
+                }
+            }
+        }
+        uint64_t o = shfl_xor_u64(key, 1);
+        key = o < key ? o : key;
+        o = shfl_xor_u64(key, 2);
+        key = o < key ? o : key;
+        o = shfl_xor_u64(key, 4);
+        key = o < key ? o : key;
+        if (e < n && member == 0) alive[e] = run && apply_bounce(*dp, g, rs, x, n3, k, key, bounce);
+    }
+}
+
+void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
+                  uint8_t* alive, int bounce, uint32_t* cap_hits, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_march, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs, alive,
+                       bounce, cap_hits);
+}
+
+// Survivors per 64-entry chunk of the live list (one wavefront per chunk, ballot count).
+__global__ __launch_bounds__(256) void k_alive_count(const uint32_t* __restrict__ n_live,
+                                                     const uint8_t* __restrict__ alive,
+                                                     uint32_t* __restrict__ chunk_count) {
     const uint32_t n = *n_live;
     const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
     const int lane = threadIdx.x & 63;
@@ -291,21 +368,15 @@ __global__ __launch_bounds__(256) void k_march(const SlotDesc* __restrict__ ds,
     const uint32_t nw = gridDim.x * 4;
     for (uint32_t c = wid; c < n_chunks; c += nw) {
         const uint32_t e = c * kWaveChunk + lane;
-        bool live = false;
-        if (e < n) {
-            live = bounce_one(ds, list[e], rs, bounce, cap_hits);
-            alive[e] = live ? 1 : 0;
-        }
-        const uint64_t bal = __ballot(live);
+        const uint64_t bal = __ballot(e < n && alive[e]);
         if (lane == 0) chunk_count[c] = (uint32_t)__popcll(bal);
     }
 }
 
-void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  uint8_t* alive, uint32_t* chunk_count, int bounce, uint32_t* cap_hits,
-                  int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_march, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs, alive,
-                       chunk_count, bounce, cap_hits);
+void launch_alive_count(const uint32_t* n_live, const uint8_t* alive, uint32_t* chunk_count,
+                        int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_alive_count, dim3(n_blocks), dim3(256), 0, st, n_live, alive,
+                       chunk_count);
 }
 
 // Order-preserving compaction of 64-entry chunks, one wavefront per chunk (grid-stride over

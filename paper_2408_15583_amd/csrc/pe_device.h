@@ -18,15 +18,23 @@ constexpr int kMaxSlots = 1 << kSlotBits;
 constexpr int kWaveChunk = 64;    // live-list entries per compaction chunk (one wavefront)
 
 // One aggregation view of a scene: a disk first-hit buffer with its min/max depth pyramid.
+// The min/max pyramid is stored square and power-of-two: level l is (P >> l)^2 texels at
+// offset 4 (P^2 - (P >> l)^2) / 3, so a march step needs no table lookup before its fetch.
 struct ViewDesc {
     float u[3], v[3], k[3];   // screen basis: u, v span the screen, k = propagation
     float pitch, R;
-    int W, H, levels;
-    const uint32_t* idx;      // W*H point indices (kNone = empty)
-    const float2* hiz;        // all levels concatenated; level 0 is the 3x3-dilated min/max
-    uint32_t lvl_off[kMaxLevels];
-    int lvl_w[kMaxLevels], lvl_h[kMaxLevels];
+    int W, H, levels;         // levels = log2(P) + 1
+    int P, lp;                // pyramid side (power of two >= max(W, H)) and log2(P)
+    const float4* pix;        // W*H x 2: the pixel's front-most disk (x, y, z, r),
+                              // (nx, ny, nz, bits(point index)); index kNone = empty pixel
+    const float2* hiz;        // all levels; level 0 (P x P): min/max over the pixel's 3x3
+                              // neighbourhood of each stored disk's depth extent
 };
+
+__host__ __device__ inline uint32_t hiz_offset(int P, int l) {
+    const uint32_t a = (uint32_t)P * (uint32_t)P, b = (uint32_t)(P >> l) * (uint32_t)(P >> l);
+    return 4u * ((a - b) / 3u);
+}
 
 // One work item of a batched launch: one screen (one incidence) on one scene.
 struct SlotDesc {
@@ -129,10 +137,9 @@ void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t
                    uint64_t* keys, hipStream_t st);
 void launch_resolve(const SlotDesc* d, const uint64_t* keys, float* depth, float* nrm,
                     uint32_t* idx, uint8_t* mask, int npix, hipStream_t st);
-void launch_view_level0(const uint64_t* keys, int W, int H, uint32_t* idx, float2* hiz0,
-                        hipStream_t st);
-void launch_hiz_down(const float2* src, int sw, int sh, float2* dst, int dw, int dh,
-                     hipStream_t st);
+void launch_view_level0(const SlotDesc* d, int slot, const uint64_t* keys, int W, int H, int P,
+                        float4* pix, float2* ext, float2* hiz0, hipStream_t st);
+void launch_hiz_down(const float2* src, int sp, float2* dst, hipStream_t st);
 
 // trace
 void launch_raygen_count(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
@@ -140,8 +147,9 @@ void launch_raygen_count(const SlotDesc* d, int n_slots, int max_pix, const uint
 void launch_raygen_write(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
                          const uint32_t* wg_off, uint32_t* list, RayState rs, hipStream_t st);
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  uint8_t* alive, uint32_t* chunk_count, int bounce, uint32_t* cap_hits,
-                  int n_blocks, hipStream_t st);
+                  uint8_t* alive, int bounce, uint32_t* cap_hits, int n_blocks, hipStream_t st);
+void launch_alive_count(const uint32_t* n_live, const uint8_t* alive, uint32_t* chunk_count,
+                        int n_blocks, hipStream_t st);
 void launch_compact(const uint32_t* list_in, const uint32_t* n_in, const uint8_t* alive,
                     const uint32_t* chunk_off, uint32_t* list_out, int n_blocks,
                     hipStream_t st);

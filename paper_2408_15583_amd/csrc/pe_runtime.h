@@ -98,6 +98,8 @@ struct Batch {
     void read_counters(uint32_t* host);
     double queries(const uint32_t* c) const;
     double records_made(const uint32_t* c) const;
+    double march_rays(const uint32_t* c) const;
+    double march_hits(const uint32_t* c) const;
     bool overflowed(const uint32_t* c);
     struct Pending {
         const char* name;

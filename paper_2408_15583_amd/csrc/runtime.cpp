@@ -373,8 +373,13 @@ void Batch::trace(bool with_records) {
         uint32_t* out = lists[b % 2 == 0 ? 1 : 2];
         uint32_t* nout = cnt + (b % 2 == 0 ? C_N1 : C_N2);
         prof_begin();
-        launch_march(dd, cur, ncur, rs, alive, ccount, b, cnt + C_CAP, persistent_blocks(), st);
-        prof_end("march");
+        launch_march(dd, cur, ncur, rs, alive, b, cnt + C_CAP, persistent_blocks(), st);
+        static const char* names[] = {"march_b2", "march_b3", "march_b4", "march_b5", "march_b6",
+                                      "march_b7", "march_b8", "march_b9+"};
+        prof_end(names[std::min(b - 2, 7)]);
+        prof_begin();
+        launch_alive_count(ncur, alive, ccount, persistent_blocks(), st);
+        prof_end("alive_count");
         prof_begin();
         launch_scan(ccount, coff, 0, ncur, kWaveChunk, nout, st);
         prof_end("compact_scan");
@@ -458,6 +463,18 @@ double Batch::queries(const uint32_t* c) const {
     double q = (double)tot_pix;
     for (int b = 2; b <= max_b; b++) q += c[C_BOUNCE0 + b];
     return q;
+}
+
+double Batch::march_rays(const uint32_t* c) const {
+    double r = 0;
+    for (int b = 2; b <= max_b; b++) r += c[C_BOUNCE0 + b];
+    return r;
+}
+
+double Batch::march_hits(const uint32_t* c) const {
+    double r = 0;
+    for (int b = 2; b <= max_b; b++) r += c[C_BOUNCE0 + 32 + b];
+    return r;
 }
 
 double Batch::records_made(const uint32_t* c) const {
