@@ -87,7 +87,8 @@ void launch_raygen_count(const SlotDesc* d, int n_slots, int max_pix, const uint
 __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict__ ds,
                                                       const uint64_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ wg_off,
-                                                      uint32_t* __restrict__ list, RayState rs) {
+                                                      uint32_t* __restrict__ list, RayState rs,
+                                                      uint64_t* __restrict__ hitkey) {
     const uint32_t slot = blockIdx.y;
     const SlotDesc& d = ds[slot];
     const int p = blockIdx.x * 256 + threadIdx.x;
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict
     for (int w = 0; w < wave; w++) off += wc[w];
     off += (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
     list[off] = make_entry(slot, (uint32_t)p);
+    hitkey[off] = kEmptyKey;
 
     const uint64_t key = keys[g];
     const float t = __uint_as_float((uint32_t)(key >> 32));
@@ -132,9 +134,10 @@ __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict
 }
 
 void launch_raygen_write(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
-                         const uint32_t* wg_off, uint32_t* list, RayState rs, hipStream_t st) {
+                         const uint32_t* wg_off, uint32_t* list, RayState rs, uint64_t* hitkey,
+                         hipStream_t st) {
     hipLaunchKernelGGL(k_raygen_write, dim3((max_pix + 255) / 256, n_slots), dim3(256), 0, st, d,
-                       keys, wg_off, list, rs);
+                       keys, wg_off, list, rs, hitkey);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -297,70 +300,58 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
     return true;
 }
 
-// One bounce for the live list.  Eight lanes cooperate on one ray: lane v of the group marches
-// views v, v + 8, ... of the ray's scene, the nearest hit (packed t|index, so ties go to the
-// lowest index) is reduced across the group with shuffles, and the group's first lane applies
-// it.  The loop over groups of 8 rays is strided by wavefront with a scalar index, so all lanes
-// of a wavefront run the same iterations (no barriers, no lane-divergent trip counts).
+// One bounce, pass 1: every wavefront marches ONE aggregation view for 64 consecutive live
+// rays (adjacent pixels of one incidence, so the lanes walk similar paths through the same
+// view data).  Work items are (view, chunk) pairs in view-major order; the nearest hit of each
+// (ray, view) is folded into the ray's packed t|index key with a 64-bit atomic minimum, so the
+// result is the same minimum over views whatever the order (ties: lowest index).
 __global__ __launch_bounds__(256, 6) void k_march(const SlotDesc* __restrict__ ds,
-                                               const uint32_t* __restrict__ list,
-                                               const uint32_t* __restrict__ n_live, RayState rs,
-                                               uint8_t* __restrict__ alive, int bounce,
-                                               uint32_t* __restrict__ cap_hits) {
+                                                  const uint32_t* __restrict__ list,
+                                                  const uint32_t* __restrict__ n_live,
+                                                  RayState rs, uint64_t* __restrict__ hitkey,
+                                                  int bounce, int max_views,
+                                                  uint32_t* __restrict__ cap_hits) {
     const uint32_t n = *n_live;
-    const uint32_t n_groups = (n + 7) / 8;
+    const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
+    const uint32_t total = n_chunks * (uint32_t)max_views;
     const int lane = threadIdx.x & 63;
-    const int member = lane & 7;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const uint32_t nw = gridDim.x * 4;
-    for (uint32_t c = wid; c < n_groups; c += nw) {
-        const uint32_t e = c * 8 + (lane >> 3);
-        uint64_t key = ~0ull;
-        uint64_t g = 0;
-        const SlotDesc* dp = nullptr;
-        f3 x = mk3(0.f, 0.f, 0.f), n3 = x, k = x;
-        bool run = false;
-        if (e < n) {
-            const uint32_t entry = list[e];
-            dp = &ds[entry_slot(entry)];
-            g = dp->pix_base + entry_pix(entry);
-            run = bounce <= dp->max_b;
-            if (run) {
-                x = ld3(rs, RX, g);
-                n3 = ld3(rs, RNX, g);
-                const f3 kin = ld3(rs, RKX, g);
-                k = mirror(kin, n3);
-                k = k * rsqrtf(dot(k, k));
-                const float tol = march_tol(*dp), smax = march_smax(*dp, x, k);
-                for (int v = member; v < dp->n_views; v += 8) {
-                    float bt = FLT_MAX;
-                    uint32_t bi = kNone;
-                    march_view(dp->views[v], x, k, dp->eps, smax, tol, bt, bi, cap_hits);
-                    const uint64_t kk = pack_hit(bt, bi);
-                    key = kk < key ? kk : key;
-                }
-            }
-        }
-        uint64_t o = shfl_xor_u64(key, 1);
-        key = o < key ? o : key;
-        o = shfl_xor_u64(key, 2);
-        key = o < key ? o : key;
-        o = shfl_xor_u64(key, 4);
-        key = o < key ? o : key;
-        if (e < n && member == 0) alive[e] = run && apply_bounce(*dp, g, rs, x, n3, k, key, bounce);
+    for (uint32_t q = wid; q < total; q += nw) {
+        const uint32_t v = q / n_chunks, c = q - v * n_chunks;
+        const uint32_t e = c * kWaveChunk + lane;
+        if (e >= n) continue;
+        const uint32_t entry = list[e];
+        const SlotDesc& d = ds[entry_slot(entry)];
+        if (bounce > d.max_b || (int)v >= d.n_views) continue;
+        const uint64_t g = d.pix_base + entry_pix(entry);
+        const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+        f3 k = mirror(kin, nn);
+        k = k * rsqrtf(dot(k, k));
+        float bt = FLT_MAX;
+        uint32_t bi = kNone;
+        march_view(d.views[v], x, k, d.eps, march_smax(d, x, k), march_tol(d), bt, bi, cap_hits);
+        if (bi != kNone)
+            atomicMin((unsigned long long*)&hitkey[e], (unsigned long long)pack_hit(bt, bi));
     }
 }
 
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  uint8_t* alive, int bounce, uint32_t* cap_hits, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_march, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs, alive,
-                       bounce, cap_hits);
+                  uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, int n_blocks,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_march, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs, hitkey,
+                       bounce, max_views, cap_hits);
 }
 
-// Survivors per 64-entry chunk of the live list (one wavefront per chunk, ballot count).
-__global__ __launch_bounds__(256) void k_alive_count(const uint32_t* __restrict__ n_live,
-                                                     const uint8_t* __restrict__ alive,
-                                                     uint32_t* __restrict__ chunk_count) {
+// One bounce, pass 2: apply each ray's nearest hit (or stop it), reset its key for the next
+// bounce, and count the survivors of each 64-entry chunk for the order-preserving compaction.
+__global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict__ ds,
+                                                      const uint32_t* __restrict__ list,
+                                                      const uint32_t* __restrict__ n_live,
+                                                      RayState rs, uint64_t* __restrict__ hitkey,
+                                                      uint8_t* __restrict__ alive,
+                                                      uint32_t* __restrict__ chunk_count,
+                                                      int bounce) {
     const uint32_t n = *n_live;
     const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
     const int lane = threadIdx.x & 63;
@@ -368,15 +359,31 @@ __global__ __launch_bounds__(256) void k_alive_count(const uint32_t* __restrict_
     const uint32_t nw = gridDim.x * 4;
     for (uint32_t c = wid; c < n_chunks; c += nw) {
         const uint32_t e = c * kWaveChunk + lane;
-        const uint64_t bal = __ballot(e < n && alive[e]);
+        bool live = false;
+        if (e < n) {
+            const uint32_t entry = list[e];
+            const SlotDesc& d = ds[entry_slot(entry)];
+            const uint64_t key = hitkey[e];
+            hitkey[e] = kEmptyKey;
+            if (bounce <= d.max_b) {
+                const uint64_t g = d.pix_base + entry_pix(entry);
+                const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                f3 k = mirror(kin, nn);
+                k = k * rsqrtf(dot(k, k));
+                live = apply_bounce(d, g, rs, x, nn, k, key, bounce);
+            }
+            alive[e] = live ? 1 : 0;
+        }
+        const uint64_t bal = __ballot(live);
         if (lane == 0) chunk_count[c] = (uint32_t)__popcll(bal);
     }
 }
 
-void launch_alive_count(const uint32_t* n_live, const uint8_t* alive, uint32_t* chunk_count,
-                        int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_alive_count, dim3(n_blocks), dim3(256), 0, st, n_live, alive,
-                       chunk_count);
+void launch_bounce_apply(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
+                         RayState rs, uint64_t* hitkey, uint8_t* alive, uint32_t* chunk_count,
+                         int bounce, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_bounce_apply, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs,
+                       hitkey, alive, chunk_count, bounce);
 }
 
 // Order-preserving compaction of 64-entry chunks, one wavefront per chunk (grid-stride over

@@ -145,11 +145,14 @@ void launch_hiz_down(const float2* src, int sp, float2* dst, hipStream_t st);
 void launch_raygen_count(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
                          uint32_t* wg_count, hipStream_t st);
 void launch_raygen_write(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
-                         const uint32_t* wg_off, uint32_t* list, RayState rs, hipStream_t st);
+                         const uint32_t* wg_off, uint32_t* list, RayState rs, uint64_t* hitkey,
+                         hipStream_t st);
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  uint8_t* alive, int bounce, uint32_t* cap_hits, int n_blocks, hipStream_t st);
-void launch_alive_count(const uint32_t* n_live, const uint8_t* alive, uint32_t* chunk_count,
-                        int n_blocks, hipStream_t st);
+                  uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, int n_blocks,
+                  hipStream_t st);
+void launch_bounce_apply(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
+                         RayState rs, uint64_t* hitkey, uint8_t* alive, uint32_t* chunk_count,
+                         int bounce, int n_blocks, hipStream_t st);
 void launch_compact(const uint32_t* list_in, const uint32_t* n_in, const uint8_t* alive,
                     const uint32_t* chunk_off, uint32_t* list_out, int n_blocks,
                     hipStream_t st);

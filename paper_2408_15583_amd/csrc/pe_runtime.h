@@ -83,6 +83,8 @@ struct Batch {
     RayState rs{};
     uint32_t* lists[3] = {nullptr, nullptr, nullptr};
     uint8_t* alive = nullptr;
+    uint64_t* hitkey = nullptr;
+    int max_views = 0;
     uint32_t *ccount = nullptr, *coff = nullptr, *seg_beg = nullptr, *seg_cnt = nullptr;
     ExitRecs er{};
 

@@ -159,7 +159,8 @@ void pol_basis(const double s_in[3], double th[3], double ph[3]) {
 enum BufId {
     B_SLOTS, B_OBS, B_FREQ, B_AABB, B_TCOUNT, B_TCURSOR, B_TOFF, B_TLIST, B_KEYS, B_RSF,
     B_RSD, B_RSM, B_RSH, B_LIST0, B_LIST1, B_LIST2, B_ALIVE, B_CCOUNT, B_COFF, B_WGC, B_WGO,
-    B_RECD, B_RECF, B_SEGB, B_SEGC, B_TPRE, B_TTMP, B_PART, B_EOUT, B_ROUT, B_CNT, B_NUMBUF
+    B_RECD, B_RECF, B_SEGB, B_SEGC, B_TPRE, B_TTMP, B_PART, B_EOUT, B_ROUT, B_CNT, B_HITKEY,
+    B_NUMBUF
 };
 
 enum Counter : int {
@@ -189,6 +190,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
     max_obs = max_freq = 1;
     tot_out = 0;
     max_b = 1;
+    max_views = 0;
     for (int i = 0; i < n; i++) {
         const SlotSpec& sp = slots[i];
         const pe_scene sc = sp.sc;
@@ -201,6 +203,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.pb = sc->pb;
         d.views = sc->views_dev;
         d.n_views = (int)sc->views.size();
+        max_views = std::max(max_views, d.n_views);
         d.n_pts = (uint32_t)sc->n;
         d.n_chunks = (uint32_t)((sc->n + kChunk - 1) / kChunk);
         d.R = (float)sc->R;
@@ -316,6 +319,7 @@ void Batch::alloc_rays() {
     lists[1] = ws.get<uint32_t>(B_LIST1, tot_pix);
     lists[2] = ws.get<uint32_t>(B_LIST2, tot_pix);
     alive = ws.get<uint8_t>(B_ALIVE, tot_pix);
+    hitkey = ws.get<uint64_t>(B_HITKEY, tot_pix);
     ccount = ws.get<uint32_t>(B_CCOUNT, tot_pix / kWaveChunk + 2);
     coff = ws.get<uint32_t>(B_COFF, tot_pix / kWaveChunk + 2);
 }
@@ -334,7 +338,7 @@ void Batch::raygen() {
     launch_scan(wgc, wgo, (uint32_t)(gx * n), nullptr, 1, cnt + C_N0, st);
     prof_end("raygen_scan");
     prof_begin();
-    launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, st);
+    launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, hitkey, st);
     prof_end("raygen_write");
     HIPCHK(hipGetLastError());
 }
@@ -373,13 +377,14 @@ void Batch::trace(bool with_records) {
         uint32_t* out = lists[b % 2 == 0 ? 1 : 2];
         uint32_t* nout = cnt + (b % 2 == 0 ? C_N1 : C_N2);
         prof_begin();
-        launch_march(dd, cur, ncur, rs, alive, b, cnt + C_CAP, persistent_blocks(), st);
+        launch_march(dd, cur, ncur, rs, hitkey, b, max_views, cnt + C_CAP, persistent_blocks(),
+                     st);
         static const char* names[] = {"march_b2", "march_b3", "march_b4", "march_b5", "march_b6",
                                       "march_b7", "march_b8", "march_b9+"};
         prof_end(names[std::min(b - 2, 7)]);
         prof_begin();
-        launch_alive_count(ncur, alive, ccount, persistent_blocks(), st);
-        prof_end("alive_count");
+        launch_bounce_apply(dd, cur, ncur, rs, hitkey, alive, ccount, b, persistent_blocks(), st);
+        prof_end("bounce_apply");
         prof_begin();
         launch_scan(ccount, coff, 0, ncur, kWaveChunk, nout, st);
         prof_end("compact_scan");
