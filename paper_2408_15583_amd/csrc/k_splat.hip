@@ -469,7 +469,7 @@ __global__ void k_view_dilate(const float2* __restrict__ ext, int W, int H, int 
             }
         }
     }
-    hiz0[p] = make_float2(mn, mx);
+    hiz0[hiz_texel(P, x, y)] = make_float2(mn, mx);
 }
 
 void launch_view_level0(const SlotDesc* d, int slot, const uint64_t* keys, int W, int H, int P,
@@ -485,10 +485,11 @@ __global__ void k_hiz_down(const float2* __restrict__ src, int sp, float2* __res
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= dp * dp) return;
     const int x = p % dp, y = p / dp;
-    const float2 a = src[(2 * y) * sp + 2 * x], b = src[(2 * y) * sp + 2 * x + 1];
-    const float2 c = src[(2 * y + 1) * sp + 2 * x], d = src[(2 * y + 1) * sp + 2 * x + 1];
-    dst[p] = make_float2(fminf(fminf(a.x, b.x), fminf(c.x, d.x)),
-                         fmaxf(fmaxf(a.y, b.y), fmaxf(c.y, d.y)));
+    const float2 a = src[hiz_texel(sp, 2 * x, 2 * y)], b = src[hiz_texel(sp, 2 * x + 1, 2 * y)];
+    const float2 c = src[hiz_texel(sp, 2 * x, 2 * y + 1)];
+    const float2 d = src[hiz_texel(sp, 2 * x + 1, 2 * y + 1)];
+    dst[hiz_texel(dp, x, y)] = make_float2(fminf(fminf(a.x, b.x), fminf(c.x, d.x)),
+                                           fmaxf(fmaxf(a.y, b.y), fmaxf(c.y, d.y)));
 }
 
 void launch_hiz_down(const float2* src, int sp, float2* dst, hipStream_t st) {

@@ -199,7 +199,7 @@ __device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax
         const float sy = db > 0.f ? (yh - b0) * idb : (db < 0.f ? (yl - b0) * idb : FLT_MAX);
         const float se = fminf(fminf(sx, sy), s_hi);
         const float za = z0 + s * dz, zb = z0 + se * dz;
-        const float2 h = hiz[hiz_offset(P, level) + cy * (P >> level) + cx];
+        const float2 h = hiz[hiz_offset(P, level) + hiz_texel(P >> level, cx, cy)];
         const bool ov = fmaxf(za, zb) + zpad >= h.x && fminf(za, zb) - zpad <= h.y;
         if (ov && level > 0) {
             level--;
@@ -315,9 +315,14 @@ __global__ __launch_bounds__(256, 6) void k_march(const SlotDesc* __restrict__ d
     const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
     const uint32_t total = n_chunks * (uint32_t)max_views;
     const int lane = threadIdx.x & 63;
-    const uint32_t wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const uint32_t nw = gridDim.x * 4;
-    for (uint32_t q = wid; q < total; q += nw) {
+    // Each XCD takes a contiguous eighth of the (view, chunk) items so that its L2 serves one
+    // region of one view; within an XCD the wavefronts stride over that range.
+    const uint32_t xcd = blockIdx.x % kNumXcd;
+    const uint32_t per_xcd_waves = (gridDim.x / kNumXcd) * 4;
+    const uint32_t wx = __builtin_amdgcn_readfirstlane((blockIdx.x / kNumXcd) * 4 + (threadIdx.x >> 6));
+    const uint32_t q0 = (uint32_t)(((uint64_t)total * xcd) / kNumXcd);
+    const uint32_t q1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kNumXcd);
+    for (uint32_t q = q0 + wx; q < q1; q += per_xcd_waves) {
         const uint32_t v = q / n_chunks, c = q - v * n_chunks;
         const uint32_t e = c * kWaveChunk + lane;
         if (e >= n) continue;

@@ -36,6 +36,15 @@ __host__ __device__ inline uint32_t hiz_offset(int P, int l) {
     return 4u * ((a - b) / 3u);
 }
 
+// Texel (x, y) of a level of side w: levels of side >= 4 are stored in 4x4 tiles (16 texels,
+// 128 B, one cache line) so a ray crossing a tile in any direction stays in one line.
+__host__ __device__ inline uint32_t hiz_texel(int w, int x, int y) {
+    if (w < 4) return (uint32_t)(y * w + x);
+    return (uint32_t)((((y >> 2) * (w >> 2) + (x >> 2)) << 4) | ((y & 3) << 2) | (x & 3));
+}
+
+constexpr int kNumXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs, each with its L2
+
 // One work item of a batched launch: one screen (one incidence) on one scene.
 struct SlotDesc {
     // scene
