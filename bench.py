@@ -32,6 +32,28 @@ HBM_PEAK_GBS = 8000.0
 # lane-ops/s (the published 157.3 TFLOP/s counts an FMA as two flops).
 FP32_LANE_OPS = 256 * 128 * 2.4e9
 
+# HBM traffic of k_march from two rocprofv3 --pmc passes over one step of the default workload
+# (mean KiB per dispatch), each scaled by what the counter reads for a plain 1 GiB device copy
+# (FETCH_SIZE reads 524302 KiB for 1 GiB: factor 2.0; WRITE_SIZE 1048576 KiB: factor 1.0).
+# Valid only for the sources they were taken on; any edit of those files reports null.
+MARCH_TRAFFIC = dict(
+    fetch_kib=1473519.8, write_kib=15127.2, fetch_factor=2.0, write_factor=1.0,
+    sources={"paper_2408_15583_amd/csrc/k_trace.hip":
+             "e64d301ef4862aa9114c15c32c3e8b579fedf3b5979a158a0d560d0f332ccbaf",
+             "paper_2408_15583_amd/csrc/pe_device.h":
+             "3ac489661c93823a323206792dbefee5abaed98d8a350228f3819327518c1109"})
+
+
+def march_traffic():
+    """Counter-measured bytes per k_march launch, or None once the kernel's sources changed."""
+    import hashlib
+    for rel, digest in MARCH_TRAFFIC["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    t = MARCH_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
 
 def po_slots_per_term():
     """Issue slots (fp32 lane-op equivalents) one PO term needs: fp64 ops count twice (half
@@ -164,7 +186,7 @@ def main():
         per_launch = per_step_bytes / (launches / args.steps)
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, kernel="k_march",
+                    frac=achieved / HBM_PEAK_GBS, traffic=march_traffic(), kernel="k_march",
                     avg_launch_ms=avg_ms, launches=launches,
                     bytes_per_launch=per_launch,
                     note="97 B state read per live ray + 97 B write per continuing ray + 1 B")
