@@ -10,6 +10,11 @@ project, residual), max-pooling down, sub-pixel convolution (conv + pixel shuffl
 shared encoder and three decoder heads (depth, normal, hit logit) -- the time complexity
 M1 (L_e + 3 L_d) of Sec. III-C counts three decoders.  Outputs are at twice the input size.
 
+The depth output is the depth head's value plus the coarse depth 1 - x of the input pixel
+the output pixel lies in (0 where the input is empty): the head learns a correction at pixel
+scale, which keeps the bf16 activations of the HIP network precise to a small fraction of a
+pixel of depth.  (The paper does not state how the depth head is parametrised.)
+
 Losses (Eq. (17)-(21)): L1 depth squared error (mean over target hits), L2 sine of the angle
 between predicted and target normals (mean over target hits), L3 alpha-balanced focal loss on
 the hit probability (alpha = 0.5, gamma = 2, mean over all pixels), L4 sine of the angle between
@@ -322,7 +327,11 @@ def forward(P, x):
         outs[head] = pixel_shuffle(zo)
         cache["head_" + head] = hc
     cache["skips"] = skips
-    return (outs["depth"][..., 0], outs["nrm"], outs["mask"][..., 0]), cache
+    # the depth head predicts a correction to the coarse depth t/D = 1 - x (0 where the coarse
+    # buffer is empty), repeated over each 2 x 2 block of output pixels
+    x0 = x[..., 0]
+    base = np.where(x0 > 0, 1.0 - x0, 0.0).repeat(2, axis=1).repeat(2, axis=2)
+    return (outs["depth"][..., 0] + base, outs["nrm"], outs["mask"][..., 0]), cache
 
 
 def backward(P, cache, d_depth, d_nrm, d_logit):
