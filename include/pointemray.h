@@ -52,7 +52,7 @@ enum { PE_F32 = 0, PE_F64 = 1 };
 enum { PE_MAT_PEC = 0, PE_MAT_ABSORBER = 1 };
 enum { PE_CONTRIB_LAST = 0, PE_CONTRIB_EVERY = 1 };
 enum { PE_PREC_FP64PHASE = 0, PE_PREC_FP32 = 1 };
-enum { PE_GEOM_PLAIN = 0, PE_GEOM_DENSIFIED = 1 };
+enum { PE_GEOM_PLAIN = 0, PE_GEOM_DENSIFIED = 1, PE_GEOM_COARSE = 2 };
 enum { PE_SPLAT_DISK = 0, PE_SPLAT_TUBE = 1 };
 
 /* Scene description (input P of Algorithm 1, with normals and a material flag per point). */
@@ -86,10 +86,22 @@ typedef struct {
     double eps;              /* minimum travel distance of secondary rays (m), >= 0 */
     int32_t contrib;         /* PE_CONTRIB_LAST (Eq. (14)) or PE_CONTRIB_EVERY */
     int32_t precision;       /* PE_PREC_FP64PHASE or PE_PREC_FP32 */
-    int32_t geometry;        /* PE_GEOM_PLAIN, or PE_GEOM_DENSIFIED (needs densifier,
-                                max_bounces == 1, screen_w == screen_h, even) */
+    int32_t geometry;        /* PE_GEOM_PLAIN: first hits from the disk splat (Algorithm 3).
+                                PE_GEOM_DENSIFIED: coarse TUBE buffer at half resolution
+                                (Algorithm 1) -> network -> GFB at the screen resolution ->
+                                Eq. (14) at the first bounce (Sec. III-A); incidences whose
+                                network output is uncertain fall back to PLAIN.
+                                PE_GEOM_COARSE: the same without the network, PO straight from
+                                the half-resolution TUBE buffer with normals from its depth
+                                gradients (Eq. (16)).  DENSIFIED and COARSE need
+                                max_bounces == 1 and a square screen, multiple of 16. */
     pe_densifier densifier;  /* network used when geometry == PE_GEOM_DENSIFIED */
     uint64_t seed;           /* reserved for stochastic variants; results do not depend on it */
+    double tube_px;          /* DENSIFIED/COARSE: tube radius delta of Algorithm 1 in coarse
+                                pixels (0 = 2.0) */
+    double max_uncertain;    /* DENSIFIED: fall back to PLAIN for an incidence when more than
+                                this fraction of its pixels with hit probability > 0.1 lie in
+                                (0.1, 0.9) (0 = 0.25) */
 } pe_solve_desc;
 
 /* Counters of one solve. */
@@ -164,6 +176,10 @@ pe_status pe_submit(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_re
 pe_status pe_wait(pe_ctx ctx, pe_ticket ticket, int64_t timeout_us);
 /* Cancels a pending or running request; pe_wait then returns PE_ECANCELED. */
 pe_status pe_cancel(pe_ctx ctx, pe_ticket ticket);
+/* HBM bytes the server charges a request for admission (its transient workspace at the
+ * largest batch share it can take); pe_submit fails with PE_ENOMEM when this exceeds the
+ * context's budget. */
+pe_status pe_request_footprint(const pe_solve_desc* desc, uint64_t* bytes);
 /* Latency/throughput counters of the server since creation (or the last reset):
  * out[0] completed, out[1] p50 latency ms, out[2] p99 latency ms, out[3] mean ms,
  * out[4] max concurrent requests on the device, out[5] mean requests per shared launch batch. */
@@ -213,10 +229,34 @@ pe_status pe_densifier_train_step(pe_densifier net, int32_t b, int32_t h, int32_
                                   const float* mask_gt, float lr, float weight_decay,
                                   double* loss_out, void* hip_stream);
 /* Inference: outputs (device, may be NULL) depth b x 2h x 2w, nrm b x 2h x 2w x 3 (unit,
- * view frame), prob b x 2h x 2w (hit probability). */
+ * view frame), prob b x 2h x 2w (hit probability).  h, w: multiples of 8. */
 pe_status pe_densifier_infer(pe_densifier net, int32_t b, int32_t h, int32_t w,
                              const float* coarse, float* depth, float* nrm, float* prob,
                              void* hip_stream);
+/* Parameter table: *n = number of tensors; for i < cap: names[i] (library-owned, valid while
+ * the network lives), offsets[i] into the flat parameter vector, shapes[4 i .. 4 i + 3]
+ * (convolutions [Cout][K][K][Cin], depthwise [C][7][7], vectors [C]; unused trailing dims 0).
+ * Any of names/offsets/shapes may be NULL. */
+pe_status pe_densifier_tensors(pe_densifier net, int32_t cap, const char** names,
+                               uint64_t* offsets, int32_t* shapes, int32_t* n);
+/* Copies a flat fp32 vector of pe_densifier_num_params values to the host: which = 0 master
+ * parameters, 1 gradients of the last train step, 2 / 3 AdamW first / second moments. */
+pe_status pe_densifier_get(pe_densifier net, int32_t which, float* host, uint64_t n);
+/* Replaces the master parameters (host fp32, n = pe_densifier_num_params) and refreshes the
+ * bf16 copies; AdamW state is kept.  PE_EINVAL on a non-finite value. */
+pe_status pe_densifier_set(pe_densifier net, const float* host, uint64_t n);
+/* Training data from a scene (Sec. IV-A recipe on synthetic scenes): for each of n_dir
+ * propagation directions (host, n_dir x 3), the network input and targets on that
+ * direction's screen (side 2R, as for pe_solve), device outputs, any group may be NULL:
+ *   coarse   n_dir x h x w        TUBE first hits (radius tube_px coarse pixels): 1 - t/D, 0 empty
+ *   depth_gt n_dir x 2h x 2w      DISK first hits: t/D (0 where empty)
+ *   nrm_gt   n_dir x 2h x 2w x 3  unit normal against the ray in the view frame (u, v, -k)
+ *   mask_gt  n_dir x 2h x 2w      1 on hits
+ * (t: distance from the screen plane along the ray, D = 2R.) */
+pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, const double* dirs,
+                                 int32_t h, int32_t w, double tube_px, float* coarse,
+                                 float* depth_gt, float* nrm_gt, float* mask_gt,
+                                 void* hip_stream);
 
 /* ---- errors ------------------------------------------------------------------------------ */
 

@@ -10,11 +10,13 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM_DENSIFIED,
-                      PE_GEOM_PLAIN, PE_MEM_DEVICE, PE_MEM_HOST, PE_PREC_FP32,
+from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM_COARSE,
+                      PE_GEOM_DENSIFIED, PE_GEOM_PLAIN, PE_MEM_DEVICE, PE_MEM_HOST, PE_PREC_FP32,
                       PE_PREC_FP64PHASE, PE_SPLAT_DISK, PE_SPLAT_TUBE, PEError, check, lib)
 
-__all__ = ["Context", "Scene", "solve", "render_gfb", "trace_pixels", "PEError", "lib", "check"]
+__all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "submit", "server_stats",
+           "render_gfb", "trace_pixels", "make_pair",
+           "PEError", "lib", "check"]
 
 
 def _torch():
@@ -168,7 +170,8 @@ _PREC = {"fp64phase": PE_PREC_FP64PHASE, "fp32": PE_PREC_FP32}
 
 
 def make_solve_desc(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=None,
-                    contrib="last", precision="fp64phase", densifier=None):
+                    contrib="last", precision="fp64phase", densifier=None, geometry=None,
+                    tube_px=0.0, max_uncertain=0.0):
     inc = np.ascontiguousarray(inc_dir, dtype=np.float64).reshape(-1, 3)
     fr = np.ascontiguousarray(freq_hz, dtype=np.float64).ravel()
     d = _native.pe_solve_desc()
@@ -188,17 +191,24 @@ def make_solve_desc(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=No
     d.eps = float(eps)
     d.contrib = _CONTRIB[contrib]
     d.precision = _PREC[precision]
+    if geometry is None:
+        geometry = "densified" if densifier is not None else "plain"
+    d.geometry = {"plain": PE_GEOM_PLAIN, "densified": PE_GEOM_DENSIFIED,
+                  "coarse": PE_GEOM_COARSE}[geometry]
     if densifier is not None:
-        d.geometry = PE_GEOM_DENSIFIED
         d.densifier = densifier.h if hasattr(densifier, "h") else densifier
+    d.tube_px = float(tube_px)
+    d.max_uncertain = float(max_uncertain)
     return d, keep
 
 
 def solve(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
-          obs_dir=None, contrib="last", precision="fp64phase", densifier=None, stream=None):
-    """Synchronous pe_solve.  Returns (E complex [inc, obs, freq, rx, tx], rcs_dbsm, stats)."""
+          obs_dir=None, contrib="last", precision="fp64phase", densifier=None, stream=None,
+          geometry=None, tube_px=0.0, max_uncertain=0.0):
+    """Synchronous pe_solve.  Returns (E complex [inc, obs, freq, rx, tx], rcs_dbsm, stats).
+    geometry: "plain" (default), "densified" (needs densifier) or "coarse"."""
     d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
-                              precision, densifier)
+                              precision, densifier, geometry, tube_px, max_uncertain)
     no = 1 if obs_dir is None else d.n_obs
     E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
     rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))
@@ -244,3 +254,156 @@ def trace_pixels(ctx: Context, scene: Scene, inc_dir, w, h, max_bounces, eps, st
     check(lib().pe_trace_pixels(ctx.h, scene.h, dr, w, h, int(max_bounces), float(eps),
                                 _dptr(nb), _dptr(lx), _dptr(ln), _dptr(path), _dptr(li), s))
     return dict(n_bounce=nb, last_x=lx, last_n=ln, path=path, last_idx=li)
+
+
+class Densifier:
+    """pe_densifier: the U-Net of Sec. III-A on the device (bf16 weights, fp32 masters, AdamW)."""
+
+    def __init__(self, ctx: Context, base: int = 32, seed: int = 0):
+        self.ctx = ctx
+        h = _native.pe_densifier()
+        check(lib().pe_densifier_create(ctx.h, int(base), int(seed), ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_uint64()
+        check(lib().pe_densifier_num_params(self.h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def tensors(self):
+        """[(name, offset, shape)] of the flat parameter vector."""
+        n = ctypes.c_int32()
+        check(lib().pe_densifier_tensors(self.h, 0, None, None, None, ctypes.byref(n)))
+        names = (ctypes.c_char_p * n.value)()
+        offs = (ctypes.c_uint64 * n.value)()
+        shp = (ctypes.c_int32 * (4 * n.value))()
+        check(lib().pe_densifier_tensors(self.h, n.value, names, offs, shp, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            shape = tuple(d for d in shp[4 * i:4 * i + 4] if d > 0)
+            out.append((names[i].decode(), offs[i], shape))
+        return out
+
+    def get(self, which="params"):
+        which = {"params": 0, "grads": 1, "m": 2, "v": 3}[which]
+        a = np.empty(self.n_params, dtype=np.float32)
+        check(lib().pe_densifier_get(self.h, which, a.ctypes.data_as(_native.c_float_p),
+                                     self.n_params))
+        return a
+
+    def set(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        check(lib().pe_densifier_set(self.h, a.ctypes.data_as(_native.c_float_p), a.size))
+
+    def get_dict(self, which="params"):
+        flat = self.get(which)
+        return {n: flat[o:o + int(np.prod(s))].reshape(s) for n, o, s in self.tensors()}
+
+    def train_step(self, coarse, depth_gt, nrm_gt, mask_gt, lr, weight_decay=0.0, stream=None):
+        """One AdamW step on torch CUDA float32 tensors [b,h,w], [b,2h,2w], [b,2h,2w,3],
+        [b,2h,2w].  Returns the losses (total, L1, L2, L3, L4)."""
+        b, h, w = coarse.shape
+        out = (ctypes.c_double * 5)()
+        s = current_stream() if stream is None else stream
+        check(lib().pe_densifier_train_step(self.h, b, h, w, _dptr(coarse), _dptr(depth_gt),
+                                            _dptr(nrm_gt), _dptr(mask_gt), float(lr),
+                                            float(weight_decay), out, s))
+        return tuple(out)
+
+    def infer(self, coarse, stream=None):
+        """(depth, unit normal, hit probability) torch tensors at twice the input size."""
+        torch = _torch()
+        b, h, w = coarse.shape
+        dev = coarse.device
+        depth = torch.empty((b, 2 * h, 2 * w), dtype=torch.float32, device=dev)
+        nrm = torch.empty((b, 2 * h, 2 * w, 3), dtype=torch.float32, device=dev)
+        prob = torch.empty((b, 2 * h, 2 * w), dtype=torch.float32, device=dev)
+        s = current_stream() if stream is None else stream
+        check(lib().pe_densifier_infer(self.h, b, h, w, _dptr(coarse), _dptr(depth), _dptr(nrm),
+                                       _dptr(prob), s))
+        return depth, nrm, prob
+
+    def save(self, path):
+        check(lib().pe_densifier_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        check(lib().pe_densifier_load(self.h, str(path).encode()))
+
+    def close(self):
+        if self.h:
+            check(lib().pe_densifier_destroy(self.h))
+            self.h = None
+
+
+def make_pair(ctx: Context, scene: Scene, dirs, h, w, tube_px=2.0, stream=None):
+    """Network input and targets for each propagation direction (torch CUDA tensors):
+    coarse [n,h,w], depth_gt [n,2h,2w], nrm_gt [n,2h,2w,3], mask_gt [n,2h,2w]."""
+    torch = _torch()
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    n = d.shape[0]
+    dev = torch.device("cuda")
+    coarse = torch.empty((n, h, w), dtype=torch.float32, device=dev)
+    dg = torch.empty((n, 2 * h, 2 * w), dtype=torch.float32, device=dev)
+    ng = torch.empty((n, 2 * h, 2 * w, 3), dtype=torch.float32, device=dev)
+    mg = torch.empty((n, 2 * h, 2 * w), dtype=torch.float32, device=dev)
+    s = current_stream() if stream is None else stream
+    check(lib().pe_densifier_make_pair(ctx.h, scene.h, n, d.ctypes.data_as(_native.c_double_p),
+                                       int(h), int(w), float(tube_px), _dptr(coarse), _dptr(dg),
+                                       _dptr(ng), _dptr(mg), s))
+    return coarse, dg, ng, mg
+
+
+class Ticket:
+    """A request submitted to the context's continuous-batching server."""
+
+    def __init__(self, ctx, ticket, E, rcs, st, res, keep):
+        self.ctx, self.id, self._E, self._rcs, self._st = ctx, ticket, E, rcs, st
+        self._res, self._keep = res, keep
+
+    def wait(self, timeout_s=None):
+        """Blocks until the request finishes; returns (E complex, rcs_dbsm, stats).  Raises
+        PEError (PE_ECANCELED, a failure) or TimeoutError (still pending)."""
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        s = lib().pe_wait(self.ctx.h, self.id, us)
+        if s == _native.PE_ETIMEOUT:
+            raise TimeoutError(f"request {self.id} still pending")
+        check(s)
+        stats = {f: getattr(self._st, f) for f, _ in _native.pe_stats._fields_}
+        return self._E[..., 0] + 1j * self._E[..., 1], self._rcs, stats
+
+    def cancel(self):
+        check(lib().pe_cancel(self.ctx.h, self.id))
+
+
+def submit(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
+           obs_dir=None, contrib="last", precision="fp64phase"):
+    """Asynchronous solve through the server (pe_submit); returns a Ticket."""
+    d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
+                              precision)
+    no = 1 if obs_dir is None else d.n_obs
+    E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
+    rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))
+    st = _native.pe_stats()
+    res = _native.pe_result(E.ctypes.data_as(_native.c_double_p),
+                            rcs.ctypes.data_as(_native.c_double_p), ctypes.pointer(st))
+    t = _native.pe_ticket()
+    check(lib().pe_submit(ctx.h, scene.h, ctypes.byref(d), ctypes.byref(res), ctypes.byref(t)))
+    return Ticket(ctx, t.value, E, rcs, st, res, keep)
+
+
+def server_stats(ctx: Context, reset=False):
+    """Server counters: completed, p50/p99/mean latency (ms), max concurrent requests, mean
+    requests per shared launch batch."""
+    out = (ctypes.c_double * 6)()
+    check(lib().pe_server_stats(ctx.h, out, int(bool(reset))))
+    keys = ("completed", "p50_ms", "p99_ms", "mean_ms", "max_concurrent", "reqs_per_batch")
+    return dict(zip(keys, list(out)))
+
+
+def request_footprint(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=None,
+                      contrib="last", precision="fp64phase"):
+    """HBM bytes the server charges a request for admission."""
+    d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
+                              precision)
+    b = ctypes.c_uint64()
+    check(lib().pe_request_footprint(ctypes.byref(d), ctypes.byref(b)))
+    del keep
+    return b.value

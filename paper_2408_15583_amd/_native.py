@@ -27,7 +27,7 @@ PE_F32, PE_F64 = 0, 1
 PE_MAT_PEC, PE_MAT_ABSORBER = 0, 1
 PE_CONTRIB_LAST, PE_CONTRIB_EVERY = 0, 1
 PE_PREC_FP64PHASE, PE_PREC_FP32 = 0, 1
-PE_GEOM_PLAIN, PE_GEOM_DENSIFIED = 0, 1
+PE_GEOM_PLAIN, PE_GEOM_DENSIFIED, PE_GEOM_COARSE = 0, 1, 2
 PE_SPLAT_DISK, PE_SPLAT_TUBE = 0, 1
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -57,7 +57,8 @@ class pe_solve_desc(ctypes.Structure):
                 ("max_bounces", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("contrib", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("geometry", ctypes.c_int32), ("densifier", pe_densifier),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("tube_px", ctypes.c_double),
+                ("max_uncertain", ctypes.c_double)]
 
 
 class pe_stats(ctypes.Structure):
@@ -90,6 +91,7 @@ _SIGS = {
     "pe_wait": [pe_ctx, pe_ticket, ctypes.c_int64],
     "pe_cancel": [pe_ctx, pe_ticket],
     "pe_server_stats": [pe_ctx, c_double_p, ctypes.c_int32],
+    "pe_request_footprint": [ctypes.POINTER(pe_solve_desc), c_u64_p],
     "pe_render_gfb": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -108,6 +110,13 @@ _SIGS = {
     "pe_densifier_infer": [pe_densifier, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                            ctypes.c_void_p],
+    "pe_densifier_tensors": [pe_densifier, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p),
+                             c_u64_p, c_i32_p, c_i32_p],
+    "pe_densifier_get": [pe_densifier, ctypes.c_int32, c_float_p, ctypes.c_uint64],
+    "pe_densifier_set": [pe_densifier, c_float_p, ctypes.c_uint64],
+    "pe_densifier_make_pair": [pe_ctx, pe_scene, ctypes.c_int32, c_double_p, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
 }
 
 _lib = None

@@ -17,21 +17,7 @@
 
 using namespace pe;
 
-#define API_BEGIN try {
-#define API_END                                                              \
-    }                                                                        \
-    catch (const Error& e) {                                                 \
-        return set_error(e.status, e.msg);                                   \
-    }                                                                        \
-    catch (const std::bad_alloc&) {                                          \
-        return set_error(PE_ENOMEM, "host allocation failed");               \
-    }                                                                        \
-    catch (const std::exception& e) {                                        \
-        return set_error(PE_EDEVICE, std::string("internal error: ") + e.what()); \
-    }                                                                        \
-    catch (...) {                                                            \
-        return set_error(PE_EDEVICE, "internal error");                      \
-    }
+
 
 namespace pe {
 
@@ -44,8 +30,8 @@ static bool finite3(const double* v) {
 }
 
 // Shared by pe_solve and pe_submit.
-void validate_solve(pe_scene sc, const pe_solve_desc* d) {
-    if (!sc || !d) throw Error{PE_EINVAL, "null scene or descriptor"};
+void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene) {
+    if ((need_scene && !sc) || !d) throw Error{PE_EINVAL, "null scene or descriptor"};
     if (d->n_inc < 1 || !d->inc_dir) throw Error{PE_EINVAL, "need n_inc >= 1 incidence directions"};
     for (int i = 0; i < d->n_inc; i++)
         if (!finite3(d->inc_dir + 3 * i)) throw Error{PE_EINVAL, "non-finite or zero incidence direction"};
@@ -63,12 +49,15 @@ void validate_solve(pe_scene sc, const pe_solve_desc* d) {
     if (!(d->eps >= 0) || !std::isfinite(d->eps)) throw Error{PE_EINVAL, "eps must be finite and >= 0"};
     if (d->contrib != PE_CONTRIB_LAST && d->contrib != PE_CONTRIB_EVERY) throw Error{PE_EINVAL, "bad contrib flag"};
     if (d->precision != PE_PREC_FP64PHASE && d->precision != PE_PREC_FP32) throw Error{PE_EINVAL, "bad precision flag"};
-    if (d->geometry != PE_GEOM_PLAIN && d->geometry != PE_GEOM_DENSIFIED) throw Error{PE_EINVAL, "bad geometry flag"};
-    if (d->geometry == PE_GEOM_DENSIFIED) {
-        if (!d->densifier) throw Error{PE_EINVAL, "densified geometry needs a densifier"};
-        if (d->max_bounces != 1) throw Error{PE_EUNSUPPORTED, "densified geometry supports max_bounces == 1"};
+    if (d->geometry != PE_GEOM_PLAIN && d->geometry != PE_GEOM_DENSIFIED && d->geometry != PE_GEOM_COARSE)
+        throw Error{PE_EINVAL, "bad geometry flag"};
+    if (d->geometry != PE_GEOM_PLAIN) {
+        if (d->geometry == PE_GEOM_DENSIFIED && !d->densifier) throw Error{PE_EINVAL, "densified geometry needs a densifier"};
+        if (d->max_bounces != 1) throw Error{PE_EUNSUPPORTED, "densified/coarse geometry supports max_bounces == 1"};
         if (d->screen_w != d->screen_h || d->screen_w % 16 != 0)
-            throw Error{PE_EINVAL, "densified geometry needs a square screen, multiple of 16"};
+            throw Error{PE_EINVAL, "densified/coarse geometry needs a square screen, multiple of 16"};
+        if (!(d->tube_px >= 0) || !std::isfinite(d->tube_px)) throw Error{PE_EINVAL, "tube_px must be finite and >= 0"};
+        if (!(d->max_uncertain >= 0) || !(d->max_uncertain <= 1)) throw Error{PE_EINVAL, "max_uncertain must be in [0, 1]"};
     }
 }
 
@@ -419,7 +408,7 @@ pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_res
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
-    if (desc->geometry == PE_GEOM_DENSIFIED) {
+    if (desc->geometry != PE_GEOM_PLAIN) {
         if (!g_densified_solve) return set_error(PE_EUNSUPPORTED, "densifier module unavailable");
         g_densified_solve(*ctx->ws, st, scene, desc, res->E, res->rcs_dbsm, &acc);
     } else {

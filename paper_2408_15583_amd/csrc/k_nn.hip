@@ -1,0 +1,878 @@
+// Kernels of the learned densifier (Sec. III-A): a U-Net with ConvNeXt encoder blocks,
+// max-pool down, sub-pixel convolution up, three decoder heads, trained with Eq. (17)-(21).
+//
+// Layout: activations NHWC in bf16 (uint16 storage), convolution weights OHWI in bf16 with
+// fp32 master copies; every GEMM-shaped convolution runs on MFMA (v_mfma_f32_16x16x32_bf16,
+// fp32 accumulation): forward and data-gradient as implicit GEMM over (pixels x Cout x taps*Cin)
+// with fragments loaded straight from NHWC/OHWI (8 contiguous bf16 per lane), weight-gradient as
+// GEMM over (Cout x Cin x pixels) with tiles transposed through LDS.  Everything that reduces
+// over pixels writes per-chunk partials summed in a fixed order, so a training step is
+// bit-reproducible.  Depthwise 7x7, LayerNorm, GELU, pooling, losses and AdamW are VALU kernels.
+#include <float.h>
+
+#include "pe_device.h"
+#include "pe_nn.h"
+
+namespace pe {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline uint16_t f2bf(float f) {  // round to nearest even
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+union Frag {
+    uint4 u;
+    v8bf v;
+};
+
+// ------------------------------------------------------------------------------------------
+// Convolution (stride 1, zero padding (K-1)/2) as implicit GEMM on MFMA
+// ------------------------------------------------------------------------------------------
+// Block: 256 threads = 2x2 wavefronts, tile 64 pixels x 64 output channels; wavefront tile
+// 32 x 32 = 2 x 2 MFMA 16x16 tiles; K advances by 32 input channels per tap.
+// Requirements (checked by the host): Cin % 32 == 0, Cout % 16 == 0.
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pm0 = blockIdx.x * 64 + (wave & 1) * 32;   // first pixel of the wavefront tile
+    const int co0 = blockIdx.y * 64 + (wave >> 1) * 32;  // first output channel
+    const int HW = a.H * a.W, M = a.N * HW;
+    const int r = lane & 15, kq = (lane >> 4) * 8;       // fragment row and k offset
+    v4f acc[2][2];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    int pn[2], py[2], px[2];
+    bool pv[2];
+    for (int i = 0; i < 2; i++) {
+        const int m = pm0 + i * 16 + r;
+        pv[i] = m < M;
+        const int mm = pv[i] ? m : 0;
+        pn[i] = mm / HW;
+        py[i] = (mm % HW) / a.W;
+        px[i] = mm % a.W;
+    }
+    const int pad = (a.K - 1) / 2;
+    const int taps = a.K * a.K;
+    for (int t = 0; t < taps; t++) {
+        const int dy = t / a.K - pad, dx = t % a.K - pad;
+        const uint16_t* xs[2];
+        bool ok[2];
+        for (int i = 0; i < 2; i++) {
+            const int y = py[i] + dy, x = px[i] + dx;
+            ok[i] = pv[i] && y >= 0 && y < a.H && x >= 0 && x < a.W;
+            xs[i] = a.x + ((size_t)(pn[i] * a.H + (ok[i] ? y : 0)) * a.W + (ok[i] ? x : 0)) * a.ldx +
+                    a.xoff;
+        }
+        const uint16_t* ws[2];
+        bool wok[2];
+        for (int j = 0; j < 2; j++) {
+            const int co = co0 + j * 16 + r;
+            wok[j] = co < a.Cout;
+            ws[j] = a.w + ((size_t)(wok[j] ? co : 0) * taps + t) * a.Cin;
+        }
+        for (int c0 = 0; c0 < a.Cin; c0 += 32) {
+            Frag fa[2], fb[2];
+            for (int i = 0; i < 2; i++)
+                fa[i].u = ok[i] ? *(const uint4*)(xs[i] + c0 + kq) : make_uint4(0, 0, 0, 0);
+            for (int j = 0; j < 2; j++)
+                fb[j].u = wok[j] ? *(const uint4*)(ws[j] + c0 + kq) : make_uint4(0, 0, 0, 0);
+            for (int i = 0; i < 2; i++)
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j],
+                                                                       0, 0, 0);
+        }
+    }
+    // D fragment: lane holds column (channel) r of rows (pixels) 4*(lane/16) + q
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            const int co = co0 + j * 16 + r;
+            if (co >= a.Cout_store) continue;
+            const float bias = a.bias ? a.bias[co] : 0.f;
+            for (int q = 0; q < 4; q++) {
+                const int m = pm0 + i * 16 + (lane >> 4) * 4 + q;
+                if (m >= M) continue;
+                float v = acc[i][j][q] + bias;
+                if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
+                const float pre = v;
+                if (a.act == 1) v = 0.5f * v * (1.f + erff(v * 0.70710678118654752f));
+                const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
+                size_t o;
+                int oc;
+                if (a.shuffle) {  // channel c*4 + 2*sy + sx -> pixel (2y+sy, 2x+sx), channel c
+                    oc = co >> 2;
+                    const int sy = (co >> 1) & 1, sx = co & 1;
+                    o = ((size_t)(n * 2 * a.H + 2 * yy + sy) * (2 * a.W) + 2 * xx + sx) * a.ldy +
+                        a.yoff + oc;
+                } else {
+                    oc = co;
+                    o = ((size_t)(n * a.H + yy) * a.W + xx) * a.ldy + a.yoff + oc;
+                }
+                if (a.y32) a.y32[o] = v;
+                else a.y[o] = f2bf(v);
+                if (a.z) a.z[o] = f2bf(pre);
+            }
+        }
+}
+
+void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
+    const int M = a.N * a.H * a.W;
+    hipLaunchKernelGGL(k_conv_fwd, dim3((M + 63) / 64, (a.Cout + 63) / 64), dim3(256), 0, st, a);
+}
+
+// Weight gradient: dW[co][t][ci] = sum_p dY[p][co] X[p + shift(t)][ci] over one chunk of
+// 256 pixels per block (partials[chunk][co][t][ci], fp32), tiles 64 co x 64 ci, K = 32 pixels
+// per step staged through LDS transposed so each fragment is 8 contiguous bf16.
+__global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
+    __shared__ uint16_t sdy[64][40];  // [co][pixel] (32 pixels + pad)
+    __shared__ uint16_t sx[64][40];   // [ci][pixel]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int taps = a.K * a.K;
+    const int t = blockIdx.z % taps, chunk = blockIdx.z / taps;
+    const int co0 = blockIdx.x * 64, ci0 = blockIdx.y * 64;
+    const int pad = (a.K - 1) / 2, dy = t / a.K - pad, dx = t % a.K - pad;
+    const int HW = a.H * a.W, M = a.N * HW;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    const int wco = (wave & 1) * 32, wci = (wave >> 1) * 32;
+    v4f acc[2][2];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    const int p_beg = chunk * a.chunk, p_end = min(M, p_beg + a.chunk);
+    // loader: thread -> (pixel lp = tid / 8, channel group cg = (tid % 8) * 8), 32 x 64 tile
+    const int lp = threadIdx.x >> 3, cg = (threadIdx.x & 7) * 8;
+    for (int p0 = p_beg; p0 < p_end; p0 += 32) {
+        const int m = p0 + lp;
+        uint4 vy = make_uint4(0, 0, 0, 0), vx = make_uint4(0, 0, 0, 0);
+        if (m < p_end) {
+            const int n = m / HW, y = (m % HW) / a.W, x = m % a.W;
+            if (co0 + cg < a.Cout)
+                vy = *(const uint4*)(a.dy + ((size_t)(n * a.H + y) * a.W + x) * a.lddy + a.dyoff +
+                                     co0 + cg);
+            const int ys = y + dy, xs = x + dx;
+            if (ys >= 0 && ys < a.H && xs >= 0 && xs < a.W && ci0 + cg < a.Cin)
+                vx = *(const uint4*)(a.x + ((size_t)(n * a.H + ys) * a.W + xs) * a.ldx + a.xoff +
+                                     ci0 + cg);
+        }
+        const uint16_t* hy = (const uint16_t*)&vy;
+        const uint16_t* hx = (const uint16_t*)&vx;
+        __syncthreads();
+        for (int j = 0; j < 8; j++) {
+            sdy[cg + j][lp] = hy[j];
+            sx[cg + j][lp] = hx[j];
+        }
+        __syncthreads();
+        Frag fa[2], fb[2];
+        for (int i = 0; i < 2; i++) fa[i].u = *(const uint4*)&sdy[wco + i * 16 + r][kq];
+        for (int j = 0; j < 2; j++) fb[j].u = *(const uint4*)&sx[wci + j * 16 + r][kq];
+        for (int i = 0; i < 2; i++)
+            for (int j = 0; j < 2; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
+                                                                   0, 0);
+    }
+    float* out = a.partial + (size_t)chunk * a.Cout * taps * a.Cin;
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            const int ci = ci0 + wci + j * 16 + r;
+            for (int q = 0; q < 4; q++) {
+                const int co = co0 + wco + i * 16 + (lane >> 4) * 4 + q;
+                if (co < a.Cout && ci < a.Cin) out[((size_t)co * taps + t) * a.Cin + ci] = acc[i][j][q];
+            }
+        }
+}
+
+void launch_conv_wgrad(const WgradArgs& a, int n_chunks, hipStream_t st) {
+    hipLaunchKernelGGL(k_conv_wgrad, dim3((a.Cout + 63) / 64, (a.Cin + 63) / 64,
+                                          n_chunks * a.K * a.K),
+                       dim3(256), 0, st, a);
+}
+
+// out[i] = sum over chunks c (in chunk order) of part[c * stride + (i / inner) * outer +
+// i % inner + off]: gathers one parameter tensor out of interleaved per-chunk partials.
+__global__ void k_reduce_chunks(const float* __restrict__ part, int n_chunks, size_t stride,
+                                size_t n, int inner, int outer, int off, float* __restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t src = (i / inner) * outer + i % inner + off;
+        float s = 0.f;
+        for (int c = 0; c < n_chunks; c++) s += part[(size_t)c * stride + src];
+        out[i] = s;
+    }
+}
+
+void launch_reduce_chunks(const float* part, int n_chunks, size_t stride, size_t n, int inner,
+                          int outer, int off, float* out, hipStream_t st) {
+    int b = (int)((n + 255) / 256);
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(b > 0 ? b : 1), dim3(256), 0, st, part, n_chunks,
+                       stride, n, inner, outer, off, out);
+}
+
+// Column sums of a bf16 [M][ld] tensor (channels off..off+C) per chunk of rows: bias grads.
+__global__ void k_colsum(const uint16_t* __restrict__ y, int M, int ld, int off, int C,
+                         int chunk, float* __restrict__ part) {
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int m0 = blockIdx.x * chunk, m1 = min(M, m0 + chunk);
+    float s = 0.f;
+    for (int m = m0; m < m1; m++) s += bf2f(y[(size_t)m * ld + off + c]);
+    part[(size_t)blockIdx.x * C + c] = s;
+}
+
+void launch_colsum(const uint16_t* y, int M, int ld, int off, int C, int chunk, float* part,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum, dim3((M + chunk - 1) / chunk, (C + 63) / 64), dim3(64), 0, st, y,
+                       M, ld, off, C, chunk, part);
+}
+
+// Flips a weight tensor for the data gradient: wt[ci][t'][co] = w[co][taps-1-t'][ci]
+// (Cin_t = Cout padded to cpad; extra output channels zero).
+__global__ void k_weight_flip(const uint16_t* __restrict__ w, int Cout, int taps, int Cin,
+                              int co_pad, uint16_t* __restrict__ wt) {
+    const size_t n = (size_t)Cin * taps * co_pad;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int co = (int)(i % co_pad);
+        const int t = (int)((i / co_pad) % taps);
+        const int ci = (int)(i / ((size_t)co_pad * taps));
+        wt[i] = co < Cout ? w[((size_t)co * taps + (taps - 1 - t)) * Cin + ci] : (uint16_t)0;
+    }
+}
+
+void launch_weight_flip(const uint16_t* w, int Cout, int taps, int Cin, int co_pad, uint16_t* wt,
+                        hipStream_t st) {
+    const size_t n = (size_t)Cin * taps * co_pad;
+    int b = (int)((n + 255) / 256);
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_weight_flip, dim3(b), dim3(256), 0, st, w, Cout, taps, Cin, co_pad, wt);
+}
+
+// ------------------------------------------------------------------------------------------
+// Elementwise / small kernels
+// ------------------------------------------------------------------------------------------
+
+// Pixel unshuffle of a gradient: d[n][y][x][c*4 + 2 sy + sx] = g[n][2y+sy][2x+sx][goff + c].
+__global__ void k_unshuffle(const uint16_t* __restrict__ g, int N, int H, int W, int C, int ldg,
+                           int goff, uint16_t* __restrict__ d, int ldd) {
+    const size_t n = (size_t)N * H * W * 4 * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % (4 * C));
+        const size_t pix = i / (4 * C);
+        const int x = (int)(pix % W), y = (int)((pix / W) % H), b = (int)(pix / ((size_t)W * H));
+        const int c = k >> 2, sy = (k >> 1) & 1, sx = k & 1;
+        d[pix * ldd + k] = g[((size_t)(b * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx) * ldg + goff + c];
+    }
+}
+
+void launch_unshuffle(const uint16_t* g, int N, int H, int W, int C, int ldg, int goff,
+                      uint16_t* d, int ldd, hipStream_t st) {
+    const size_t n = (size_t)N * H * W * 4 * C;
+    int b = (int)((n + 255) / 256);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_unshuffle, dim3(b), dim3(256), 0, st, g, N, H, W, C, ldg, goff, d, ldd);
+}
+
+// GELU backward: dz = dy * (Phi(z) + z phi(z)) (exact erf form).
+__global__ void k_gelu_bwd(const uint16_t* __restrict__ z, const uint16_t* __restrict__ dy,
+                           size_t n, uint16_t* __restrict__ dz) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float v = bf2f(z[i]);
+        const float cdf = 0.5f * (1.f + erff(v * 0.70710678118654752f));
+        const float pdf = 0.3989422804014327f * __expf(-0.5f * v * v);
+        dz[i] = f2bf(bf2f(dy[i]) * (cdf + v * pdf));
+    }
+}
+
+void launch_gelu_bwd(const uint16_t* z, const uint16_t* dy, size_t n, uint16_t* dz,
+                     hipStream_t st) {
+    int b = (int)((n + 255) / 256);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(b), dim3(256), 0, st, z, dy, n, dz);
+}
+
+// y[i] = a[i] + b[i] over strided channel slices: rows M, C channels.
+__global__ void k_add(const uint16_t* __restrict__ a, int lda, int aoff,
+                      const uint16_t* __restrict__ b, int ldb, int boff, int M, int C,
+                      uint16_t* __restrict__ y, int ldy, int yoff) {
+    const size_t n = (size_t)M * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t m = i / C;
+        const int c = (int)(i % C);
+        y[m * ldy + yoff + c] = f2bf(bf2f(a[m * lda + aoff + c]) + bf2f(b[m * ldb + boff + c]));
+    }
+}
+
+void launch_add(const uint16_t* a, int lda, int aoff, const uint16_t* b, int ldb, int boff, int M,
+                int C, uint16_t* y, int ldy, int yoff, hipStream_t st) {
+    const size_t n = (size_t)M * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_add, dim3(bl), dim3(256), 0, st, a, lda, aoff, b, ldb, boff, M, C, y, ldy,
+                       yoff);
+}
+
+// Copy of a channel slice (concat of skips into a decoder buffer).
+__global__ void k_copy_slice(const uint16_t* __restrict__ a, int lda, int aoff, int M, int C,
+                             uint16_t* __restrict__ y, int ldy, int yoff) {
+    const size_t n = (size_t)M * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t m = i / C;
+        const int c = (int)(i % C);
+        y[m * ldy + yoff + c] = a[m * lda + aoff + c];
+    }
+}
+
+void launch_copy_slice(const uint16_t* a, int lda, int aoff, int M, int C, uint16_t* y, int ldy,
+                       int yoff, hipStream_t st) {
+    const size_t n = (size_t)M * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_copy_slice, dim3(bl), dim3(256), 0, st, a, lda, aoff, M, C, y, ldy, yoff);
+}
+
+// Stem: 3x3 convolution of the one-channel input (fp32) into C channels, + bias, pre-activation
+// z and GELU a (bf16).
+__global__ void k_stem_fwd(const float* __restrict__ x, int N, int H, int W, int C,
+                           const float* __restrict__ w, const float* __restrict__ b,
+                           uint16_t* __restrict__ z, uint16_t* __restrict__ a) {
+    const size_t n = (size_t)N * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t pix = i / C;
+        const int xx = (int)(pix % W), yy = (int)((pix / W) % H), bn = (int)(pix / ((size_t)W * H));
+        float s = b[c];
+        for (int t = 0; t < 9; t++) {
+            const int y = yy + t / 3 - 1, x2 = xx + t % 3 - 1;
+            if (y >= 0 && y < H && x2 >= 0 && x2 < W) s += x[(size_t)(bn * H + y) * W + x2] * w[c * 9 + t];
+        }
+        z[i] = f2bf(s);
+        a[i] = f2bf(0.5f * s * (1.f + erff(s * 0.70710678118654752f)));
+    }
+}
+
+void launch_stem_fwd(const float* x, int N, int H, int W, int C, const float* w, const float* b,
+                     uint16_t* z, uint16_t* a, hipStream_t st) {
+    const size_t n = (size_t)N * H * W * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_stem_fwd, dim3(bl), dim3(256), 0, st, x, N, H, W, C, w, b, z, a);
+}
+
+// Stem weight/bias gradient partials: block = chunk of pixels; part[chunk][c*10 + t] (t = 9: bias).
+__global__ void k_stem_wgrad(const float* __restrict__ x, int N, int H, int W, int C,
+                             const uint16_t* __restrict__ dz, int chunk, float* __restrict__ part) {
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    const int M = N * H * W;
+    const int m0 = blockIdx.x * chunk, m1 = min(M, m0 + chunk);
+    float s[10];
+    for (int t = 0; t < 10; t++) s[t] = 0.f;
+    for (int m = m0; m < m1; m++) {
+        const int xx = m % W, yy = (m / W) % H, bn = m / (W * H);
+        const float g = bf2f(dz[(size_t)m * C + c]);
+        for (int t = 0; t < 9; t++) {
+            const int y = yy + t / 3 - 1, x2 = xx + t % 3 - 1;
+            if (y >= 0 && y < H && x2 >= 0 && x2 < W) s[t] += g * x[(size_t)(bn * H + y) * W + x2];
+        }
+        s[9] += g;
+    }
+    for (int t = 0; t < 10; t++) part[((size_t)blockIdx.x * C + c) * 10 + t] = s[t];
+}
+
+void launch_stem_wgrad(const float* x, int N, int H, int W, int C, const uint16_t* dz, int chunk,
+                       float* part, hipStream_t st) {
+    const int M = N * H * W;
+    hipLaunchKernelGGL(k_stem_wgrad, dim3((M + chunk - 1) / chunk), dim3(C <= 64 ? 64 : 256), 0, st,
+                       x, N, H, W, C, dz, chunk, part);
+}
+
+// Depthwise 7x7: y = dw(x) + b (bf16 in/out, fp32 weights).
+__global__ void k_dw_fwd(const uint16_t* __restrict__ x, int N, int H, int W, int C,
+                         const float* __restrict__ w, const float* __restrict__ b,
+                         uint16_t* __restrict__ y) {
+    const size_t n = (size_t)N * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t pix = i / C;
+        const int xx = (int)(pix % W), yy = (int)((pix / W) % H), bn = (int)(pix / ((size_t)W * H));
+        float s = b[c];
+        for (int a = 0; a < 7; a++) {
+            const int yi = yy + a - 3;
+            if (yi < 0 || yi >= H) continue;
+            for (int q = 0; q < 7; q++) {
+                const int xi = xx + q - 3;
+                if (xi < 0 || xi >= W) continue;
+                s += bf2f(x[((size_t)(bn * H + yi) * W + xi) * C + c]) * w[c * 49 + a * 7 + q];
+            }
+        }
+        y[i] = f2bf(s);
+    }
+}
+
+void launch_dw_fwd(const uint16_t* x, int N, int H, int W, int C, const float* w, const float* b,
+                   uint16_t* y, hipStream_t st) {
+    const size_t n = (size_t)N * H * W * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_dw_fwd, dim3(bl), dim3(256), 0, st, x, N, H, W, C, w, b, y);
+}
+
+// Depthwise data gradient: dx[p] = sum_taps dy[p - shift] w[tap] (correlation, flipped).
+__global__ void k_dw_dgrad(const uint16_t* __restrict__ dy, int N, int H, int W, int C,
+                           const float* __restrict__ w, uint16_t* __restrict__ dx) {
+    const size_t n = (size_t)N * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t pix = i / C;
+        const int xx = (int)(pix % W), yy = (int)((pix / W) % H), bn = (int)(pix / ((size_t)W * H));
+        float s = 0.f;
+        for (int a = 0; a < 7; a++) {
+            const int yo = yy - a + 3;
+            if (yo < 0 || yo >= H) continue;
+            for (int q = 0; q < 7; q++) {
+                const int xo = xx - q + 3;
+                if (xo < 0 || xo >= W) continue;
+                s += bf2f(dy[((size_t)(bn * H + yo) * W + xo) * C + c]) * w[c * 49 + a * 7 + q];
+            }
+        }
+        dx[i] = f2bf(s);
+    }
+}
+
+void launch_dw_dgrad(const uint16_t* dy, int N, int H, int W, int C, const float* w, uint16_t* dx,
+                     hipStream_t st) {
+    const size_t n = (size_t)N * H * W * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_dw_dgrad, dim3(bl), dim3(256), 0, st, dy, N, H, W, C, w, dx);
+}
+
+// Depthwise weight/bias gradient partials: block (row chunk, channel group of 64); each thread
+// owns one channel and accumulates its 49 taps + bias over the block's rows.
+__global__ void k_dw_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
+                           int N, int H, int W, int C, int rows, float* __restrict__ part) {
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= C) return;
+    const int NH = N * H;
+    const int r0 = blockIdx.x * rows, r1 = min(NH, r0 + rows);
+    float s[50];
+    for (int t = 0; t < 50; t++) s[t] = 0.f;
+    for (int r = r0; r < r1; r++) {
+        const int bn = r / H, yy = r % H;
+        for (int xx = 0; xx < W; xx++) {
+            const float g = bf2f(dy[((size_t)r * W + xx) * C + c]);
+            s[49] += g;
+            for (int a = 0; a < 7; a++) {
+                const int yi = yy + a - 3;
+                if (yi < 0 || yi >= H) continue;
+                for (int q = 0; q < 7; q++) {
+                    const int xi = xx + q - 3;
+                    if (xi < 0 || xi >= W) continue;
+                    s[a * 7 + q] += g * bf2f(x[((size_t)(bn * H + yi) * W + xi) * C + c]);
+                }
+            }
+        }
+    }
+    for (int t = 0; t < 50; t++) part[((size_t)blockIdx.x * C + c) * 50 + t] = s[t];
+}
+
+void launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, int N, int H, int W, int C, int rows,
+                     float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_dw_wgrad, dim3((N * H + rows - 1) / rows, (C + 63) / 64), dim3(64), 0, st,
+                       x, dy, N, H, W, C, rows, part);
+}
+
+// LayerNorm over C per pixel (one wavefront per pixel): y = (x - mu) rstd * g + b; saves
+// mu and rstd.
+__global__ void k_ln_fwd(const uint16_t* __restrict__ x, int M, int C, const float* __restrict__ g,
+                         const float* __restrict__ b, float eps, uint16_t* __restrict__ y,
+                         float* __restrict__ stats) {
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= M) return;
+    const uint16_t* xr = x + (size_t)m * C;
+    float s = 0.f, s2 = 0.f;
+    for (int c = lane; c < C; c += 64) {
+        const float v = bf2f(xr[c]);
+        s += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    const float mu = s / C;
+    for (int c = lane; c < C; c += 64) {
+        const float v = bf2f(xr[c]) - mu;
+        s2 += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    const float rstd = rsqrtf(s2 / C + eps);
+    for (int c = lane; c < C; c += 64) y[(size_t)m * C + c] = f2bf((bf2f(xr[c]) - mu) * rstd * g[c] + b[c]);
+    if (lane == 0) {
+        stats[2 * m] = mu;
+        stats[2 * m + 1] = rstd;
+    }
+}
+
+void launch_ln_fwd(const uint16_t* x, int M, int C, const float* g, const float* b, float eps,
+                   uint16_t* y, float* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_ln_fwd, dim3((M + 3) / 4), dim3(256), 0, st, x, M, C, g, b, eps, y, stats);
+}
+
+// LayerNorm backward: dx = rstd (dxh - mean(dxh) - xh mean(dxh xh)), dxh = dy g.
+__global__ void k_ln_bwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy, int M,
+                         int C, const float* __restrict__ g, const float* __restrict__ stats,
+                         uint16_t* __restrict__ dx) {
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= M) return;
+    const float mu = stats[2 * m], rstd = stats[2 * m + 1];
+    const uint16_t* xr = x + (size_t)m * C;
+    const uint16_t* dr = dy + (size_t)m * C;
+    float a = 0.f, b2 = 0.f;
+    for (int c = lane; c < C; c += 64) {
+        const float xh = (bf2f(xr[c]) - mu) * rstd, d = bf2f(dr[c]) * g[c];
+        a += d;
+        b2 += d * xh;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b2 += __shfl_xor(b2, o);
+    }
+    a /= C;
+    b2 /= C;
+    for (int c = lane; c < C; c += 64) {
+        const float xh = (bf2f(xr[c]) - mu) * rstd, d = bf2f(dr[c]) * g[c];
+        dx[(size_t)m * C + c] = f2bf(rstd * (d - a - xh * b2));
+    }
+}
+
+void launch_ln_bwd(const uint16_t* x, const uint16_t* dy, int M, int C, const float* g,
+                   const float* stats, uint16_t* dx, hipStream_t st) {
+    hipLaunchKernelGGL(k_ln_bwd, dim3((M + 3) / 4), dim3(256), 0, st, x, dy, M, C, g, stats, dx);
+}
+
+// LayerNorm gamma/beta gradient partials per chunk of rows: part[chunk][c][2] = (dy*xh, dy).
+__global__ void k_ln_pgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy, int M,
+                           int C, const float* __restrict__ stats, int chunk,
+                           float* __restrict__ part) {
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= C) return;
+    const int m0 = blockIdx.x * chunk, m1 = min(M, m0 + chunk);
+    float sg = 0.f, sb = 0.f;
+    for (int m = m0; m < m1; m++) {
+        const float xh = (bf2f(x[(size_t)m * C + c]) - stats[2 * m]) * stats[2 * m + 1];
+        const float d = bf2f(dy[(size_t)m * C + c]);
+        sg += d * xh;
+        sb += d;
+    }
+    part[((size_t)blockIdx.x * C + c) * 2] = sg;
+    part[((size_t)blockIdx.x * C + c) * 2 + 1] = sb;
+}
+
+void launch_ln_pgrad(const uint16_t* x, const uint16_t* dy, int M, int C, const float* stats,
+                     int chunk, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_ln_pgrad, dim3((M + chunk - 1) / chunk, (C + 63) / 64), dim3(64), 0, st,
+                       x, dy, M, C, stats, chunk, part);
+}
+
+// 2x2 max pooling (first maximum in (0,0),(0,1),(1,0),(1,1) order wins); arg in 0..3.
+__global__ void k_pool_fwd(const uint16_t* __restrict__ x, int N, int H, int W, int C,
+                           uint16_t* __restrict__ y, uint8_t* __restrict__ arg) {
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)N * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t pix = i / C;
+        const int xo = (int)(pix % Wo), yo = (int)((pix / Wo) % Ho), bn = (int)(pix / ((size_t)Wo * Ho));
+        float best = -FLT_MAX;
+        int ba = 0;
+        for (int k = 0; k < 4; k++) {
+            const float v = bf2f(x[((size_t)(bn * H + 2 * yo + (k >> 1)) * W + 2 * xo + (k & 1)) * C + c]);
+            if (v > best) {
+                best = v;
+                ba = k;
+            }
+        }
+        y[i] = f2bf(best);
+        arg[i] = (uint8_t)ba;
+    }
+}
+
+void launch_pool_fwd(const uint16_t* x, int N, int H, int W, int C, uint16_t* y, uint8_t* arg,
+                     hipStream_t st) {
+    const size_t n = (size_t)N * (H / 2) * (W / 2) * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_pool_fwd, dim3(bl), dim3(256), 0, st, x, N, H, W, C, y, arg);
+}
+
+// Pool backward, added into dx (which already holds the skip-path gradient): each input element
+// receives the pooled gradient if it was its block's maximum.
+__global__ void k_pool_bwd(const uint16_t* __restrict__ dy, const uint8_t* __restrict__ arg,
+                           int N, int H, int W, int C, uint16_t* __restrict__ dx) {
+    const size_t n = (size_t)N * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t pix = i / C;
+        const int xx = (int)(pix % W), yy = (int)((pix / W) % H), bn = (int)(pix / ((size_t)W * H));
+        const size_t o = ((size_t)(bn * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c;
+        const int k = (yy & 1) * 2 + (xx & 1);
+        if (arg[o] == k) dx[i] = f2bf(bf2f(dx[i]) + bf2f(dy[o]));
+    }
+}
+
+void launch_pool_bwd(const uint16_t* dy, const uint8_t* arg, int N, int H, int W, int C,
+                     uint16_t* dx, hipStream_t st) {
+    const size_t n = (size_t)N * H * W * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(bl), dim3(256), 0, st, dy, arg, N, H, W, C, dx);
+}
+
+// ------------------------------------------------------------------------------------------
+// Losses (Eq. (17)-(21)) and their gradients
+// ------------------------------------------------------------------------------------------
+// Inputs fp32 maps [N][H][W] (depth, logit), [N][H][W][3] (normal) with targets.  One pass
+// writes per-pixel gradient numerators and per-block partial sums of the four loss numerators
+// and the two valid counts; the normalisations (counts) are applied by k_loss_scale.
+__global__ __launch_bounds__(256) void k_loss(LossArgs a) {
+    __shared__ float red[6][256];
+    const int tid = threadIdx.x;
+    const size_t total = (size_t)a.N * a.H * a.W;
+    float acc[6] = {0, 0, 0, 0, 0, 0};  // L1num, L2num, L3num, L4num, n_valid, n_valid4
+    const size_t i = (size_t)blockIdx.x * 256 + tid;
+    if (i < total) {
+        const int x = (int)(i % a.W), y = (int)((i / a.W) % a.H);
+        const float m = a.mask_gt[i];
+        const float d = a.depth[i], dg = a.depth_gt[i];
+        // L1
+        acc[0] = m * (d - dg) * (d - dg);
+        a.gd[i] = m * 2.f * (d - dg);
+        acc[4] = m;
+        // L2
+        const float px = a.nrm[3 * i], py = a.nrm[3 * i + 1], pz = a.nrm[3 * i + 2];
+        const float gx = a.nrm_gt[3 * i], gy = a.nrm_gt[3 * i + 1], gz = a.nrm_gt[3 * i + 2];
+        const float cx = py * gz - pz * gy, cy = pz * gx - px * gz, cz = px * gy - py * gx;
+        const float cn = sqrtf(cx * cx + cy * cy + cz * cz);
+        const float pn = sqrtf(px * px + py * py + pz * pz), gn = sqrtf(gx * gx + gy * gy + gz * gz);
+        const float den = fmaxf(pn * gn, 1e-12f);
+        const float s = cn / den;
+        acc[1] = m * s;
+        float ux = 0.f, uy = 0.f, uz = 0.f;
+        if (cn > 0.f) {
+            ux = cx / cn;
+            uy = cy / cn;
+            uz = cz / cn;
+        }
+        const float ip2 = pn > 0.f ? 1.f / (pn * pn) : 0.f;
+        a.gn[3 * i] = m * ((gy * uz - gz * uy) / den - s * ip2 * px);
+        a.gn[3 * i + 1] = m * ((gz * ux - gx * uz) / den - s * ip2 * py);
+        a.gn[3 * i + 2] = m * ((gx * uy - gy * ux) / den - s * ip2 * pz);
+        // L3 focal
+        const float h = 1.f / (1.f + __expf(-a.logit[i]));
+        const float al = 0.5f, lh = logf(fmaxf(h, 1e-12f)), l1h = logf(fmaxf(1.f - h, 1e-12f));
+        float l3, dl;
+        if (m > 0.f) {
+            l3 = -al * (1.f - h) * (1.f - h) * lh;
+            dl = al * 2.f * (1.f - h) * lh - al * (1.f - h) * (1.f - h) / fmaxf(h, 1e-12f);
+        } else {
+            l3 = -(1.f - al) * h * h * l1h;
+            dl = -(1.f - al) * 2.f * h * l1h + (1.f - al) * h * h / fmaxf(1.f - h, 1e-12f);
+        }
+        acc[2] = l3;
+        a.gl[i] = dl * h * (1.f - h);
+        // L4 contribution of the quad at (y, x): needs (y, x+1), (y+1, x) hits
+        if (x + 1 < a.W && y + 1 < a.H) {
+            const float mr = a.mask_gt[i + 1], md = a.mask_gt[i + a.W];
+            const float v = m * mr * md;
+            acc[5] = v;
+            if (v > 0.f) {
+                const float du = a.depth[i + 1] - d, dv = a.depth[i + a.W] - d;
+                const float du2 = a.depth_gt[i + 1] - dg, dv2 = a.depth_gt[i + a.W] - dg;
+                const float P0 = -du, P1 = -dv, P2 = 1.f, G0 = -du2, G1 = -dv2, G2 = 1.f;
+                const float c0 = P1 * G2 - P2 * G1, c1 = P2 * G0 - P0 * G2, c2 = P0 * G1 - P1 * G0;
+                const float c4 = sqrtf(c0 * c0 + c1 * c1 + c2 * c2);
+                const float pp = sqrtf(P0 * P0 + P1 * P1 + P2 * P2), pg = sqrtf(G0 * G0 + G1 * G1 + G2 * G2);
+                const float s4 = c4 / (pp * pg);
+                acc[3] = s4;
+                float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+                if (c4 > 0.f) {
+                    u0 = c0 / c4;
+                    u1 = c1 / c4;
+                    u2 = c2 / c4;
+                }
+                // d s4 / d P (components 0, 1 only; P2 is constant)
+                const float w0 = (G1 * u2 - G2 * u1) / (pp * pg) - s4 / (pp * pp) * P0;
+                const float w1 = (G2 * u0 - G0 * u2) / (pp * pg) - s4 / (pp * pp) * P1;
+                a.w4[2 * i] = w0;
+                a.w4[2 * i + 1] = w1;
+            } else {
+                a.w4[2 * i] = 0.f;
+                a.w4[2 * i + 1] = 0.f;
+            }
+        } else {
+            a.w4[2 * i] = 0.f;
+            a.w4[2 * i + 1] = 0.f;
+        }
+    }
+    for (int k = 0; k < 6; k++) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < 6; k++) red[k][tid] += red[k][tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < 6; k++) a.partial[blockIdx.x * 6 + k] = red[k][0];
+}
+
+void launch_loss(const LossArgs& a, hipStream_t st) {
+    const size_t total = (size_t)a.N * a.H * a.W;
+    hipLaunchKernelGGL(k_loss, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a);
+}
+
+// Sums the loss partials in block order: sums[0..5].
+__global__ void k_loss_sum(const float* __restrict__ partial, int nb, double* __restrict__ sums) {
+    const int k = threadIdx.x;
+    if (k >= 6) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; b++) s += partial[b * 6 + k];
+    sums[k] = s;
+}
+
+void launch_loss_sum(const float* partial, int nb, double* sums, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, partial, nb, sums);
+}
+
+// Final per-pixel gradients with the normalisations and lambdas of Eq. (21); converts the
+// L4 quad weights into depth gradients (each quad touches (y,x), (y,x+1), (y+1,x)).
+__global__ void k_loss_scale(LossArgs a, const double* __restrict__ sums) {
+    const size_t total = (size_t)a.N * a.H * a.W;
+    const float nv = (float)fmax(sums[4], 1.0), nv4 = (float)fmax(sums[5], 1.0);
+    const float inv_all = 1.f / (float)total;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % a.W), y = (int)((i / a.W) % a.H);
+        float g4 = 0.f;
+        // own quad: d P0/d d(y,x) = +1, d P1/d d(y,x) = +1
+        g4 += a.w4[2 * i] + a.w4[2 * i + 1];
+        if (x > 0) g4 -= a.w4[2 * (i - 1)];            // quad (y, x-1): P0 depends on d(y,x) with -1
+        if (y > 0) g4 -= a.w4[2 * (i - a.W) + 1];       // quad (y-1, x): P1 depends on d(y,x) with -1
+        a.out_gd[i] = 1.0f * a.gd[i] / nv + 0.5f * g4 / nv4;
+        for (int c = 0; c < 3; c++) a.out_gn[3 * i + c] = 0.5f * a.gn[3 * i + c] / nv;
+        a.out_gl[i] = 1.0f * a.gl[i] * inv_all;
+    }
+}
+
+void launch_loss_scale(const LossArgs& a, const double* sums, hipStream_t st) {
+    const size_t total = (size_t)a.N * a.H * a.W;
+    int bl = (int)((total + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_loss_scale, dim3(bl), dim3(256), 0, st, a, sums);
+}
+
+// Gathers an fp32 head gradient map into the bf16 gradient of the head's last convolution
+// output before the pixel shuffle (un-shuffle + cast): d[n][y][x][c*4+2sy+sx].
+__global__ void k_head_grad(const float* __restrict__ g, int N, int H, int W, int C,
+                            uint16_t* __restrict__ d, int ldd) {
+    const size_t n = (size_t)N * H * W * 4 * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % (4 * C));
+        const size_t pix = i / (4 * C);
+        const int x = (int)(pix % W), y = (int)((pix / W) % H), b = (int)(pix / ((size_t)W * H));
+        const int c = k >> 2, sy = (k >> 1) & 1, sx = k & 1;
+        d[pix * ldd + k] = f2bf(g[((size_t)(b * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx) * C + c]);
+    }
+}
+
+void launch_head_grad(const float* g, int N, int H, int W, int C, uint16_t* d, int ldd,
+                      hipStream_t st) {
+    const size_t n = (size_t)N * H * W * 4 * C;
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_head_grad, dim3(bl), dim3(256), 0, st, g, N, H, W, C, d, ldd);
+}
+
+// AdamW on fp32 masters; refreshes the bf16 copy (the conv weights) where bf != null.
+__global__ void k_adamw(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                        float* __restrict__ v, uint16_t* __restrict__ bf, size_t n, float lr,
+                        float wd, float b1, float b2, float c1, float c2, float eps) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
+        p[i] = pi;
+        if (bf) bf[i] = f2bf(pi);
+    }
+}
+
+void launch_adamw(float* p, const float* g, float* m, float* v, uint16_t* bf, size_t n, float lr,
+                  float wd, int step, hipStream_t st) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_adamw, dim3(bl > 0 ? bl : 1), dim3(256), 0, st, p, g, m, v, bf, n, lr, wd,
+                       b1, b2, c1, c2, 1e-8f);
+}
+
+// Depth output = head value + coarse depth 1 - x of the input pixel containing the output
+// pixel (0 where the input is empty).
+__global__ void k_depth_base(float* __restrict__ out, const float* __restrict__ x, int N, int H,
+                             int W) {
+    const size_t n = (size_t)N * 4 * H * W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int X = (int)(i % (2 * W)), Y = (int)((i / (2 * W)) % (2 * H));
+        const int b = (int)(i / ((size_t)4 * H * W));
+        const float v = x[((size_t)b * H + Y / 2) * W + X / 2];
+        out[i] += v > 0.f ? 1.f - v : 0.f;
+    }
+}
+
+void launch_depth_base(float* out, const float* x, int N, int H, int W, hipStream_t st) {
+    const size_t n = (size_t)N * 4 * H * W;
+    int b = (int)((n + 255) / 256);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_depth_base, dim3(b), dim3(256), 0, st, out, x, N, H, W);
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ a, size_t n, uint16_t* __restrict__ b) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+
+void launch_f32_to_bf16(const float* a, size_t n, uint16_t* b, hipStream_t st) {
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(bl > 0 ? bl : 1), dim3(256), 0, st, a, n, b);
+}
+
+__global__ void k_bf16_to_f32(const uint16_t* __restrict__ a, size_t n, float* __restrict__ b) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        b[i] = bf2f(a[i]);
+}
+
+void launch_bf16_to_f32(const uint16_t* a, size_t n, float* b, hipStream_t st) {
+    int bl = (int)((n + 255) / 256);
+    if (bl > 8192) bl = 8192;
+    hipLaunchKernelGGL(k_bf16_to_f32, dim3(bl > 0 ? bl : 1), dim3(256), 0, st, a, n, b);
+}
+
+}  // namespace pe

@@ -43,11 +43,20 @@ void launch_slot_ranges(const uint32_t* list, const uint32_t* n_list, int n_slot
                        n_list, n_slots, beg, cnt);
 }
 
+// Frequency lanes of one slot's tiles: a function of that slot alone, so that the order in
+// which a slot's terms are summed does not depend on the other slots of the batch.
+__host__ __device__ inline int slot_ft(int n_freq) {
+    int p = 1;
+    while (p < n_freq && p < 64) p <<= 1;
+    return p;
+}
+
 __global__ void k_po_tile_count(const SlotDesc* __restrict__ ds, const uint32_t* __restrict__ cnt,
-                                int n_seg, int n_slots, int ft, uint32_t* __restrict__ out) {
+                                int n_seg, int n_slots, uint32_t* __restrict__ out) {
     const int gs = blockIdx.x * blockDim.x + threadIdx.x;
     if (gs >= n_seg * n_slots) return;
     const SlotDesc& d = ds[gs % n_slots];
+    const int ft = slot_ft(d.n_freq);
     const uint32_t nrt = (cnt[gs] + kRT - 1) / kRT;
     const uint32_t nft = (d.n_freq + ft - 1) / ft;
     out[gs] = nrt * nft * d.n_obs;
@@ -56,8 +65,9 @@ __global__ void k_po_tile_count(const SlotDesc* __restrict__ ds, const uint32_t*
 void launch_po_tiles(const SlotDesc* d, const uint32_t* seg_cnt, int n_seg, int n_slots, int ft,
                      uint32_t* tmp, uint32_t* tile_prefix, hipStream_t st) {
     const int n = n_seg * n_slots;
+    (void)ft;
     hipLaunchKernelGGL(k_po_tile_count, dim3((n + 255) / 256), dim3(256), 0, st, d, seg_cnt, n_seg,
-                       n_slots, ft, tmp);
+                       n_slots, tmp);
     launch_scan(tmp, tile_prefix, (uint32_t)n, nullptr, 1, tile_prefix + n, st);
 }
 
@@ -114,12 +124,11 @@ __global__ __launch_bounds__(256) void k_po_sum(const SlotDesc* __restrict__ ds,
                                                 int n_slots, const double* __restrict__ freq,
                                                 ExitRecs er, uint32_t rec_stride,
                                                 const uint32_t* __restrict__ tile_prefix,
-                                                int fp32, int ft, double* __restrict__ partial) {
+                                                int fp32, int FT, double* __restrict__ partial) {
     __shared__ double red[8][256];
     const int n_gs = n_seg * n_slots;
     const uint32_t total = tile_prefix[n_gs];
-    const int RL = 256 / ft;
-    const int tid = threadIdx.x, fi = tid & (ft - 1), rl = tid / ft;
+    const int tid = threadIdx.x;
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         int lo = 0, hi = n_gs - 1;
         while (lo < hi) {
@@ -129,6 +138,7 @@ __global__ __launch_bounds__(256) void k_po_sum(const SlotDesc* __restrict__ ds,
         }
         const int gs = lo, g = gs / n_slots, s = gs % n_slots;
         const SlotDesc& d = ds[s];
+        const int ft = slot_ft(d.n_freq), RL = 256 / ft, fi = tid & (ft - 1), rl = tid / ft;
         const uint32_t cnt = seg_cnt[gs];
         const uint32_t nrt = (cnt + kRT - 1) / kRT;
         const uint32_t nft = (d.n_freq + ft - 1) / ft;
@@ -154,7 +164,7 @@ __global__ __launch_bounds__(256) void k_po_sum(const SlotDesc* __restrict__ ds,
             __syncthreads();
         }
         if (rl == 0)
-            for (int c = 0; c < 8; c++) partial[((uint64_t)t * ft + fi) * 8 + c] = red[c][tid];
+            for (int c = 0; c < 8; c++) partial[((uint64_t)t * FT + fi) * 8 + c] = red[c][tid];
         __syncthreads();
     }
 }
@@ -170,7 +180,7 @@ void launch_po_sum(const SlotDesc* d, const uint32_t* seg_beg, const uint32_t* s
 __global__ void k_po_reduce(const SlotDesc* __restrict__ ds, const ObsDesc* __restrict__ obs,
                             int n_slots, int max_obs, int max_freq, int n_seg,
                             const double* __restrict__ freq, const uint32_t* __restrict__ seg_cnt,
-                            const uint32_t* __restrict__ tile_prefix, int ft,
+                            const uint32_t* __restrict__ tile_prefix, int FT,
                             const double* __restrict__ partial, int fp32,
                             double* __restrict__ E_out, double* __restrict__ rcs_out) {
     const uint64_t total = (uint64_t)n_slots * max_obs * max_freq;
@@ -181,6 +191,7 @@ __global__ void k_po_reduce(const SlotDesc* __restrict__ ds, const ObsDesc* __re
         const int s = (int)(w / ((uint64_t)max_freq * max_obs));
         const SlotDesc& d = ds[s];
         if (o >= d.n_obs || f >= d.n_freq) continue;
+        const int ft = slot_ft(d.n_freq);
         const int nft = (d.n_freq + ft - 1) / ft;
         const int ftile = f / ft, fi = f % ft;
         double S[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -190,7 +201,7 @@ __global__ void k_po_reduce(const SlotDesc* __restrict__ ds, const ObsDesc* __re
             const uint32_t nrt = (seg_cnt[gs] + kRT - 1) / kRT;
             const uint64_t b = tile_prefix[gs] + ((uint64_t)o * nft + ftile) * nrt;
             for (uint32_t rt = 0; rt < nrt; rt++) {
-                const double* p = partial + ((b + rt) * ft + fi) * 8;
+                const double* p = partial + ((b + rt) * FT + fi) * 8;
                 for (int c = 0; c < 8; c++) {
                     if (fp32) Sf[c] += (float)p[c];
                     else S[c] += p[c];

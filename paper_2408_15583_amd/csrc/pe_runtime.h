@@ -93,6 +93,10 @@ struct Batch {
     void splat();
     void alloc_rays();
     void raygen();
+    // Primary rays from a GFB on every slot's screen (depth t/D, view-frame normals, hit
+    // probability >= thresh) instead of the splat keys; slots with use[s] == 0 get none.
+    void raygen_gfb(const float* depth, const float* nrm, const float* prob, const uint8_t* use,
+                    float thresh);
     void alloc_records();
     void records(int seg, const uint32_t* list, const uint32_t* n_list);
     void trace(bool with_records);
@@ -163,11 +167,28 @@ struct pe_scene_s {
     }
 };
 
+// Exception barrier of every C entry point: no C++ exception crosses the ABI.
+#define API_BEGIN try {
+#define API_END                                                              \
+    }                                                                        \
+    catch (const ::pe::Error& e) {                                                 \
+        return ::pe::set_error(e.status, e.msg);                                   \
+    }                                                                        \
+    catch (const std::bad_alloc&) {                                          \
+        return ::pe::set_error(PE_ENOMEM, "host allocation failed");               \
+    }                                                                        \
+    catch (const std::exception& e) {                                        \
+        return ::pe::set_error(PE_EDEVICE, std::string("internal error: ") + e.what()); \
+    }                                                                        \
+    catch (...) {                                                            \
+        return ::pe::set_error(PE_EDEVICE, "internal error");                      \
+    }
+
 namespace pe {
 typedef void (*solve_fn)(Workspace& ws, hipStream_t st, pe_scene sc, const pe_solve_desc* d,
                          double* E, double* rcs, pe_stats* acc);
 extern solve_fn g_densified_solve;
-void validate_solve(pe_scene sc, const pe_solve_desc* d);
+void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene = true);
 int slots_per_batch(const pe_solve_desc* d);
 std::vector<SlotSpec> make_slots(pe_scene sc, const pe_solve_desc* d, int i0, int count);
 void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>& slots,

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "pe_device.h"
+#include "pe_gfb.h"
 #include "pe_runtime.h"
 #include "pointemray.h"
 
@@ -340,6 +341,19 @@ void Batch::raygen() {
     prof_begin();
     launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, hitkey, st);
     prof_end("raygen_write");
+    HIPCHK(hipGetLastError());
+}
+
+void Batch::raygen_gfb(const float* depth, const float* nrm, const float* prob,
+                       const uint8_t* use, float thresh) {
+    alloc_rays();
+    const int gx = (max_pix + 255) / 256;
+    uint32_t* wgc = ws.get<uint32_t>(B_WGC, (uint64_t)gx * n + 1);
+    uint32_t* wgo = ws.get<uint32_t>(B_WGO, (uint64_t)gx * n + 1);
+    prof_begin();
+    launch_gfb_raygen(dd, n, max_pix, depth, nrm, prob, use, thresh, wgc, wgo, lists[0], rs,
+                      hitkey, cnt + C_N0, st);
+    prof_end("gfb_raygen");
     HIPCHK(hipGetLastError());
 }
 

@@ -1,0 +1,235 @@
+"""Densifier kernels (bf16 MFMA convolutions, fp32 accumulation) vs the FP64 oracle of
+oracle/nn.py, through the C ABI on a HIP device.
+
+The oracle runs on the same parameters, with the weights the GPU reads in bf16 (the MFMA
+convolutions) rounded to bf16 first, so the comparison measures only the kernels' arithmetic:
+bf16 activations and gradients (unit roundoff 2^-9) through about 30 layers forward and as many
+backward.  Bars: relative L2 error <= 2 % on the forward outputs and the loss terms; for every
+parameter gradient tensor, cosine similarity >= 0.995 and relative L2 error <= 6 % plus the
+sensitivity of the exact gradient to the forward's own error (the oracle's gradient recomputed
+from the GPU's forward outputs: the normal sine loss of Eq. (18) is not differentiable where
+predicted and target normals align, so a 1 % forward error moves its gradient by several %);
+AdamW's update to fp32 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import nn as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    import paper_2408_15583_amd as pe_mod
+    assert torch.cuda.is_available()
+    return pe_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(pe):
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+def bf16(a):
+    """Round to bfloat16 (nearest even), returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mfma_weight(name):
+    return name.endswith(".w") and not name.endswith(".dw.w") and name != "stem.w"
+
+
+def oracle_params(net):
+    P = {}
+    for k, v in net.get_dict("params").items():
+        P[k] = bf16(v) if mfma_weight(k) else v.astype(np.float64)
+    return P
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def batch(seed, n=2, h=16, w=16):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.2, 1.0, (n, h, w)) * (rng.uniform(size=(n, h, w)) < 0.8)
+    dg = rng.uniform(0.2, 0.8, (n, 2 * h, 2 * w))
+    ng = rng.normal(size=(n, 2 * h, 2 * w, 3))
+    ng[..., 2] = np.abs(ng[..., 2]) + 0.5
+    ng /= np.linalg.norm(ng, axis=-1, keepdims=True)
+    mg = (rng.uniform(size=(n, 2 * h, 2 * w)) < 0.7).astype(np.float64)
+    return x, dg, ng, mg
+
+
+def to_dev(*arrays):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda() for a in arrays]
+
+
+def test_registry_matches_oracle(pe, ctx):
+    net = pe.Densifier(ctx, base=32, seed=1)
+    ref = N.init_params(base=32, seed=0)
+    got = {n: s for n, _, s in net.tensors()}
+    assert set(got) == set(ref)
+    for k, v in ref.items():
+        assert got[k] == v.shape, k
+    net.close()
+
+
+def test_forward_and_gradients_match_oracle(pe, ctx):
+    net = pe.Densifier(ctx, base=32, seed=3)
+    P = oracle_params(net)
+    x, dg, ng, mg = batch(5)
+    xd, dgd, ngd, mgd = to_dev(x, dg, ng, mg)
+    # forward (inference outputs)
+    d_gpu, n_gpu, p_gpu = [t.cpu().numpy() for t in net.infer(xd)]
+    (dp, npr, lp), cache = N.forward(P, x[..., None])
+    assert rel(d_gpu, dp) < 0.02
+    nref = npr / np.linalg.norm(npr, axis=-1, keepdims=True)
+    assert rel(n_gpu, nref) < 0.02
+    assert rel(p_gpu, N.sigmoid(lp)) < 0.02
+    # loss terms and every gradient (lr = 0: parameters unchanged)
+    p_before = net.get("params")
+    losses = net.train_step(xd, dgd, ngd, mgd, lr=0.0)
+    L, parts, (gd, gn, gl) = N.losses(dp, npr, lp, dg, ng, mg)
+    assert abs(losses[0] - L) <= 0.02 * abs(L)
+    for a, b in zip(losses[1:], parts):
+        assert abs(a - b) <= 0.02 * abs(b) + 1e-6, (losses, parts)
+    G = N.backward(P, cache, gd, gn, gl)
+    Gb = N.backward(P, cache, bf16(gd), bf16(gn), bf16(gl))
+    Gg = net.get_dict("grads")
+    errs = {k: rel(Gg[k], G[k]) for k in G}
+    errs_b = {k: rel(Gg[k], Gb[k]) for k in G}
+    floor = {k: rel(Gb[k], G[k]) for k in G}
+    cos = {k: float(np.dot(Gg[k].ravel(), G[k].ravel()) /
+                    max(np.linalg.norm(Gg[k]) * np.linalg.norm(G[k]), 1e-30)) for k in G}
+    for k in sorted(errs, key=errs.get, reverse=True):
+        print(f"GRAD {k:18s} rel {errs[k]:.4f} rel_vs_bf16grad {errs_b[k]:.4f} "
+              f"floor {floor[k]:.4f} cos {cos[k]:.5f}")
+    # sensitivity of the oracle's own gradient to the forward error: oracle gradients from the
+    # GPU's forward outputs (normal directions and probabilities as the GPU produced them)
+    n_pert = n_gpu * np.linalg.norm(npr, axis=-1, keepdims=True)
+    l_pert = np.log(np.clip(p_gpu, 1e-7, 1 - 1e-7) / np.clip(1 - p_gpu, 1e-7, 1))
+    _, _, (gd2, gn2, gl2) = N.losses(d_gpu.astype(np.float64), n_pert, l_pert, dg, ng, mg)
+    Gs = N.backward(P, cache, gd2, gn2, gl2)
+    sens = {k: rel(Gs[k], G[k]) for k in G}
+    for k in sorted(errs, key=errs.get, reverse=True)[:20]:
+        print(f"SENS {k:18s} rel {errs[k]:.4f} oracle-from-gpu-forward {sens[k]:.4f}")
+    bad = {k: (errs[k], sens[k], cos[k]) for k in G
+           if not (errs[k] <= 0.06 + sens[k] and cos[k] >= 0.995)}
+    assert not bad, bad
+    # parameters untouched at lr = 0
+    assert np.array_equal(net.get("params"), p_before)
+    net.close()
+
+
+def test_adamw_step_matches_oracle(pe, ctx):
+    net = pe.Densifier(ctx, base=32, seed=4)
+    x, dg, ng, mg = batch(6)
+    xd, dgd, ngd, mgd = to_dev(x, dg, ng, mg)
+    net.train_step(xd, dgd, ngd, mgd, lr=0.0)          # step 1 fills the moments
+    p0, m0, v0 = net.get("params"), net.get("m"), net.get("v")
+    net.train_step(xd, dgd, ngd, mgd, lr=1e-3, weight_decay=0.01)  # step 2
+    g = net.get("grads")
+    p1 = net.get("params")
+    pe_, me, ve = N.adamw_step(p0.astype(np.float64), g.astype(np.float64), m0.astype(np.float64),
+                               v0.astype(np.float64), 2, lr=1e-3, wd=0.01)
+    assert np.allclose(net.get("m"), me, rtol=1e-5, atol=1e-12)
+    assert np.allclose(net.get("v"), ve, rtol=1e-5, atol=1e-15)
+    assert np.allclose(p1, pe_, rtol=1e-5, atol=1e-7)
+    net.close()
+
+
+def test_training_is_deterministic_and_checkpoint_resumes(pe, ctx, tmp_path):
+    x, dg, ng, mg = batch(7)
+    xd, dgd, ngd, mgd = to_dev(x, dg, ng, mg)
+    a = pe.Densifier(ctx, base=32, seed=9)
+    b = pe.Densifier(ctx, base=32, seed=9)
+    la = [a.train_step(xd, dgd, ngd, mgd, lr=1e-3) for _ in range(3)]
+    lb = [b.train_step(xd, dgd, ngd, mgd, lr=1e-3) for _ in range(2)]
+    path = tmp_path / "ck.bin"
+    b.save(path)
+    c = pe.Densifier(ctx, base=32, seed=123)
+    c.load(path)
+    assert np.array_equal(c.get("params"), b.get("params"))
+    lc = c.train_step(xd, dgd, ngd, mgd, lr=1e-3)
+    assert lc == la[2] and lb[:2] == la[:2]
+    assert np.array_equal(c.get("params"), a.get("params"))
+    with pytest.raises(pe.PEError):
+        pe.Densifier(ctx, base=64, seed=0).load(path)
+    for n in (a, b, c):
+        n.close()
+
+
+def test_loss_decreases_on_fixed_batch(pe, ctx):
+    net = pe.Densifier(ctx, base=32, seed=2)
+    x, dg, ng, mg = batch(8)
+    xd, dgd, ngd, mgd = to_dev(x, dg, ng, mg)
+    first = net.train_step(xd, dgd, ngd, mgd, lr=2e-3)[0]
+    for _ in range(40):
+        last = net.train_step(xd, dgd, ngd, mgd, lr=2e-3)[0]
+    assert last < 0.7 * first, (first, last)
+    net.close()
+
+
+def test_make_pair_matches_oracle_buffers(pe, ctx):
+    sc = scenes.dihedral()
+    s = pe.Scene.from_scene(ctx, sc, view_res=64)
+    o = oracle.OracleScene(sc, grid=64)
+    c, R = o.frame()
+    D = 2 * R
+    az = np.deg2rad(30.0)
+    k = -np.array([np.cos(az), np.sin(az), 0.2])
+    k /= np.linalg.norm(k)
+    h = w = 32
+    coarse, dgt, ngt, mgt = [t.cpu().numpy()[0] for t in pe.make_pair(ctx, s, k[None], h, w,
+                                                                        tube_px=2.0)]
+    # targets vs the oracle DISK buffer at 2h x 2w
+    dep, idx, nrm, mask = o.render_disk(k, 2 * w, 2 * h)
+    agree = (mgt > 0.5) == (mask > 0)
+    assert agree.mean() >= 0.999
+    both = (mgt > 0.5) & (mask > 0)
+    assert np.abs(dgt[both] * D - dep[both]).max() <= 1e-5 * D
+    _, du, dv = o.screen(k, 2 * w, 2 * h)
+    u, v = du / np.linalg.norm(du), dv / np.linalg.norm(dv)
+    nv = np.stack([nrm @ u, nrm @ v, -(nrm @ k)], axis=-1)
+    assert np.abs(ngt[both] - nv[both]).max() < 1e-4
+    # coarse input vs the oracle TUBE buffer at h x w
+    pitch = D / w
+    tdep, tidx = o.render_tube(k, w, h, 2.0 * pitch)
+    thit = tidx >= 0
+    ghit = coarse > 0
+    assert (thit == ghit).mean() >= 0.99
+    bb = thit & ghit
+    assert np.abs((1 - coarse[bb]) * D - tdep[bb]).max() <= 1e-5 * D
+    s.close()
+
+
+def test_coarse_and_densified_geometry_run(pe, ctx):
+    sc = scenes.plate()
+    s = pe.Scene.from_scene(ctx, sc, view_res=64)
+    k = np.array([[-1.0, 0.0, 0.0]])  # broadside: the plate lies on x = 0
+    f = np.array([10e9])
+    _, r_plain, _ = pe.solve(ctx, s, k, f, 128)
+    _, r_coarse, st_c = pe.solve(ctx, s, k, f, 128, geometry="coarse")
+    assert abs(r_coarse[0, 0, 0, 0, 0] - r_plain[0, 0, 0, 0, 0]) < 1.0
+    net = pe.Densifier(ctx, base=32, seed=0)
+    E, r_d, st_d = pe.solve(ctx, s, k, f, 128, densifier=net)
+    assert np.isfinite(E).all()
+    assert st_d["densifier_fallbacks"] in (0.0, 1.0)
+    with pytest.raises(pe.PEError):
+        pe.solve(ctx, s, k, f, 128, max_bounces=2, geometry="coarse")
+    with pytest.raises(pe.PEError):
+        pe.solve(ctx, s, k, f, 120, densifier=net)
+    net.close()
+    s.close()

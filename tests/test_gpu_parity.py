@@ -1,6 +1,6 @@
 """GPU path vs the FP64 CPU oracle, element by element, on seeded inputs (needs a HIP device).
 
-Tolerances (stated by the task's parity bar):
+Tolerances:
   - hit masks agree on >= 99.9 % of the pixels hit by either side;
   - depth |dt| <= 1e-5 * D (D = 2R, the screen width) where both hit;
   - RCS within 0.1 dB at every (angle, freq, pol) where the oracle's sigma is within 30 dB of

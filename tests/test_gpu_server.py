@@ -1,0 +1,128 @@
+"""Continuous-batching server through the C ABI (pe_submit / pe_wait / pe_cancel).
+
+A request's field must be bitwise identical whether solved alone (pe_solve) or packed into
+shared launches with other requests (different scenes, screens, frequency sets, bounce
+limits); admission must respect the context's HBM budget; cancellation and time-outs are
+forced from the host.
+"""
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    import paper_2408_15583_amd as pe_mod
+    assert torch.cuda.is_available()
+    return pe_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(pe):
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def two_scenes(ctx, pe):
+    a = scenes.dihedral()
+    b = scenes.random_disks(seed=21, n=3000)
+    sa = pe.Scene.from_scene(ctx, a, view_res=128)
+    sb = pe.Scene.from_scene(ctx, b, view_res=128)
+    yield (a, sa), (b, sb)
+    sa.close()
+    sb.close()
+
+
+def requests(two_scenes, seed=0, n=8):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        sc, s = two_scenes[i % 2]
+        n_inc = int(rng.integers(1, 7))
+        az = rng.uniform(0, 360, n_inc)
+        inc = scenes.azimuth_sweep(az, float(rng.uniform(-20, 40)))
+        nf = int(rng.integers(1, 6))
+        freq = np.sort(rng.uniform(2e9, 12e9, nf))
+        screen = int(rng.choice([64, 96, 128]))
+        B = int(rng.integers(1, 4))
+        eps = 0.5 * float(np.max(sc.radius))
+        out.append(dict(scene=s, inc_dir=inc, freq_hz=freq, screen=screen, max_bounces=B,
+                        eps=eps))
+    return out
+
+
+def test_mix_equals_alone_bitwise(pe, ctx, two_scenes):
+    reqs = requests(two_scenes)
+    alone = [pe.solve(ctx, r["scene"], r["inc_dir"], r["freq_hz"], r["screen"],
+                      max_bounces=r["max_bounces"], eps=r["eps"]) for r in reqs]
+    pe.server_stats(ctx, reset=True)
+    tickets = [pe.submit(ctx, r["scene"], r["inc_dir"], r["freq_hz"], r["screen"],
+                         max_bounces=r["max_bounces"], eps=r["eps"]) for r in reqs]
+    for t, (E0, r0, _) in zip(tickets, alone):
+        E1, r1, st = t.wait(timeout_s=60)
+        assert np.array_equal(E0, E1)
+        assert np.array_equal(r0, r1)
+        assert st["ray_queries"] > 0
+    s = pe.server_stats(ctx)
+    assert s["completed"] == len(reqs)
+    assert s["p50_ms"] <= s["p99_ms"]
+    assert s["reqs_per_batch"] > 1.0  # requests really shared launches
+
+
+def test_admission_under_small_budget(pe, two_scenes):
+    (sc, _), _ = two_scenes
+    inc = scenes.azimuth_sweep(np.arange(0, 40, 10.0), 0.0)
+    f = np.array([10e9])
+    fp = pe.request_footprint(inc, f, 128, max_bounces=2)
+    # a context whose budget holds the scene and one request, not two
+    small = pe.Context(0, budget=0)
+    s = pe.Scene.from_scene(small, sc, view_res=128)
+    scene_bytes = small.footprint()[0]
+    s.close()
+    small.close()
+    ctx2 = pe.Context(0, budget=int(scene_bytes + 1.5 * fp))
+    s2 = pe.Scene.from_scene(ctx2, sc, view_res=128)
+    ts = [pe.submit(ctx2, s2, inc, f, 128, max_bounces=2, eps=0.5 * sc.radius) for _ in range(4)]
+    res = [t.wait(timeout_s=60) for t in ts]
+    for E, _, _ in res[1:]:
+        assert np.array_equal(E, res[0][0])
+    st = pe.server_stats(ctx2)
+    assert st["max_concurrent"] == 1.0
+    # a request that cannot fit at all is refused at submit
+    big = scenes.azimuth_sweep(np.arange(0, 360, 1.0), 0.0)
+    with pytest.raises(pe.PEError) as e:
+        pe.submit(ctx2, s2, big, f, 2048, max_bounces=2)
+    assert "PE_ENOMEM" in str(e.value)
+    s2.close()
+    ctx2.close()
+
+
+def test_cancel_and_timeout(pe, ctx, two_scenes):
+    (sc, s), _ = two_scenes
+    many = scenes.azimuth_sweep(np.arange(0, 360, 0.5), 10.0)
+    f = np.linspace(2e9, 12e9, 16)
+    blocker = pe.submit(ctx, s, many, f, 512, max_bounces=3, eps=0.5 * sc.radius)
+    victim = pe.submit(ctx, s, many, f, 512, max_bounces=3, eps=0.5 * sc.radius)
+    with pytest.raises(TimeoutError):
+        blocker.wait(timeout_s=0)
+    victim.cancel()
+    with pytest.raises(pe.PEError) as e:
+        victim.wait(timeout_s=120)
+    assert "PE_ECANCELED" in str(e.value)
+    E, _, _ = blocker.wait(timeout_s=120)
+    assert np.isfinite(E).all()
+
+
+def test_submit_errors(pe, ctx, two_scenes):
+    (sc, s), _ = two_scenes
+    inc = scenes.azimuth_sweep([0.0], 0.0)
+    with pytest.raises(pe.PEError):
+        pe.submit(ctx, s, inc, [-1.0], 64)
+    with pytest.raises(pe.PEError):
+        pe.submit(ctx, s, inc, [1e9], 64, max_bounces=0)
