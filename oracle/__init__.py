@@ -55,10 +55,15 @@ def _load():
                                    ctypes.c_double, _d, _i64]
     lib.or_trace_pixels.argtypes = [ctypes.c_void_p, _d, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int64, _i64, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_int, _i32, _d, _i64]
+                                    ctypes.c_int, ctypes.c_int, _i32, _d, _i64]
     lib.or_solve.argtypes = [ctypes.c_void_p, ctypes.c_int, _d, ctypes.c_int, _d, ctypes.c_int,
                              _d, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                             ctypes.c_int, ctypes.c_int, _d, _d]
+                             ctypes.c_int, ctypes.c_int, ctypes.c_int, _d, _d]
+    lib.or_scene_set_views.argtypes = [ctypes.c_void_p, ctypes.c_int, _d, ctypes.c_int,
+                                       ctypes.c_int]
+    lib.or_first_hit_views.restype = ctypes.c_int64
+    lib.or_first_hit_views.argtypes = [ctypes.c_void_p, _d, _d, ctypes.c_double, _d]
+    lib.or_admissible.argtypes = [ctypes.c_void_p, ctypes.c_int64, _d]
     lib.or_reflect_field_decomposed.argtypes = [_d, _d, _d, _d, _d]
     lib.or_reflect_field_vector.argtypes = [_d, _d, _d, _d, _d]
     lib.or_pol_basis.argtypes = [_d, _d, _d]
@@ -146,7 +151,31 @@ class OracleScene:
         _load().or_render_tube(self._h, _p(_f64(k)), W, H, float(delta), _p(depth), _p(idx, _i64))
         return depth.reshape(H, W), idx.reshape(H, W)
 
-    def trace_pixels(self, k, W, H, pix, max_bounces, eps, grid=None):
+    AXIS_VIEWS = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]],
+                          dtype=np.float64)
+
+    def set_views(self, res, dirs=None):
+        """Aggregation views of the method's secondary-hit rule (default: the six axis
+        directions) as first-hit index maps at res x res."""
+        d = _f64(self.AXIS_VIEWS if dirs is None else dirs).reshape(-1, 3)
+        if _load().or_scene_set_views(self._h, d.shape[0], _p(d), int(res), self.use_grid):
+            raise ValueError("bad views")
+        self.views = (d, int(res))
+
+    def first_hit_views(self, o, k, tmin):
+        t = np.zeros(1)
+        i = _load().or_first_hit_views(self._h, _p(_f64(o)), _p(_f64(k)), float(tmin), _p(t))
+        if i == -2:
+            raise ValueError("set_views first")
+        return int(i), float(t[0])
+
+    def admissible(self, i, pt):
+        r = _load().or_admissible(self._h, int(i), _p(_f64(pt)))
+        if r < 0:
+            raise ValueError("set_views first")
+        return bool(r)
+
+    def trace_pixels(self, k, W, H, pix, max_bounces, eps, grid=None, restricted=False):
         """Per pixel: number of bounces M and the per-bounce records (see oracle.c)."""
         pix = np.ascontiguousarray(pix, dtype=np.int64)
         m = pix.size
@@ -154,13 +183,16 @@ class OracleScene:
         rec = np.zeros((m, max_bounces, 22))
         hidx = np.full((m, max_bounces), -1, np.int64)
         g = self.use_grid if grid is None else int(grid)
-        _load().or_trace_pixels(self._h, _p(_f64(k)), W, H, m, _p(pix, _i64), max_bounces,
-                                float(eps), g, _p(nb, _i32), _p(rec), _p(hidx, _i64))
+        if _load().or_trace_pixels(self._h, _p(_f64(k)), W, H, m, _p(pix, _i64), max_bounces,
+                                   float(eps), g, int(restricted), _p(nb, _i32), _p(rec),
+                                   _p(hidx, _i64)):
+            raise ValueError("restricted tracing needs set_views")
         return nb, rec, hidx
 
     def solve(self, inc_dir, freq_hz, W, H, max_bounces, eps, obs_dir=None, contrib="last",
-              grid=None):
-        """Complex field E[inc][obs][freq][rx][tx] (rx, tx in (theta, phi)) and stats."""
+              grid=None, restricted=False):
+        """Complex field E[inc][obs][freq][rx][tx] (rx, tx in (theta, phi)) and stats.
+        restricted=True applies the method's secondary-hit and visibility rules (set_views)."""
         inc = _f64(inc_dir).reshape(-1, 3)
         fr = _f64(freq_hz).ravel()
         no = 1 if obs_dir is None else _f64(obs_dir).reshape(-1, 3).shape[0]
@@ -168,9 +200,11 @@ class OracleScene:
         stats = np.zeros(3)
         obs = None if obs_dir is None else _f64(obs_dir).reshape(-1, 3)
         g = self.use_grid if grid is None else int(grid)
-        _load().or_solve(self._h, inc.shape[0], _p(inc), no, None if obs is None else _p(obs),
-                         fr.size, _p(fr), W, H, max_bounces, float(eps),
-                         1 if contrib == "every" else 0, g, _p(out), _p(stats))
+        if _load().or_solve(self._h, inc.shape[0], _p(inc), no, None if obs is None else _p(obs),
+                            fr.size, _p(fr), W, H, max_bounces, float(eps),
+                            1 if contrib == "every" else 0, g, int(restricted), _p(out),
+                            _p(stats)):
+            raise ValueError("restricted solve needs set_views")
         E = out[..., 0] + 1j * out[..., 1]
         return E, dict(disk_tests=stats[0], queries=stats[1], facets=stats[2])
 

@@ -64,6 +64,10 @@ typedef struct {
     double lo[3], h;
     int64_t* cell_start; /* G^3 + 1 */
     int32_t* cell_ids;
+    /* aggregation views (see or_scene_set_views): n_views first-hit index maps res x res */
+    int n_views, view_res;
+    double* view_basis;  /* n_views x 9: u, v, k */
+    int64_t* view_idx;   /* n_views x res x res, -1 where empty */
 } or_scene;
 
 /* Returns NULL and *err != 0 on invalid input: non-finite position, zero/non-finite normal,
@@ -116,6 +120,7 @@ void or_scene_free(void* p) {
     if (!s) return;
     free(s->xyz); free(s->nrm); free(s->rad); free(s->mat);
     free(s->cell_start); free(s->cell_ids);
+    free(s->view_basis); free(s->view_idx);
     free(s);
 }
 
@@ -304,6 +309,154 @@ int64_t or_first_hit(const void* p, const double* o, const double* k, double tmi
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* The method's secondary-hit rule (Sec. III-B: bounces are traced against the geometry the   */
+/* frame buffers of a set of views retain).  Each aggregation view is the first-hit index map */
+/* (c.4) of a res x res screen along the view's direction.  A secondary intersection of disk  */
+/* i at point p is ADMISSIBLE iff some view stores i at a pixel within one pixel (in both     */
+/* screen axes) of p's projection; the restricted first hit is the nearest admissible         */
+/* intersection (ties: smallest index).  Exact tracing (first_hit) is the special case where  */
+/* every intersection is admissible.                                                          */
+/* ------------------------------------------------------------------------------------------ */
+
+void or_render_disk(const void* p, const double* kin, int W, int H, int use_grid, double* depth,
+                    int64_t* idx, double* nrm, uint8_t* mask);
+
+int or_scene_set_views(void* p, int n_views, const double* dirs, int res, int use_grid) {
+    or_scene* s = (or_scene*)p;
+    if (n_views < 1 || res < 1) return 1;
+    free(s->view_basis); free(s->view_idx);
+    s->n_views = n_views;
+    s->view_res = res;
+    s->view_basis = (double*)malloc(sizeof(double) * 9 * n_views);
+    s->view_idx = (int64_t*)malloc(sizeof(int64_t) * (int64_t)n_views * res * res);
+    double* depth = (double*)malloc(sizeof(double) * (int64_t)res * res);
+    uint8_t* mask = (uint8_t*)malloc((size_t)res * res);
+    for (int v = 0; v < n_views; v++) {
+        double o00[3], du[3], dv[3];
+        or_screen(p, dirs + 3 * v, res, res, o00, du, dv);
+        st(s->view_basis + 9 * v + 0, unit(ld(du)));
+        st(s->view_basis + 9 * v + 3, unit(ld(dv)));
+        st(s->view_basis + 9 * v + 6, unit(ld(dirs + 3 * v)));
+        or_render_disk(p, dirs + 3 * v, res, res, use_grid, depth,
+                       s->view_idx + (int64_t)v * res * res, NULL, mask);
+    }
+    free(depth);
+    free(mask);
+    return 0;
+}
+
+static int admissible(const or_scene* s, int64_t i, v3 pt) {
+    const int res = s->view_res;
+    const double pitch = 2.0 * s->R / res;
+    v3 q = sub(pt, ld(s->c));
+    for (int v = 0; v < s->n_views; v++) {
+        const double* b = s->view_basis + 9 * v;
+        int ia = (int)floor(dot(q, ld(b + 0)) / pitch + 0.5 * res);
+        int ib = (int)floor(dot(q, ld(b + 3)) / pitch + 0.5 * res);
+        const int64_t* m = s->view_idx + (int64_t)v * res * res;
+        for (int dy = -1; dy <= 1; dy++) {
+            int y = ib + dy;
+            if (y < 0 || y >= res) continue;
+            for (int dx = -1; dx <= 1; dx++) {
+                int x = ia + dx;
+                if (x < 0 || x >= res) continue;
+                if (m[(int64_t)y * res + x] == i) return 1;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Same traversal as first_hit_grid (or all disks without a grid); only admissible
+ * intersections compete. */
+static int64_t first_hit_views(const or_scene* s, v3 o, v3 k, double tmin, double* tbest,
+                               int64_t* ntests) {
+    int64_t best = -1;
+    double bt = INFINITY, t;
+    if (!s->cell_start) {
+        for (int64_t i = 0; i < s->n; i++)
+            if (disk_hit(s, i, o, k, tmin, &t) && (t < bt || (t == bt && i < best)) &&
+                admissible(s, i, add(o, scl(k, t)))) {
+                bt = t;
+                best = i;
+            }
+        *ntests += s->n;
+        *tbest = bt;
+        return best;
+    }
+    int G = s->G;
+    double t0 = tmin > 0 ? tmin : 0, t1 = INFINITY;
+    double oo[3] = {o.x, o.y, o.z}, kk[3] = {k.x, k.y, k.z};
+    double hi[3];
+    for (int a = 0; a < 3; a++) hi[a] = s->lo[a] + G * s->h;
+    for (int a = 0; a < 3; a++) {
+        if (kk[a] == 0.0) {
+            if (oo[a] < s->lo[a] || oo[a] > hi[a]) { *tbest = INFINITY; return -1; }
+        } else {
+            double ta = (s->lo[a] - oo[a]) / kk[a], tb = (hi[a] - oo[a]) / kk[a];
+            if (ta > tb) { double tt = ta; ta = tb; tb = tt; }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        }
+    }
+    if (t0 > t1) { *tbest = INFINITY; return -1; }
+    int cell[3], step[3];
+    double tmax[3], tdel[3];
+    for (int a = 0; a < 3; a++) {
+        double pa = oo[a] + t0 * kk[a];
+        int q = (int)floor((pa - s->lo[a]) / s->h);
+        cell[a] = q < 0 ? 0 : (q >= G ? G - 1 : q);
+        if (kk[a] > 0) {
+            step[a] = 1;
+            tmax[a] = (s->lo[a] + (cell[a] + 1) * s->h - oo[a]) / kk[a];
+            tdel[a] = s->h / kk[a];
+        } else if (kk[a] < 0) {
+            step[a] = -1;
+            tmax[a] = (s->lo[a] + cell[a] * s->h - oo[a]) / kk[a];
+            tdel[a] = -s->h / kk[a];
+        } else {
+            step[a] = 0;
+            tmax[a] = INFINITY;
+            tdel[a] = INFINITY;
+        }
+    }
+    for (;;) {
+        int64_t c = ((int64_t)cell[2] * G + cell[1]) * G + cell[0];
+        for (int64_t j = s->cell_start[c]; j < s->cell_start[c + 1]; j++) {
+            int64_t i = s->cell_ids[j];
+            (*ntests)++;
+            if (disk_hit(s, i, o, k, tmin, &t) && (t < bt || (t == bt && i < best)) &&
+                admissible(s, i, add(o, scl(k, t)))) {
+                bt = t;
+                best = i;
+            }
+        }
+        int a = (tmax[0] < tmax[1]) ? (tmax[0] < tmax[2] ? 0 : 2) : (tmax[1] < tmax[2] ? 1 : 2);
+        double texit = tmax[a];
+        if (best >= 0 && bt <= texit) break;
+        cell[a] += step[a];
+        if (cell[a] < 0 || cell[a] >= G) break;
+        tmax[a] += tdel[a];
+    }
+    *tbest = bt;
+    return best;
+}
+
+int64_t or_first_hit_views(const void* p, const double* o, const double* k, double tmin,
+                           double* t) {
+    int64_t nt = 0;
+    const or_scene* s = (const or_scene*)p;
+    if (!s->view_idx) return -2;
+    return first_hit_views(s, ld(o), unit(ld(k)), tmin, t, &nt);
+}
+
+int or_admissible(const void* p, int64_t i, const double* pt) {
+    const or_scene* s = (const or_scene*)p;
+    if (!s->view_idx) return -1;
+    return admissible(s, i, ld(pt));
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Primary geometric frame buffer with disks (c.4): first hit with tmin = 0 at every pixel;   */
 /* normal oriented against the ray (two-sided splats, "oriented normal map").                 */
 /* ------------------------------------------------------------------------------------------ */
@@ -386,7 +539,8 @@ static void pol_basis(v3 s, v3* th, v3* ph) {
 }
 
 static int trace_ray(const or_scene* s, v3 o, v3 k0, v3 u0, v3 v0, int max_b, double eps,
-                     int use_grid, double* rec, int64_t* hit_idx, int64_t* ntests) {
+                     int use_grid, int restricted, double* rec, int64_t* hit_idx,
+                     int64_t* ntests) {
     v3 th, ph;
     pol_basis(scl(k0, -1.0), &th, &ph);
     v3 k = k0, Et = th, Ep = ph, u = u0, v = v0;
@@ -394,7 +548,9 @@ static int trace_ray(const or_scene* s, v3 o, v3 k0, v3 u0, v3 v0, int max_b, do
     int M = 0;
     for (int b = 1; b <= max_b; b++) {
         double t;
-        int64_t h = first_hit(s, o, k, b == 1 ? 0.0 : eps, use_grid, &t, ntests);
+        int64_t h = (restricted && b > 1) ? first_hit_views(s, o, k, eps, &t, ntests)
+                                          : first_hit(s, o, k, b == 1 ? 0.0 : eps, use_grid, &t,
+                                                      ntests);
         if (h < 0) break;
         if (s->mat[h] != 0) break; /* absorber: the ray ends, nothing recorded */
         v3 x = add(o, scl(k, t));
@@ -449,9 +605,10 @@ void or_pol_basis(const double* s, double* th, double* ph) {
 }
 
 int or_trace_pixels(const void* p, const double* kin, int W, int H, int64_t n_pix,
-                    const int64_t* pix, int max_b, double eps, int use_grid, int32_t* n_bounce,
-                    double* rec, int64_t* hit_idx) {
+                    const int64_t* pix, int max_b, double eps, int use_grid, int restricted,
+                    int32_t* n_bounce, double* rec, int64_t* hit_idx) {
     const or_scene* s = (const or_scene*)p;
+    if (restricted && !s->view_idx) return 1;
     double o00[3], du[3], dv[3];
     or_screen(p, kin, W, H, o00, du, dv);
     v3 k = unit(ld(kin));
@@ -461,7 +618,7 @@ int or_trace_pixels(const void* p, const double* kin, int W, int H, int64_t n_pi
         int i = (int)(q % W), j = (int)(q / W);
         v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
         int64_t nt = 0;
-        n_bounce[m] = trace_ray(s, o, k, ld(du), ld(dv), max_b, eps, use_grid,
+        n_bounce[m] = trace_ray(s, o, k, ld(du), ld(dv), max_b, eps, use_grid, restricted,
                                 rec + m * (int64_t)max_b * REC,
                                 hit_idx ? hit_idx + m * (int64_t)max_b : NULL, &nt);
     }
@@ -505,16 +662,50 @@ static void facet_field(const double* r, v3 ks, double kw, v3 rth, v3 rph, doubl
     }
 }
 
+/* Visibility Psi of Eq. (14) under the method's rule (restricted solve).  Monostatic: a
+ * first-bounce facet is the nearest hit along its own central ray and is visible; a later
+ * facet at x is hidden iff a disk stored in the primary first-hit buffer within one pixel of
+ * x's projection onto the incidence screen is intersected by the ray from x toward k_s beyond
+ * eps.  Bistatic: the restricted first hit from x toward k_s beyond eps is empty. */
+static int psi_restricted(const or_scene* s, const int64_t* prim, int W, int H, const double* o00,
+                          v3 du, v3 dv, int mono, int bounce, v3 x, v3 ks, double eps,
+                          int64_t* nt) {
+    double t;
+    if (!mono) return first_hit_views(s, x, ks, eps, &t, nt) < 0;
+    if (bounce == 1) return 1;
+    v3 r = sub(x, ld(o00));
+    double pu = len(du), pv = len(dv);
+    int ia = (int)floor(dot(r, scl(du, 1.0 / pu)) / pu + 0.5);
+    int ib = (int)floor(dot(r, scl(dv, 1.0 / pv)) / pv + 0.5);
+    for (int dy = -1; dy <= 1; dy++) {
+        int y = ib + dy;
+        if (y < 0 || y >= H) continue;
+        for (int dx = -1; dx <= 1; dx++) {
+            int xx = ia + dx;
+            if (xx < 0 || xx >= W) continue;
+            int64_t i = prim[(int64_t)y * W + xx];
+            if (i < 0) continue;
+            (*nt)++;
+            if (disk_hit(s, i, x, ks, eps, &t)) return 0;
+        }
+    }
+    return 1;
+}
+
 /* Full solve (c.6 + c.7): E[inc][obs][freq][rx][tx][re,im].  obs_dir == NULL means monostatic
  * (k_s = -k_inc).  contrib 0 = last bounce only (Eq. (14)), 1 = every bounce.
- * Visibility psi of a radiating facet: the ray from x toward k_s with tmin = eps hits nothing.
+ * Visibility psi of a radiating facet: the ray from x toward k_s with tmin = eps hits nothing
+ * (exact solve); psi_restricted with restricted != 0, where secondary hits are also restricted
+ * to admissible intersections (needs or_scene_set_views).
  * Summation order: pixels row by row; rows summed in order (independent of thread count).
  * stats[0] += ray-disk tests, stats[1] += rays traced (queries), stats[2] += radiating facets. */
 int or_solve(const void* p, int n_inc, const double* inc_dir, int n_obs, const double* obs_dir,
              int n_freq, const double* freq, int W, int H, int max_b, double eps, int contrib,
-             int use_grid, double* E, double* stats) {
+             int use_grid, int restricted, double* E, double* stats) {
     const or_scene* s = (const or_scene*)p;
+    if (restricted && !s->view_idx) return 1;
     int mono = obs_dir == NULL;
+    int64_t* prim = restricted ? (int64_t*)malloc(sizeof(int64_t) * (int64_t)W * H) : NULL;
     int no = mono ? 1 : n_obs;
     size_t per_row = (size_t)no * n_freq * 8;
     double* rows = (double*)malloc(sizeof(double) * per_row * H);
@@ -524,6 +715,17 @@ int or_solve(const void* p, int n_inc, const double* inc_dir, int n_obs, const d
         or_screen(p, inc_dir + 3 * ia, W, H, o00, du, dv);
         v3 k0 = unit(ld(inc_dir + 3 * ia));
         memset(rows, 0, sizeof(double) * per_row * H);
+        if (prim) {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int j = 0; j < H; j++) {
+                int64_t nt = 0;
+                for (int i = 0; i < W; i++) {
+                    double t;
+                    v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
+                    prim[(int64_t)j * W + i] = first_hit(s, o, k0, 0.0, use_grid, &t, &nt);
+                }
+            }
+        }
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : tests, queries, facets)
         for (int j = 0; j < H; j++) {
             double* rec = (double*)malloc(sizeof(double) * REC * max_b);
@@ -531,7 +733,8 @@ int or_solve(const void* p, int n_inc, const double* inc_dir, int n_obs, const d
             int64_t nt = 0, nq = 0, nf = 0;
             for (int i = 0; i < W; i++) {
                 v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
-                int M = trace_ray(s, o, k0, ld(du), ld(dv), max_b, eps, use_grid, rec, NULL, &nt);
+                int M = trace_ray(s, o, k0, ld(du), ld(dv), max_b, eps, use_grid, restricted,
+                                  rec, NULL, &nt);
                 nq += M + (M < max_b ? 1 : 0);
                 if (M == 0) continue;
                 int b0 = contrib == 1 ? 1 : M;
@@ -541,11 +744,16 @@ int or_solve(const void* p, int n_inc, const double* inc_dir, int n_obs, const d
                     pol_basis(ks, &rth, &rph);
                     for (int b = b0; b <= M; b++) {
                         const double* r = rec + (int64_t)(b - 1) * REC;
-                        double tv;
-                        int64_t blk = first_hit(s, ld(r), ks, eps, use_grid, &tv, &nt);
+                        double psi;
+                        if (restricted) {
+                            psi = psi_restricted(s, prim, W, H, o00, ld(du), ld(dv), mono, b,
+                                                 ld(r), ks, eps, &nt) ? 1.0 : 0.0;
+                        } else {
+                            double tv;
+                            psi = first_hit(s, ld(r), ks, eps, use_grid, &tv, &nt) >= 0 ? 0.0 : 1.0;
+                        }
                         nq++;
                         nf++;
-                        double psi = blk >= 0 ? 0.0 : 1.0;
                         if (psi == 0.0) continue;
                         for (int f = 0; f < n_freq; f++) {
                             double kw = 2 * OR_PI * freq[f] / OR_C0;
@@ -568,6 +776,7 @@ int or_solve(const void* p, int n_inc, const double* inc_dir, int n_obs, const d
             for (size_t t = 0; t < per_row; t++) out[t] += rows[per_row * j + t];
     }
     free(rows);
+    free(prim);
     if (stats) {
         stats[0] += (double)tests;
         stats[1] += (double)queries;
