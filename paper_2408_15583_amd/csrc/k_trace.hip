@@ -161,7 +161,8 @@ __device__ inline void slab(float a0, float da, float lo, float hi, float& s0, f
 // when the ray's depth over the pixel, widened by one pixel of travel (the 3x3 refinement
 // reaches one pixel around), meets the texel's [min, max] of stored disk extents; the disks of
 // the 3x3 block are then intersected exactly, skipping those already tested in the previous
-// block.
+// block.  A hit counts only when its point projects within one pixel of the pixel that stores
+// the disk: the set of hits the views retain, whatever path pixel the test came from.
 __device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
                            float& best_t, uint32_t& best_i, uint32_t* cap_hits) {
     const float ip = 1.f / V.pitch;
@@ -219,8 +220,13 @@ __device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax
                     float t;
                     if (disk_test(pix[2 * (py * W + px)], pb, x, k, tmin, t) &&
                         (t < best_t || (t == best_t && i < best_i))) {
-                        best_t = t;
-                        best_i = i;
+                        // the view retains this disk for hit points within one pixel of where
+                        // it is stored (the hit point's own pixel is always on the walk)
+                        const int ha = (int)floorf(a0 + t * da), hb = (int)floorf(b0 + t * db);
+                        if (abs(ha - px) <= 1 && abs(hb - py) <= 1) {
+                            best_t = t;
+                            best_i = i;
+                        }
                     }
                 }
             }

@@ -1,0 +1,173 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configuration bench.py
+times (2M-point composite: 1024^2 screen, six 1024^2 aggregation views, 64 frequencies
+2-12 GHz, up to 4 bounces; 4M-point sphere of radius 4 m at 1024^2, 64 frequencies 2-24 GHz).
+
+The oracle computes sampled pixels one by one and the RCS of a few azimuths with its
+culled-exact grid.  Bars:
+  - primary buffers: hit masks agree on >= 99.9 % of sampled pixels, depth within 1e-5 D;
+  - single bounce: RCS within 0.1 dB wherever the oracle is within 30 dB of the curve's peak
+    over the sampled azimuths;
+  - multi-bounce: against the oracle with the method's own secondary-hit and visibility rules
+    (restricted to what the aggregation views retain): bounce counts agree on >= 99.99 % and
+    last facets on >= 99.9 % of sampled pixels, hit points within 1e-4 m.  The RCS then agrees
+    to a median below 0.05 dB; rare fp32-vs-fp64 flips of a ray at a disk edge or a pixel
+    boundary move low-level samples of this many-ray sum by up to a few dB, so the RCS bar is a
+    median and a 90th percentile (stated in the test), not a maximum.  The difference between
+    the restricted and the exact oracle -- what the aggregation views lose -- is printed.
+  - sphere (precision study): single bounce, FP64-phase within 0.1 dB of the exact oracle at
+    every angle and frequency, the all-FP32 error printed per frequency; the workload's four
+    bounces (grazing limb rays of the noisy sphere bounce again) against the restricted oracle
+    with the multi-bounce bars above.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    import paper_2408_15583_amd as pe_mod
+    assert torch.cuda.is_available()
+    return pe_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(pe):
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def composite(pe, ctx):
+    sc, sw = scenes.workload_composite()
+    s = pe.Scene.from_scene(ctx, sc, view_res=sw.view_res)
+    o = oracle.OracleScene(sc, grid=256)
+    o.set_views(sw.view_res)
+    yield sc, sw, s, o
+    s.close()
+
+
+def db_errors(r, ro, dyn=30.0):
+    out = []
+    for p in range(2):
+        a, b = r[..., p, p], ro[..., p, p]
+        sel = b >= b.max(axis=0, keepdims=True) - dyn
+        out.append(np.abs(a - b)[sel])
+    return np.concatenate(out)
+
+
+def test_composite_primary_buffers(pe, ctx, composite):
+    sc, sw, s, o = composite
+    c, R = o.frame()
+    rng = np.random.default_rng(7)
+    for az_i in (0, 211):
+        k = sw.inc_dir[az_i]
+        g = pe.render_gfb(ctx, s, k, 1024, 1024)
+        mask = g["mask"].cpu().numpy().ravel()
+        dep = g["depth"].cpu().numpy().ravel()
+        pix = rng.choice(1024 * 1024, 60000, replace=False)
+        nbo, rec, _ = o.trace_pixels(k, 1024, 1024, pix, 1, sw.eps)
+        hit_o = nbo > 0
+        assert (hit_o == (mask[pix] > 0)).mean() >= 0.999
+        both = hit_o & (mask[pix] > 0)
+        o00, du, dv = o.screen(k, 1024, 1024)
+        pu = np.linalg.norm(du)
+        i, j = pix % 1024, pix // 1024
+        origin = o00 + np.outer(i, du) + np.outer(j, dv)
+        t_o = np.einsum("ij,j->i", rec[:, 0, 0:3] - origin, k / np.linalg.norm(k))
+        assert np.abs(dep[pix][both] - t_o[both]).max() <= 1e-5 * 2 * R
+
+
+def test_composite_single_bounce_rcs(pe, ctx, composite):
+    sc, sw, s, o = composite
+    inc = sw.inc_dir[[0, 37, 123, 200, 290]]
+    _, r, _ = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=1, eps=sw.eps)
+    Eo, _ = o.solve(inc, sw.freq_hz, 1024, 1024, 1, sw.eps)
+    e = db_errors(r, oracle.rcs_dbsm(Eo))
+    print(f"FULLSIZE composite B=1: max {e.max():.4f} dB median {np.median(e):.4f} dB over {e.size}")
+    assert e.max() < 0.1
+
+
+def test_composite_multibounce_per_ray(pe, ctx, composite):
+    sc, sw, s, o = composite
+    rng = np.random.default_rng(11)
+    c, _ = o.frame()
+    for az_i in (0, 123):
+        k = sw.inc_dir[az_i]
+        g = pe.trace_pixels(ctx, s, k, 1024, 1024, sw.max_bounces, sw.eps)
+        nb = g["n_bounce"].cpu().numpy().ravel()
+        li = g["last_idx"].cpu().numpy().ravel().astype(np.int64)
+        lx = g["last_x"].cpu().numpy().reshape(-1, 3) + c
+        pix = rng.choice(1024 * 1024, 60000, replace=False)
+        nbr, rec, hidx = o.trace_pixels(k, 1024, 1024, pix, sw.max_bounces, sw.eps,
+                                        restricted=True)
+        nbe, _, _ = o.trace_pixels(k, 1024, 1024, pix, sw.max_bounces, sw.eps)
+        agree = (nb[pix] == nbr).mean()
+        same = (nb[pix] == nbr) & (nbr > 0)
+        m = np.where(same)[0]
+        last = hidx[m, nbr[m] - 1]
+        idx_agree = (li[pix[m]] == last).mean()
+        ok = li[pix[m]] == last
+        dx = np.linalg.norm(lx[pix[m]] - rec[m, nbr[m] - 1, 0:3], axis=1)[ok]
+        print(f"FULLSIZE composite az {az_i}: bounce counts {agree:.5f}, last facet {idx_agree:.5f},"
+              f" |dx| max {dx.max():.2e} m; exact-oracle bounce agreement {(nb[pix] == nbe).mean():.5f}")
+        assert agree >= 0.9999
+        assert idx_agree >= 0.999
+        assert dx.max() <= 1e-4
+
+
+def test_composite_multibounce_rcs(pe, ctx, composite):
+    sc, sw, s, o = composite
+    inc = sw.inc_dir[[0, 37, 123, 200, 290]]
+    _, r, _ = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=sw.max_bounces, eps=sw.eps)
+    Er, _ = o.solve(inc, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps, restricted=True)
+    Ee, _ = o.solve(inc, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps)
+    rr, re = oracle.rcs_dbsm(Er), oracle.rcs_dbsm(Ee)
+    e = db_errors(r, rr)
+    agg = db_errors(rr, re)
+    print(f"FULLSIZE composite B=4 vs restricted oracle: median {np.median(e):.4f} dB, "
+          f"p90 {np.percentile(e, 90):.3f}, p99 {np.percentile(e, 99):.3f}, max {e.max():.3f}; "
+          f"within 0.1 dB: {(e <= 0.1).mean():.4f}")
+    print(f"FULLSIZE composite B=4 aggregation loss (restricted vs exact oracle): median "
+          f"{np.median(agg):.3f} dB, p90 {np.percentile(agg, 90):.3f}, max {agg.max():.3f}")
+    assert np.median(e) <= 0.05
+    assert np.percentile(e, 90) <= 0.25
+
+
+def test_sphere_4m_precision(pe, ctx):
+    sc, sw = scenes.workload_sphere()
+    s = pe.Scene.from_scene(ctx, sc, view_res=sw.view_res)
+    o = oracle.OracleScene(sc, grid=256)
+    o.set_views(sw.view_res)
+    inc = sw.inc_dir[[0, 90, 200]]
+    # single bounce: precision study against the exact oracle
+    _, r64, _ = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=1, eps=sw.eps)
+    _, r32, _ = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=1, eps=sw.eps,
+                         precision="fp32")
+    Eo, _ = o.solve(inc, sw.freq_hz, 1024, 1024, 1, sw.eps)
+    ro = oracle.rcs_dbsm(Eo)
+    e64 = np.max([np.abs(r64[..., p, p] - ro[..., p, p]) for p in range(2)], axis=0)  # [a,1,f]
+    e32 = np.max([np.abs(r32[..., p, p] - ro[..., p, p]) for p in range(2)], axis=0)
+    for f in range(0, len(sw.freq_hz), 7):
+        print(f"FULLSIZE sphere B=1 {sw.freq_hz[f] / 1e9:5.1f} GHz: fp64-phase max "
+              f"{e64[:, 0, f].max():.4f} dB, fp32 max {e32[:, 0, f].max():.4f} dB")
+    print(f"FULLSIZE sphere B=1 all: fp64-phase max {e64.max():.4f} dB, fp32 max {e32.max():.4f} dB")
+    assert e64.max() < 0.1
+    # the workload's 4 bounces (grazing rays at the noisy limb bounce again)
+    _, r4, st = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=sw.max_bounces, eps=sw.eps)
+    Er, _ = o.solve(inc, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps, restricted=True)
+    Ee, _ = o.solve(inc, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps)
+    e = db_errors(r4, oracle.rcs_dbsm(Er))
+    agg = db_errors(oracle.rcs_dbsm(Er), oracle.rcs_dbsm(Ee))
+    print(f"FULLSIZE sphere B=4 vs restricted oracle: median {np.median(e):.4f} dB, p90 "
+          f"{np.percentile(e, 90):.3f}, max {e.max():.3f}; aggregation loss median "
+          f"{np.median(agg):.4f} dB, max {agg.max():.3f}; march rays {st['march_rays']:.0f}")
+    assert np.median(e) <= 0.05
+    assert np.percentile(e, 90) <= 0.25
+    s.close()
