@@ -83,6 +83,137 @@ def cpu_baseline(sc, sw, sample_px, seed=11):
                        f"({q:.0f} queries in {dt:.1f} s)")
 
 
+def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
+    """Continuous-batching server under the request mix of the serving workload: scenes drawn
+    from a resident pool (composite generator, N log-uniform in [5e4, 4e6]), screens uniform in
+    {256, 512, 1024, 2048}^2, angle counts log-uniform in [1, 720], frequency counts log-uniform
+    in [1, 128] (2-12 GHz), 1-5 bounces.  Phase 1 submits a closed batch of requests at once
+    (saturation: solves/s the GPU sustains); phase 2 offers Poisson arrivals at 70 % of that
+    rate for `seconds` and reports latency percentiles from submit to completion."""
+    import numpy as np
+    import scenes
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(n_scenes):
+        n = int(np.exp(rng.uniform(np.log(5e4), np.log(4e6))))
+        sc = scenes.composite(seed=1000 + i, n_points=n)
+        pool.append((sc, pe.Scene.from_scene(ctx, sc, view_res=1024)))
+    if log:
+        log(f"serving pool: {[sc.n for sc, _ in pool]} points")
+
+    def request():
+        sc, s = pool[int(rng.integers(len(pool)))]
+        screen = int(rng.choice([256, 512, 1024, 2048]))
+        n_ang = int(np.exp(rng.uniform(0.0, np.log(720.0))))
+        n_f = int(np.exp(rng.uniform(0.0, np.log(128.0))))
+        az = (rng.uniform(0, 360) + np.arange(n_ang) * (360.0 / n_ang)) % 360.0
+        inc = scenes.azimuth_sweep(az, 30.0)
+        freq = np.linspace(2e9, 12e9, n_f)
+        eps = max(0.5 * float(sc.radius), 6.0 * sc.noise_sigma)
+        B = int(rng.integers(1, 6))
+        return s, inc, freq, screen, B, eps
+
+    def submit(r):
+        s, inc, freq, screen, B, eps = r
+        return pe.submit(ctx, s, inc, freq, screen, max_bounces=B, eps=eps)
+
+    # phase 1: saturation
+    reqs = [request() for _ in range(24)]
+    pe.server_stats(ctx, reset=True)
+    t0 = time.perf_counter()
+    ts = [submit(r) for r in reqs]
+    samples = 0
+    for t, r in zip(ts, reqs):
+        t.wait()
+        samples += len(r[1]) * len(r[2])
+    dt = time.perf_counter() - t0
+    cap = len(reqs) / dt
+    sat = pe.server_stats(ctx, reset=True)
+    if log:
+        log(f"serving saturation: {len(reqs)} requests in {dt:.2f} s ({cap:.2f} solves/s)")
+    # phase 2: Poisson arrivals at 70 % of capacity
+    rate = 0.7 * cap
+    arrivals = []
+    t = 0.0
+    while t < seconds:
+        t += rng.exponential(1.0 / rate)
+        arrivals.append(t)
+    reqs = [request() for _ in arrivals]
+    t0 = time.perf_counter()
+    ts = []
+    for a, r in zip(arrivals, reqs):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        ts.append(submit(r))
+    for t in ts:
+        t.wait()
+    dt2 = time.perf_counter() - t0
+    st = pe.server_stats(ctx, reset=True)
+    for _, s in pool:
+        s.close()
+    return dict(saturation_solves_per_s=cap, saturation_rcs_samples_per_s=samples / dt,
+                saturation_reqs_per_batch=sat["reqs_per_batch"],
+                offered_rate_per_s=rate, requests=len(ts), completed=st["completed"],
+                p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
+                max_concurrent=st["max_concurrent"], reqs_per_batch=st["reqs_per_batch"],
+                window_s=dt2,
+                note="workload request mix (scene pool of %d); Poisson at 70%% of the measured "
+                     "saturation rate; 200 req/s of this mix is %.0fx one GPU's capacity"
+                     % (len(pool), 200.0 / cap))
+
+
+# Dense MFMA flops of one densifier forward pass at base 32 from a coarse h x w input
+def densifier_flops(base, h, w):
+    C = [base << l for l in range(4)]
+    f = 0.0
+    for l in range(4):
+        M = (h >> l) * (w >> l)
+        f += 2 * M * C[l] * 4 * C[l] * 2           # ConvNeXt 1x1 expand + project
+        if l > 0:
+            f += 2 * M * C[l - 1] * C[l]           # 1x1 down
+    for co in (1, 3, 1):
+        for l in (3, 2, 1):
+            Ml = (h >> l) * (w >> l)
+            f += 2 * Ml * 9 * C[l] * 4 * C[l - 1]          # 3x3 up (before the shuffle)
+            f += 2 * (4 * Ml) * 9 * 2 * C[l - 1] * C[l - 1]  # 3x3 fuse
+        f += 2 * h * w * 9 * C[0] * 4 * co                 # 3x3 out
+    return f
+
+
+def densifier_bench(pe, ctx, batch=8, h=256, steps=10, log=None):
+    """Inference and training throughput of the densifier at the workload size (coarse
+    256^2 -> 512^2, base 32), on synthetic inputs; dense-conv flops / wall time."""
+    import torch
+    net = pe.Densifier(ctx, base=32, seed=1)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = (torch.rand((batch, h, h), generator=g) * (torch.rand((batch, h, h), generator=g) < 0.7)).cuda()
+    dg = torch.rand((batch, 2 * h, 2 * h), generator=g).cuda()
+    ng = torch.nn.functional.normalize(torch.randn((batch, 2 * h, 2 * h, 3), generator=g), dim=-1).cuda()
+    mg = (torch.rand((batch, 2 * h, 2 * h), generator=g) < 0.6).float().cuda()
+    net.infer(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.infer(x)
+    torch.cuda.synchronize()
+    ti = (time.perf_counter() - t0) / steps
+    net.train_step(x, dg, ng, mg, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x, dg, ng, mg, lr=1e-4)
+    torch.cuda.synchronize()
+    tt = (time.perf_counter() - t0) / steps
+    net.close()
+    fl = densifier_flops(32, h, h) * batch
+    return dict(batch=batch, coarse=h, infer_ms=ti * 1e3, infer_images_per_s=batch / ti,
+                train_step_ms=tt * 1e3, train_pairs_per_s=batch / tt,
+                infer_tflops=fl / ti / 1e12, train_tflops=3 * fl / tt / 1e12,
+                mfma_bf16_peak_tflops=2500.0, infer_frac=fl / ti / 2.5e15,
+                note="dense-conv flops of the network / wall time (whole pass incl. VALU layers)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +229,9 @@ def main():
                     help="pixel rays traced by the CPU oracle (0 = skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="Poisson serving window (0 = skip the serving measurement)")
+    ap.add_argument("--no-densifier", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path shards by "
@@ -226,6 +360,9 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in sorted(ks.items(),
                                                                         key=lambda kv: -kv[1][0])},
     }
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    out["densifier"] = None if args.no_densifier else densifier_bench(pe, ctx, log=log)
+    out["serving"] = serving(pe, ctx, args.serve_seconds, log=log) if args.serve_seconds > 0 else None
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(sc, sw, args.cpu_sample)
     else:
