@@ -33,94 +33,132 @@ union Frag {
 // ------------------------------------------------------------------------------------------
 // Convolution (stride 1, zero padding (K-1)/2) as implicit GEMM on MFMA
 // ------------------------------------------------------------------------------------------
-// Block: 256 threads = 2x2 wavefronts, tile 64 pixels x 64 output channels; wavefront tile
-// 32 x 32 = 2 x 2 MFMA 16x16 tiles; K advances by 32 input channels per tap.
-// Requirements (checked by the host): Cin % 32 == 0, Cout % 16 == 0.
+// Block: 256 threads = 2 x 2 wavefronts over a tile of 128 pixels x BN output channels.  Each
+// K step covers 32 input channels of one tap: the block stages the A tile (128 pixels x 32
+// channels of the shifted input) and the B tile (BN channels x 32) in LDS, double-buffered, and
+// issues the next step's global loads before the current step's MFMAs.  A wavefront computes
+// 64 x BN/2 outputs as 4 x BN/32 tiles of v_mfma_f32_16x16x32_bf16.
+// Requirements (checked by the host): Cin % 32 == 0.
+template <int BN>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int pm0 = blockIdx.x * 64 + (wave & 1) * 32;   // first pixel of the wavefront tile
-    const int co0 = blockIdx.y * 64 + (wave >> 1) * 32;  // first output channel
+    constexpr int BM = 128, LDS = 40;             // 32 k + 8 pad (bf16) per row
+    constexpr int TM = 4, TN = BN / 32;           // MFMA tiles per wavefront
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDS];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][LDS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
     const int HW = a.H * a.W, M = a.N * HW;
-    const int r = lane & 15, kq = (lane >> 4) * 8;       // fragment row and k offset
-    v4f acc[2][2];
-    for (int i = 0; i < 2; i++)
-        for (int j = 0; j < 2; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int pad = (a.K - 1) / 2, taps = a.K * a.K, kpt = a.Cin / 32, steps = taps * kpt;
+    // loader: A chunk c = tid + 256 i (i = 0, 1): row c >> 2, 8 channels at (c & 3) * 8
+    const int kc = (tid & 3) * 8;
     int pn[2], py[2], px[2];
     bool pv[2];
     for (int i = 0; i < 2; i++) {
-        const int m = pm0 + i * 16 + r;
+        const int m = m0 + (tid >> 2) + 64 * i;
         pv[i] = m < M;
         const int mm = pv[i] ? m : 0;
         pn[i] = mm / HW;
         py[i] = (mm % HW) / a.W;
         px[i] = mm % a.W;
     }
-    const int pad = (a.K - 1) / 2;
-    const int taps = a.K * a.K;
-    for (int t = 0; t < taps; t++) {
+    constexpr int BCH = BN * 4;                  // B chunks of 8 channels
+    uint4 ra[2], rb[2];
+    auto gload = [&](int step) {
+        const int t = step / kpt, c0 = (step - t * kpt) * 32;
         const int dy = t / a.K - pad, dx = t % a.K - pad;
-        const uint16_t* xs[2];
-        bool ok[2];
         for (int i = 0; i < 2; i++) {
             const int y = py[i] + dy, x = px[i] + dx;
-            ok[i] = pv[i] && y >= 0 && y < a.H && x >= 0 && x < a.W;
-            xs[i] = a.x + ((size_t)(pn[i] * a.H + (ok[i] ? y : 0)) * a.W + (ok[i] ? x : 0)) * a.ldx +
-                    a.xoff;
+            const bool ok = pv[i] && y >= 0 && y < a.H && x >= 0 && x < a.W;
+            ra[i] = ok ? *(const uint4*)(a.x + ((size_t)(pn[i] * a.H + y) * a.W + x) * a.ldx +
+                                         a.xoff + c0 + kc)
+                       : make_uint4(0, 0, 0, 0);
         }
-        const uint16_t* ws[2];
-        bool wok[2];
-        for (int j = 0; j < 2; j++) {
-            const int co = co0 + j * 16 + r;
-            wok[j] = co < a.Cout;
-            ws[j] = a.w + ((size_t)(wok[j] ? co : 0) * taps + t) * a.Cin;
+        for (int i = 0; i < 2; i++) {
+            const int c = tid + 256 * i;
+            rb[i] = make_uint4(0, 0, 0, 0);
+            if (c < BCH) {
+                const int co = n0 + (c >> 2);
+                if (co < a.Cout)
+                    rb[i] = *(const uint4*)(a.w + ((size_t)co * taps + t) * a.Cin + c0 + (c & 3) * 8);
+            }
         }
-        for (int c0 = 0; c0 < a.Cin; c0 += 32) {
-            Frag fa[2], fb[2];
-            for (int i = 0; i < 2; i++)
-                fa[i].u = ok[i] ? *(const uint4*)(xs[i] + c0 + kq) : make_uint4(0, 0, 0, 0);
-            for (int j = 0; j < 2; j++)
-                fb[j].u = wok[j] ? *(const uint4*)(ws[j] + c0 + kq) : make_uint4(0, 0, 0, 0);
-            for (int i = 0; i < 2; i++)
-                for (int j = 0; j < 2; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j],
-                                                                       0, 0, 0);
+    };
+    auto sstore = [&](int buf) {
+        for (int i = 0; i < 2; i++) *(uint4*)&As[buf][(tid >> 2) + 64 * i][kc] = ra[i];
+        for (int i = 0; i < 2; i++) {
+            const int c = tid + 256 * i;
+            if (c < BCH) *(uint4*)&Bs[buf][c >> 2][(c & 3) * 8] = rb[i];
         }
+    };
+    v4f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    for (int step = 0; step < steps; step++) {
+        const int buf = step & 1;
+        if (step + 1 < steps) gload(step + 1);
+        Frag fa[TM], fb[TN];
+#pragma unroll
+        for (int i = 0; i < TM; i++) fa[i].u = *(const uint4*)&As[buf][wm * 64 + i * 16 + r][kq];
+#pragma unroll
+        for (int j = 0; j < TN; j++) fb[j].u = *(const uint4*)&Bs[buf][wn * (BN / 2) + j * 16 + r][kq];
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
+                                                                   0, 0);
+        if (step + 1 < steps) sstore(buf ^ 1);
+        __syncthreads();
     }
-    // D fragment: lane holds column (channel) r of rows (pixels) 4*(lane/16) + q
-    for (int i = 0; i < 2; i++)
-        for (int j = 0; j < 2; j++) {
-            const int co = co0 + j * 16 + r;
-            if (co >= a.Cout_store) continue;
-            const float bias = a.bias ? a.bias[co] : 0.f;
+    // D fragment: lane holds column (channel) r of rows (pixels) 4 * (lane / 16) + q
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) {
+            const int co = n0 + wn * (BN / 2) + j * 16 + r;
+            const bool cok = co < a.Cout_store;
+            const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
+#pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int m = pm0 + i * 16 + (lane >> 4) * 4 + q;
-                if (m >= M) continue;
-                float v = acc[i][j][q] + bias;
-                if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
-                const float pre = v;
-                if (a.act == 1) v = 0.5f * v * (1.f + erff(v * 0.70710678118654752f));
-                const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
-                size_t o;
-                int oc;
-                if (a.shuffle) {  // channel c*4 + 2*sy + sx -> pixel (2y+sy, 2x+sx), channel c
-                    oc = co >> 2;
-                    const int sy = (co >> 1) & 1, sx = co & 1;
-                    o = ((size_t)(n * 2 * a.H + 2 * yy + sy) * (2 * a.W) + 2 * xx + sx) * a.ldy +
-                        a.yoff + oc;
-                } else {
-                    oc = co;
-                    o = ((size_t)(n * a.H + yy) * a.W + xx) * a.ldy + a.yoff + oc;
+                const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + q;
+                if (cok && m < M) {
+                    float v = acc[i][j][q] + bias;
+                    if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
+                    const float pre = v;
+                    if (a.act == 1) v = 0.5f * v * (1.f + erff(v * 0.70710678118654752f));
+                    const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
+                    size_t o;
+                    if (a.shuffle) {  // channel c*4 + 2*sy + sx -> pixel (2y+sy, 2x+sx), channel c
+                        const int oc = co >> 2, sy = (co >> 1) & 1, sx = co & 1;
+                        o = ((size_t)(n * 2 * a.H + 2 * yy + sy) * (2 * a.W) + 2 * xx + sx) * a.ldy +
+                            a.yoff + oc;
+                    } else {
+                        o = ((size_t)(n * a.H + yy) * a.W + xx) * a.ldy + a.yoff + co;
+                    }
+                    if (a.y32) a.y32[o] = v;
+                    else a.y[o] = f2bf(v);
+                    if (a.z) a.z[o] = f2bf(pre);
                 }
-                if (a.y32) a.y32[o] = v;
-                else a.y[o] = f2bf(v);
-                if (a.z) a.z[o] = f2bf(pre);
             }
         }
 }
 
 void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     const int M = a.N * a.H * a.W;
-    hipLaunchKernelGGL(k_conv_fwd, dim3((M + 63) / 64, (a.Cout + 63) / 64), dim3(256), 0, st, a);
+    const unsigned gx = (unsigned)((M + 127) / 128);
+    if (a.Cout > 64)
+        hipLaunchKernelGGL(k_conv_fwd<128>, dim3(gx, (a.Cout + 127) / 128), dim3(256), 0, st, a);
+    else if (a.Cout > 32)
+        hipLaunchKernelGGL(k_conv_fwd<64>, dim3(gx, 1), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_conv_fwd<32>, dim3(gx, 1), dim3(256), 0, st, a);
 }
 
 // Weight gradient: dW[co][t][ci] = sum_p dY[p][co] X[p + shift(t)][ci] over one chunk of

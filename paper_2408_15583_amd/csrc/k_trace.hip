@@ -339,10 +339,19 @@ __global__ __launch_bounds__(256, 6) void k_march(const SlotDesc* __restrict__ d
         const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
         f3 k = mirror(kin, nn);
         k = k * rsqrtf(dot(k, k));
+        // Start from the best hit other views have already published for this ray: the walk
+        // then stops at that depth, and only strictly better (t, index) hits are kept, so the
+        // final minimum over views is the same whatever the order in which views finish.
+        const uint64_t known =
+            __hip_atomic_load(&hitkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         float bt = FLT_MAX;
         uint32_t bi = kNone;
+        if (known != kEmptyKey) {
+            bt = __uint_as_float((uint32_t)(known >> 32));
+            bi = (uint32_t)(known & 0xFFFFFFFFu);
+        }
         march_view(d.views[v], x, k, d.eps, march_smax(d, x, k), march_tol(d), bt, bi, cap_hits);
-        if (bi != kNone)
+        if (bi != kNone && pack_hit(bt, bi) < known)
             atomicMin((unsigned long long*)&hitkey[e], (unsigned long long)pack_hit(bt, bi));
     }
 }
