@@ -28,6 +28,7 @@ constexpr int kHeadCo[kHeads] = {1, 3, 1};
 constexpr int kPadCo = 32;       // padded channel count of the head-output gradients
 constexpr int kNetBatch = 8;     // incidences per network batch in a densified solve
 constexpr float kLnEps = 1e-6f;
+constexpr int kRowChunk = 64;    // rows per partial of the column-sum style gradient reductions
 
 struct Tensor {
     std::string name;
@@ -102,6 +103,7 @@ struct pe_densifier_s {
     uint16_t* pb = nullptr;
     uint16_t* wt = nullptr;
     uint64_t wt_n = 0;
+    float* dwt[4] = {nullptr, nullptr, nullptr, nullptr};  // tap-major depthwise weights
     int step = 0;
     std::mutex mu;
     std::vector<std::pair<void*, size_t>> allocs;
@@ -285,15 +287,15 @@ struct pe_densifier_s {
         bias_grad(c.b, dy, lddy, M, c.co, st);
     }
     void bias_grad(int t, const uint16_t* dy, int lddy, int M, int C, hipStream_t st) const {
-        const int nch = (M + 1023) / 1024;
-        launch_colsum(dy, M, lddy, 0, C, 1024, A.part, st);
+        const int nch = (M + kRowChunk - 1) / kRowChunk;
+        launch_colsum(dy, M, lddy, 0, C, kRowChunk, A.part, st);
         launch_reduce_chunks(A.part, nch, C, C, C, C, 0, G(t), st);
     }
 
     void block_fwd(int l, int N, int H, int W, bool train, hipStream_t st) {
         const BlockL& b = enc[l];
         const int c = C[l], M = N * H * W;
-        launch_dw_fwd(A.bx[l], N, H, W, c, P(b.dww), P(b.dwb), A.dwo[l], st);
+        launch_dw_fwd(A.bx[l], N, H, W, c, dwt[l], P(b.dwb), A.dwo[l], st);
         launch_ln_fwd(A.dwo[l], M, c, P(b.lng), P(b.lnb), kLnEps, A.lno[l], A.lst[l], st);
         conv_fwd(b.pw1, A.lno[l], c, 0, N, H, W, A.a1[l], nullptr, 4 * c, 0, 1, 0,
                  train ? A.z1[l] : nullptr, nullptr, st);
@@ -302,6 +304,7 @@ struct pe_densifier_s {
     }
 
     void forward(int N, int H, int W, const float* x, bool train, hipStream_t st) {
+        for (int l = 0; l < 4; l++) launch_dw_wt(P(enc[l].dww), C[l], dwt[l], st);
         launch_stem_fwd(x, N, H, W, C[0], P(stem.w), P(stem.b), A.stem_z, A.bx[0], st);
         for (int l = 0; l < 4; l++) {
             const int Hl = H >> l, Wl = W >> l;
@@ -345,17 +348,15 @@ struct pe_densifier_s {
         // LayerNorm
         launch_ln_bwd(A.dwo[l], A.dln, M, c, P(b.lng), A.lst[l], A.ddw, st);
         {
-            const int nch = (M + 1023) / 1024;
-            launch_ln_pgrad(A.dwo[l], A.dln, M, c, A.lst[l], 1024, A.part, st);
+            const int nch = (M + kRowChunk - 1) / kRowChunk;
+            launch_ln_pgrad(A.dwo[l], A.dln, M, c, A.lst[l], kRowChunk, A.part, st);
             launch_reduce_chunks(A.part, nch, (size_t)2 * c, c, 1, 2, 0, G(b.lng), st);
             launch_reduce_chunks(A.part, nch, (size_t)2 * c, c, 1, 2, 1, G(b.lnb), st);
         }
         // depthwise 7x7
-        launch_dw_dgrad(A.ddw, N, H, W, c, P(b.dww), A.dxdw, st);
+        launch_dw_dgrad(A.ddw, N, H, W, c, dwt[l], A.dxdw, st);
         {
-            const int by = (c + 63) / 64;
-            const int rows = std::max(1, (N * H * by + 511) / 512);
-            const int nch = (N * H + rows - 1) / rows;
+            const int rows = 1, nch = N * H;  // one image row per partial
             launch_dw_wgrad(A.bx[l], A.ddw, N, H, W, c, rows, A.part, st);
             launch_reduce_chunks(A.part, nch, (size_t)50 * c, (size_t)49 * c, 49, 50, 0, G(b.dww), st);
             launch_reduce_chunks(A.part, nch, (size_t)50 * c, c, 1, 50, 49, G(b.dwb), st);
@@ -414,8 +415,8 @@ struct pe_densifier_s {
         const int M0 = N * H * W;
         launch_gelu_bwd(A.stem_z, A.dxdw, (size_t)M0 * C[0], A.dxdw, st);
         {
-            const int nch = (M0 + 1023) / 1024;
-            launch_stem_wgrad(x, N, H, W, C[0], A.dxdw, 1024, A.part, st);
+            const int nch = (M0 + kRowChunk - 1) / kRowChunk;
+            launch_stem_wgrad(x, N, H, W, C[0], A.dxdw, kRowChunk, A.part, st);
             launch_reduce_chunks(A.part, nch, (size_t)10 * C[0], (size_t)9 * C[0], 9, 10, 0,
                                  G(stem.w), st);
             launch_reduce_chunks(A.part, nch, (size_t)10 * C[0], C[0], 1, 10, 9, G(stem.b), st);
@@ -466,17 +467,15 @@ size_t pe_densifier_s::part_floats(int N, int H, int W) const {
         int chunk = 0;
         const int nch = wgrad_chunks(c, M, &chunk);
         best = std::max(best, (size_t)nch * c.co * c.k * c.k * c.ci);
-        best = std::max(best, (size_t)((M + 1023) / 1024) * c.co);
+        best = std::max(best, (size_t)((M + kRowChunk - 1) / kRowChunk) * c.co);
     };
     for (int l = 0; l < 4; l++) {
         const int Hl = H >> l, Wl = W >> l, M = N * Hl * Wl, c = C[l];
         convp(enc[l].pw1, M);
         convp(enc[l].pw2, M);
         if (l > 0) convp(down[l], M);
-        best = std::max(best, (size_t)((M + 1023) / 1024) * 2 * c);
-        const int by = (c + 63) / 64;
-        const int rows = std::max(1, (N * Hl * by + 511) / 512);
-        best = std::max(best, (size_t)((N * Hl + rows - 1) / rows) * 50 * c);
+        best = std::max(best, (size_t)((M + kRowChunk - 1) / kRowChunk) * 2 * c);
+        best = std::max(best, (size_t)(N * Hl) * 50 * c);
     }
     for (int h = 0; h < kHeads; h++) {
         for (int l = 1; l < 4; l++) {
@@ -485,7 +484,7 @@ size_t pe_densifier_s::part_floats(int N, int H, int W) const {
         }
         convp(out[h], N * H * W);
     }
-    best = std::max(best, (size_t)((N * H * W + 1023) / 1024) * 10 * C[0]);
+    best = std::max(best, (size_t)((N * H * W + kRowChunk - 1) / kRowChunk) * 10 * C[0]);
     return best;
 }
 
@@ -730,6 +729,7 @@ pe_status pe_densifier_create(pe_ctx ctx, int32_t base_ch, uint64_t seed, pe_den
     net->v = (float*)net->alloc(n * 4);
     net->pb = (uint16_t*)net->alloc(n * 2);
     net->wt = (uint16_t*)net->alloc(net->wt_n * 2);
+    for (int l = 0; l < 4; l++) net->dwt[l] = (float*)net->alloc((size_t)49 * net->C[l] * 4);
     std::vector<float> h = net->init_values(seed);
     HIPCHK(hipMemcpy(net->p, h.data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(net->g, 0, n * 4));

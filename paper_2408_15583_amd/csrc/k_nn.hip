@@ -10,6 +10,8 @@
 // bit-reproducible.  Depthwise 7x7, LayerNorm, GELU, pooling, losses and AdamW are VALU kernels.
 #include <float.h>
 
+#include <algorithm>
+
 #include "pe_device.h"
 #include "pe_nn.h"
 
@@ -227,8 +229,11 @@ void launch_conv_wgrad(const WgradArgs& a, int n_chunks, hipStream_t st) {
                        dim3(256), 0, st, a);
 }
 
-// out[i] = sum over chunks c (in chunk order) of part[c * stride + (i / inner) * outer +
-// i % inner + off]: gathers one parameter tensor out of interleaved per-chunk partials.
+// out[i] = sum over chunks c of part[c * stride + (i / inner) * outer + i % inner + off]:
+// gathers one parameter tensor out of interleaved per-chunk partials.  Few chunks: one thread
+// per output sums them in chunk order.  Many chunks: one block per output, thread t sums
+// chunks t, t + 256, ... in order and a fixed tree combines the threads.  Either way the
+// result depends only on the shapes, never on timing.
 __global__ void k_reduce_chunks(const float* __restrict__ part, int n_chunks, size_t stride,
                                 size_t n, int inner, int outer, int off, float* __restrict__ out) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -240,8 +245,35 @@ __global__ void k_reduce_chunks(const float* __restrict__ part, int n_chunks, si
     }
 }
 
+__global__ __launch_bounds__(256) void k_reduce_chunks_tree(const float* __restrict__ part,
+                                                            int n_chunks, size_t stride, size_t n,
+                                                            int inner, int outer, int off,
+                                                            float* __restrict__ out) {
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    for (size_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const size_t src = (i / inner) * outer + i % inner + off;
+        float s = 0.f;
+        for (int c = tid; c < n_chunks; c += 256) s += part[(size_t)c * stride + src];
+        red[tid] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) out[i] = red[0];
+        __syncthreads();
+    }
+}
+
 void launch_reduce_chunks(const float* part, int n_chunks, size_t stride, size_t n, int inner,
                           int outer, int off, float* out, hipStream_t st) {
+    if (n_chunks > 32) {
+        const unsigned b = (unsigned)std::min<size_t>(n, 65536);
+        hipLaunchKernelGGL(k_reduce_chunks_tree, dim3(b > 0 ? b : 1), dim3(256), 0, st, part,
+                           n_chunks, stride, n, inner, outer, off, out);
+        return;
+    }
     int b = (int)((n + 255) / 256);
     if (b > 4096) b = 4096;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(b > 0 ? b : 1), dim3(256), 0, st, part, n_chunks,
@@ -431,67 +463,75 @@ void launch_stem_wgrad(const float* x, int N, int H, int W, int C, const uint16_
                        x, N, H, W, C, dz, chunk, part);
 }
 
-// Depthwise 7x7: y = dw(x) + b (bf16 in/out, fp32 weights).
-__global__ void k_dw_fwd(const uint16_t* __restrict__ x, int N, int H, int W, int C,
-                         const float* __restrict__ w, const float* __restrict__ b,
-                         uint16_t* __restrict__ y) {
-    const size_t n = (size_t)N * H * W * C;
+// Tap-major copy of depthwise weights: wt[tap][c] = w[c][tap].
+__global__ void k_dw_wt(const float* __restrict__ w, int C, float* __restrict__ wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 49 * C) wt[i] = w[(i % C) * 49 + i / C];
+}
+
+void launch_dw_wt(const float* w, int C, float* wt, hipStream_t st) {
+    hipLaunchKernelGGL(k_dw_wt, dim3((49 * C + 255) / 256), dim3(256), 0, st, w, C, wt);
+}
+
+// Depthwise 7x7 (C % 8 == 0): one thread per (pixel, 8 channels), 16-byte activation loads and
+// 32-byte weight loads per tap.  FLIP = 0: y = dw(x) + b.  FLIP = 1: data gradient,
+// dx[p] = sum over taps of dy[p - shift] w[tap] (no bias).
+template <int FLIP>
+__global__ void k_dw8(const uint16_t* __restrict__ x, int N, int H, int W, int C,
+                      const float* __restrict__ wt, const float* __restrict__ b,
+                      uint16_t* __restrict__ y) {
+    const int G = C / 8;
+    const size_t n = (size_t)N * H * W * G;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const size_t pix = i / C;
+        const int c0 = (int)(i % G) * 8;
+        const size_t pix = i / G;
         const int xx = (int)(pix % W), yy = (int)((pix / W) % H), bn = (int)(pix / ((size_t)W * H));
-        float s = b[c];
+        float acc[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) acc[k] = (!FLIP && b) ? b[c0 + k] : 0.f;
         for (int a = 0; a < 7; a++) {
-            const int yi = yy + a - 3;
+            const int yi = FLIP ? yy - a + 3 : yy + a - 3;
             if (yi < 0 || yi >= H) continue;
             for (int q = 0; q < 7; q++) {
-                const int xi = xx + q - 3;
+                const int xi = FLIP ? xx - q + 3 : xx + q - 3;
                 if (xi < 0 || xi >= W) continue;
-                s += bf2f(x[((size_t)(bn * H + yi) * W + xi) * C + c]) * w[c * 49 + a * 7 + q];
+                const uint4 v = *(const uint4*)(x + ((size_t)(bn * H + yi) * W + xi) * C + c0);
+                const float4 w0 = *(const float4*)(wt + (a * 7 + q) * C + c0);
+                const float4 w1 = *(const float4*)(wt + (a * 7 + q) * C + c0 + 4);
+                const uint16_t* h = (const uint16_t*)&v;
+                acc[0] += bf2f(h[0]) * w0.x;
+                acc[1] += bf2f(h[1]) * w0.y;
+                acc[2] += bf2f(h[2]) * w0.z;
+                acc[3] += bf2f(h[3]) * w0.w;
+                acc[4] += bf2f(h[4]) * w1.x;
+                acc[5] += bf2f(h[5]) * w1.y;
+                acc[6] += bf2f(h[6]) * w1.z;
+                acc[7] += bf2f(h[7]) * w1.w;
             }
         }
-        y[i] = f2bf(s);
+        uint4 o;
+        uint16_t* oh = (uint16_t*)&o;
+#pragma unroll
+        for (int k = 0; k < 8; k++) oh[k] = f2bf(acc[k]);
+        *(uint4*)(y + pix * C + c0) = o;
     }
 }
 
-void launch_dw_fwd(const uint16_t* x, int N, int H, int W, int C, const float* w, const float* b,
+void launch_dw_fwd(const uint16_t* x, int N, int H, int W, int C, const float* wt, const float* b,
                    uint16_t* y, hipStream_t st) {
-    const size_t n = (size_t)N * H * W * C;
+    const size_t n = (size_t)N * H * W * (C / 8);
     int bl = (int)((n + 255) / 256);
-    if (bl > 8192) bl = 8192;
-    hipLaunchKernelGGL(k_dw_fwd, dim3(bl), dim3(256), 0, st, x, N, H, W, C, w, b, y);
+    if (bl > 16384) bl = 16384;
+    hipLaunchKernelGGL(k_dw8<0>, dim3(bl), dim3(256), 0, st, x, N, H, W, C, wt, b, y);
 }
 
-// Depthwise data gradient: dx[p] = sum_taps dy[p - shift] w[tap] (correlation, flipped).
-__global__ void k_dw_dgrad(const uint16_t* __restrict__ dy, int N, int H, int W, int C,
-                           const float* __restrict__ w, uint16_t* __restrict__ dx) {
-    const size_t n = (size_t)N * H * W * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const size_t pix = i / C;
-        const int xx = (int)(pix % W), yy = (int)((pix / W) % H), bn = (int)(pix / ((size_t)W * H));
-        float s = 0.f;
-        for (int a = 0; a < 7; a++) {
-            const int yo = yy - a + 3;
-            if (yo < 0 || yo >= H) continue;
-            for (int q = 0; q < 7; q++) {
-                const int xo = xx - q + 3;
-                if (xo < 0 || xo >= W) continue;
-                s += bf2f(dy[((size_t)(bn * H + yo) * W + xo) * C + c]) * w[c * 49 + a * 7 + q];
-            }
-        }
-        dx[i] = f2bf(s);
-    }
-}
-
-void launch_dw_dgrad(const uint16_t* dy, int N, int H, int W, int C, const float* w, uint16_t* dx,
+void launch_dw_dgrad(const uint16_t* dy, int N, int H, int W, int C, const float* wt, uint16_t* dx,
                      hipStream_t st) {
-    const size_t n = (size_t)N * H * W * C;
+    const size_t n = (size_t)N * H * W * (C / 8);
     int bl = (int)((n + 255) / 256);
-    if (bl > 8192) bl = 8192;
-    hipLaunchKernelGGL(k_dw_dgrad, dim3(bl), dim3(256), 0, st, dy, N, H, W, C, w, dx);
+    if (bl > 16384) bl = 16384;
+    hipLaunchKernelGGL(k_dw8<1>, dim3(bl), dim3(256), 0, st, dy, N, H, W, C, wt, nullptr, dx);
 }
 
 // Depthwise weight/bias gradient partials: block (row chunk, channel group of 64); each thread
@@ -778,17 +818,25 @@ void launch_loss(const LossArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a);
 }
 
-// Sums the loss partials in block order: sums[0..5].
-__global__ void k_loss_sum(const float* __restrict__ partial, int nb, double* __restrict__ sums) {
-    const int k = threadIdx.x;
-    if (k >= 6) return;
+// Sums the loss partials: block k sums component k, thread t over partials t, t + 256, ...,
+// then a fixed tree (deterministic).
+__global__ __launch_bounds__(256) void k_loss_sum(const float* __restrict__ partial, int nb,
+                                                  double* __restrict__ sums) {
+    __shared__ double red[256];
+    const int k = blockIdx.x, tid = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nb; b++) s += partial[b * 6 + k];
-    sums[k] = s;
+    for (int b = tid; b < nb; b += 256) s += partial[b * 6 + k];
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) sums[k] = red[0];
 }
 
 void launch_loss_sum(const float* partial, int nb, double* sums, hipStream_t st) {
-    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, partial, nb, sums);
+    hipLaunchKernelGGL(k_loss_sum, dim3(6), dim3(256), 0, st, partial, nb, sums);
 }
 
 // Final per-pixel gradients with the normalisations and lambdas of Eq. (21); converts the

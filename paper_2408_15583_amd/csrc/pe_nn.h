@@ -64,9 +64,11 @@ void launch_stem_fwd(const float* x, int N, int H, int W, int C, const float* w,
                      uint16_t* z, uint16_t* a, hipStream_t st);
 void launch_stem_wgrad(const float* x, int N, int H, int W, int C, const uint16_t* dz, int chunk,
                        float* part, hipStream_t st);
-void launch_dw_fwd(const uint16_t* x, int N, int H, int W, int C, const float* w, const float* b,
+// Depthwise 7x7 over 8-channel groups (C % 8 == 0) with tap-major weights wt[49][C].
+void launch_dw_wt(const float* w, int C, float* wt, hipStream_t st);
+void launch_dw_fwd(const uint16_t* x, int N, int H, int W, int C, const float* wt, const float* b,
                    uint16_t* y, hipStream_t st);
-void launch_dw_dgrad(const uint16_t* dy, int N, int H, int W, int C, const float* w, uint16_t* dx,
+void launch_dw_dgrad(const uint16_t* dy, int N, int H, int W, int C, const float* wt, uint16_t* dx,
                      hipStream_t st);
 void launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, int N, int H, int W, int C, int rows,
                      float* part, hipStream_t st);
