@@ -130,6 +130,74 @@ def plate(seed: int = 1, n_side: int = 100, size: float = 0.3, jitter: float = 0
                  material=np.zeros(n, np.uint8), name="plate", meta=d.meta)
 
 
+def _jittered_plate(rng, u_rng, v_rng, n_u, n_v, jitter):
+    """Cell-centred jittered grid over [u0,u1] x [v0,v1]; returns (u, v) arrays and spacing."""
+    su = (u_rng[1] - u_rng[0]) / n_u
+    sv = (v_rng[1] - v_rng[0]) / n_v
+    u, v = np.meshgrid(u_rng[0] + (np.arange(n_u) + 0.5) * su,
+                       v_rng[0] + (np.arange(n_v) + 0.5) * sv, indexing="ij")
+    u = u.ravel() + rng.uniform(-jitter * su, jitter * su, u.size)
+    v = v.ravel() + rng.uniform(-jitter * sv, jitter * sv, v.size)
+    return u, v, max(su, sv)
+
+
+def trihedral(seed: int = 6, n_side: int = 100, size: float = 0.3, jitter: float = 0.2,
+              radius_factor: float = 1.5) -> Scene:
+    """Square trihedral corner in the first octant: plates on z=0, y=0 and x=0 (normals +z, +y,
+    +x), each size x size, sampled like the dihedral's plates."""
+    rng = _rng(seed)
+    parts, nrms = [], []
+    for axis in (2, 1, 0):
+        u, v, s = _jittered_plate(rng, (0.0, size), (0.0, size), n_side, n_side, jitter)
+        p = np.zeros((u.size, 3))
+        others = [a for a in range(3) if a != axis]
+        p[:, others[0]] = u
+        p[:, others[1]] = v
+        nn = np.zeros((u.size, 3))
+        nn[:, axis] = 1.0
+        parts.append(p)
+        nrms.append(nn)
+    xyz = np.concatenate(parts)
+    return Scene(xyz=xyz, nrm=np.concatenate(nrms), radius=radius_factor * size / n_side,
+                 material=np.zeros(len(xyz), np.uint8), name="trihedral",
+                 meta=dict(size=size, spacing=size / n_side))
+
+
+def octar(seed: int = 7, half: float = 1.0, spacing: float = 0.01, jitter: float = 0.2,
+          radius_factor: float = 1.5) -> Scene:
+    """Three mutually orthogonal square plates through the origin, each spanning
+    [-half, half]^2: eight square trihedral corners of edge `half` (a synthetic stand-in for the
+    OctAR target).  Two-sided disks on a jittered grid of the given spacing."""
+    rng = _rng(seed)
+    n = int(round(2 * half / spacing))
+    parts, nrms = [], []
+    for axis in (2, 1, 0):
+        u, v, s = _jittered_plate(rng, (-half, half), (-half, half), n, n, jitter)
+        p = np.zeros((u.size, 3))
+        others = [a for a in range(3) if a != axis]
+        p[:, others[0]] = u
+        p[:, others[1]] = v
+        nn = np.zeros((u.size, 3))
+        nn[:, axis] = 1.0
+        parts.append(p)
+        nrms.append(nn)
+    xyz = np.concatenate(parts)
+    return Scene(xyz=xyz, nrm=np.concatenate(nrms), radius=radius_factor * spacing,
+                 material=np.zeros(len(xyz), np.uint8), name="octar",
+                 meta=dict(half=half, spacing=spacing))
+
+
+def octar_views() -> np.ndarray:
+    """The eight sensor positions of the OctAR experiment (theta in {60, 120} deg, phi in
+    {45, 135, 225, 315} deg) as propagation directions (sensor toward the target)."""
+    out = []
+    for th in (60.0, 120.0):
+        for ph in (45.0, 135.0, 225.0, 315.0):
+            t, p = math.radians(th), math.radians(ph)
+            out.append([-math.sin(t) * math.cos(p), -math.sin(t) * math.sin(p), -math.cos(t)])
+    return np.array(out)
+
+
 # ---------------------------------------------------------------------------------------------
 # Analytic primitives for the composite scene.
 # ---------------------------------------------------------------------------------------------

@@ -345,3 +345,35 @@ def test_invalid_scene_rejected():
         _one([0, 0, 0], [0, 0, 0], 1.0)
     with pytest.raises(ValueError):
         _one([0, 0, 0], [0, 0, 1], 1.0, np.array([7], np.uint8))
+
+
+def test_trihedral_triple_bounce_peak():
+    """Square trihedral of edge a viewed along its symmetry axis: the rays entering the
+    hexagonal region of projected area sqrt(3) a^2 bounce three times and leave antiparallel,
+    all with the same image-method path, so sigma = 4 pi (sqrt(3) a^2)^2 / lambda^2 =
+    12 pi a^4 / lambda^2 (25.31 dBsm for a = 0.3 m at 10 GHz).  With the aperture measured as
+    n_triple * pitch^2 the facet sum matches to 0.1 dB (single and double bounces leave in other
+    directions); the measured aperture is the hexagon to within the splats' overhang."""
+    sc = scenes.trihedral()
+    o = oracle.OracleScene(sc, grid=64)
+    f = 10e9
+    lam = C0 / f
+    W = 192
+    _, R = o.frame()
+    pitch = 2 * R / W
+    k = -np.ones(3) / math.sqrt(3.0)        # arriving from (1, 1, 1)
+    eps = 0.5 * sc.radius
+    E, _ = o.solve(k[None], [f], W, W, 3, eps)
+    nb, _, _ = o.trace_pixels(k, W, W, np.arange(W * W), 3, eps)
+    A = (nb == 3).sum() * pitch ** 2
+    expect = 10 * math.log10(4 * math.pi * A ** 2 / lam ** 2)
+    got = oracle.rcs_dbsm(E)[0, 0, 0]
+    assert abs(got[0, 0] - expect) < 0.1
+    assert abs(got[1, 1] - expect) < 0.1
+    nominal = 10 * math.log10(12 * math.pi * 0.3 ** 4 / lam ** 2)
+    assert abs(nominal - 25.3117) < 1e-3
+    assert abs(A / (math.sqrt(3.0) * 0.3 ** 2) - 1.0) < 0.05
+    assert abs(got[0, 0] - nominal) < 0.5
+    # with two bounces at most there is no retro-reflection along the axis
+    E2, _ = o.solve(k[None], [f], W, W, 2, eps)
+    assert oracle.rcs_dbsm(E2)[0, 0, 0, 0, 0] < expect - 10
