@@ -59,6 +59,8 @@ def _load():
     lib.or_solve.argtypes = [ctypes.c_void_p, ctypes.c_int, _d, ctypes.c_int, _d, ctypes.c_int,
                              _d, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                              ctypes.c_int, ctypes.c_int, ctypes.c_int, _d, _d]
+    lib.or_render_tube_topk.argtypes = [ctypes.c_void_p, _d, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_int, _d, _i64]
     lib.or_scene_set_views.argtypes = [ctypes.c_void_p, ctypes.c_int, _d, ctypes.c_int,
                                        ctypes.c_int]
     lib.or_first_hit_views.restype = ctypes.c_int64
@@ -174,6 +176,13 @@ class OracleScene:
         if r < 0:
             raise ValueError("set_views first")
         return bool(r)
+
+    def render_tube_topk(self, k, W, H, delta, K):
+        """Algorithm 1 with a K-point heap: Euclidean depth |p - o| of the chosen point."""
+        depth = np.zeros(W * H); idx = np.zeros(W * H, np.int64)
+        _load().or_render_tube_topk(self._h, _p(_f64(k)), W, H, float(delta), int(K), _p(depth),
+                                    _p(idx, _i64))
+        return depth.reshape(H, W), idx.reshape(H, W)
 
     def trace_pixels(self, k, W, H, pix, max_bounces, eps, grid=None, restricted=False):
         """Per pixel: number of bounces M and the per-bounce records (see oracle.c)."""

@@ -521,6 +521,52 @@ void or_render_tube(const void* p, const double* kin, int W, int H, double delta
     }
 }
 
+/* Algorithm 1 with a bounded heap (Sec. III-A): the candidates of a tube are the points within
+ * delta of its central ray and in front of the screen; the K candidates nearest the ray are
+ * kept (ties: smallest index), and of those the one nearest the tube origin o is chosen (ties:
+ * smallest index); the coarse depth is its Euclidean distance |p - o|.  Brute force. */
+void or_render_tube_topk(const void* p, const double* kin, int W, int H, double delta, int K,
+                         double* depth, int64_t* idx) {
+    const or_scene* s = (const or_scene*)p;
+    double o00[3], du[3], dv[3];
+    or_screen(p, kin, W, H, o00, du, dv);
+    v3 k = unit(ld(kin));
+    double d2 = delta * delta;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < H; j++) {
+        double* hd = (double*)malloc(sizeof(double) * (K + 1));
+        int64_t* hi = (int64_t*)malloc(sizeof(int64_t) * (K + 1));
+        for (int i = 0; i < W; i++) {
+            v3 o = add(ld(o00), add(scl(ld(du), i), scl(ld(dv), j)));
+            int n = 0;  /* kept candidates, ascending by (axis distance^2, index) */
+            for (int64_t m = 0; m < s->n; m++) {
+                v3 w = sub(ld(s->xyz + 3 * m), o);
+                double tc = dot(w, k);
+                if (!(tc > 0)) continue;
+                v3 c = cross(w, k);
+                double a2 = dot(c, c);
+                if (!(a2 < d2)) continue;
+                if (n == K && !(a2 < hd[n - 1])) continue; /* m > kept indices on equal a2 */
+                int q = n < K ? n++ : K - 1;
+                while (q > 0 && hd[q - 1] > a2) { hd[q] = hd[q - 1]; hi[q] = hi[q - 1]; q--; }
+                hd[q] = a2;
+                hi[q] = m;
+            }
+            double bd = INFINITY;
+            int64_t best = -1;
+            for (int q = 0; q < n; q++) {
+                double dist = len(sub(ld(s->xyz + 3 * hi[q]), o));
+                if (dist < bd || (dist == bd && hi[q] < best)) { bd = dist; best = hi[q]; }
+            }
+            int64_t qq = (int64_t)j * W + i;
+            depth[qq] = bd;
+            idx[qq] = best;
+        }
+        free(hd);
+        free(hi);
+    }
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Bounce recursion for one central ray (c.6).                                                  */
 /* Record per bounce b (22 doubles): x(3) hit point, n(3) oriented normal, kin(3) incoming     */

@@ -377,3 +377,39 @@ def test_trihedral_triple_bounce_peak():
     # with two bounces at most there is no retro-reflection along the axis
     E2, _ = o.solve(k[None], [f], W, W, 2, eps)
     assert oracle.rcs_dbsm(E2)[0, 0, 0, 0, 0] < expect - 10
+
+
+def test_tube_topk_brute_force_tiny_clouds():
+    """Algorithm 1 with a K-point heap, checked against an independent all-points loop: keep the
+    K candidates (axis distance < delta, in front of the screen) nearest the central ray, pick
+    the one nearest the tube origin, depth = |p - o|.  K = 1 is the point nearest the axis; a
+    K above the candidate count is the nearest candidate to the origin; the depth always lies
+    between the along-ray distance and sqrt(t^2 + delta^2)."""
+    rng = np.random.default_rng(5)
+    for seed in range(3):
+        sc = scenes.random_disks(seed=200 + seed, n=60, r_lo=0.02, r_hi=0.05)
+        o = oracle.OracleScene(sc)
+        W = H = 12
+        for K in (1, 2, 3, 100):
+            k = rng.normal(size=3)
+            k /= np.linalg.norm(k)
+            delta = 0.15
+            dep, idx = o.render_tube_topk(k, W, H, delta, K)
+            o00, du, dv = o.screen(k, W, H)
+            for j in range(H):
+                for i in range(W):
+                    org = o00 + i * du + j * dv
+                    w = o.xyz - org
+                    tc = w @ k
+                    a2 = np.sum(np.cross(w, k) ** 2, axis=1)
+                    cand = np.where((tc > 0) & (a2 < delta ** 2))[0]
+                    if cand.size == 0:
+                        assert idx[j, i] == -1 and np.isinf(dep[j, i])
+                        continue
+                    kept = sorted(cand, key=lambda m: (a2[m], m))[:K]
+                    dist = np.linalg.norm(w[kept], axis=1)
+                    best = min(zip(dist, kept))
+                    assert idx[j, i] == best[1]
+                    assert abs(dep[j, i] - best[0]) < 1e-12
+                    m = best[1]
+                    assert tc[m] - 1e-12 <= dep[j, i] <= math.sqrt(tc[m] ** 2 + delta ** 2) + 1e-12
