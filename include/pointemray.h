@@ -197,6 +197,16 @@ pe_status pe_render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t
                         int32_t mode, double tube_radius, float* depth, float* nrm,
                         uint32_t* idx, uint8_t* mask, void* hip_stream);
 
+/* Coarse buffer of Algorithm 1 with a K-point heap (Sec. III-A): for each pixel's ray tube of
+ * radius tube_radius (m), the K points nearest the central ray (in front of the screen; ties:
+ * lowest index) are kept and the one nearest the tube origin is chosen (ties: lowest index).
+ * Outputs as pe_render_gfb, with depth = Euclidean distance |p - o| from the pixel centre on the
+ * screen.  K in 1..1024 (PE_EINVAL otherwise); K at least the candidate count of every tube
+ * selects the nearest candidate to the origin. */
+pe_status pe_render_tube_topk(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w,
+                              int32_t h, double tube_radius, int32_t K, float* depth, float* nrm,
+                              uint32_t* idx, uint8_t* mask, void* hip_stream);
+
 /* Per-pixel bounce records of one incidence (what the PO sum consumes), device outputs,
  * row-major h x w: n_bounce (0 = no hit), last_x (x3, scene frame: add the centre for world),
  * last_n (x3, oriented), path (image-method path length to last_x in the scene frame), last_idx

@@ -15,7 +15,7 @@ from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM
                       PE_PREC_FP64PHASE, PE_SPLAT_DISK, PE_SPLAT_TUBE, PEError, check, lib)
 
 __all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "submit", "server_stats",
-           "render_gfb", "trace_pixels", "make_pair",
+           "render_gfb", "render_tube_topk", "trace_pixels", "make_pair",
            "PEError", "lib", "check"]
 
 
@@ -237,6 +237,22 @@ def render_gfb(ctx: Context, scene: Scene, direction, w, h, mode="disk", tube_ra
                               PE_SPLAT_TUBE if mode == "tube" else PE_SPLAT_DISK,
                               float(tube_radius), _dptr(depth), _dptr(nrm), _dptr(idx),
                               _dptr(mask), s))
+    return dict(depth=depth, nrm=nrm, idx=idx, mask=mask)
+
+
+def render_tube_topk(ctx: Context, scene: Scene, direction, w, h, tube_radius, K, stream=None):
+    """Coarse buffer of Algorithm 1 with a K-point heap (torch CUDA tensors depth, nrm, idx,
+    mask); depth is the Euclidean distance from the pixel centre."""
+    torch = _torch()
+    dev = torch.device("cuda")
+    depth = torch.empty((h, w), dtype=torch.float32, device=dev)
+    nrm = torch.empty((h, w, 3), dtype=torch.float32, device=dev)
+    idx = torch.empty((h, w), dtype=torch.int32, device=dev)
+    mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    dr = (ctypes.c_double * 3)(*[float(x) for x in direction])
+    s = current_stream() if stream is None else stream
+    check(lib().pe_render_tube_topk(ctx.h, scene.h, dr, w, h, float(tube_radius), int(K),
+                                    _dptr(depth), _dptr(nrm), _dptr(idx), _dptr(mask), s))
     return dict(depth=depth, nrm=nrm, idx=idx, mask=mask)
 
 

@@ -95,6 +95,9 @@ _SIGS = {
     "pe_render_gfb": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "pe_render_tube_topk": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "pe_trace_pixels": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],

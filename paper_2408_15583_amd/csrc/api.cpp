@@ -434,9 +434,37 @@ pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_res
     API_END
 }
 
+}  // extern "C"
+
+namespace pe {
+static pe_status render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w, int32_t h,
+                           int32_t mode, double tube_radius, int32_t topk, float* depth,
+                           float* nrm, uint32_t* idx, uint8_t* mask, void* hip_stream);
+}  // namespace pe
+
+extern "C" {
+
 pe_status pe_render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w, int32_t h,
                         int32_t mode, double tube_radius, float* depth, float* nrm,
                         uint32_t* idx, uint8_t* mask, void* hip_stream) {
+    return render_gfb(ctx, scene, dir, w, h, mode, tube_radius, 0, depth, nrm, idx, mask,
+                      hip_stream);
+}
+
+pe_status pe_render_tube_topk(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w,
+                              int32_t h, double tube_radius, int32_t K, float* depth, float* nrm,
+                              uint32_t* idx, uint8_t* mask, void* hip_stream) {
+    if (K < 1 || K > 1024) return set_error(PE_EINVAL, "K must be 1..1024");
+    return render_gfb(ctx, scene, dir, w, h, PE_SPLAT_TUBE, tube_radius, K, depth, nrm, idx, mask,
+                      hip_stream);
+}
+
+}  // extern "C"
+
+namespace pe {
+static pe_status render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t w, int32_t h,
+                           int32_t mode, double tube_radius, int32_t topk, float* depth,
+                           float* nrm, uint32_t* idx, uint8_t* mask, void* hip_stream) {
     API_BEGIN
     if (!ctx || !scene || !dir) return set_error(PE_EINVAL, "null argument");
     if (!finite3(dir)) return set_error(PE_EINVAL, "non-finite or zero direction");
@@ -455,6 +483,7 @@ pe_status pe_render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t
     s[0].mode = mode;
     s[0].tube_r = tube_radius;
     Batch b(*ctx->ws, st);
+    b.topk = topk;
     b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
     uint32_t c[kNumCounters];
     for (int attempt = 0;; attempt++) {
@@ -470,6 +499,9 @@ pe_status pe_render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int32_t
     return PE_OK;
     API_END
 }
+}  // namespace pe
+
+extern "C" {
 
 pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], int32_t w,
                           int32_t h, int32_t max_bounces, double eps, int32_t* n_bounce,

@@ -12,6 +12,7 @@
 #include <limits.h>
 
 #include "pe_device.h"
+#include "pe_gfb.h"
 
 namespace pe {
 
@@ -388,6 +389,93 @@ void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t
                    uint64_t* keys, hipStream_t st) {
     hipLaunchKernelGGL(k_raster, dim3(max_tiles, n_slots), dim3(256), 0, st, d, tile_off,
                        tile_count, list, capacity, keys);
+}
+
+// Algorithm 1 with a K-point heap (TUBE slots): per pixel, the K candidates nearest the central
+// ray (keys axis distance^2 | index) are found in K rounds of an LDS atomic minimum, each round
+// taking the smallest key above the previous round's; the pixel's own thread keeps, among
+// them, the point nearest the tube origin (|p - o|^2 = axis^2 + t_c^2; ties: lowest index) and
+// writes the key (|p - o| | index).  Rounds stop early once no pixel of the tile has more.
+__global__ __launch_bounds__(256) void k_raster_topk(const SlotDesc* __restrict__ ds,
+                                                     const uint32_t* __restrict__ tile_off,
+                                                     const uint32_t* __restrict__ tile_count,
+                                                     const uint32_t* __restrict__ list,
+                                                     uint32_t capacity, int K,
+                                                     uint64_t* __restrict__ keys) {
+    const SlotDesc& d = ds[blockIdx.y];
+    const int tile = blockIdx.x;
+    if (tile >= d.tiles_x * d.tiles_y) return;
+    __shared__ unsigned long long cur[kTile * kTile];
+    __shared__ unsigned long long thr[kTile * kTile];
+    const Screen s = screen_of(d);
+    const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
+    const int px0 = tx * kTile, py0 = ty * kTile;
+    const int px1 = min(px0 + kTile, s.W) - 1, py1 = min(py0 + kTile, s.H) - 1;
+    const uint32_t beg = tile_off[d.tile_base + tile];
+    const uint32_t cnt = tile_count[d.tile_base + tile];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float zoff = s.R, d2 = s.tube_r * s.tube_r;
+    thr[threadIdx.x] = 0ull;
+    float best_d = FLT_MAX;
+    uint32_t best_i = kNone;
+    for (int round = 0; round < K; round++) {
+        cur[threadIdx.x] = kEmptyKey;
+        __syncthreads();
+        for (uint32_t e = wave; e < cnt; e += 4) {
+            if (beg + e >= capacity) break;
+            const uint32_t chunk = list[beg + e];
+            const uint32_t i = chunk * kChunk + lane;
+            if (i >= d.n_pts) continue;
+            const float4 a = d.pa_s[i], b = d.pb_s[i];
+            const Proj p = project(s, a, b);
+            if (!(p.xk + zoff > 0.f)) continue;
+            int x0, y0, x1, y1;
+            footprint(s, p, x0, y0, x1, y1);
+            x0 = max(x0, px0); x1 = min(x1, px1); y0 = max(y0, py0); y1 = min(y1, py1);
+            const uint64_t idx = __float_as_uint(b.w);
+            for (int y = y0; y <= y1; y++) {
+                const float dv = (y + 0.5f - s.hh) * s.pitch - p.xb;
+                for (int x = x0; x <= x1; x++) {
+                    const float du = (x + 0.5f - s.hw) * s.pitch - p.xa;
+                    const float a2 = du * du + dv * dv;
+                    if (a2 < d2) {
+                        const int q = (y - py0) * kTile + (x - px0);
+                        const uint64_t key = ((uint64_t)__float_as_uint(a2) << 32) | idx;
+                        if (key >= thr[q]) atomicMin(&cur[q], (unsigned long long)key);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const uint64_t c = cur[threadIdx.x];
+        if (c != kEmptyKey) {
+            const uint32_t i = (uint32_t)(c & 0xFFFFFFFFu);
+            const float a2 = __uint_as_float((uint32_t)(c >> 32));
+            const float4 a = d.pa[i];
+            const float tc = a.x * s.k0 + a.y * s.k1 + a.z * s.k2 + zoff;
+            const float dist = sqrtf(a2 + tc * tc);
+            if (dist < best_d || (dist == best_d && i < best_i)) {
+                best_d = dist;
+                best_i = i;
+            }
+            thr[threadIdx.x] = c + 1;
+        } else {
+            thr[threadIdx.x] = kEmptyKey;
+        }
+        if (!__syncthreads_or(c != kEmptyKey)) break;
+    }
+    const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
+    const int x = px0 + lx, y = py0 + ly;
+    if (x < s.W && y < s.H)
+        keys[d.pix_base + (uint64_t)y * s.W + x] =
+            best_i == kNone ? kEmptyKey : (((uint64_t)__float_as_uint(best_d) << 32) | best_i);
+}
+
+void launch_raster_topk(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
+                        const uint32_t* tile_count, const uint32_t* list, uint32_t capacity, int K,
+                        uint64_t* keys, hipStream_t st) {
+    hipLaunchKernelGGL(k_raster_topk, dim3(max_tiles, n_slots), dim3(256), 0, st, d, tile_off,
+                       tile_count, list, capacity, K, keys);
 }
 
 // Geometric frame buffer of slot 0: depth, oriented normal, index, mask.

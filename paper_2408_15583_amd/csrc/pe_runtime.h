@@ -76,6 +76,7 @@ struct Batch {
     double* dfreq = nullptr;
     uint32_t* cnt = nullptr;
     int n = 0, contrib = 0, precision = 0, n_seg = 1, ft = 1, max_b = 1;
+    int topk = 0;  // > 0: TUBE slots keep a K-point heap (Algorithm 1) instead of K unbounded
     int max_chunks = 0, max_tiles = 0, max_pix = 0, max_obs = 1, max_freq = 1, tot_out = 0;
     uint64_t tot_pix = 0;
     uint32_t tot_tiles = 0, tot_chunks = 0, tlist_cap = 0, rec_stride = 0;

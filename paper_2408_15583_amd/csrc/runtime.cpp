@@ -305,7 +305,10 @@ void Batch::splat() {
                         cnt + C_OVERFLOW, st);
     prof_end("tile_scatter");
     prof_begin();
-    launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, st);
+    if (topk > 0)
+        launch_raster_topk(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, topk, keys, st);
+    else
+        launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, st);
     prof_end("raster");
     HIPCHK(hipGetLastError());
 }
