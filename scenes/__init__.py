@@ -164,10 +164,11 @@ def trihedral(seed: int = 6, n_side: int = 100, size: float = 0.3, jitter: float
 
 
 def octar(seed: int = 7, half: float = 1.0, spacing: float = 0.01, jitter: float = 0.2,
-          radius_factor: float = 1.5) -> Scene:
+          radius_factor: float = 1.5, noise_sigma: float = 0.0) -> Scene:
     """Three mutually orthogonal square plates through the origin, each spanning
     [-half, half]^2: eight square trihedral corners of edge `half` (a synthetic stand-in for the
-    OctAR target).  Two-sided disks on a jittered grid of the given spacing."""
+    OctAR target).  Two-sided disks on a jittered grid of the given spacing; optional Gaussian
+    position noise (exact normals kept)."""
     rng = _rng(seed)
     n = int(round(2 * half / spacing))
     parts, nrms = [], []
@@ -182,8 +183,10 @@ def octar(seed: int = 7, half: float = 1.0, spacing: float = 0.01, jitter: float
         parts.append(p)
         nrms.append(nn)
     xyz = np.concatenate(parts)
+    if noise_sigma > 0:
+        xyz = xyz + rng.normal(0.0, noise_sigma, xyz.shape)
     return Scene(xyz=xyz, nrm=np.concatenate(nrms), radius=radius_factor * spacing,
-                 material=np.zeros(len(xyz), np.uint8), name="octar",
+                 material=np.zeros(len(xyz), np.uint8), name="octar", noise_sigma=noise_sigma,
                  meta=dict(half=half, spacing=spacing))
 
 

@@ -88,3 +88,39 @@ def test_octar_sweep(pe, ctx):
         assert agree >= 0.999
     assert e.max() < 0.1
     s.close()
+
+
+def test_octar_bistatic(pe, ctx):
+    """Bistatic observation sets (exit rays x observation directions x frequencies): two
+    incidences, sixteen observation directions around the target, up to three bounces; Psi of
+    each facet toward each observation direction from the aggregation views.  Within 0.1 dB of
+    the restricted oracle wherever it is within 30 dB of the peak over observation directions.
+    The plates carry 0.2 mm of out-of-plane noise, as sampled clouds do: on exactly coplanar
+    overlapping disks the front-most disk a view stores is a tie that fp32 and fp64 break
+    differently, which moves bistatic visibility of a few facets and low-level samples by up to
+    ~0.4 dB (the noise-free monostatic sweep above is unaffected)."""
+    sc = scenes.octar(spacing=0.02, noise_sigma=2e-4)
+    views = scenes.octar_views()
+    s = pe.Scene.from_scene(ctx, sc, view_res=384, view_dirs=views)
+    o = oracle.OracleScene(sc, grid=96)
+    o.set_views(384, views)
+    eps = 0.5 * float(sc.radius)
+    inc = scenes.azimuth_sweep([40.0, 130.0], 30.0)
+    obs = -scenes.azimuth_sweep(np.arange(0.0, 360.0, 22.5), 20.0)  # k_s pointing outward
+    f = [3e9, 5e9]
+    _, r, _ = pe.solve(ctx, s, inc, f, 384, max_bounces=3, eps=eps, obs_dir=obs)
+    Er, _ = o.solve(inc, f, 384, 384, 3, eps, obs_dir=obs, restricted=True)
+    Ee, _ = o.solve(inc, f, 384, 384, 3, eps, obs_dir=obs)
+    rr, re = oracle.rcs_dbsm(Er), oracle.rcs_dbsm(Ee)
+    errs, aggs = [], []
+    for i in range(len(inc)):
+        for p in range(2):
+            a, b, c = r[i, :, :, p, p], rr[i, :, :, p, p], re[i, :, :, p, p]
+            sel = b >= b.max(axis=0, keepdims=True) - 30.0
+            errs.append(np.abs(a - b)[sel])
+            aggs.append(np.abs(b - c)[sel])
+    e, g = np.concatenate(errs), np.concatenate(aggs)
+    print(f"OCTAR bistatic vs restricted oracle: max {e.max():.4f} dB median {np.median(e):.4f};"
+          f" restricted vs exact max {g.max():.4f} dB")
+    assert e.max() < 0.1
+    s.close()
