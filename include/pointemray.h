@@ -268,6 +268,46 @@ pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, cons
                                  float* depth_gt, float* nrm_gt, float* mask_gt,
                                  void* hip_stream);
 
+/* ---- GFB fusion for multi-bounce geometry (Sec. III-B, Algorithm 3, Eq. (22)) ------------- */
+
+/* Geometric frame buffers of n_views screens over one scene frame, in the layout of
+ * pe_densifier_make_pair's targets and pe_densifier_infer's outputs. */
+typedef struct {
+    int32_t n_views;          /* 1 .. 64 */
+    const double* view_dirs;  /* host, n_views x 3 propagation directions of the screens */
+    int32_t w, h;             /* square buffers (w == h, 8 .. 8192); pitch 2R / w */
+    double centre[3];         /* frame of the screens: centre c and radius R (pe_scene_info); */
+    double R;                 /* each screen is 2R wide, centred on c, R before c along k */
+    const float* depth;       /* device n_views x h x w: t / (2R), t from the screen plane */
+    const float* nrm;         /* device n_views x h x w x 3: normals in the view frame (u, v, -k) */
+    const float* hit;         /* device n_views x h x w: a hit where >= 0.5 (mask or probability) */
+} pe_gfb_set;
+
+typedef struct {
+    int32_t grid;             /* cells per axis of the fusion grid, 8 .. 512 (0 = 256) */
+    double grid_side;         /* side of the cubic grid about c (m); 0 = 2R.  The pixel side L
+                                 of Eq. (22) is grid_side / grid. */
+    double edge_lo, edge_hi;  /* Canny thresholds on the depth slope (depth change per pixel
+                                 pitch); 0 = 2 and 4 */
+    int32_t edge_dilate;      /* pixels within this many pixels of an edge are dropped too;
+                                 0 .. 8, negative = 1 */
+} pe_fuse_desc;
+
+/* Edge filtering and fusion: the depth of each buffer (empty pixels at 2R) is smoothed by a
+ * 5 x 5 Gaussian (sigma 1 pixel), its Sobel gradient thinned by non-maximum suppression and
+ * double-thresholded with 8-connected hysteresis; hit pixels away from those edges are placed
+ * in the grid, and every occupied cell becomes one splat: mean position, normalised mean of
+ * the normals (each turned so that its largest component is positive), and the radius of
+ * Eq. (22) for the contributing view that sees the mean normal most squarely.
+ * Outputs (device, splats in cell order, x fastest): xyz (n x 3 doubles, world), nrm (n x 3),
+ * radius (n), count (n pixels fused per splat; may be NULL), edge (n_views x h x w, 1 on Canny
+ * edges; may be NULL).  At most `cap` splats are written; *n_out = number of splats (cap =
+ * n_views * w * h always suffices; cap = 0 only counts).  The splats suit pe_scene_create
+ * with mem_kind PE_MEM_DEVICE, xyz_type PE_F64 and per-point radii. */
+pe_status pe_fuse_gfbs(pe_ctx ctx, const pe_gfb_set* gfbs, const pe_fuse_desc* desc, double* xyz,
+                       float* nrm, float* radius, uint32_t* count, uint8_t* edge, uint64_t cap,
+                       uint64_t* n_out, void* hip_stream);
+
 /* ---- errors ------------------------------------------------------------------------------ */
 
 /* Thread-local description of the last failure on the calling thread (valid until the next

@@ -15,7 +15,7 @@ from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM
                       PE_PREC_FP64PHASE, PE_SPLAT_DISK, PE_SPLAT_TUBE, PEError, check, lib)
 
 __all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "submit", "server_stats",
-           "render_gfb", "render_tube_topk", "trace_pixels", "make_pair",
+           "render_gfb", "render_tube_topk", "trace_pixels", "make_pair", "fuse_gfbs",
            "PEError", "lib", "check"]
 
 
@@ -365,6 +365,42 @@ def make_pair(ctx: Context, scene: Scene, dirs, h, w, tube_px=2.0, stream=None):
                                        int(h), int(w), float(tube_px), _dptr(coarse), _dptr(dg),
                                        _dptr(ng), _dptr(mg), s))
     return coarse, dg, ng, mg
+
+
+def fuse_gfbs(ctx: Context, view_dirs, depth, nrm, hit, centre, R, grid=256, grid_side=0.0,
+              edge_lo=0.0, edge_hi=0.0, edge_dilate=-1, stream=None):
+    """Edge filtering and grid fusion of GFBs into splats (pe_fuse_gfbs).  depth [n,h,w] (t/D),
+    nrm [n,h,w,3] (view frame), hit [n,h,w] float torch CUDA tensors; returns torch CUDA
+    tensors xyz [m,3] f64 (world), nrm [m,3], radius [m], count [m] and edge [n,h,w] u8."""
+    torch = _torch()
+    vd = np.ascontiguousarray(view_dirs, dtype=np.float64).reshape(-1, 3)
+    dev = depth.device
+    depth = depth.to(torch.float32).contiguous()
+    nrm = nrm.to(torch.float32).contiguous()
+    hit = hit.to(torch.float32).contiguous()
+    n, h, w = depth.shape
+    g = _native.pe_gfb_set()
+    g.n_views = n
+    g.view_dirs = vd.ctypes.data_as(_native.c_double_p)
+    g.w, g.h = w, h
+    for k in range(3):
+        g.centre[k] = float(centre[k])
+    g.R = float(R)
+    g.depth, g.nrm, g.hit = depth.data_ptr(), nrm.data_ptr(), hit.data_ptr()
+    f = _native.pe_fuse_desc(int(grid), float(grid_side), float(edge_lo), float(edge_hi),
+                             int(edge_dilate))
+    cap = n * h * w
+    xyz = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+    nr = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+    rad = torch.empty((cap,), dtype=torch.float32, device=dev)
+    cnt = torch.empty((cap,), dtype=torch.int32, device=dev)
+    edge = torch.empty((n, h, w), dtype=torch.uint8, device=dev)
+    m = ctypes.c_uint64()
+    s = current_stream() if stream is None else stream
+    check(lib().pe_fuse_gfbs(ctx.h, ctypes.byref(g), ctypes.byref(f), _dptr(xyz), _dptr(nr),
+                             _dptr(rad), _dptr(cnt), _dptr(edge), cap, ctypes.byref(m), s))
+    k = m.value
+    return dict(xyz=xyz[:k], nrm=nr[:k], radius=rad[:k], count=cnt[:k], edge=edge)
 
 
 class Ticket:

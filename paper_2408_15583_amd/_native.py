@@ -68,6 +68,18 @@ class pe_stats(ctypes.Structure):
                 ("march_rays", ctypes.c_double), ("march_hits", ctypes.c_double)]
 
 
+class pe_gfb_set(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("view_dirs", c_double_p), ("w", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("centre", ctypes.c_double * 3), ("R", ctypes.c_double),
+                ("depth", ctypes.c_void_p), ("nrm", ctypes.c_void_p), ("hit", ctypes.c_void_p)]
+
+
+class pe_fuse_desc(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("grid_side", ctypes.c_double),
+                ("edge_lo", ctypes.c_double), ("edge_hi", ctypes.c_double),
+                ("edge_dilate", ctypes.c_int32)]
+
+
 class pe_result(ctypes.Structure):
     _fields_ = [("E", c_double_p), ("rcs_dbsm", c_double_p),
                 ("stats", ctypes.POINTER(pe_stats))]
@@ -101,6 +113,9 @@ _SIGS = {
     "pe_trace_pixels": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "pe_fuse_gfbs": [pe_ctx, ctypes.POINTER(pe_gfb_set), ctypes.POINTER(pe_fuse_desc),
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_uint64, c_u64_p, ctypes.c_void_p],
     "pe_densifier_create": [pe_ctx, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(pe_densifier)],
     "pe_densifier_destroy": [pe_densifier],
     "pe_densifier_save": [pe_densifier, ctypes.c_char_p],

@@ -201,6 +201,51 @@ def octar_views() -> np.ndarray:
     return np.array(out)
 
 
+def synthetic_gfbs(seed: int, n_views: int, res: int, n_regions: int = 4,
+                   soft_hit: bool = False) -> dict:
+    """GFB-shaped input buffers for the fusion step, with the structure of rendered or predicted
+    frame buffers: each view holds a few elliptical regions (the hit mask) of smooth depth
+    (a tilted ramp plus gentle ripples, t/D in [0.15, 0.85]), regions in front of one another
+    with depth steps between them, and a smooth unit normal field per region facing the screen
+    (third component, along -k, positive).  soft_hit=True gives probabilities in (0, 1) instead
+    of a 0/1 mask.  Returns float32 arrays depth [n,res,res], nrm [n,res,res,3], hit
+    [n,res,res] and float64 view_dirs [n,3] (random unit vectors)."""
+    rng = _rng(seed)
+    yy, xx = np.meshgrid(np.linspace(-1, 1, res), np.linspace(-1, 1, res), indexing="ij")
+    depth = np.zeros((n_views, res, res))
+    nrm = np.zeros((n_views, res, res, 3))
+    hit = np.zeros((n_views, res, res))
+    for v in range(n_views):
+        zbuf = np.full((res, res), np.inf)
+        for _ in range(n_regions):
+            cx, cy = rng.uniform(-0.5, 0.5, 2)
+            a, b = rng.uniform(0.25, 0.6, 2)
+            th = rng.uniform(0, math.pi)
+            xr = (xx - cx) * math.cos(th) + (yy - cy) * math.sin(th)
+            yr = -(xx - cx) * math.sin(th) + (yy - cy) * math.cos(th)
+            inside = (xr / a) ** 2 + (yr / b) ** 2 <= 1.0
+            d0 = rng.uniform(0.3, 0.6)
+            gx, gy = rng.uniform(-0.15, 0.15, 2)
+            amp, fx, fy = rng.uniform(0.0, 0.03), rng.uniform(1, 4), rng.uniform(1, 4)
+            d = d0 + gx * xx + gy * yy + amp * np.sin(fx * xx * math.pi) * np.cos(fy * yy * math.pi)
+            d = np.clip(d, 0.15, 0.85)
+            n0 = rng.normal(0, 0.4, 3)
+            n0[2] = abs(n0[2]) + 0.5
+            nf = np.stack([n0[0] + 0.2 * np.sin(2 * xx + v), n0[1] + 0.2 * np.cos(3 * yy - v),
+                           np.full_like(xx, n0[2])], -1)
+            nf /= np.linalg.norm(nf, axis=-1, keepdims=True)
+            front = inside & (d < zbuf)
+            zbuf[front] = d[front]
+            depth[v][front] = d[front]
+            nrm[v][front] = nf[front]
+            hit[v][front] = 1.0
+        if soft_hit:
+            p = rng.uniform(0.02, 0.45, hit[v].shape)
+            hit[v] = np.where(hit[v] > 0, 1.0 - p, p)
+    return dict(depth=depth.astype(np.float32), nrm=nrm.astype(np.float32),
+                hit=hit.astype(np.float32), view_dirs=random_unit_vectors(rng, n_views))
+
+
 # ---------------------------------------------------------------------------------------------
 # Analytic primitives for the composite scene.
 # ---------------------------------------------------------------------------------------------

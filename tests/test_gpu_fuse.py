@@ -1,0 +1,170 @@
+"""GPU parity of GFB edge filtering and fusion (pe_fuse_gfbs) against oracle/fuse.py, and the
+fused-splat geometry driving a three-bounce OctAR sweep.
+
+Inputs are seeded synthetic GFB stacks (scenes.synthetic_gfbs) shared by both sides.  Bars:
+  - Canny edge maps identical (both sides take every edge decision in fp32 with each
+    operation rounded on its own);
+  - the same occupied cells in the same order with the same pixel counts (cell indices and
+    normal sides are fp32 decisions too);
+  - fused positions within 1e-5 R; normals within 1e-6 / coherence (coherence = |sum of the
+    cell's unit normals| / count: nearly cancelling normals amplify input rounding) and Eq. (22)
+    radii within 1e-6 / (coherence |n.p|) relative (fp32 point/normal arithmetic on the GPU
+    against fp64 values in the oracle).
+Sizes: 3 views of 96^2 on a 64^3 grid (tiles and ragged tails), soft hit probabilities,
+dilation 0..2, a clipped grid, and 8 views of 512^2 on the paper's 256^3 grid.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import fuse as ofuse
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    import paper_2408_15583_amd as pe_mod
+    assert torch.cuda.is_available()
+    return pe_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(pe):
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+def run_both(pe, ctx, g, centre, R, grid, side=0.0, dilate=1, lo=2.0, hi=4.0):
+    import torch
+    dev = torch.device("cuda")
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("depth", "nrm", "hit")}
+    r = pe.fuse_gfbs(ctx, g["view_dirs"], t["depth"], t["nrm"], t["hit"], centre, R, grid=grid,
+                     grid_side=side, edge_lo=lo, edge_hi=hi, edge_dilate=dilate)
+    gpu = {k: v.cpu().numpy() for k, v in r.items()}
+    o = ofuse.fuse(g["view_dirs"], g["depth"], g["nrm"], g["hit"], centre, R, grid=grid, side=side,
+                   lo=lo, hi=hi, dilate=dilate)
+    return gpu, o
+
+
+def check(gpu, o, R, tag):
+    ne = int((gpu["edge"].astype(bool) != o["edge"]).sum())
+    print(f"{tag}: {len(o['xyz'])} splats, {int(o['edge'].sum())} edge pixels, edge mismatches {ne}")
+    assert ne == 0
+    assert len(gpu["xyz"]) == len(o["xyz"])
+    np.testing.assert_array_equal(gpu["count"], o["count"])
+    dx = np.abs(gpu["xyz"] - o["xyz"]).max() / R
+    # normals and radii: 1e-6 scaled by the splat's conditioning (1 / coherence of its unit
+    # normals; the radius moves by half the relative change of |n.p|)
+    en = np.abs(gpu["nrm"] - o["nrm"]).max(axis=1) * o["coherence"]
+    er = np.abs(gpu["radius"] - o["radius"]) / o["radius"] * o["coherence"] * o["best_cos"]
+    print(f"{tag}: max |dx|/R {dx:.2e}, scaled |dn| {en.max():.2e}, scaled radius {er.max():.2e}, "
+          f"raw |dn| {np.abs(gpu['nrm'] - o['nrm']).max():.2e}")
+    assert dx < 1e-5 and en.max() < 1e-6 and er.max() < 1e-6
+
+
+@pytest.mark.parametrize("soft,dilate", [(False, 1), (True, 0), (False, 2)])
+def test_fuse_parity_small(pe, ctx, soft, dilate):
+    g = scenes.synthetic_gfbs(11, 3, 96, soft_hit=soft)
+    centre, R = np.array([0.5, -1.0, 2.0]), 1.3
+    gpu, o = run_both(pe, ctx, g, centre, R, 64, dilate=dilate)
+    check(gpu, o, R, f"96^2 x3 soft={soft} dilate={dilate}")
+
+
+def test_fuse_parity_clipped_grid(pe, ctx):
+    """A grid smaller than the screens: points beyond one cell outside are ignored, those
+    within one cell go to the boundary cells."""
+    g = scenes.synthetic_gfbs(12, 2, 80)
+    gpu, o = run_both(pe, ctx, g, np.zeros(3), 1.0, 40, side=1.1)
+    check(gpu, o, 1.0, "clipped grid")
+
+
+def test_fuse_parity_full_size(pe, ctx):
+    g = scenes.synthetic_gfbs(13, 8, 512, n_regions=6)
+    gpu, o = run_both(pe, ctx, g, np.zeros(3), 10.0, 256)
+    check(gpu, o, 10.0, "512^2 x8, 256^3")
+
+
+def test_fuse_cap_and_count_only(pe, ctx):
+    import torch
+    g = scenes.synthetic_gfbs(14, 2, 64)
+    dev = torch.device("cuda")
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("depth", "nrm", "hit")}
+    full = pe.fuse_gfbs(ctx, g["view_dirs"], t["depth"], t["nrm"], t["hit"], np.zeros(3), 1.0,
+                        grid=32)
+    n = full["xyz"].shape[0]
+    assert n > 10
+    import ctypes
+    from paper_2408_15583_amd import _native
+    gs = _native.pe_gfb_set()
+    vd = np.ascontiguousarray(g["view_dirs"])
+    gs.n_views, gs.view_dirs, gs.w, gs.h, gs.R = 2, vd.ctypes.data_as(_native.c_double_p), 64, 64, 1.0
+    gs.depth, gs.nrm, gs.hit = t["depth"].data_ptr(), t["nrm"].data_ptr(), t["hit"].data_ptr()
+    f = _native.pe_fuse_desc(32, 0.0, 0.0, 0.0, -1)
+    m = ctypes.c_uint64()
+    pe.check(pe.lib().pe_fuse_gfbs(ctx.h, ctypes.byref(gs), ctypes.byref(f), None, None, None,
+                                   None, None, 0, ctypes.byref(m), None))
+    assert m.value == n
+    cap = n // 3
+    xyz = torch.full((cap, 3), -7.0, dtype=torch.float64, device=dev)
+    nr = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+    rad = torch.empty((cap,), dtype=torch.float32, device=dev)
+    pe.check(pe.lib().pe_fuse_gfbs(ctx.h, ctypes.byref(gs), ctypes.byref(f),
+                                   ctypes.c_void_p(xyz.data_ptr()), ctypes.c_void_p(nr.data_ptr()),
+                                   ctypes.c_void_p(rad.data_ptr()), None, None, cap,
+                                   ctypes.byref(m), None))
+    torch.cuda.synchronize()
+    assert m.value == n
+    np.testing.assert_array_equal(xyz.cpu().numpy(), full["xyz"][:cap].cpu().numpy())
+    # invalid arguments
+    gs.h = 32
+    assert pe.lib().pe_fuse_gfbs(ctx.h, ctypes.byref(gs), ctypes.byref(f), None, None, None, None,
+                                 None, 0, ctypes.byref(m), None) == _native.PE_EINVAL
+    gs.h = 64
+    f.grid = 1024
+    assert pe.lib().pe_fuse_gfbs(ctx.h, ctypes.byref(gs), ctypes.byref(f), None, None, None, None,
+                                 None, 0, ctypes.byref(m), None) == _native.PE_EINVAL
+
+
+def test_octar_fused_splats_three_bounces(pe, ctx):
+    """Algorithm 3 end to end on the synthetic OctAR: first-hit GFBs at the eight sensor views
+    (512^2 each), edge filtering and fusion on the 256^3 grid over the target's longest edge,
+    one splat per cell with the Eq. (22) radius, then a 1-3 bounce monostatic sweep at
+    theta = 60 deg on those splats.  Compared with the exact oracle on the original cloud (RMSE
+    in dB over the sweep, both polarisations), beside the same sweep on the original cloud."""
+    import torch
+    sc = scenes.octar()
+    views = scenes.octar_views()
+    s = pe.Scene.from_scene(ctx, sc, view_res=512, view_dirs=views)
+    info = s.info()
+    _, dg, ng, mg = pe.make_pair(ctx, s, views, 256, 256)
+    side = 2.0 * float(sc.meta["half"])
+    fz = pe.fuse_gfbs(ctx, views, dg, ng, mg, info["centre"], info["R"], grid=256, grid_side=side)
+    n_spl = fz["xyz"].shape[0]
+    print(f"fused {n_spl} splats from {len(sc.xyz)} points; radius {fz['radius'].min().item():.4f}"
+          f" .. {fz['radius'].max().item():.4f} m")
+    assert n_spl > 0.8 * 3 * 256 * 256
+    fs = pe.Scene(ctx, fz["xyz"], fz["nrm"], fz["radius"], view_dirs=views, view_res=512)
+    eps = 0.5 * float(sc.radius)
+    inc = scenes.azimuth_sweep(np.arange(0.0, 360.0, 10.0), 30.0)
+    f = [5e9]
+    _, rf, _ = pe.solve(ctx, fs, inc, f, 512, max_bounces=3, eps=eps)
+    _, rp, _ = pe.solve(ctx, s, inc, f, 512, max_bounces=3, eps=eps)
+    o = oracle.OracleScene(sc, grid=128)
+    Ee, _ = o.solve(inc, f, 512, 512, 3, eps)
+    re = oracle.rcs_dbsm(Ee)
+
+    def rmse(a):
+        d = np.concatenate([(a[..., p, p] - re[..., p, p]).ravel() for p in range(2)])
+        return float(np.sqrt(np.mean(d * d)))
+
+    ef, ep = rmse(rf), rmse(rp)
+    print(f"OCTAR theta 60: fused-splat RMSE {ef:.3f} dB, original-cloud RMSE {ep:.3f} dB")
+    assert ef < 0.5
+    fs.close()
+    s.close()
