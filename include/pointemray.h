@@ -102,6 +102,9 @@ typedef struct {
     double max_uncertain;    /* DENSIFIED: fall back to PLAIN for an incidence when more than
                                 this fraction of its pixels with hit probability > 0.1 lie in
                                 (0.1, 0.9) (0 = 0.25) */
+    int32_t tube_k;          /* DENSIFIED/COARSE: heap size K of Algorithm 1 for the coarse
+                                buffer, 1 .. 1024 (see pe_render_tube_topk); 0 = unbounded K
+                                (the front-most point in the tube, depth along the ray) */
 } pe_solve_desc;
 
 /* Counters of one solve. */
@@ -258,14 +261,17 @@ pe_status pe_densifier_set(pe_densifier net, const float* host, uint64_t n);
 /* Training data from a scene (Sec. IV-A recipe on synthetic scenes): for each of n_dir
  * propagation directions (host, n_dir x 3), the network input and targets on that
  * direction's screen (side 2R, as for pe_solve), device outputs, any group may be NULL:
- *   coarse   n_dir x h x w        TUBE first hits (radius tube_px coarse pixels): 1 - t/D, 0 empty
+ *   coarse   n_dir x h x w        TUBE first hits (radius tube_px coarse pixels): 1 - t/D, 0 empty;
+ *                                  tube_k = 0: the front-most point in each tube (t along the
+ *                                  ray); 1 .. 1024: the K-point heap of pe_render_tube_topk
+ *                                  (t = distance from the pixel centre)
  *   depth_gt n_dir x 2h x 2w      DISK first hits: t/D (0 where empty)
  *   nrm_gt   n_dir x 2h x 2w x 3  unit normal against the ray in the view frame (u, v, -k)
  *   mask_gt  n_dir x 2h x 2w      1 on hits
  * (t: distance from the screen plane along the ray, D = 2R.) */
 pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, const double* dirs,
-                                 int32_t h, int32_t w, double tube_px, float* coarse,
-                                 float* depth_gt, float* nrm_gt, float* mask_gt,
+                                 int32_t h, int32_t w, double tube_px, int32_t tube_k,
+                                 float* coarse, float* depth_gt, float* nrm_gt, float* mask_gt,
                                  void* hip_stream);
 
 /* ---- GFB fusion for multi-bounce geometry (Sec. III-B, Algorithm 3, Eq. (22)) ------------- */

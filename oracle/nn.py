@@ -10,10 +10,11 @@ project, residual), max-pooling down, sub-pixel convolution (conv + pixel shuffl
 shared encoder and three decoder heads (depth, normal, hit logit) -- the time complexity
 M1 (L_e + 3 L_d) of Sec. III-C counts three decoders.  Outputs are at twice the input size.
 
-The depth output is the depth head's value plus the coarse depth 1 - x of the input pixel
-the output pixel lies in (0 where the input is empty): the head learns a correction at pixel
-scale, which keeps the bf16 activations of the HIP network precise to a small fraction of a
-pixel of depth.  (The paper does not state how the depth head is parametrised.)
+The depth output is the coarse depth 1 - x of the input pixel the output pixel lies in (0
+where the input is empty) plus the depth head's value in units of one input pixel pitch
+(t/D per pitch = 1 / max(H, W) for a screen of side D): the head learns a correction of a few
+pixels at unit scale, which keeps the bf16 activations of the HIP network precise to a small
+fraction of a pixel of depth.  (The paper does not state how the depth head is parametrised.)
 
 Losses (Eq. (17)-(21)): L1 depth squared error (mean over target hits), L2 sine of the angle
 between predicted and target normals (mean over target hits), L3 alpha-balanced focal loss on
@@ -331,14 +332,22 @@ def forward(P, x):
     # buffer is empty), repeated over each 2 x 2 block of output pixels
     x0 = x[..., 0]
     base = np.where(x0 > 0, 1.0 - x0, 0.0).repeat(2, axis=1).repeat(2, axis=2)
-    return (outs["depth"][..., 0] + base, outs["nrm"], outs["mask"][..., 0]), cache
+    scale = depth_scale(x)
+    return (outs["depth"][..., 0] * scale + base, outs["nrm"], outs["mask"][..., 0]), cache
+
+
+def depth_scale(x):
+    """t/D of one input pixel pitch: the unit of the depth head."""
+    return 1.0 / max(x.shape[1], x.shape[2])
 
 
 def backward(P, cache, d_depth, d_nrm, d_logit):
     G = {}
     skips = cache["skips"]
     dskips = [np.zeros_like(s) for s in skips]
-    for head, dout in (("depth", d_depth[..., None]), ("nrm", d_nrm), ("mask", d_logit[..., None])):
+    sc = depth_scale(cache["x"])
+    for head, dout in (("depth", sc * d_depth[..., None]), ("nrm", d_nrm),
+                       ("mask", d_logit[..., None])):
         hc = cache["head_" + head]
         dzo = pixel_unshuffle(dout)
         du, G[f"{head}.out.w"], G[f"{head}.out.b"] = conv2d_backward(hc["out_in"], P[f"{head}.out.w"], dzo)

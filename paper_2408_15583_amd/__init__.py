@@ -171,7 +171,7 @@ _PREC = {"fp64phase": PE_PREC_FP64PHASE, "fp32": PE_PREC_FP32}
 
 def make_solve_desc(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=None,
                     contrib="last", precision="fp64phase", densifier=None, geometry=None,
-                    tube_px=0.0, max_uncertain=0.0):
+                    tube_px=0.0, max_uncertain=0.0, tube_k=0):
     inc = np.ascontiguousarray(inc_dir, dtype=np.float64).reshape(-1, 3)
     fr = np.ascontiguousarray(freq_hz, dtype=np.float64).ravel()
     d = _native.pe_solve_desc()
@@ -199,16 +199,18 @@ def make_solve_desc(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=No
         d.densifier = densifier.h if hasattr(densifier, "h") else densifier
     d.tube_px = float(tube_px)
     d.max_uncertain = float(max_uncertain)
+    d.tube_k = int(tube_k)
     return d, keep
 
 
 def solve(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
           obs_dir=None, contrib="last", precision="fp64phase", densifier=None, stream=None,
-          geometry=None, tube_px=0.0, max_uncertain=0.0):
+          geometry=None, tube_px=0.0, max_uncertain=0.0, tube_k=0):
     """Synchronous pe_solve.  Returns (E complex [inc, obs, freq, rx, tx], rcs_dbsm, stats).
-    geometry: "plain" (default), "densified" (needs densifier) or "coarse"."""
+    geometry: "plain" (default), "densified" (needs densifier) or "coarse"; tube_k: heap size
+    of the coarse buffer (0 = unbounded)."""
     d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
-                              precision, densifier, geometry, tube_px, max_uncertain)
+                              precision, densifier, geometry, tube_px, max_uncertain, tube_k)
     no = 1 if obs_dir is None else d.n_obs
     E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
     rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))
@@ -349,7 +351,7 @@ class Densifier:
             self.h = None
 
 
-def make_pair(ctx: Context, scene: Scene, dirs, h, w, tube_px=2.0, stream=None):
+def make_pair(ctx: Context, scene: Scene, dirs, h, w, tube_px=2.0, tube_k=0, stream=None):
     """Network input and targets for each propagation direction (torch CUDA tensors):
     coarse [n,h,w], depth_gt [n,2h,2w], nrm_gt [n,2h,2w,3], mask_gt [n,2h,2w]."""
     torch = _torch()
@@ -362,7 +364,8 @@ def make_pair(ctx: Context, scene: Scene, dirs, h, w, tube_px=2.0, stream=None):
     mg = torch.empty((n, 2 * h, 2 * w), dtype=torch.float32, device=dev)
     s = current_stream() if stream is None else stream
     check(lib().pe_densifier_make_pair(ctx.h, scene.h, n, d.ctypes.data_as(_native.c_double_p),
-                                       int(h), int(w), float(tube_px), _dptr(coarse), _dptr(dg),
+                                       int(h), int(w), float(tube_px), int(tube_k),
+                                       _dptr(coarse), _dptr(dg),
                                        _dptr(ng), _dptr(mg), s))
     return coarse, dg, ng, mg
 

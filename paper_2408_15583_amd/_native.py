@@ -58,7 +58,7 @@ class pe_solve_desc(ctypes.Structure):
                 ("contrib", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("geometry", ctypes.c_int32), ("densifier", pe_densifier),
                 ("seed", ctypes.c_uint64), ("tube_px", ctypes.c_double),
-                ("max_uncertain", ctypes.c_double)]
+                ("max_uncertain", ctypes.c_double), ("tube_k", ctypes.c_int32)]
 
 
 class pe_stats(ctypes.Structure):
@@ -133,8 +133,9 @@ _SIGS = {
     "pe_densifier_get": [pe_densifier, ctypes.c_int32, c_float_p, ctypes.c_uint64],
     "pe_densifier_set": [pe_densifier, c_float_p, ctypes.c_uint64],
     "pe_densifier_make_pair": [pe_ctx, pe_scene, ctypes.c_int32, c_double_p, ctypes.c_int32,
-                               ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
-                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                               ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p],
 }
 
 _lib = None

@@ -58,6 +58,7 @@ void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene) {
             throw Error{PE_EINVAL, "densified/coarse geometry needs a square screen, multiple of 16"};
         if (!(d->tube_px >= 0) || !std::isfinite(d->tube_px)) throw Error{PE_EINVAL, "tube_px must be finite and >= 0"};
         if (!(d->max_uncertain >= 0) || !(d->max_uncertain <= 1)) throw Error{PE_EINVAL, "max_uncertain must be in [0, 1]"};
+        if (d->tube_k < 0 || d->tube_k > 1024) throw Error{PE_EINVAL, "tube_k must be 0..1024"};
     }
 }
 

@@ -387,7 +387,9 @@ struct pe_densifier_s {
         const float* og[kHeads] = {A.ogd, A.ogn, A.ogl};
         for (int h = 0; h < kHeads; h++) {
             launch_fill_u32((uint32_t*)A.dzo, 0u, (uint64_t)N * H * W * kPadCo / 2, st);
-            launch_head_grad(og[h], N, H, W, kHeadCo[h], A.dzo, kPadCo, st);
+            // the depth output is head / max(H, W) + coarse depth
+            const float gs = h == 0 ? 1.f / (float)std::max(H, W) : 1.f;
+            launch_head_grad(og[h], N, H, W, kHeadCo[h], gs, A.dzo, kPadCo, st);
             conv_wgrad(out[h], A.u[h][0], C[0], 0, A.dzo, kPadCo, N, H, W, st);
             conv_dgrad(out[h], A.dzo, kPadCo, N, H, W, A.du, C[0], 0, st);
             for (int l = 1; l <= 3; l++) {
@@ -610,6 +612,7 @@ static void densified_solve(Workspace& ws, hipStream_t st, pe_scene sc, const pe
     pe_densifier_s* net = d->geometry == PE_GEOM_DENSIFIED ? as_net(d->densifier) : nullptr;
     const int W = d->screen_w, h = W / 2;
     const double tube_px = d->tube_px > 0 ? d->tube_px : 2.0;
+    const int tube_k = d->tube_k;
     const double max_unc = d->max_uncertain > 0 ? d->max_uncertain : 0.25;
     const double coarse_pitch = 2.0 * sc->R / h;
     const int n_obs = d->obs_dir ? d->n_obs : 1;
@@ -624,6 +627,7 @@ static void densified_solve(Workspace& ws, hipStream_t st, pe_scene sc, const pe
             s.max_b = 1;
         }
         Batch cb(ws, st);
+        cb.topk = tube_k;
         cb.setup(cs, PE_CONTRIB_LAST, d->precision);
         splat_checked(cb, cs, PE_CONTRIB_LAST, d->precision);
         double* Ei = E + (uint64_t)i0 * per_inc * 2;
@@ -913,8 +917,8 @@ pe_status pe_densifier_infer(pe_densifier net, int32_t b, int32_t h, int32_t w,
 }
 
 pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, const double* dirs,
-                                 int32_t h, int32_t w, double tube_px, float* coarse,
-                                 float* depth_gt, float* nrm_gt, float* mask_gt,
+                                 int32_t h, int32_t w, double tube_px, int32_t tube_k,
+                                 float* coarse, float* depth_gt, float* nrm_gt, float* mask_gt,
                                  void* hip_stream) {
     API_BEGIN
     if (!ctx || !scene || !dirs) return set_error(PE_EINVAL, "null argument");
@@ -923,6 +927,7 @@ pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, cons
     if (h < 1 || w < 1 || (uint64_t)4 * h * w > (1u << kPixBits)) return set_error(PE_EINVAL, "bad size");
     if ((uint64_t)4 * h * w * n_dir >= 0xFFFFFFF0ull) return set_error(PE_EINVAL, "batch too large");
     if (!(tube_px > 0) || !std::isfinite(tube_px)) return set_error(PE_EINVAL, "tube_px must be > 0");
+    if (tube_k < 0 || tube_k > 1024) return set_error(PE_EINVAL, "tube_k must be 0..1024");
     for (int i = 0; i < n_dir; i++) {
         const double* k = dirs + 3 * i;
         const double l = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
@@ -944,6 +949,7 @@ pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, cons
             x.tube_r = tube_px * 2.0 * scene->R / std::max(w, h);
         }
         Batch b(*ctx->ws, st);
+        b.topk = tube_k;
         b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
         splat_checked(b, s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
         launch_coarse_encode(b.dd, n_dir, h * w, b.keys, coarse, st);

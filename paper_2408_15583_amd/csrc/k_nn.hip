@@ -869,7 +869,7 @@ void launch_loss_scale(const LossArgs& a, const double* sums, hipStream_t st) {
 // Gathers an fp32 head gradient map into the bf16 gradient of the head's last convolution
 // output before the pixel shuffle (un-shuffle + cast): d[n][y][x][c*4+2sy+sx].
 __global__ void k_head_grad(const float* __restrict__ g, int N, int H, int W, int C,
-                            uint16_t* __restrict__ d, int ldd) {
+                            float scale, uint16_t* __restrict__ d, int ldd) {
     const size_t n = (size_t)N * H * W * 4 * C;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
@@ -877,16 +877,17 @@ __global__ void k_head_grad(const float* __restrict__ g, int N, int H, int W, in
         const size_t pix = i / (4 * C);
         const int x = (int)(pix % W), y = (int)((pix / W) % H), b = (int)(pix / ((size_t)W * H));
         const int c = k >> 2, sy = (k >> 1) & 1, sx = k & 1;
-        d[pix * ldd + k] = f2bf(g[((size_t)(b * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx) * C + c]);
+        d[pix * ldd + k] =
+            f2bf(scale * g[((size_t)(b * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx) * C + c]);
     }
 }
 
-void launch_head_grad(const float* g, int N, int H, int W, int C, uint16_t* d, int ldd,
-                      hipStream_t st) {
+void launch_head_grad(const float* g, int N, int H, int W, int C, float scale, uint16_t* d,
+                      int ldd, hipStream_t st) {
     const size_t n = (size_t)N * H * W * 4 * C;
     int bl = (int)((n + 255) / 256);
     if (bl > 8192) bl = 8192;
-    hipLaunchKernelGGL(k_head_grad, dim3(bl), dim3(256), 0, st, g, N, H, W, C, d, ldd);
+    hipLaunchKernelGGL(k_head_grad, dim3(bl), dim3(256), 0, st, g, N, H, W, C, scale, d, ldd);
 }
 
 // AdamW on fp32 masters; refreshes the bf16 copy (the conv weights) where bf != null.
@@ -919,14 +920,14 @@ void launch_adamw(float* p, const float* g, float* m, float* v, uint16_t* bf, si
 // Depth output = head value + coarse depth 1 - x of the input pixel containing the output
 // pixel (0 where the input is empty).
 __global__ void k_depth_base(float* __restrict__ out, const float* __restrict__ x, int N, int H,
-                             int W) {
+                             int W, float scale) {
     const size_t n = (size_t)N * 4 * H * W;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const int X = (int)(i % (2 * W)), Y = (int)((i / (2 * W)) % (2 * H));
         const int b = (int)(i / ((size_t)4 * H * W));
         const float v = x[((size_t)b * H + Y / 2) * W + X / 2];
-        out[i] += v > 0.f ? 1.f - v : 0.f;
+        out[i] = out[i] * scale + (v > 0.f ? 1.f - v : 0.f);
     }
 }
 
@@ -934,7 +935,8 @@ void launch_depth_base(float* out, const float* x, int N, int H, int W, hipStrea
     const size_t n = (size_t)N * 4 * H * W;
     int b = (int)((n + 255) / 256);
     if (b > 8192) b = 8192;
-    hipLaunchKernelGGL(k_depth_base, dim3(b), dim3(256), 0, st, out, x, N, H, W);
+    hipLaunchKernelGGL(k_depth_base, dim3(b), dim3(256), 0, st, out, x, N, H, W,
+                       1.f / (float)(H > W ? H : W));
 }
 
 __global__ void k_f32_to_bf16(const float* __restrict__ a, size_t n, uint16_t* __restrict__ b) {

@@ -85,10 +85,13 @@ void launch_pool_bwd(const uint16_t* dy, const uint8_t* arg, int N, int H, int W
 void launch_loss(const LossArgs& a, hipStream_t st);
 void launch_loss_sum(const float* partial, int nb, double* sums, hipStream_t st);
 void launch_loss_scale(const LossArgs& a, const double* sums, hipStream_t st);
-void launch_head_grad(const float* g, int N, int H, int W, int C, uint16_t* d, int ldd,
-                      hipStream_t st);
+// Output-map gradient of one head into its last convolution's (unshuffled) layout, times scale.
+void launch_head_grad(const float* g, int N, int H, int W, int C, float scale, uint16_t* d,
+                      int ldd, hipStream_t st);
 void launch_adamw(float* p, const float* g, float* m, float* v, uint16_t* bf, size_t n, float lr,
                   float wd, int step, hipStream_t st);
+// Depth output = head / max(H, W) + coarse depth (1 - x where x > 0, else 0), in place: one
+// unit of the head is one coarse pixel pitch of depth (t/D).
 void launch_depth_base(float* out, const float* x, int N, int H, int W, hipStream_t st);
 void launch_f32_to_bf16(const float* a, size_t n, uint16_t* b, hipStream_t st);
 void launch_bf16_to_f32(const uint16_t* a, size_t n, float* b, hipStream_t st);

@@ -36,18 +36,27 @@ def sphere_dirs(rng, n):
     return v / np.linalg.norm(v, axis=1, keepdims=True)
 
 
-def make_dataset(pe, ctx, n_scenes, views, h, seed, n_lo=100_000, n_hi=500_000, view_res=256):
-    """Returns device tensors (coarse, depth_gt, nrm_gt, mask_gt) with n_scenes * views pairs."""
+def make_dataset(pe, ctx, n_scenes, views, h, seed, n_lo=100_000, n_hi=500_000, view_res=256,
+                 tube_k=0, corner_frac=0.0):
+    """Returns device tensors (coarse, depth_gt, nrm_gt, mask_gt) with n_scenes * views pairs;
+    tube_k: heap size of Algorithm 1 for the coarse buffers (0 = unbounded); corner_frac: the
+    share of scenes drawn as concave plate corners (scenes.corner_assembly) instead of
+    composites."""
     import torch
     import scenes
     rng = np.random.default_rng(seed)
     parts = []
     for i in range(n_scenes):
         n = int(rng.integers(n_lo, n_hi + 1))
-        sc = scenes.composite(seed=int(rng.integers(1 << 30)), n_points=n)
+        sd = int(rng.integers(1 << 30))
+        if rng.uniform() < corner_frac:
+            sc = scenes.corner_assembly(seed=sd, n_points=n)
+        else:
+            sc = scenes.composite(seed=sd, n_points=n)
         s = pe.Scene.from_scene(ctx, sc, view_res=view_res)
         dirs = sphere_dirs(rng, views)
-        parts.append(pe.make_pair(ctx, s, dirs, h, h, tube_px=float(rng.uniform(1.0, 3.0))))
+        parts.append(pe.make_pair(ctx, s, dirs, h, h, tube_px=float(rng.uniform(1.0, 3.0)),
+                                  tube_k=tube_k))
         s.close()
     return tuple(torch.cat([p[j] for p in parts]) for j in range(4))
 
@@ -85,7 +94,7 @@ def rmse_db(r, ref, dyn=30.0):
 
 
 def evaluate(pe, ctx, net, n_scenes, az, el, freqs, screen, seed, n_lo=100_000,
-             n_hi=500_000, view_res=256, max_uncertain=0.0):
+             n_hi=500_000, view_res=256, max_uncertain=0.0, tube_k=0):
     """max_uncertain: fallback threshold of the densified solve (0 = library default,
     1 = never fall back, which measures the network alone)."""
     import scenes
@@ -97,9 +106,9 @@ def evaluate(pe, ctx, net, n_scenes, az, el, freqs, screen, seed, n_lo=100_000,
         s = pe.Scene.from_scene(ctx, sc, view_res=view_res)
         inc = scenes.azimuth_sweep(az, el)
         _, r_plain, _ = pe.solve(ctx, s, inc, freqs, screen)
-        _, r_coarse, _ = pe.solve(ctx, s, inc, freqs, screen, geometry="coarse")
+        _, r_coarse, _ = pe.solve(ctx, s, inc, freqs, screen, geometry="coarse", tube_k=tube_k)
         _, r_dens, st = pe.solve(ctx, s, inc, freqs, screen, densifier=net,
-                                 max_uncertain=max_uncertain)
+                                 max_uncertain=max_uncertain, tube_k=tube_k)
         out.append(dict(n=n, coarse=rmse_db(r_coarse, r_plain), densified=rmse_db(r_dens, r_plain),
                         fallbacks=st["densifier_fallbacks"]))
         s.close()
@@ -117,6 +126,10 @@ def main():
     ap.add_argument("--base", type=int, default=32)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--eval-scenes", type=int, default=2)
+    ap.add_argument("--tube-k", type=int, default=0, help="heap size K of the coarse buffer "
+                    "(0 = unbounded)")
+    ap.add_argument("--corner-frac", type=float, default=0.0,
+                    help="share of concave plate-corner training scenes")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     import torch
@@ -124,7 +137,8 @@ def main():
     log = lambda m: print(f"[train] {m}", flush=True)
     ctx = pe.Context(0)
     t0 = time.time()
-    data = make_dataset(pe, ctx, args.scenes, args.views, args.coarse, args.seed)
+    data = make_dataset(pe, ctx, args.scenes, args.views, args.coarse, args.seed,
+                        tube_k=args.tube_k, corner_frac=args.corner_frac)
     torch.cuda.synchronize()
     log(f"{data[0].shape[0]} pairs at {args.coarse}^2 -> {2 * args.coarse}^2 in {time.time() - t0:.1f} s")
     net = pe.Densifier(ctx, base=args.base, seed=args.seed)
@@ -139,7 +153,7 @@ def main():
     for mu, what in ((1.0, "network alone"), (0.0, "default fallback")):
         res = evaluate(pe, ctx, net, args.eval_scenes, np.arange(0, 360, 10.0), 30.0,
                        np.linspace(2e9, 12e9, 16), 2 * args.coarse, args.seed + 1000,
-                       max_uncertain=mu)
+                       max_uncertain=mu, tube_k=args.tube_k)
         for r in res:
             log(f"eval ({what}) N={r['n']}: RMSE vs plain: coarse {r['coarse']:.2f} dB, "
                 f"densified {r['densified']:.2f} dB, fallbacks {r['fallbacks']:.0f}")

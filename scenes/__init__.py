@@ -201,6 +201,48 @@ def octar_views() -> np.ndarray:
     return np.array(out)
 
 
+def corner_assembly(seed: int, n_points: int = 200_000, size: float = 1.0,
+                    jitter: float = 0.2, radius_factor: float = 1.5) -> Scene:
+    """Concave corners (training data of the same structure as corner reflectors, never the
+    OctAR itself): one to three vertices, each with three edge vectors at pairwise angles in
+    [60, 120] deg and lengths in [0.4, 1] x size; the parallelogram spanned by each pair of
+    edges is a plate (one of the three is dropped with probability 0.3, leaving a dihedral),
+    placed with a random rotation and offset.  Plates are sampled on jittered grids at a common
+    spacing so that the assembly holds about n_points points; exact normals."""
+    rng = _rng(seed)
+    n_vert = int(rng.integers(1, 4))
+    plates = []  # (origin, edge a, edge b)
+    for _ in range(n_vert):
+        while True:
+            e = random_unit_vectors(rng, 3)
+            c = [abs(float(e[i] @ e[j])) for i, j in ((0, 1), (0, 2), (1, 2))]
+            if max(c) <= 0.5 and abs(float(np.linalg.det(e))) > 0.3:
+                break
+        e = e * rng.uniform(0.4, 1.0, (3, 1)) * size
+        o = rng.uniform(-0.5, 0.5, 3) * size * (n_vert > 1)
+        pairs = [(0, 1), (0, 2), (1, 2)]
+        if rng.uniform() < 0.3:
+            pairs.pop(int(rng.integers(3)))
+        for i, j in pairs:
+            plates.append((o, e[i], e[j]))
+    areas = np.array([np.linalg.norm(np.cross(a, b)) for _, a, b in plates])
+    spacing = math.sqrt(areas.sum() / n_points)
+    parts, nrms = [], []
+    for (o, a, b), A in zip(plates, areas):
+        na = max(2, int(round(np.linalg.norm(a) / spacing)))
+        nb = max(2, int(round(A / np.linalg.norm(a) / spacing)))
+        u, v, _ = _jittered_plate(rng, (0.0, 1.0), (0.0, 1.0), na, nb, jitter)
+        parts.append(o + u[:, None] * a + v[:, None] * b)
+        n = np.cross(a, b)
+        nrms.append(np.tile(n / np.linalg.norm(n), (u.size, 1)))
+    rot = _random_rotation(rng)
+    xyz = np.concatenate(parts) @ rot.T
+    nrm = np.concatenate(nrms) @ rot.T
+    return Scene(xyz=xyz, nrm=nrm, radius=radius_factor * spacing,
+                 material=np.zeros(len(xyz), np.uint8), name="corners",
+                 meta=dict(spacing=spacing, plates=len(plates)))
+
+
 def synthetic_gfbs(seed: int, n_views: int, res: int, n_regions: int = 4,
                    soft_hit: bool = False) -> dict:
     """GFB-shaped input buffers for the fusion step, with the structure of rendered or predicted

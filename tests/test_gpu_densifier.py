@@ -212,6 +212,14 @@ def test_make_pair_matches_oracle_buffers(pe, ctx):
     assert (thit == ghit).mean() >= 0.99
     bb = thit & ghit
     assert np.abs((1 - coarse[bb]) * D - tdep[bb]).max() <= 1e-5 * D
+    # with the K-point heap of Algorithm 1 (K = 4): vs the oracle's heap buffer; fp32 and fp64
+    # may break near-ties between candidates differently, so depths agree on >= 99 % of hits
+    c4 = pe.make_pair(ctx, s, k[None], h, w, tube_px=2.0, tube_k=4)[0].cpu().numpy()[0]
+    kdep, kidx = o.render_tube_topk(k, w, h, 2.0 * pitch, 4)[:2]
+    khit, g4 = kidx >= 0, c4 > 0
+    assert (khit == g4).mean() >= 0.99
+    bb = khit & g4
+    assert (np.abs((1 - c4[bb]) * D - kdep[bb]) <= 1e-5 * D).mean() >= 0.99
     s.close()
 
 

@@ -200,17 +200,20 @@ def test_adamw_first_step():
     assert np.allclose(p2, p - 1e-3 * (np.sign(g) * (np.abs(g) / (np.abs(g) + 1e-8)) + 0.01 * p))
 
 
-def test_depth_output_is_coarse_depth_plus_head():
-    """With the depth head's last convolution zeroed, the depth output is the coarse depth
-    1 - x of the input pixel each output pixel lies in (0 where the input is empty)."""
+@pytest.mark.parametrize("bias", [0.0, 1.5])
+def test_depth_output_is_coarse_depth_plus_head(bias):
+    """With the depth head's last convolution reduced to a bias b, the depth output is the
+    coarse depth 1 - x of the input pixel each output pixel lies in (0 where the input is
+    empty) plus b input-pixel pitches of depth, b / max(H, W) in t/D (here 8 x 16 inputs)."""
     rng = np.random.default_rng(12)
     P = N.init_params(base=4, seed=3)
     P["depth.out.w"][:] = 0.0
-    P["depth.out.b"][:] = 0.0
-    x = rng.uniform(0.1, 1.0, (2, 8, 8, 1)) * (rng.uniform(size=(2, 8, 8, 1)) < 0.7)
+    P["depth.out.b"][:] = bias
+    x = rng.uniform(0.1, 1.0, (2, 8, 16, 1)) * (rng.uniform(size=(2, 8, 16, 1)) < 0.7)
     (d, _, _), _ = N.forward(P, x)
     for n in range(2):
         for i in range(16):
-            for j in range(16):
+            for j in range(32):
                 v = x[n, i // 2, j // 2, 0]
-                assert d[n, i, j] == (1.0 - v if v > 0 else 0.0)
+                assert d[n, i, j] == pytest.approx((1.0 - v if v > 0 else 0.0) + bias / 16.0,
+                                                   abs=1e-15)
