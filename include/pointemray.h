@@ -69,6 +69,12 @@ typedef struct {
     int32_t n_views;         /* aggregation views for the bounce march; 0 = six axis views */
     const double* view_dirs; /* n_views x 3 propagation directions (host), NULL with n_views=0 */
     int32_t view_res;        /* square resolution of each aggregation view (16 .. 4096) */
+    double blend_radius;     /* > 0: every hit (primary and secondary) is refined by Eq. (23):
+                                of the splats the ray crosses within this distance (m) beyond
+                                the nearest hit, the one crossed relatively closest to its
+                                centre gives the hit point, and the normal is the blend of
+                                their normals with weights 1 - |p_i - c_i| / R_i (Sec. III-B,
+                                Fig. 4(a)); 0 = off */
 } pe_scene_desc;
 
 /* Solve description (inputs tx, rx, mb and E_i of Algorithm 3, plus frequencies). */

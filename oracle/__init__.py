@@ -13,7 +13,10 @@ Pins (tests/test_oracle_*.py, run with -m "not gpu"):
   - monostatic reciprocity, zero single-bounce cross-polarisation;
   - frequency independence of the trace;
   - hand-derived hits on 1-3 disks; grid-culled first hit == brute force, bitwise.
-The densifier's FP64 layers live in oracle/nn.py with their own pins.
+Eq. (23) overlap refinement and normal blending (set_blend) is pinned in
+tests/test_oracle_blend.py; the K-point heap of Algorithm 1 (render_tube_topk) by brute force in
+tests/test_oracle_pins.py.  GFB edge filtering and fusion live in oracle/fuse.py and the
+densifier's FP64 layers in oracle/nn.py, each with their own pins.
 """
 from __future__ import annotations
 
@@ -69,6 +72,9 @@ def _load():
     lib.or_reflect_field_decomposed.argtypes = [_d, _d, _d, _d, _d]
     lib.or_reflect_field_vector.argtypes = [_d, _d, _d, _d, _d]
     lib.or_pol_basis.argtypes = [_d, _d, _d]
+    lib.or_scene_set_blend.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    lib.or_blend_hit.restype = ctypes.c_int64
+    lib.or_blend_hit.argtypes = [ctypes.c_void_p, _d, _d, ctypes.c_int64, _d, _d, _d]
     lib.or_num_threads.restype = ctypes.c_int
     lib.or_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -155,6 +161,17 @@ class OracleScene:
 
     AXIS_VIEWS = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]],
                           dtype=np.float64)
+
+    def set_blend(self, r):
+        """Eq. (23) overlap refinement and normal blending of every hit within r (0 = off)."""
+        _load().or_scene_set_blend(self._h, float(r))
+
+    def blend_hit(self, x, k, h0):
+        """Refinement of one hit at x on disk h0 along k: (disk, point, normal, offset)."""
+        xo = np.zeros(3); no = np.zeros(3); so = np.zeros(1)
+        h = _load().or_blend_hit(self._h, _p(_f64(x)), _p(_f64(k)), int(h0), _p(xo), _p(no),
+                                 _p(so))
+        return int(h), xo, no, float(so[0])
 
     def set_views(self, res, dirs=None):
         """Aggregation views of the method's secondary-hit rule (default: the six axis

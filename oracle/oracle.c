@@ -68,6 +68,7 @@ typedef struct {
     int n_views, view_res;
     double* view_basis;  /* n_views x 9: u, v, k */
     int64_t* view_idx;   /* n_views x res x res, -1 where empty */
+    double blend_r;      /* Eq. (23) refinement radius (0 = off), see blend_hit */
 } or_scene;
 
 /* Returns NULL and *err != 0 on invalid input: non-finite position, zero/non-finite normal,
@@ -576,6 +577,113 @@ void or_render_tube_topk(const void* p, const double* kin, int W, int H, double 
 
 #define REC 22
 
+/* ------------------------------------------------------------------------------------------ */
+/* Overlap refinement and normal blending of a hit (Sec. III-B, Eq. (23), Fig. 4(a)).          */
+/* Reading: the sphere of radius r about the nearest hit P' selects the splats the ray crosses */
+/* at or beyond P' within distance r (signed offset s in [-1e-6 R, r] along k, crossing inside */
+/* the disk).  The hit moves to the candidate crossed relatively closest to its centre         */
+/* (smallest |p_i - c_i| / R_i, ties lowest index), and the normal is Eq. (23): the sum of the */
+/* candidates' normals (each turned against the ray) weighted by 1 - |p_i - c_i| / R_i,       */
+/* normalised.  Absorbers are not candidates.                                                  */
+/* ------------------------------------------------------------------------------------------ */
+
+static int cmp_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void blend_hit(const or_scene* s, v3 xp, v3 k, int64_t h0, v3* x_out, v3* n_out,
+                      int64_t* h_out, double* s_out) {
+    const double r = s->blend_r, tol = 1e-6 * s->R;
+    int64_t* cand = NULL;
+    int64_t nc = 0;
+    if (s->cell_start) {
+        int c0[3], c1[3];
+        double xx[3] = {xp.x, xp.y, xp.z};
+        for (int a = 0; a < 3; a++) {
+            int q0 = (int)floor((xx[a] - r - s->lo[a]) / s->h);
+            int q1 = (int)floor((xx[a] + r - s->lo[a]) / s->h);
+            c0[a] = q0 < 0 ? 0 : (q0 >= s->G ? s->G - 1 : q0);
+            c1[a] = q1 < 0 ? 0 : (q1 >= s->G ? s->G - 1 : q1);
+        }
+        int64_t cap = 0;
+        for (int z = c0[2]; z <= c1[2]; z++)
+            for (int y = c0[1]; y <= c1[1]; y++)
+                for (int x = c0[0]; x <= c1[0]; x++) {
+                    int64_t c = ((int64_t)z * s->G + y) * s->G + x;
+                    cap += s->cell_start[c + 1] - s->cell_start[c];
+                }
+        cand = (int64_t*)malloc(sizeof(int64_t) * (cap + 1));
+        for (int z = c0[2]; z <= c1[2]; z++)
+            for (int y = c0[1]; y <= c1[1]; y++)
+                for (int x = c0[0]; x <= c1[0]; x++) {
+                    int64_t c = ((int64_t)z * s->G + y) * s->G + x;
+                    for (int64_t j = s->cell_start[c]; j < s->cell_start[c + 1]; j++)
+                        cand[nc++] = s->cell_ids[j];
+                }
+        qsort(cand, (size_t)nc, sizeof(int64_t), cmp_i64);
+    } else {
+        cand = (int64_t*)malloc(sizeof(int64_t) * (s->n + 1));
+        for (int64_t i = 0; i < s->n; i++) cand[nc++] = i;
+    }
+    int64_t best = -1;
+    double best_ratio = INFINITY, best_s = 0;
+    v3 acc = mk(0, 0, 0);
+    double accw = 0;
+    for (int64_t m = 0; m < nc; m++) {
+        int64_t i = cand[m];
+        if (m > 0 && cand[m - 1] == i) continue; /* a disk listed by several cells */
+        if (s->mat[i] != 0) continue;
+        v3 c = ld(s->xyz + 3 * i), n = ld(s->nrm + 3 * i);
+        double nk = dot(n, k);
+        if (fabs(nk) < OR_GRAZE) continue;
+        double sv = dot(sub(c, xp), n) / nk;
+        if (sv < -tol || sv > r) continue;
+        double dd = len(sub(add(xp, scl(k, sv)), c));
+        if (!(dd <= s->rad[i])) continue;
+        double ratio = dd / s->rad[i];
+        if (ratio < best_ratio || (ratio == best_ratio && i < best)) {
+            best_ratio = ratio;
+            best = i;
+            best_s = sv;
+        }
+        v3 no = nk > 0 ? scl(n, -1.0) : n;
+        acc = add(acc, scl(no, 1.0 - ratio));
+        accw += 1.0 - ratio;
+    }
+    free(cand);
+    if (best < 0) { /* no candidate: the hit stays as found */
+        v3 n = ld(s->nrm + 3 * h0);
+        *x_out = xp;
+        *n_out = dot(n, k) > 0 ? scl(n, -1.0) : n;
+        *h_out = h0;
+        *s_out = 0;
+        return;
+    }
+    *x_out = add(xp, scl(k, best_s));
+    if (accw > 0 && len(acc) > 0) {
+        *n_out = unit(acc);
+    } else {
+        v3 n = ld(s->nrm + 3 * best);
+        *n_out = dot(n, k) > 0 ? scl(n, -1.0) : n;
+    }
+    *h_out = best;
+    *s_out = best_s;
+}
+
+void or_scene_set_blend(void* p, double r) { ((or_scene*)p)->blend_r = r > 0 ? r : 0; }
+
+/* Refinement of one hit for the pins: returns the chosen disk, writes the point and normal. */
+int64_t or_blend_hit(const void* p, const double* x, const double* k, int64_t h0, double* x_out,
+                     double* n_out, double* s_out) {
+    v3 xo, no;
+    int64_t h;
+    blend_hit((const or_scene*)p, ld(x), unit(ld(k)), h0, &xo, &no, &h, s_out);
+    st(x_out, xo);
+    st(n_out, no);
+    return h;
+}
+
 /* polarisation basis (theta-hat, phi-hat) of a direction s (spherical angles of s) */
 static void pol_basis(v3 s, v3* th, v3* ph) {
     double theta = acos(s.z > 1 ? 1 : (s.z < -1 ? -1 : s.z));
@@ -602,6 +710,11 @@ static int trace_ray(const or_scene* s, v3 o, v3 k0, v3 u0, v3 v0, int max_b, do
         v3 x = add(o, scl(k, t));
         v3 n = ld(s->nrm + 3 * h);
         if (dot(n, k) > 0) n = scl(n, -1.0);
+        if (s->blend_r > 0) {
+            double ds;
+            blend_hit(s, x, k, h, &x, &n, &h, &ds);
+            t += ds;
+        }
         double* r = rec + (int64_t)(b - 1) * REC;
         st(r + 0, x); st(r + 3, n); st(r + 6, k); st(r + 9, Et); st(r + 12, Ep);
         st(r + 15, u); st(r + 18, v); r[21] = d + t;

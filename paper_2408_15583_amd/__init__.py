@@ -80,7 +80,7 @@ class Scene:
     from host memory, torch CUDA tensors from device memory."""
 
     def __init__(self, ctx: Context, xyz, nrm, radius, material=None, view_dirs=None,
-                 view_res: int = 256, stream=None):
+                 view_res: int = 256, stream=None, blend_radius: float = 0.0):
         torch = _torch()
         self.ctx = ctx
         d = _native.pe_scene_desc()
@@ -132,13 +132,14 @@ class Scene:
             d.n_views = vd.shape[0]
             d.view_dirs = vd.ctypes.data_as(_native.c_double_p)
         d.view_res = int(view_res)
+        d.blend_radius = float(blend_radius)
         self.h = _native.pe_scene()
         st = current_stream() if stream is None else stream
         check(lib().pe_scene_create(ctx.h, ctypes.byref(d), st, ctypes.byref(self.h)))
         del keep
 
     @classmethod
-    def from_scene(cls, ctx, sc, view_res=256, view_dirs=None, device=True):
+    def from_scene(cls, ctx, sc, view_res=256, view_dirs=None, device=True, blend_radius=0.0):
         """Builds from a scenes.Scene; device=True uploads through torch first."""
         torch = _torch()
         if device and torch.cuda.is_available():
@@ -147,9 +148,10 @@ class Scene:
             mat = torch.from_numpy(np.ascontiguousarray(sc.material)).cuda()
             rad = sc.radius if np.isscalar(sc.radius) else torch.from_numpy(
                 np.asarray(sc.radius, np.float32)).cuda()
-            return cls(ctx, xyz, nrm, rad, mat, view_dirs=view_dirs, view_res=view_res)
+            return cls(ctx, xyz, nrm, rad, mat, view_dirs=view_dirs, view_res=view_res,
+                       blend_radius=blend_radius)
         return cls(ctx, sc.xyz, sc.nrm, sc.radius, sc.material, view_dirs=view_dirs,
-                   view_res=view_res)
+                   view_res=view_res, blend_radius=blend_radius)
 
     def info(self):
         c = (ctypes.c_double * 3)()

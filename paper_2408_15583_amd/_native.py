@@ -47,7 +47,7 @@ class pe_scene_desc(ctypes.Structure):
                 ("nrm", c_float_p), ("material", c_u8_p), ("radius", c_float_p),
                 ("radius_scalar", ctypes.c_float), ("mem_kind", ctypes.c_int32),
                 ("n_views", ctypes.c_int32), ("view_dirs", c_double_p),
-                ("view_res", ctypes.c_int32)]
+                ("view_res", ctypes.c_int32), ("blend_radius", ctypes.c_double)]
 
 
 class pe_solve_desc(ctypes.Structure):

@@ -210,6 +210,8 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
         return set_error(PE_EINVAL, "n_views must be 0..64 with view_dirs");
     for (int v = 0; v < d.n_views; v++)
         if (!finite3(d.view_dirs + 3 * v)) return set_error(PE_EINVAL, "non-finite or zero view direction");
+    if (!(d.blend_radius >= 0) || !std::isfinite(d.blend_radius))
+        return set_error(PE_EINVAL, "blend_radius must be finite and >= 0");
     HIPCHK(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)hip_stream;
@@ -367,6 +369,22 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
     sc->views_dev = (ViewDesc*)sc->alloc(sizeof(ViewDesc) * V);
     HIPCHK(hipMemcpyAsync(sc->views_dev, sc->views.data(), sizeof(ViewDesc) * V,
                           hipMemcpyHostToDevice, st));
+    if (d.blend_radius > 0) {
+        // Eq. (23) candidates: grid over the splat centres, cell edge >= r + r_max, <= 256^3
+        const double h0 = d.blend_radius + sc->r_max;
+        const int G = (int)std::max(1.0, std::min(256.0, std::floor(2.0 * sc->R / h0)));
+        sc->blend_r = (float)d.blend_radius;
+        sc->bl_G = G;
+        sc->bl_h = (float)(2.0 * sc->R / G * (1 + 1e-6));
+        const uint64_t nc = (uint64_t)G * G * G;
+        sc->bl_start = (uint32_t*)sc->alloc(4 * (nc + 1));
+        sc->bl_items = (uint32_t*)sc->alloc(4 * n);
+        uint32_t* cell_of2 = (uint32_t*)tmp.get(4 * n);
+        uint32_t* cnt2 = (uint32_t*)tmp.get(4 * nc);
+        uint32_t* cur2 = (uint32_t*)tmp.get(4 * nc);
+        launch_blend_grid(sc->pa, n, (float)sc->R, sc->bl_h, G, cell_of2, cnt2, sc->bl_start, cur2,
+                          sc->bl_items, st);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     *out = sc.release();

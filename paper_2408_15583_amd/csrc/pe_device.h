@@ -74,6 +74,12 @@ struct SlotDesc {
     int mono;
     int n_freq, freq_base;
     int out_base;             // output index of (slot, obs 0, freq 0)
+    // Eq. (23) overlap refinement (blend_r > 0): uniform grid of G^3 cells of edge bl_h over
+    // [-R, R]^3, CSR lists of splat indices by centre
+    float blend_r, bl_h;
+    int bl_G;
+    const uint32_t* bl_start;
+    const uint32_t* bl_items;
 };
 
 struct ObsDesc {
@@ -159,6 +165,12 @@ void launch_raygen_write(const SlotDesc* d, int n_slots, int max_pix, const uint
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
                   uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, int n_blocks,
                   hipStream_t st);
+// Eq. (23): centre grid of a scene's splats, and the refinement/blend pass over a live list.
+void launch_blend_grid(const float4* pa, uint64_t n, float R, float h, int G, uint32_t* cell_of,
+                       uint32_t* counts, uint32_t* start, uint32_t* cursor, uint32_t* items,
+                       hipStream_t st);
+void launch_blend(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
+                  int n_blocks, hipStream_t st);
 void launch_bounce_apply(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
                          RayState rs, uint64_t* hitkey, uint8_t* alive, uint32_t* chunk_count,
                          int bounce, int n_blocks, hipStream_t st);

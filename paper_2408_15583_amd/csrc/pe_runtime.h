@@ -77,6 +77,7 @@ struct Batch {
     uint32_t* cnt = nullptr;
     int n = 0, contrib = 0, precision = 0, n_seg = 1, ft = 1, max_b = 1;
     int topk = 0;  // > 0: TUBE slots keep a K-point heap (Algorithm 1) instead of K unbounded
+    bool blend = false;  // some slot's scene refines hits by Eq. (23)
     int max_chunks = 0, max_tiles = 0, max_pix = 0, max_obs = 1, max_freq = 1, tot_out = 0;
     uint64_t tot_pix = 0;
     uint32_t tot_tiles = 0, tot_chunks = 0, tlist_cap = 0, rec_stride = 0;
@@ -155,6 +156,9 @@ struct pe_scene_s {
     float4 *pa = nullptr, *pb = nullptr, *pa_s = nullptr, *pb_s = nullptr;
     std::vector<pe::ViewDesc> views;
     pe::ViewDesc* views_dev = nullptr;
+    float blend_r = 0.f, bl_h = 0.f;  // Eq. (23) refinement radius and centre-grid cell edge
+    int bl_G = 0;
+    uint32_t *bl_start = nullptr, *bl_items = nullptr;
     std::vector<std::pair<void*, size_t>> allocs;
     uint64_t bytes = 0;
     void* alloc(size_t b) {

@@ -183,6 +183,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
     contrib = contrib_;
     precision = precision_;
     hd.assign(n, SlotDesc{});
+    blend = false;
     ho.clear();
     hf.clear();
     max_chunks = max_tiles = max_pix = 0;
@@ -202,6 +203,12 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.pb_s = sc->pb_s;
         d.pa = sc->pa;
         d.pb = sc->pb;
+        d.blend_r = sc->blend_r;
+        d.bl_h = sc->bl_h;
+        d.bl_G = sc->bl_G;
+        d.bl_start = sc->bl_start;
+        d.bl_items = sc->bl_items;
+        if (sc->blend_r > 0.f) blend = true;
         d.views = sc->views_dev;
         d.n_views = (int)sc->views.size();
         max_views = std::max(max_views, d.n_views);
@@ -344,6 +351,11 @@ void Batch::raygen() {
     prof_begin();
     launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, hitkey, st);
     prof_end("raygen_write");
+    if (blend) {
+        prof_begin();
+        launch_blend(dd, lists[0], cnt + C_N0, rs, persistent_blocks(), st);
+        prof_end("blend");
+    }
     HIPCHK(hipGetLastError());
 }
 
@@ -408,6 +420,11 @@ void Batch::trace(bool with_records) {
         prof_begin();
         launch_compact(cur, ncur, alive, coff, out, persistent_blocks(), st);
         prof_end("compact");
+        if (blend) {
+            prof_begin();
+            launch_blend(dd, out, nout, rs, persistent_blocks(), st);
+            prof_end("blend");
+        }
         HIPCHK(hipMemcpyAsync(cnt + C_BOUNCE0 + b, ncur, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(cnt + C_BOUNCE0 + 32 + b, nout, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
         if (with_records && contrib == PE_CONTRIB_EVERY) records(b - 1, out, nout);

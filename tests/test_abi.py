@@ -53,12 +53,13 @@ def _struct_fields(name):
         ty_and_names = " ".join(parts[1:]) if parts[0] == "const" else " ".join(parts)
         toks = ty_and_names.split(",")
         first = toks[0].split()
-        fields.append(first[-1])
-        fields += [t.strip() for t in toks[1:]]
+        fields.append(first[-1].split("[")[0])
+        fields += [t.strip().split("[")[0] for t in toks[1:]]
     return fields
 
 
-@pytest.mark.parametrize("name", ["pe_scene_desc", "pe_solve_desc", "pe_stats", "pe_result"])
+@pytest.mark.parametrize("name", ["pe_scene_desc", "pe_solve_desc", "pe_stats", "pe_result",
+                                  "pe_gfb_set", "pe_fuse_desc"])
 def test_struct_layout_matches_header(name):
     from paper_2408_15583_amd import _native
     py = [f for f, _ in getattr(_native, name)._fields_]

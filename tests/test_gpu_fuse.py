@@ -213,8 +213,15 @@ def test_octar_learned_gfbs_three_bounces(pe, ctx):
         _, r, _ = pe.solve(ctx, fs, inc, f, 512, max_bounces=3, eps=eps)
         out[tag] = (rmse(r), fz["xyz"].shape[0])
         fs.close()
+        if tag == "learned":  # the same splats with Eq. (23) refinement (r = one grid cell)
+            fs = pe.Scene(ctx, fz["xyz"], fz["nrm"], fz["radius"], view_dirs=views,
+                          view_res=512, blend_radius=2.0 / 256)
+            _, r, _ = pe.solve(ctx, fs, inc, f, 512, max_bounces=3, eps=eps)
+            out["learned_blend"] = (rmse(r), fz["xyz"].shape[0])
+            fs.close()
     _, rp, _ = pe.solve(ctx, s, inc, f, 512, max_bounces=3, eps=0.5 * float(sparse.radius))
-    print(f"OCTAR learned-GFB splats: {out['learned'][1]} splats, RMSE {out['learned'][0]:.3f} dB;"
+    print(f"OCTAR learned-GFB splats: {out['learned'][1]} splats, RMSE {out['learned'][0]:.3f} dB"
+          f" ({out['learned_blend'][0]:.3f} dB with Eq. (23) refinement);"
           f" exact-GFB splats: {out['exact'][1]}, RMSE {out['exact'][0]:.3f} dB; 50k cloud "
           f"directly: RMSE {rmse(rp):.3f} dB")
     assert out["exact"][0] < 0.75
