@@ -280,6 +280,19 @@ pe_status pe_densifier_make_pair(pe_ctx ctx, pe_scene scene, int32_t n_dir, cons
                                  float* coarse, float* depth_gt, float* nrm_gt, float* mask_gt,
                                  void* hip_stream);
 
+/* ---- point-cloud normals ---------------------------------------------------------------- */
+
+/* Normals of a point cloud that carries none (the point-cloud baseline of Sec. IV estimates them
+ * by principal component analysis): for every point, its k nearest points (itself included;
+ * ties: lowest index) are found exactly through a uniform grid, and the normal is the
+ * eigenvector of their covariance with the smallest eigenvalue, turned so that its largest
+ * component is positive (unoriented: splats are two-sided).  xyz: n x 3 (xyz_type) and nrm:
+ * n x 3 floats, both in mem_kind memory.  k: 3 .. 64.  Errors: PE_EINVAL (bad arguments,
+ * non-finite positions).  Collinear or coincident neighbourhoods give an arbitrary unit vector
+ * orthogonal to them (or +z). */
+pe_status pe_estimate_normals(pe_ctx ctx, uint64_t n, const void* xyz, int32_t xyz_type,
+                              int32_t mem_kind, int32_t k, float* nrm, void* hip_stream);
+
 /* ---- GFB fusion for multi-bounce geometry (Sec. III-B, Algorithm 3, Eq. (22)) ------------- */
 
 /* Geometric frame buffers of n_views screens over one scene frame, in the layout of

@@ -16,6 +16,7 @@ from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM
 
 __all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "submit", "server_stats",
            "render_gfb", "render_tube_topk", "trace_pixels", "make_pair", "fuse_gfbs",
+           "estimate_normals",
            "PEError", "lib", "check"]
 
 
@@ -370,6 +371,30 @@ def make_pair(ctx: Context, scene: Scene, dirs, h, w, tube_px=2.0, tube_k=0, str
                                        _dptr(coarse), _dptr(dg),
                                        _dptr(ng), _dptr(mg), s))
     return coarse, dg, ng, mg
+
+
+def estimate_normals(ctx: Context, xyz, k=16, stream=None):
+    """PCA normals of the k nearest neighbours (pe_estimate_normals).  xyz: numpy (n,3) f32/f64
+    (returns numpy) or a torch CUDA tensor (returns a torch CUDA tensor)."""
+    torch = _torch()
+    s = current_stream() if stream is None else stream
+    if isinstance(xyz, torch.Tensor) and xyz.is_cuda:
+        x = xyz.contiguous()
+        if x.dtype not in (torch.float32, torch.float64):
+            x = x.to(torch.float64)
+        out = torch.empty((x.shape[0], 3), dtype=torch.float32, device=x.device)
+        check(lib().pe_estimate_normals(ctx.h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                        PE_F64 if x.dtype == torch.float64 else PE_F32,
+                                        PE_MEM_DEVICE, int(k), ctypes.c_void_p(out.data_ptr()), s))
+        return out
+    x = np.ascontiguousarray(xyz)
+    if x.dtype not in (np.float32, np.float64):
+        x = x.astype(np.float64)
+    out = np.empty((x.shape[0], 3), np.float32)
+    check(lib().pe_estimate_normals(ctx.h, x.shape[0], ctypes.c_void_p(x.ctypes.data),
+                                    PE_F64 if x.dtype == np.float64 else PE_F32, PE_MEM_HOST,
+                                    int(k), ctypes.c_void_p(out.ctypes.data), s))
+    return out
 
 
 def fuse_gfbs(ctx: Context, view_dirs, depth, nrm, hit, centre, R, grid=256, grid_side=0.0,

@@ -113,6 +113,8 @@ _SIGS = {
     "pe_trace_pixels": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "pe_estimate_normals": [pe_ctx, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int32,
+                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
     "pe_fuse_gfbs": [pe_ctx, ctypes.POINTER(pe_gfb_set), ctypes.POINTER(pe_fuse_desc),
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.c_void_p, ctypes.c_uint64, c_u64_p, ctypes.c_void_p],

@@ -15,6 +15,7 @@ constexpr int kSlotBits = 10;       // list entry = slot << 22 | pixel
 constexpr int kPixBits = 22;
 constexpr int kMaxLevels = 14;
 constexpr int kMaxSlots = 1 << kSlotBits;
+constexpr int kMaxNormalK = 64;   // largest neighbourhood of the PCA normal estimate
 constexpr int kWaveChunk = 64;    // live-list entries per compaction chunk (one wavefront)
 
 // One aggregation view of a scene: a disk first-hit buffer with its min/max depth pyramid.
@@ -171,6 +172,15 @@ void launch_blend_grid(const float4* pa, uint64_t n, float R, float h, int G, ui
                        hipStream_t st);
 void launch_blend(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
                   int n_blocks, hipStream_t st);
+// PCA normals: bounding box partials (7 doubles per block: lo xyz, hi xyz, non-finite count),
+// grid of G^3 cells of edge h from lo (box-centred frame), k-nearest PCA.
+void launch_nrm_bbox(const void* xyz, int is_f64, uint64_t n, double* partial, int nb,
+                     hipStream_t st);
+void launch_nrm_grid(const void* xyz, int is_f64, uint64_t n, const double c[3], float lo,
+                     float h, int G, float4* p, float4* ps, uint32_t* cell_of, uint32_t* counts,
+                     uint32_t* start, uint32_t* cursor, hipStream_t st);
+void launch_nrm_pca(const float4* p, uint64_t n, const float4* ps, const uint32_t* start,
+                    float lo, float h, int G, int k, float* nrm, hipStream_t st);
 void launch_bounce_apply(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
                          RayState rs, uint64_t* hitkey, uint8_t* alive, uint32_t* chunk_count,
                          int bounce, int n_blocks, hipStream_t st);
