@@ -21,7 +21,7 @@
 
 namespace pe {
 
-enum : int { B_GFB_COARSE = 32, B_GFB_DEPTH, B_GFB_NRM, B_GFB_PROB, B_GFB_CNT, B_GFB_USE };
+enum : int { B_GFB_COARSE = 34, B_GFB_DEPTH, B_GFB_NRM, B_GFB_PROB, B_GFB_CNT, B_GFB_USE };
 
 constexpr int kHeads = 3;
 constexpr int kHeadCo[kHeads] = {1, 3, 1};

@@ -163,88 +163,127 @@ __device__ inline void slab(float a0, float da, float lo, float hi, float& s0, f
 // the 3x3 block are then intersected exactly, skipping those already tested in the previous
 // block.  A hit counts only when its point projects within one pixel of the pixel that stores
 // the disk: the set of hits the views retain, whatever path pixel the test came from.
-__device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
-                           float& best_t, uint32_t& best_i, uint32_t* cap_hits) {
+//
+// The walk is a small state machine (walk_init, then walk_step until it returns false) so
+// that a lane can finish one walk and start the next without waiting for its wavefront.
+struct Walk {
+    const float2* hiz;  // the view's pyramid and pixel records, held in registers
+    const float4* pix;
+    int W, H, P, lp;
+    float tmin;
+    float a0, b0, z0, da, db, dz, ida, idb, zpad;
+    float s, s_hi;
+    int ix, iy, px_prev, py_prev, level, it, cap;
+};
+
+__device__ inline bool walk_init(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
+                                 float best_t, Walk& w) {
     const float ip = 1.f / V.pitch;
     const f3 vu = mk3(V.u[0], V.u[1], V.u[2]), vv = mk3(V.v[0], V.v[1], V.v[2]);
     const f3 vk = mk3(V.k[0], V.k[1], V.k[2]);
-    const int W = V.W, H = V.H, P = V.P;
-    const float2* __restrict__ hiz = V.hiz;
-    const float4* __restrict__ pix = V.pix;
-    const float a0 = dot(x, vu) * ip + 0.5f * W, b0 = dot(x, vv) * ip + 0.5f * H;
-    const float z0 = dot(x, vk) + V.R;
-    const float da = dot(k, vu) * ip, db = dot(k, vv) * ip, dz = dot(k, vk);
-    float s_lo = tmin, s_hi = fminf(smax, best_t);
-    slab(a0, da, 0.f, (float)W, s_lo, s_hi);
-    slab(b0, db, 0.f, (float)H, s_lo, s_hi);
-    if (!(s_lo <= s_hi)) return;
-    const float ida = da != 0.f ? 1.f / da : 0.f, idb = db != 0.f ? 1.f / db : 0.f;
-    const float lat = fmaxf(fabsf(da), fabsf(db));
-    const float zpad = (lat > 0.f ? fabsf(dz) / lat : 0.f) + tol;  // depth change per pixel
-    float s = s_lo;
-    int ix = min(max((int)floorf(a0 + s * da), 0), W - 1);
-    int iy = min(max((int)floorf(b0 + s * db), 0), H - 1);
-    int px_prev = -1000, py_prev = -1000;
-    int level = 0;
-    const int lmax = V.lp;
-    const int cap = 4 * (W + H) * (lmax + 1) + 64;
-    for (int it = 0;; it++) {
-        if (it > cap) {
-            atomicAdd(cap_hits, 1u);
-            break;
-        }
-        const int cx = ix >> level, cy = iy >> level;
-        const int xl = cx << level, xh = min((cx + 1) << level, W);
-        const int yl = cy << level, yh = min((cy + 1) << level, H);
-        const float sx = da > 0.f ? (xh - a0) * ida : (da < 0.f ? (xl - a0) * ida : FLT_MAX);
-        const float sy = db > 0.f ? (yh - b0) * idb : (db < 0.f ? (yl - b0) * idb : FLT_MAX);
-        const float se = fminf(fminf(sx, sy), s_hi);
-        const float za = z0 + s * dz, zb = z0 + se * dz;
-        const float2 h = hiz[hiz_offset(P, level) + hiz_texel(P >> level, cx, cy)];
-        const bool ov = fmaxf(za, zb) + zpad >= h.x && fminf(za, zb) - zpad <= h.y;
-        if (ov && level > 0) {
-            level--;
-            continue;
-        }
-        if (ov) {
-            for (int dy = -1; dy <= 1; dy++) {
-                const int py = iy + dy;
-                if (py < 0 || py >= H) continue;
-                for (int dx = -1; dx <= 1; dx++) {
-                    const int px = ix + dx;
-                    if (px < 0 || px >= W) continue;
-                    if (abs(px - px_prev) <= 1 && abs(py - py_prev) <= 1) continue;
-                    const float4 pb = pix[2 * (py * W + px) + 1];
-                    const uint32_t i = __float_as_uint(pb.w);
-                    if (i == kNone) continue;
-                    float t;
-                    if (disk_test(pix[2 * (py * W + px)], pb, x, k, tmin, t) &&
-                        (t < best_t || (t == best_t && i < best_i))) {
-                        // the view retains this disk for hit points within one pixel of where
-                        // it is stored (the hit point's own pixel is always on the walk)
-                        const int ha = (int)floorf(a0 + t * da), hb = (int)floorf(b0 + t * db);
-                        if (abs(ha - px) <= 1 && abs(hb - py) <= 1) {
-                            best_t = t;
-                            best_i = i;
-                        }
+    const int W = V.W, H = V.H;
+    w.hiz = V.hiz;
+    w.pix = V.pix;
+    w.W = W;
+    w.H = H;
+    w.P = V.P;
+    w.lp = V.lp;
+    w.tmin = tmin;
+    w.a0 = dot(x, vu) * ip + 0.5f * W;
+    w.b0 = dot(x, vv) * ip + 0.5f * H;
+    w.z0 = dot(x, vk) + V.R;
+    w.da = dot(k, vu) * ip;
+    w.db = dot(k, vv) * ip;
+    w.dz = dot(k, vk);
+    float s_lo = tmin;
+    w.s_hi = fminf(smax, best_t);
+    slab(w.a0, w.da, 0.f, (float)W, s_lo, w.s_hi);
+    slab(w.b0, w.db, 0.f, (float)H, s_lo, w.s_hi);
+    if (!(s_lo <= w.s_hi)) return false;
+    w.ida = w.da != 0.f ? 1.f / w.da : 0.f;
+    w.idb = w.db != 0.f ? 1.f / w.db : 0.f;
+    const float lat = fmaxf(fabsf(w.da), fabsf(w.db));
+    w.zpad = (lat > 0.f ? fabsf(w.dz) / lat : 0.f) + tol;  // depth change per pixel
+    w.s = s_lo;
+    w.ix = min(max((int)floorf(w.a0 + s_lo * w.da), 0), W - 1);
+    w.iy = min(max((int)floorf(w.b0 + s_lo * w.db), 0), H - 1);
+    w.px_prev = -1000;
+    w.py_prev = -1000;
+    w.level = 0;
+    w.it = 0;
+    w.cap = 4 * (W + H) * (V.lp + 1) + 64;
+    return true;
+}
+
+// One cell of the walk; false once the walk is over.
+__device__ inline bool walk_step(f3 x, f3 k, Walk& w, float& best_t, uint32_t& best_i,
+                                 uint32_t* cap_hits) {
+    if (w.it++ > w.cap) {
+        atomicAdd(cap_hits, 1u);
+        return false;
+    }
+    const int W = w.W, H = w.H, P = w.P;
+    const int cx = w.ix >> w.level, cy = w.iy >> w.level;
+    const int xl = cx << w.level, xh = min((cx + 1) << w.level, W);
+    const int yl = cy << w.level, yh = min((cy + 1) << w.level, H);
+    const float sx = w.da > 0.f ? (xh - w.a0) * w.ida : (w.da < 0.f ? (xl - w.a0) * w.ida : FLT_MAX);
+    const float sy = w.db > 0.f ? (yh - w.b0) * w.idb : (w.db < 0.f ? (yl - w.b0) * w.idb : FLT_MAX);
+    const float se = fminf(fminf(sx, sy), w.s_hi);
+    const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz;
+    const float2 h = w.hiz[hiz_offset(P, w.level) + hiz_texel(P >> w.level, cx, cy)];
+    const bool ov = fmaxf(za, zb) + w.zpad >= h.x && fminf(za, zb) - w.zpad <= h.y;
+    if (ov && w.level > 0) {
+        w.level--;
+        return true;
+    }
+    if (ov) {
+        const float4* __restrict__ pix = w.pix;
+        for (int dy = -1; dy <= 1; dy++) {
+            const int py = w.iy + dy;
+            if (py < 0 || py >= H) continue;
+            for (int dx = -1; dx <= 1; dx++) {
+                const int px = w.ix + dx;
+                if (px < 0 || px >= W) continue;
+                if (abs(px - w.px_prev) <= 1 && abs(py - w.py_prev) <= 1) continue;
+                const float4 pb = pix[2 * (py * W + px) + 1];
+                const uint32_t i = __float_as_uint(pb.w);
+                if (i == kNone) continue;
+                float t;
+                if (disk_test(pix[2 * (py * W + px)], pb, x, k, w.tmin, t) &&
+                    (t < best_t || (t == best_t && i < best_i))) {
+                    // the view retains this disk for hit points within one pixel of where
+                    // it is stored (the hit point's own pixel is always on the walk)
+                    const int ha = (int)floorf(w.a0 + t * w.da), hb = (int)floorf(w.b0 + t * w.db);
+                    if (abs(ha - px) <= 1 && abs(hb - py) <= 1) {
+                        best_t = t;
+                        best_i = i;
                     }
                 }
             }
-            px_prev = ix;
-            py_prev = iy;
-            s_hi = fminf(s_hi, best_t);
         }
-        if (se >= s_hi) break;
-        if (sx <= sy) {
-            ix = da > 0.f ? xh : xl - 1;
-            iy = min(max((int)floorf(b0 + se * db), yl), yh - 1);
-        } else {
-            iy = db > 0.f ? yh : yl - 1;
-            ix = min(max((int)floorf(a0 + se * da), xl), xh - 1);
-        }
-        if (ix < 0 || ix >= W || iy < 0 || iy >= H) break;
-        s = se;
-        if (level < lmax) level++;
+        w.px_prev = w.ix;
+        w.py_prev = w.iy;
+        w.s_hi = fminf(w.s_hi, best_t);
+    }
+    if (se >= w.s_hi) return false;
+    if (sx <= sy) {
+        w.ix = w.da > 0.f ? xh : xl - 1;
+        w.iy = min(max((int)floorf(w.b0 + se * w.db), yl), yh - 1);
+    } else {
+        w.iy = w.db > 0.f ? yh : yl - 1;
+        w.ix = min(max((int)floorf(w.a0 + se * w.da), xl), xh - 1);
+    }
+    if (w.ix < 0 || w.ix >= W || w.iy < 0 || w.iy >= H) return false;
+    w.s = se;
+    if (w.level < w.lp) w.level++;
+    return true;
+}
+
+__device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
+                           float& best_t, uint32_t& best_i, uint32_t* cap_hits) {
+    Walk w;
+    if (!walk_init(V, x, k, tmin, smax, tol, best_t, w)) return;
+    while (walk_step(x, k, w, best_t, best_i, cap_hits)) {
     }
 }
 
@@ -306,61 +345,100 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
     return true;
 }
 
-// One bounce, pass 1: every wavefront marches ONE aggregation view for 64 consecutive live
-// rays (adjacent pixels of one incidence, so the lanes walk similar paths through the same
-// view data).  Work items are (view, chunk) pairs in view-major order; the nearest hit of each
-// (ray, view) is folded into the ray's packed t|index key with a 64-bit atomic minimum, so the
-// result is the same minimum over views whatever the order (ties: lowest index).
-__global__ __launch_bounds__(256, 6) void k_march(const SlotDesc* __restrict__ ds,
+// One bounce, pass 1: the (view, ray) walks of the live list, view-major, each XCD taking a
+// contiguous eighth so that its L2 serves few views at a time (and then helping the other
+// XCDs once its own eighth is drained).  Lanes run walks independently: a lane that finishes
+// publishes its hit and, once three quarters of its wavefront are idle, the wavefront takes
+// the next walks with one atomic (consecutive rays of one view, so the new lanes are coherent
+// with each other; refilling earlier trades that coherence for fewer idle lanes and was
+// measured slower).  Each walk starts from the best hit already published
+// for its ray and keeps only strictly better (t, index) hits, and the hits fold into the
+// ray's packed t|index key with a 64-bit atomic minimum: the result is the minimum over views
+// whatever the order in which walks run.
+__global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ ds,
                                                   const uint32_t* __restrict__ list,
                                                   const uint32_t* __restrict__ n_live,
                                                   RayState rs, uint64_t* __restrict__ hitkey,
                                                   int bounce, int max_views,
-                                                  uint32_t* __restrict__ cap_hits) {
+                                                  uint32_t* __restrict__ cap_hits,
+                                                  uint32_t* __restrict__ queue) {
     const uint32_t n = *n_live;
-    const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
-    const uint32_t total = n_chunks * (uint32_t)max_views;
+    const uint64_t total = (uint64_t)n * (uint32_t)max_views;
     const int lane = threadIdx.x & 63;
-    // Each XCD takes a contiguous eighth of the (view, chunk) items so that its L2 serves one
-    // region of one view; within an XCD the wavefronts stride over that range.
-    const uint32_t xcd = blockIdx.x % kNumXcd;
-    const uint32_t per_xcd_waves = (gridDim.x / kNumXcd) * 4;
-    const uint32_t wx = __builtin_amdgcn_readfirstlane((blockIdx.x / kNumXcd) * 4 + (threadIdx.x >> 6));
-    const uint32_t q0 = (uint32_t)(((uint64_t)total * xcd) / kNumXcd);
-    const uint32_t q1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kNumXcd);
-    for (uint32_t q = q0 + wx; q < q1; q += per_xcd_waves) {
-        const uint32_t v = q / n_chunks, c = q - v * n_chunks;
-        const uint32_t e = c * kWaveChunk + lane;
-        if (e >= n) continue;
-        const uint32_t entry = list[e];
-        const SlotDesc& d = ds[entry_slot(entry)];
-        if (bounce > d.max_b || (int)v >= d.n_views) continue;
-        const uint64_t g = d.pix_base + entry_pix(entry);
-        const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
-        f3 k = mirror(kin, nn);
-        k = k * rsqrtf(dot(k, k));
-        // Start from the best hit other views have already published for this ray: the walk
-        // then stops at that depth, and only strictly better (t, index) hits are kept, so the
-        // final minimum over views is the same whatever the order in which views finish.
-        const uint64_t known =
-            __hip_atomic_load(&hitkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        float bt = FLT_MAX;
-        uint32_t bi = kNone;
-        if (known != kEmptyKey) {
-            bt = __uint_as_float((uint32_t)(known >> 32));
-            bi = (uint32_t)(known & 0xFFFFFFFFu);
+    // the XCD's own eighth first, then the other eighths in turn (work left at the end)
+    uint32_t src = blockIdx.x % kNumXcd;
+    int tried = 1;
+    uint64_t q0 = (total * src) / kNumXcd, q1 = (total * (src + 1)) / kNumXcd;
+    bool active = false, exhausted = total == 0;
+    uint32_t e = 0;
+    const SlotDesc* d = ds;
+    f3 x = mk3(0.f, 0.f, 0.f), k = x;
+    float bt = FLT_MAX;
+    uint32_t bi = kNone;
+    uint64_t known = kEmptyKey;
+    Walk w;
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        const int n_idle = __popcll(idle);
+        if (!exhausted && n_idle >= 48) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(queue + src, (uint32_t)n_idle);
+            base = __shfl(base, 0);
+            if (!active) {
+                const uint64_t j = q0 + base + (uint64_t)__popcll(idle & ((1ull << lane) - 1ull));
+                if (j < q1) {
+                    const uint32_t v = (uint32_t)(j / n);
+                    e = (uint32_t)(j - (uint64_t)v * n);
+                    const uint32_t entry = list[e];
+                    d = &ds[entry_slot(entry)];
+                    if (bounce <= d->max_b && (int)v < d->n_views) {
+                        const uint64_t g = d->pix_base + entry_pix(entry);
+                        x = ld3(rs, RX, g);
+                        const f3 nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                        k = mirror(kin, nn);
+                        k = k * rsqrtf(dot(k, k));
+                        // start from the best hit other views have already published
+                        known = __hip_atomic_load(&hitkey[e], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        bt = FLT_MAX;
+                        bi = kNone;
+                        if (known != kEmptyKey) {
+                            bt = __uint_as_float((uint32_t)(known >> 32));
+                            bi = (uint32_t)(known & 0xFFFFFFFFu);
+                        }
+                        active = walk_init(d->views[v], x, k, d->eps, march_smax(*d, x, k),
+                                           march_tol(*d), bt, w);
+                    }
+                }
+            }
+            if (q0 + base + (uint64_t)n_idle >= q1) {
+                if (tried == kNumXcd) {
+                    exhausted = true;
+                } else {
+                    src = (src + 1) % kNumXcd;
+                    tried++;
+                    q0 = (total * src) / kNumXcd;
+                    q1 = (total * (src + 1)) / kNumXcd;
+                }
+            }
         }
-        march_view(d.views[v], x, k, d.eps, march_smax(d, x, k), march_tol(d), bt, bi, cap_hits);
-        if (bi != kNone && pack_hit(bt, bi) < known)
-            atomicMin((unsigned long long*)&hitkey[e], (unsigned long long)pack_hit(bt, bi));
+        if (exhausted && __ballot(active) == 0ull) break;
+        if (active) {
+            if (!walk_step(x, k, w, bt, bi, cap_hits)) {
+                active = false;
+                if (bi != kNone && pack_hit(bt, bi) < known)
+                    atomicMin((unsigned long long*)&hitkey[e], (unsigned long long)pack_hit(bt, bi));
+            }
+        }
     }
 }
 
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, int n_blocks,
-                  hipStream_t st) {
+                  uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, uint32_t* queue,
+                  int n_blocks, hipStream_t st) {
+    launch_fill_u32(queue, 0u, kNumXcd, st);
     hipLaunchKernelGGL(k_march, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs, hitkey,
-                       bounce, max_views, cap_hits);
+                       bounce, max_views, cap_hits, queue);
 }
 
 // One bounce, pass 2: apply each ray's nearest hit (or stop it), reset its key for the next

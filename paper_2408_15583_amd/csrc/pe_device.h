@@ -163,9 +163,10 @@ void launch_raygen_count(const SlotDesc* d, int n_slots, int max_pix, const uint
 void launch_raygen_write(const SlotDesc* d, int n_slots, int max_pix, const uint64_t* keys,
                          const uint32_t* wg_off, uint32_t* list, RayState rs, uint64_t* hitkey,
                          hipStream_t st);
+// queue: kNumXcd u32 work counters (cleared by the launcher).
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, int n_blocks,
-                  hipStream_t st);
+                  uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, uint32_t* queue,
+                  int n_blocks, hipStream_t st);
 // Eq. (23): centre grid of a scene's splats, and the refinement/blend pass over a live list.
 void launch_blend_grid(const float4* pa, uint64_t n, float R, float h, int G, uint32_t* cell_of,
                        uint32_t* counts, uint32_t* start, uint32_t* cursor, uint32_t* items,

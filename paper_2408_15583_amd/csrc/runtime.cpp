@@ -161,8 +161,9 @@ enum BufId {
     B_SLOTS, B_OBS, B_FREQ, B_AABB, B_TCOUNT, B_TCURSOR, B_TOFF, B_TLIST, B_KEYS, B_RSF,
     B_RSD, B_RSM, B_RSH, B_LIST0, B_LIST1, B_LIST2, B_ALIVE, B_CCOUNT, B_COFF, B_WGC, B_WGO,
     B_RECD, B_RECF, B_SEGB, B_SEGC, B_TPRE, B_TTMP, B_PART, B_EOUT, B_ROUT, B_CNT, B_HITKEY,
-    B_NUMBUF
+    B_MQUEUE, B_NUMBUF
 };
+static_assert(B_NUMBUF <= 34, "workspace ids 34..39 belong to the densified solve");
 
 enum Counter : int {
     C_TILES = 0, C_OVERFLOW, C_N0, C_N1, C_N2, C_WORK, C_CAP, C_BOUNCE0, C_NCOUNT = C_BOUNCE0 + 64
@@ -406,8 +407,8 @@ void Batch::trace(bool with_records) {
         uint32_t* out = lists[b % 2 == 0 ? 1 : 2];
         uint32_t* nout = cnt + (b % 2 == 0 ? C_N1 : C_N2);
         prof_begin();
-        launch_march(dd, cur, ncur, rs, hitkey, b, max_views, cnt + C_CAP, persistent_blocks(),
-                     st);
+        launch_march(dd, cur, ncur, rs, hitkey, b, max_views, cnt + C_CAP,
+                     ws.get<uint32_t>(B_MQUEUE, kNumXcd), persistent_blocks(), st);
         static const char* names[] = {"march_b2", "march_b3", "march_b4", "march_b5", "march_b6",
                                       "march_b7", "march_b8", "march_b9+"};
         prof_end(names[std::min(b - 2, 7)]);
