@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_blend(const SlotDesc* __restrict__ ds,
                     const uint32_t c = ((uint32_t)cz * d.bl_G + cy) * d.bl_G + cx;
                     for (uint32_t j = d.bl_start[c]; j < d.bl_start[c + 1]; j++) {
                         const uint32_t i = d.bl_items[j];
-                        const float4 a = d.pa[i], b = d.pb[i];
+                        const float4 a = gld(d.pa + i), b = gld(d.pb + i);
                         if (b.w != 0.f) continue;  // absorbers neither move nor shade a hit
                         const v3f ci = mkv(a.x, a.y, a.z), ni = mkv(b.x, b.y, b.z);
                         const v3f w = sub(ci, x);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_blend(const SlotDesc* __restrict__ ds,
         if (accw > 0 && l > 0) {
             nn = mkv((float)(sx / l), (float)(sy / l), (float)(sz / l));
         } else {
-            const float4 b = d.pb[bi];
+            const float4 b = gld(d.pb + bi);
             nn = mkv(b.x, b.y, b.z);
             if (vdot(nn, k) > 0.f) nn = scl(nn, -1.f);
         }

@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict
     const uint32_t i = chunk * kChunk + lane;
     int x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
     if (i < d.n_pts) {
-        const Proj p = project(s, d.pa_s[i], d.pb_s[i]);
+        const Proj p = project(s, gld(d.pa_s + i), gld(d.pb_s + i));
         footprint(s, p, x0, y0, x1, y1);
         if (x0 > x1 || y0 > y1) { x0 = y0 = INT_MAX; x1 = y1 = INT_MIN; }
     }
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
         const uint32_t chunk = list[beg + e];
         const uint32_t i = chunk * kChunk + lane;
         if (i >= d.n_pts) continue;
-        const float4 a = d.pa_s[i], b = d.pb_s[i];
+        const float4 a = gld(d.pa_s + i), b = gld(d.pb_s + i);
         const Proj p = project(s, a, b);
         int x0, y0, x1, y1;
         footprint(s, p, x0, y0, x1, y1);
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void k_raster_topk(const SlotDesc* __restrict_
             const uint32_t chunk = list[beg + e];
             const uint32_t i = chunk * kChunk + lane;
             if (i >= d.n_pts) continue;
-            const float4 a = d.pa_s[i], b = d.pb_s[i];
+            const float4 a = gld(d.pa_s + i), b = gld(d.pb_s + i);
             const Proj p = project(s, a, b);
             if (!(p.xk + zoff > 0.f)) continue;
             int x0, y0, x1, y1;

@@ -61,7 +61,7 @@ __device__ inline bool primary_live(const SlotDesc& d, const uint64_t* keys, int
     const uint64_t key = keys[d.pix_base + p];
     if (key == kEmptyKey) return false;
     const uint32_t i = (uint32_t)(key & 0xFFFFFFFFu);
-    return d.pb[i].w == 0.f;  // absorbers end the ray before its first record
+    return gld(d.pb + i).w == 0.f;  // absorbers end the ray before its first record
 }
 
 __global__ __launch_bounds__(256) void k_raygen_count(const SlotDesc* __restrict__ ds,
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict
     const f3 K = mk3(d.k[0], d.k[1], d.k[2]);
     const float ou = (px + 0.5f - 0.5f * d.W) * d.pitch, ov = (py + 0.5f - 0.5f * d.H) * d.pitch;
     const f3 x = U * ou + V * ov + K * (t - d.R);
-    const float4 b = d.pb[i];
+    const float4 b = gld(d.pb + i);
     f3 n = mk3(b.x, b.y, b.z);
     if (dot(n, K) > 0.f) n = n * -1.f;
     st3(rs, RX, g, x);
@@ -176,8 +176,10 @@ struct Walk {
     int ix, iy, px_prev, py_prev, level, it, cap;
 };
 
-__device__ inline bool walk_init(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
-                                 float best_t, Walk& w) {
+__device__ inline bool walk_init(const ViewDesc& Vr, f3 x, f3 k, float tmin, float smax,
+                                 float tol, float best_t, Walk& w) {
+    typedef const __attribute__((address_space(1))) ViewDesc& GView;
+    GView V = (GView)Vr;  // the view table lives in global memory
     const float ip = 1.f / V.pitch;
     const f3 vu = mk3(V.u[0], V.u[1], V.u[2]), vv = mk3(V.v[0], V.v[1], V.v[2]);
     const f3 vk = mk3(V.k[0], V.k[1], V.k[2]);
@@ -230,7 +232,7 @@ __device__ inline bool walk_step(f3 x, f3 k, Walk& w, float& best_t, uint32_t& b
     const float sy = w.db > 0.f ? (yh - w.b0) * w.idb : (w.db < 0.f ? (yl - w.b0) * w.idb : FLT_MAX);
     const float se = fminf(fminf(sx, sy), w.s_hi);
     const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz;
-    const float2 h = w.hiz[hiz_offset(P, w.level) + hiz_texel(P >> w.level, cx, cy)];
+    const float2 h = gld(w.hiz + hiz_offset(P, w.level) + hiz_texel(P >> w.level, cx, cy));
     const bool ov = fmaxf(za, zb) + w.zpad >= h.x && fminf(za, zb) - w.zpad <= h.y;
     if (ov && w.level > 0) {
         w.level--;
@@ -245,11 +247,11 @@ __device__ inline bool walk_step(f3 x, f3 k, Walk& w, float& best_t, uint32_t& b
                 const int px = w.ix + dx;
                 if (px < 0 || px >= W) continue;
                 if (abs(px - w.px_prev) <= 1 && abs(py - w.py_prev) <= 1) continue;
-                const float4 pb = pix[2 * (py * W + px) + 1];
+                const float4 pb = gld(pix + 2 * (py * W + px) + 1);
                 const uint32_t i = __float_as_uint(pb.w);
                 if (i == kNone) continue;
                 float t;
-                if (disk_test(pix[2 * (py * W + px)], pb, x, k, w.tmin, t) &&
+                if (disk_test(gld(pix + 2 * (py * W + px)), pb, x, k, w.tmin, t) &&
                     (t < best_t || (t == best_t && i < best_i))) {
                     // the view retains this disk for hit points within one pixel of where
                     // it is stored (the hit point's own pixel is always on the walk)
@@ -327,7 +329,7 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
     const uint32_t best_i = (uint32_t)(key & 0xFFFFFFFFu);
     if (best_i == kNone) return false;
     const float best_t = __uint_as_float((uint32_t)(key >> 32));
-    const float4 b = d.pb[best_i];
+    const float4 b = gld(d.pb + best_i);
     if (b.w != 0.f) return false;
     f3 nn = mk3(b.x, b.y, b.z);
     if (dot(nn, k) > 0.f) nn = nn * -1.f;
@@ -573,7 +575,7 @@ __device__ bool visible_primary(const SlotDesc& d, const uint64_t* __restrict__ 
             if (key == kEmptyKey) continue;
             const uint32_t i = (uint32_t)(key & 0xFFFFFFFFu);
             float t;
-            if (disk_test(d.pa[i], d.pb[i], x, ks, d.eps, t)) return false;
+            if (disk_test(gld(d.pa + i), gld(d.pb + i), x, ks, d.eps, t)) return false;
         }
     }
     return true;

@@ -32,6 +32,21 @@ struct ViewDesc {
                               // neighbourhood of each stored disk's depth extent
 };
 
+// Loads through the global address space.  Pointers read from descriptors or kept in per-lane
+// state are generic to the compiler, which would otherwise emit flat loads (slower, and counted
+// on two waitcnt queues); the load goes through a native clang vector because HIP's float2 and
+// float4 copy through a generic reference.
+__device__ inline float4 gld(const float4* p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 r = *(const __attribute__((address_space(1))) v4*)p;
+    return make_float4(r.x, r.y, r.z, r.w);
+}
+__device__ inline float2 gld(const float2* p) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 r = *(const __attribute__((address_space(1))) v2*)p;
+    return make_float2(r.x, r.y);
+}
+
 __host__ __device__ inline uint32_t hiz_offset(int P, int l) {
     const uint32_t a = (uint32_t)P * (uint32_t)P, b = (uint32_t)(P >> l) * (uint32_t)(P >> l);
     return 4u * ((a - b) / 3u);
