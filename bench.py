@@ -37,11 +37,11 @@ FP32_LANE_OPS = 256 * 128 * 2.4e9
 # (FETCH_SIZE reads 524302 KiB for 1 GiB: factor 2.0; WRITE_SIZE 1048576 KiB: factor 1.0).
 # Valid only for the sources they were taken on; any edit of those files reports null.
 MARCH_TRAFFIC = dict(
-    fetch_kib=1049628.9, write_kib=27180.4, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=1053280.6, write_kib=27113.3, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_trace.hip":
-             "9653e9ce7de4151b2af8ce080bc43ed48e2e0edc21725f3505035721c4c7726e",
+             "4bfd27a0c717df2671c6cbc2e975b209ea3121a167abb2b176bb872fc0e4cd39",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "f6fbfbdbf567b8939718ba1efdea3c49876f332cc93d03ad662b6470ea2ecae8"})
+             "786a15ab8e5c679d9197e41692c2317faa24f153480d41b05948dd918664cb6c"})
 
 
 def march_traffic():
@@ -88,8 +88,12 @@ def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
     from a resident pool (composite generator, N log-uniform in [5e4, 4e6]), screens uniform in
     {256, 512, 1024, 2048}^2, angle counts log-uniform in [1, 720], frequency counts log-uniform
     in [1, 128] (2-12 GHz), 1-5 bounces.  Phase 1 submits a closed batch of requests at once
-    (saturation: solves/s the GPU sustains); phase 2 offers Poisson arrivals at 70 % of that
-    rate for `seconds` and reports latency percentiles from submit to completion."""
+    (saturation: solves/s and work/s the GPU sustains); phase 2 offers Poisson arrivals for
+    `seconds` at 70 % of the saturated work rate and reports latency percentiles from submit
+    to completion.  Work per request follows a cost model, pixels x angles x (bounces +
+    frequencies / 16), whose mean over the mix is estimated from 20000 draws; the request
+    sizes span five orders of magnitude, so a rate set from request counts alone would offer a
+    load that depends on which few large requests the saturation sample happened to hold."""
     import numpy as np
     import scenes
     rng = np.random.default_rng(seed)
@@ -117,8 +121,17 @@ def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
         s, inc, freq, screen, B, eps = r
         return pe.submit(ctx, s, inc, freq, screen, max_bounces=B, eps=eps)
 
+    def work(screen, n_ang, n_f, B):
+        return float(screen) ** 2 * n_ang * (B + n_f / 16.0)
+
+    mrng = np.random.default_rng(seed + 1)
+    mean_work = float(np.mean([work(mrng.choice([256, 512, 1024, 2048]),
+                                    int(np.exp(mrng.uniform(0.0, np.log(720.0)))),
+                                    int(np.exp(mrng.uniform(0.0, np.log(128.0)))),
+                                    int(mrng.integers(1, 6))) for _ in range(20000)]))
+
     # phase 1: saturation
-    reqs = [request() for _ in range(24)]
+    reqs = [request() for _ in range(64)]
     pe.server_stats(ctx, reset=True)
     t0 = time.perf_counter()
     ts = [submit(r) for r in reqs]
@@ -128,11 +141,12 @@ def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
         samples += len(r[1]) * len(r[2])
     dt = time.perf_counter() - t0
     cap = len(reqs) / dt
+    work_rate = sum(work(r[3], len(r[1]), len(r[2]), r[4]) for r in reqs) / dt
     sat = pe.server_stats(ctx, reset=True)
     if log:
         log(f"serving saturation: {len(reqs)} requests in {dt:.2f} s ({cap:.2f} solves/s)")
-    # phase 2: Poisson arrivals at 70 % of capacity
-    rate = 0.7 * cap
+    # phase 2: Poisson arrivals offering 70 % of the saturated work rate
+    rate = 0.7 * work_rate / mean_work
     arrivals = []
     t = 0.0
     while t < seconds:
@@ -157,10 +171,11 @@ def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
                 offered_rate_per_s=rate, requests=len(ts), completed=st["completed"],
                 p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
                 max_concurrent=st["max_concurrent"], reqs_per_batch=st["reqs_per_batch"],
-                window_s=dt2,
-                note="workload request mix (scene pool of %d); Poisson at 70%% of the measured "
-                     "saturation rate; 200 req/s of this mix is %.0fx one GPU's capacity"
-                     % (len(pool), 200.0 / cap))
+                window_s=dt2, capacity_for_mix_per_s=work_rate / mean_work,
+                note="workload request mix (scene pool of %d); Poisson arrivals offering 70%% of "
+                     "the saturated work rate (cost model pixels x angles x (bounces + freqs/16)); "
+                     "200 req/s of this mix is %.0fx one GPU's capacity"
+                     % (len(pool), 200.0 * mean_work / work_rate))
 
 
 # Dense MFMA flops of one densifier forward pass at base 32 from a coarse h x w input
