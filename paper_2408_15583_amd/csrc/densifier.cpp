@@ -356,8 +356,8 @@ struct pe_densifier_s {
         // depthwise 7x7
         launch_dw_dgrad(A.ddw, N, H, W, c, dwt[l], A.dxdw, st);
         {
-            const int rows = 1, nch = N * H;  // one image row per partial
-            launch_dw_wgrad(A.bx[l], A.ddw, N, H, W, c, rows, A.part, st);
+            const int nch = dw_wgrad_chunks(N, H, W, c);  // image row (segments) per partial
+            launch_dw_wgrad_auto(A.bx[l], A.ddw, N, H, W, c, A.part, st);
             launch_reduce_chunks(A.part, nch, (size_t)50 * c, (size_t)49 * c, 49, 50, 0, G(b.dww), st);
             launch_reduce_chunks(A.part, nch, (size_t)50 * c, c, 1, 50, 49, G(b.dwb), st);
         }
@@ -477,7 +477,7 @@ size_t pe_densifier_s::part_floats(int N, int H, int W) const {
         convp(enc[l].pw2, M);
         if (l > 0) convp(down[l], M);
         best = std::max(best, (size_t)((M + kRowChunk - 1) / kRowChunk) * 2 * c);
-        best = std::max(best, (size_t)(N * Hl) * 50 * c);
+        best = std::max(best, (size_t)dw_wgrad_chunks(N, Hl, Wl, c) * 50 * c);
     }
     for (int h = 0; h < kHeads; h++) {
         for (int l = 1; l < 4; l++) {

@@ -775,6 +775,99 @@ void launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, int N, int H, int W,
                        x, dy, N, H, W, C, rows, part);
 }
 
+// The same partials per (image row, segment of kDwSeg pixels): one thread per (chunk, tap row
+// a, 8 channels) slides a 7-pixel window of the input row yy + a - 3 along its segment, so each
+// input and output-gradient value is loaded once per thread (16-byte loads) and used for 7 taps
+// x 8 channels; the a = 0 thread also sums the bias gradient.  C % 8 == 0.
+__global__ __launch_bounds__(256, 2) void k_dw_wgrad8(const uint16_t* __restrict__ x,
+                                                      const uint16_t* __restrict__ dy, int N,
+                                                      int H, int W, int C,
+                                                      float* __restrict__ part) {
+    const uint32_t G = (uint32_t)C / 8, nseg = (uint32_t)(W + kDwSeg - 1) / kDwSeg;
+    const uint32_t n = (uint32_t)N * H * nseg * 7 * G;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t g = i % G;
+        uint32_t t = i / G;
+        const int a = (int)(t % 7);
+        t /= 7;
+        const uint32_t sg = t % nseg, r = t / nseg, chunk = t;
+        const int bn = (int)(r / (uint32_t)H), yy = (int)(r % (uint32_t)H), yi = yy + a - 3;
+        const int c0 = (int)g * 8, xs = (int)sg * kDwSeg, xe = min(W, xs + kDwSeg);
+        const bool rowok = yi >= 0 && yi < H;
+        float acc[7][8], bsum[8];
+#pragma unroll
+        for (int q = 0; q < 7; q++)
+#pragma unroll
+            for (int k = 0; k < 8; k++) acc[q][k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; k++) bsum[k] = 0.f;
+        if (rowok || a == 0) {
+            const uint16_t* xrow = x + ((size_t)(bn * H + (rowok ? yi : 0)) * W) * C + c0;
+            auto ldx = [&](int xi, float* o) {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (rowok && xi >= 0 && xi < W) v = *(const uint4*)(xrow + (size_t)xi * C);
+                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    o[2 * e] = bf2f((uint16_t)(w4[e] & 0xFFFFu));
+                    o[2 * e + 1] = bf2f((uint16_t)(w4[e] >> 16));
+                }
+            };
+            float win[7][8];
+#pragma unroll
+            for (int q = 0; q < 7; q++) ldx(xs + q - 3, win[q]);
+            const uint16_t* drow = dy + ((size_t)r * W) * C + c0;
+            for (int xx = xs; xx < xe; xx++) {
+                const uint4 dv = *(const uint4*)(drow + (size_t)xx * C);
+                const uint32_t d4[4] = {dv.x, dv.y, dv.z, dv.w};
+                float d[8];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    d[2 * e] = bf2f((uint16_t)(d4[e] & 0xFFFFu));
+                    d[2 * e + 1] = bf2f((uint16_t)(d4[e] >> 16));
+                }
+#pragma unroll
+                for (int k = 0; k < 8; k++) bsum[k] += d[k];
+#pragma unroll
+                for (int q = 0; q < 7; q++)
+#pragma unroll
+                    for (int k = 0; k < 8; k++) acc[q][k] += d[k] * win[q][k];
+#pragma unroll
+                for (int q = 0; q < 6; q++)
+#pragma unroll
+                    for (int k = 0; k < 8; k++) win[q][k] = win[q + 1][k];
+                ldx(xx + 4, win[6]);
+            }
+        }
+        float* out = part + ((size_t)chunk * C + c0) * 50;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+#pragma unroll
+            for (int q = 0; q < 7; q++) out[(size_t)k * 50 + a * 7 + q] = acc[q][k];
+            if (a == 0) out[(size_t)k * 50 + 49] = bsum[k];
+        }
+    }
+}
+
+static bool dw_wgrad8_ok(int N, int H, int W, int C) {
+    return C % 8 == 0 && (uint64_t)N * H * W * C < (1ull << 31);
+}
+
+int dw_wgrad_chunks(int N, int H, int W, int C) {
+    return dw_wgrad8_ok(N, H, W, C) ? N * H * ((W + kDwSeg - 1) / kDwSeg) : N * H;
+}
+
+void launch_dw_wgrad_auto(const uint16_t* x, const uint16_t* dy, int N, int H, int W, int C,
+                          float* part, hipStream_t st) {
+    if (dw_wgrad8_ok(N, H, W, C)) {
+        const size_t n = (size_t)dw_wgrad_chunks(N, H, W, C) * 7 * (C / 8);
+        const int bl = (int)std::min<size_t>(16384, (n + 255) / 256);
+        hipLaunchKernelGGL(k_dw_wgrad8, dim3(bl), dim3(256), 0, st, x, dy, N, H, W, C, part);
+        return;
+    }
+    launch_dw_wgrad(x, dy, N, H, W, C, 1, part, st);
+}
+
 // LayerNorm over C per pixel (one wavefront per pixel): y = (x - mu) rstd * g + b; saves
 // mu and rstd.
 __global__ void k_ln_fwd(const uint16_t* __restrict__ x, int M, int C, const float* __restrict__ g,

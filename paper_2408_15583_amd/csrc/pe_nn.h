@@ -72,6 +72,12 @@ void launch_dw_dgrad(const uint16_t* dy, int N, int H, int W, int C, const float
                      hipStream_t st);
 void launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, int N, int H, int W, int C, int rows,
                      float* part, hipStream_t st);
+// Depthwise weight/bias gradient partials [chunks][C][49 taps + bias] with the fastest kernel
+// for the shape; dw_wgrad_chunks gives the number of chunks it writes.
+constexpr int kDwSeg = 64;  // pixels of a row per partial in the sliding-window kernel
+int dw_wgrad_chunks(int N, int H, int W, int C);
+void launch_dw_wgrad_auto(const uint16_t* x, const uint16_t* dy, int N, int H, int W, int C,
+                          float* part, hipStream_t st);
 void launch_ln_fwd(const uint16_t* x, int M, int C, const float* g, const float* b, float eps,
                    uint16_t* y, float* stats, hipStream_t st);
 void launch_ln_bwd(const uint16_t* x, const uint16_t* dy, int M, int C, const float* g,
