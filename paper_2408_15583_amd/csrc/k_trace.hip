@@ -176,13 +176,37 @@ struct Walk {
     int ix, iy, px_prev, py_prev, level, it, cap;
 };
 
-__device__ inline bool walk_init(const ViewDesc& Vr, f3 x, f3 k, float tmin, float smax,
-                                 float tol, float best_t, Walk& w) {
+// The fields of a view descriptor a walk starts from, read in one round of loads.
+struct ViewFields {
+    f3 u, v, k;
+    float pitch, R;
+    int W, H, P, lp;
+    const float2* hiz;
+    const float4* pix;
+};
+
+__device__ inline ViewFields view_fields(const ViewDesc& Vr) {
     typedef const __attribute__((address_space(1))) ViewDesc& GView;
     GView V = (GView)Vr;  // the view table lives in global memory
+    ViewFields f;
+    f.u = mk3(V.u[0], V.u[1], V.u[2]);
+    f.v = mk3(V.v[0], V.v[1], V.v[2]);
+    f.k = mk3(V.k[0], V.k[1], V.k[2]);
+    f.pitch = V.pitch;
+    f.R = V.R;
+    f.W = V.W;
+    f.H = V.H;
+    f.P = V.P;
+    f.lp = V.lp;
+    f.hiz = V.hiz;
+    f.pix = V.pix;
+    return f;
+}
+
+__device__ inline bool walk_init(const ViewFields& V, f3 x, f3 k, float tmin, float smax,
+                                 float tol, float best_t, Walk& w) {
     const float ip = 1.f / V.pitch;
-    const f3 vu = mk3(V.u[0], V.u[1], V.u[2]), vv = mk3(V.v[0], V.v[1], V.v[2]);
-    const f3 vk = mk3(V.k[0], V.k[1], V.k[2]);
+    const f3 vu = V.u, vv = V.v, vk = V.k;
     const int W = V.W, H = V.H;
     w.hiz = V.hiz;
     w.pix = V.pix;
@@ -217,56 +241,10 @@ __device__ inline bool walk_init(const ViewDesc& Vr, f3 x, f3 k, float tmin, flo
     return true;
 }
 
-// One cell of the walk; false once the walk is over.
-__device__ inline bool walk_step(f3 x, f3 k, Walk& w, float& best_t, uint32_t& best_i,
-                                 uint32_t* cap_hits) {
-    if (w.it++ > w.cap) {
-        atomicAdd(cap_hits, 1u);
-        return false;
-    }
-    const int W = w.W, H = w.H, P = w.P;
-    const int cx = w.ix >> w.level, cy = w.iy >> w.level;
-    const int xl = cx << w.level, xh = min((cx + 1) << w.level, W);
-    const int yl = cy << w.level, yh = min((cy + 1) << w.level, H);
-    const float sx = w.da > 0.f ? (xh - w.a0) * w.ida : (w.da < 0.f ? (xl - w.a0) * w.ida : FLT_MAX);
-    const float sy = w.db > 0.f ? (yh - w.b0) * w.idb : (w.db < 0.f ? (yl - w.b0) * w.idb : FLT_MAX);
-    const float se = fminf(fminf(sx, sy), w.s_hi);
-    const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz;
-    const float2 h = gld(w.hiz + hiz_offset(P, w.level) + hiz_texel(P >> w.level, cx, cy));
-    const bool ov = fmaxf(za, zb) + w.zpad >= h.x && fminf(za, zb) - w.zpad <= h.y;
-    if (ov && w.level > 0) {
-        w.level--;
-        return true;
-    }
-    if (ov) {
-        const float4* __restrict__ pix = w.pix;
-        for (int dy = -1; dy <= 1; dy++) {
-            const int py = w.iy + dy;
-            if (py < 0 || py >= H) continue;
-            for (int dx = -1; dx <= 1; dx++) {
-                const int px = w.ix + dx;
-                if (px < 0 || px >= W) continue;
-                if (abs(px - w.px_prev) <= 1 && abs(py - w.py_prev) <= 1) continue;
-                const float4 pb = gld(pix + 2 * (py * W + px) + 1);
-                const uint32_t i = __float_as_uint(pb.w);
-                if (i == kNone) continue;
-                float t;
-                if (disk_test(gld(pix + 2 * (py * W + px)), pb, x, k, w.tmin, t) &&
-                    (t < best_t || (t == best_t && i < best_i))) {
-                    // the view retains this disk for hit points within one pixel of where
-                    // it is stored (the hit point's own pixel is always on the walk)
-                    const int ha = (int)floorf(w.a0 + t * w.da), hb = (int)floorf(w.b0 + t * w.db);
-                    if (abs(ha - px) <= 1 && abs(hb - py) <= 1) {
-                        best_t = t;
-                        best_i = i;
-                    }
-                }
-            }
-        }
-        w.px_prev = w.ix;
-        w.py_prev = w.iy;
-        w.s_hi = fminf(w.s_hi, best_t);
-    }
+// Moves the walk past the cell [xl, xh) x [yl, yh) whose exit is at se (sx, sy: exits through
+// the x and y sides); false once the walk is over.
+__device__ inline bool walk_advance(Walk& w, float sx, float sy, float se, int xl, int xh, int yl,
+                                    int yh) {
     if (se >= w.s_hi) return false;
     if (sx <= sy) {
         w.ix = w.da > 0.f ? xh : xl - 1;
@@ -275,16 +253,116 @@ __device__ inline bool walk_step(f3 x, f3 k, Walk& w, float& best_t, uint32_t& b
         w.iy = w.db > 0.f ? yh : yl - 1;
         w.ix = min(max((int)floorf(w.a0 + se * w.da), xl), xh - 1);
     }
-    if (w.ix < 0 || w.ix >= W || w.iy < 0 || w.iy >= H) return false;
+    if (w.ix < 0 || w.ix >= w.W || w.iy < 0 || w.iy >= w.H) return false;
     w.s = se;
     if (w.level < w.lp) w.level++;
     return true;
 }
 
+__device__ inline void cell_exits(const Walk& w, int xl, int xh, int yl, int yh, float& sx,
+                                  float& sy, float& se) {
+    sx = w.da > 0.f ? (xh - w.a0) * w.ida : (w.da < 0.f ? (xl - w.a0) * w.ida : FLT_MAX);
+    sy = w.db > 0.f ? (yh - w.b0) * w.idb : (w.db < 0.f ? (yl - w.b0) * w.idb : FLT_MAX);
+    se = fminf(fminf(sx, sy), w.s_hi);
+}
+
+enum { kWalkOver = 0, kWalkMoved = 1, kWalkRefine = 2 };
+
+// Probe of the walk's current cell against the pyramid: the walk descends on overlap above
+// level 0, moves on past a cell it misses, and at an overlapping level-0 cell reports that the
+// exact 3x3 refinement (walk_refine) is due before it moves on.
+__device__ inline int walk_probe(Walk& w, uint32_t* cap_hits) {
+    if (w.it++ > w.cap) {
+        atomicAdd(cap_hits, 1u);
+        return kWalkOver;
+    }
+    const int W = w.W, H = w.H, P = w.P;
+    const int cx = w.ix >> w.level, cy = w.iy >> w.level;
+    const int xl = cx << w.level, xh = min((cx + 1) << w.level, W);
+    const int yl = cy << w.level, yh = min((cy + 1) << w.level, H);
+    float sx, sy, se;
+    cell_exits(w, xl, xh, yl, yh, sx, sy, se);
+    const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz;
+    const float2 h = gld(w.hiz + hiz_offset(P, w.level) + hiz_texel(P >> w.level, cx, cy));
+    const bool ov = fmaxf(za, zb) + w.zpad >= h.x && fminf(za, zb) - w.zpad <= h.y;
+    if (ov && w.level > 0) {
+        w.level--;
+        return kWalkMoved;
+    }
+    if (ov) return kWalkRefine;
+    return walk_advance(w, sx, sy, se, xl, xh, yl, yh) ? kWalkMoved : kWalkOver;
+}
+
+// The exact test of the 3x3 block around the walk's level-0 cell, then the move past the cell;
+// false once the walk is over.
+__device__ inline bool walk_refine(f3 x, f3 k, Walk& w, float& best_t, uint32_t& best_i) {
+    const int W = w.W, H = w.H;
+    const int xl = w.ix, xh = min(w.ix + 1, W), yl = w.iy, yh = min(w.iy + 1, H);
+    float sx, sy, se;
+    cell_exits(w, xl, xh, yl, yh, sx, sy, se);
+    // The pixels of the 3x3 block not tested in the previous block, one line of three at a
+    // time with all of a line's records requested before any is used (one memory round trip
+    // per line).  Lines are columns when the walk moved along x, since the new pixels then
+    // form one column, and rows otherwise.  The kept hit is the minimum of (t, index) over
+    // retained hits, so the visiting order does not change it.
+    const float4* __restrict__ pix = w.pix;
+    const bool cols = w.iy == w.py_prev;
+    for (int l = -1; l <= 1; l++) {
+        float4 ra[3], rb[3];
+        bool use[3];
+        int qx[3], qy[3];
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+            qx[m] = w.ix + (cols ? l : m - 1);
+            qy[m] = w.iy + (cols ? m - 1 : l);
+            use[m] = qx[m] >= 0 && qx[m] < W && qy[m] >= 0 && qy[m] < H &&
+                     !(abs(qx[m] - w.px_prev) <= 1 && abs(qy[m] - w.py_prev) <= 1);
+            any |= use[m];
+        }
+        if (!any) continue;
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+            // unused slots read the walk's own pixel, which is in bounds
+            const int q = use[m] ? qy[m] * W + qx[m] : w.iy * W + w.ix;
+            ra[m] = gld(pix + 2 * q);
+            rb[m] = gld(pix + 2 * q + 1);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+            const uint32_t i = __float_as_uint(rb[m].w);
+            if (!use[m] || i == kNone) continue;
+            float t;
+            if (disk_test(ra[m], rb[m], x, k, w.tmin, t) &&
+                (t < best_t || (t == best_t && i < best_i))) {
+                // the view retains this disk for hit points within one pixel of where it is
+                // stored (the hit point's own pixel is always on the walk)
+                const int ha = (int)floorf(w.a0 + t * w.da), hb = (int)floorf(w.b0 + t * w.db);
+                if (abs(ha - qx[m]) <= 1 && abs(hb - qy[m]) <= 1) {
+                    best_t = t;
+                    best_i = i;
+                }
+            }
+        }
+    }
+    w.px_prev = w.ix;
+    w.py_prev = w.iy;
+    w.s_hi = fminf(w.s_hi, best_t);
+    return walk_advance(w, sx, sy, se, xl, xh, yl, yh);
+}
+
+// One cell of the walk; false once the walk is over.
+__device__ inline bool walk_step(f3 x, f3 k, Walk& w, float& best_t, uint32_t& best_i,
+                                 uint32_t* cap_hits) {
+    const int r = walk_probe(w, cap_hits);
+    if (r == kWalkRefine) return walk_refine(x, k, w, best_t, best_i);
+    return r == kWalkMoved;
+}
+
 __device__ void march_view(const ViewDesc& V, f3 x, f3 k, float tmin, float smax, float tol,
                            float& best_t, uint32_t& best_i, uint32_t* cap_hits) {
     Walk w;
-    if (!walk_init(V, x, k, tmin, smax, tol, best_t, w)) return;
+    if (!walk_init(view_fields(V), x, k, tmin, smax, tol, best_t, w)) return;
     while (walk_step(x, k, w, best_t, best_i, cap_hits)) {
     }
 }
@@ -296,9 +374,13 @@ __device__ inline float sphere_exit(f3 x, f3 k, float R) {
 }
 
 // fp32 tolerance of depth comparisons in the march (scene-size relative).
-__device__ inline float march_tol(const SlotDesc& d) { return 4e-6f * d.R; }
+__device__ inline float march_tol(float R) { return 4e-6f * R; }
+__device__ inline float march_tol(const SlotDesc& d) { return march_tol(d.R); }
+__device__ inline float march_smax(float R, float r_max, f3 x, f3 k) {
+    return sphere_exit(x, k, R * 1.0001f) + 2.f * r_max;
+}
 __device__ inline float march_smax(const SlotDesc& d, f3 x, f3 k) {
-    return sphere_exit(x, k, d.R * 1.0001f) + 2.f * d.r_max;
+    return march_smax(d.R, d.r_max, x, k);
 }
 
 // Nearest hit of the ray (x, k) beyond tmin over all aggregation views, one lane (used for the
@@ -347,6 +429,11 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
     return true;
 }
 
+// A wavefront runs its pending refinements once kRefineBatch lanes wait for one, or once the
+// waiting lanes are at least 1 / kRefineRatio of its busy lanes.
+constexpr int kRefineBatch = 16;
+constexpr int kRefineRatio = 2;
+
 // One bounce, pass 1: the (view, ray) walks of the live list, view-major, each XCD taking a
 // contiguous eighth so that its L2 serves few views at a time (and then helping the other
 // XCDs once its own eighth is drained).  Lanes run walks independently: a lane that finishes
@@ -373,11 +460,11 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
     uint64_t q0 = (total * src) / kNumXcd, q1 = (total * (src + 1)) / kNumXcd;
     bool active = false, exhausted = total == 0;
     uint32_t e = 0;
-    const SlotDesc* d = ds;
     f3 x = mk3(0.f, 0.f, 0.f), k = x;
     float bt = FLT_MAX;
     uint32_t bi = kNone;
-    uint64_t known = kEmptyKey;
+    uint32_t known_i = kNone;  // index of the published hit the walk started from
+    bool pend = false;         // the walk waits for its level-0 refinement
     Walk w;
     for (;;) {
         const uint64_t idle = __ballot(!active);
@@ -391,25 +478,42 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                 if (j < q1) {
                     const uint32_t v = (uint32_t)(j / n);
                     e = (uint32_t)(j - (uint64_t)v * n);
+                    // three rounds of dependent loads: the entry and the best hit other views
+                    // have already published for the ray; the slot's fields; the ray state and
+                    // the view's descriptor
                     const uint32_t entry = list[e];
-                    d = &ds[entry_slot(entry)];
-                    if (bounce <= d->max_b && (int)v < d->n_views) {
-                        const uint64_t g = d->pix_base + entry_pix(entry);
-                        x = ld3(rs, RX, g);
-                        const f3 nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                    const uint64_t known = __hip_atomic_load(&hitkey[e], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                    typedef const __attribute__((address_space(1))) SlotDesc& GSlot;
+                    GSlot sd = (GSlot)ds[entry_slot(entry)];
+                    int max_b = sd.max_b, n_views = sd.n_views;
+                    uint64_t pix_base = sd.pix_base;
+                    const ViewDesc* views = sd.views;
+                    float eps = sd.eps, R = sd.R, r_max = sd.r_max;
+                    // keep the compiler from sinking these loads into their later uses (which
+                    // would make them rounds of their own)
+                    asm volatile("" : "+v"(max_b), "+v"(n_views), "+v"(pix_base), "+v"(views),
+                                 "+v"(eps), "+v"(R), "+v"(r_max));
+                    // the ray state is read whatever the guard says (the entry's pixel is
+                    // always in range), so that it shares a round with the view's descriptor
+                    const bool take = (bounce <= max_b) & ((int)v < n_views);
+                    const uint64_t g = pix_base + entry_pix(entry);
+                    const f3 xs = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                    bt = FLT_MAX;
+                    bi = kNone;
+                    if (known != kEmptyKey) {
+                        bt = __uint_as_float((uint32_t)(known >> 32));
+                        bi = (uint32_t)(known & 0xFFFFFFFFu);
+                    }
+                    known_i = bi;
+                    if (take) {
+                        const ViewFields vf = view_fields(views[v]);
+                        __builtin_amdgcn_sched_barrier(0);  // issue these before waiting above
+                        x = xs;
                         k = mirror(kin, nn);
                         k = k * rsqrtf(dot(k, k));
-                        // start from the best hit other views have already published
-                        known = __hip_atomic_load(&hitkey[e], __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                        bt = FLT_MAX;
-                        bi = kNone;
-                        if (known != kEmptyKey) {
-                            bt = __uint_as_float((uint32_t)(known >> 32));
-                            bi = (uint32_t)(known & 0xFFFFFFFFu);
-                        }
-                        active = walk_init(d->views[v], x, k, d->eps, march_smax(*d, x, k),
-                                           march_tol(*d), bt, w);
+                        active = walk_init(vf, x, k, eps, march_smax(R, r_max, x, k),
+                                           march_tol(R), bt, w);
                     }
                 }
             }
@@ -425,12 +529,31 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
             }
         }
         if (exhausted && __ballot(active) == 0ull) break;
-        if (active) {
-            if (!walk_step(x, k, w, bt, bi, cap_hits)) {
-                active = false;
-                if (bi != kNone && pack_hit(bt, bi) < known)
-                    atomicMin((unsigned long long*)&hitkey[e], (unsigned long long)pack_hit(bt, bi));
+        bool over = false;
+        if (active && !pend) {
+            const int r = walk_probe(w, cap_hits);
+            pend = r == kWalkRefine;
+            over = r == kWalkOver;
+        }
+        // Refinements wait until enough lanes of the wavefront need one, so that the long
+        // refinement path runs for many lanes at once instead of stalling the traversal of
+        // all the others at nearly every step.
+        const int n_pend = __popcll(__ballot(pend));
+        if (n_pend > 0) {
+            const int n_busy = __popcll(__ballot(active));
+            if (n_pend >= kRefineBatch || kRefineRatio * n_pend >= n_busy) {
+                if (pend) {
+                    pend = false;
+                    over = !walk_refine(x, k, w, bt, bi);
+                }
             }
+        }
+        if (over) {
+            active = false;
+            // a walk keeps only strictly better hits than the one it started from, and one
+            // disk always gives one t, so a changed index is an improvement
+            if (bi != known_i)
+                atomicMin((unsigned long long*)&hitkey[e], (unsigned long long)pack_hit(bt, bi));
         }
     }
 }
