@@ -241,28 +241,36 @@ __device__ inline bool walk_init(const ViewFields& V, f3 x, f3 k, float tmin, fl
     return true;
 }
 
-// Moves the walk past the cell [xl, xh) x [yl, yh) whose exit is at se (sx, sy: exits through
-// the x and y sides); false once the walk is over.
+// The cell after [xl, xh) x [yl, yh) whose exit is at se (sx, sy: exits through the x and y
+// sides); false when the walk ends there.  Written with selects, not branches: lanes of a
+// wavefront take both sides at once.
+__device__ inline bool cell_next(const Walk& w, float sx, float sy, float se, int xl, int xh,
+                                 int yl, int yh, int& nix, int& niy) {
+    const bool along_x = sx <= sy;
+    const int cxn = min(max((int)floorf(w.a0 + se * w.da), xl), xh - 1);
+    const int cyn = min(max((int)floorf(w.b0 + se * w.db), yl), yh - 1);
+    nix = along_x ? (w.da > 0.f ? xh : xl - 1) : cxn;
+    niy = along_x ? cyn : (w.db > 0.f ? yh : yl - 1);
+    return (se < w.s_hi) & (nix >= 0) & (nix < w.W) & (niy >= 0) & (niy < w.H);
+}
+
+// Moves the walk past its current cell (see cell_next); false once the walk is over.
 __device__ inline bool walk_advance(Walk& w, float sx, float sy, float se, int xl, int xh, int yl,
                                     int yh) {
-    if (se >= w.s_hi) return false;
-    if (sx <= sy) {
-        w.ix = w.da > 0.f ? xh : xl - 1;
-        w.iy = min(max((int)floorf(w.b0 + se * w.db), yl), yh - 1);
-    } else {
-        w.iy = w.db > 0.f ? yh : yl - 1;
-        w.ix = min(max((int)floorf(w.a0 + se * w.da), xl), xh - 1);
-    }
-    if (w.ix < 0 || w.ix >= w.W || w.iy < 0 || w.iy >= w.H) return false;
+    int nix, niy;
+    if (!cell_next(w, sx, sy, se, xl, xh, yl, yh, nix, niy)) return false;
+    w.ix = nix;
+    w.iy = niy;
     w.s = se;
-    if (w.level < w.lp) w.level++;
+    w.level = min(w.level + 1, w.lp);
     return true;
 }
 
 __device__ inline void cell_exits(const Walk& w, int xl, int xh, int yl, int yh, float& sx,
                                   float& sy, float& se) {
-    sx = w.da > 0.f ? (xh - w.a0) * w.ida : (w.da < 0.f ? (xl - w.a0) * w.ida : FLT_MAX);
-    sy = w.db > 0.f ? (yh - w.b0) * w.idb : (w.db < 0.f ? (yl - w.b0) * w.idb : FLT_MAX);
+    const float bx = (float)(w.da > 0.f ? xh : xl), by = (float)(w.db > 0.f ? yh : yl);
+    sx = w.da != 0.f ? (bx - w.a0) * w.ida : FLT_MAX;
+    sy = w.db != 0.f ? (by - w.b0) * w.idb : FLT_MAX;
     se = fminf(fminf(sx, sy), w.s_hi);
 }
 
@@ -270,27 +278,30 @@ enum { kWalkOver = 0, kWalkMoved = 1, kWalkRefine = 2 };
 
 // Probe of the walk's current cell against the pyramid: the walk descends on overlap above
 // level 0, moves on past a cell it misses, and at an overlapping level-0 cell reports that the
-// exact 3x3 refinement (walk_refine) is due before it moves on.
+// exact 3x3 refinement (walk_refine) is due before it moves on.  The outcome is applied with
+// selects.
 __device__ inline int walk_probe(Walk& w, uint32_t* cap_hits) {
     if (w.it++ > w.cap) {
         atomicAdd(cap_hits, 1u);
         return kWalkOver;
     }
-    const int W = w.W, H = w.H, P = w.P;
-    const int cx = w.ix >> w.level, cy = w.iy >> w.level;
-    const int xl = cx << w.level, xh = min((cx + 1) << w.level, W);
-    const int yl = cy << w.level, yh = min((cy + 1) << w.level, H);
+    const int W = w.W, H = w.H, P = w.P, lv = w.level;
+    const int cx = w.ix >> lv, cy = w.iy >> lv;
+    const int xl = cx << lv, xh = min((cx + 1) << lv, W);
+    const int yl = cy << lv, yh = min((cy + 1) << lv, H);
     float sx, sy, se;
     cell_exits(w, xl, xh, yl, yh, sx, sy, se);
     const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz;
-    const float2 h = gld(w.hiz + hiz_offset(P, w.level) + hiz_texel(P >> w.level, cx, cy));
-    const bool ov = fmaxf(za, zb) + w.zpad >= h.x && fminf(za, zb) - w.zpad <= h.y;
-    if (ov && w.level > 0) {
-        w.level--;
-        return kWalkMoved;
-    }
-    if (ov) return kWalkRefine;
-    return walk_advance(w, sx, sy, se, xl, xh, yl, yh) ? kWalkMoved : kWalkOver;
+    const float2 h = gld(w.hiz + hiz_offset(P, lv) + hiz_texel(P >> lv, cx, cy));
+    int nix, niy;
+    const bool ok = cell_next(w, sx, sy, se, xl, xh, yl, yh, nix, niy);
+    const bool ov = (fmaxf(za, zb) + w.zpad >= h.x) & (fminf(za, zb) - w.zpad <= h.y);
+    const bool down = ov & (lv > 0), move = !ov & ok;
+    w.level = down ? lv - 1 : (move ? min(lv + 1, w.lp) : lv);
+    w.ix = move ? nix : w.ix;
+    w.iy = move ? niy : w.iy;
+    w.s = move ? se : w.s;
+    return (down | move) ? kWalkMoved : (ov ? kWalkRefine : kWalkOver);
 }
 
 // The exact test of the 3x3 block around the walk's level-0 cell, then the move past the cell;
