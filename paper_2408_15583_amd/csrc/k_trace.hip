@@ -440,6 +440,35 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
     return true;
 }
 
+// Lane-parallel refinement of a wavefront's pending walks: every pending lane publishes its
+// ray, its level-0 cell and the new pixels of its 3x3 block (those outside the previous block)
+// in LDS; then all 64 lanes take the (walk, pixel) candidates in turn, test them exactly and
+// fold retained hits into the owner's packed (t, index) key with an LDS 64-bit minimum (t > 0,
+// so the key order is the order of t, then of the index: the same choice as the serial test).
+struct RefineWave {
+    float prm[64][12];             // x, k, tmin, a0, b0, da, db (owner lane)
+    int cell[64][4];               // ix, iy, W of the owner's view; unused
+    const float4* pix[64];         // the owner's view pixel records
+    unsigned long long key[64];    // the owner's best (t, index) so far
+    uint32_t cand[64 * 9];         // owner lane | (3x3 position << 6)
+};
+
+// The 3x3 positions (bit (dy + 1) * 3 + dx + 1) of the walk's block that are inside the view
+// and outside the previous block.
+__device__ inline uint32_t refine_mask(const Walk& w) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) {
+            const int px = w.ix + dx, py = w.iy + dy;
+            const bool use = (px >= 0) & (px < w.W) & (py >= 0) & (py < w.H) &
+                             !((abs(px - w.px_prev) <= 1) & (abs(py - w.py_prev) <= 1));
+            m |= use ? 1u << ((dy + 1) * 3 + dx + 1) : 0u;
+        }
+    return m;
+}
+
 // A wavefront runs its pending refinements once kRefineBatch lanes wait for one, or once the
 // waiting lanes are at least 1 / kRefineRatio of its busy lanes.
 constexpr int kRefineBatch = 16;
@@ -477,6 +506,8 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
     uint32_t known_i = kNone;  // index of the published hit the walk started from
     bool pend = false;         // the walk waits for its level-0 refinement
     Walk w;
+    __shared__ RefineWave rwave[4];
+    RefineWave& R = rwave[threadIdx.x >> 6];
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int n_idle = __popcll(idle);
@@ -553,9 +584,74 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
         if (n_pend > 0) {
             const int n_busy = __popcll(__ballot(active));
             if (n_pend >= kRefineBatch || kRefineRatio * n_pend >= n_busy) {
+                uint32_t m = 0;
+                if (pend) {
+                    m = refine_mask(w);
+                    float* pr = R.prm[lane];
+                    pr[0] = x.x; pr[1] = x.y; pr[2] = x.z;
+                    pr[3] = k.x; pr[4] = k.y; pr[5] = k.z;
+                    pr[6] = w.tmin; pr[7] = w.a0; pr[8] = w.b0; pr[9] = w.da; pr[10] = w.db;
+                    R.cell[lane][0] = w.ix;
+                    R.cell[lane][1] = w.iy;
+                    R.cell[lane][2] = w.W;
+                    R.pix[lane] = w.pix;
+                    R.key[lane] = pack_hit(bt, bi);
+                }
+                // exclusive scan of the candidate counts over the wavefront
+                const int cnt = __popc(m);
+                int incl = cnt;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o);
+                    if (lane >= o) incl += v;
+                }
+                const int n_cand = __shfl(incl, 63);
+                int off = incl - cnt;
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1;
+                    R.cand[off++] = (uint32_t)lane | ((uint32_t)b << 6);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int j = lane; j < n_cand; j += 64) {
+                    const uint32_t c = R.cand[j];
+                    const int o = (int)(c & 63u), b = (int)(c >> 6);
+                    const float* pr = R.prm[o];
+                    const int qx = R.cell[o][0] + b % 3 - 1, qy = R.cell[o][1] + b / 3 - 1;
+                    const int q = qy * R.cell[o][2] + qx;
+                    const float4* pix = R.pix[o];
+                    const float4 ra = gld(pix + 2 * q), rb = gld(pix + 2 * q + 1);
+                    const uint32_t i = __float_as_uint(rb.w);
+                    float t;
+                    if (i != kNone &&
+                        disk_test(ra, rb, mk3(pr[0], pr[1], pr[2]), mk3(pr[3], pr[4], pr[5]),
+                                  pr[6], t)) {
+                        // retained by the view for hit points within one pixel of where it is
+                        // stored
+                        const int ha = (int)floorf(pr[7] + t * pr[9]);
+                        const int hb = (int)floorf(pr[8] + t * pr[10]);
+                        if (abs(ha - qx) <= 1 && abs(hb - qy) <= 1)
+                            atomicMin(&R.key[o], (unsigned long long)pack_hit(t, i));
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 if (pend) {
                     pend = false;
-                    over = !walk_refine(x, k, w, bt, bi);
+                    const unsigned long long kk = R.key[lane];
+                    bt = __uint_as_float((uint32_t)(kk >> 32));
+                    bi = (uint32_t)(kk & 0xFFFFFFFFu);
+                    const int xl = w.ix, xh = min(w.ix + 1, w.W), yl = w.iy,
+                              yh = min(w.iy + 1, w.H);
+                    float sx, sy, se;
+                    cell_exits(w, xl, xh, yl, yh, sx, sy, se);
+                    w.px_prev = w.ix;
+                    w.py_prev = w.iy;
+                    w.s_hi = fminf(w.s_hi, bt);
+                    over = !walk_advance(w, sx, sy, se, xl, xh, yl, yh);
                 }
             }
         }
