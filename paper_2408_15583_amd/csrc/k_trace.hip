@@ -471,8 +471,8 @@ __device__ inline uint32_t refine_mask(const Walk& w) {
 
 // A wavefront runs its pending refinements once kRefineBatch lanes wait for one, or once the
 // waiting lanes are at least 1 / kRefineRatio of its busy lanes.
-constexpr int kRefineBatch = 16;
-constexpr int kRefineRatio = 2;
+constexpr int kRefineBatch = 8;
+constexpr int kRefineRatio = 4;
 
 // One bounce, pass 1: the (view, ray) walks of the live list, view-major, each XCD taking a
 // contiguous eighth so that its L2 serves few views at a time (and then helping the other
