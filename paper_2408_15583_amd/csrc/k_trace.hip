@@ -278,30 +278,43 @@ enum { kWalkOver = 0, kWalkMoved = 1, kWalkRefine = 2 };
 
 // Probe of the walk's current cell against the pyramid: the walk descends on overlap above
 // level 0, moves on past a cell it misses, and at an overlapping level-0 cell reports that the
-// exact 3x3 refinement (walk_refine) is due before it moves on.  The outcome is applied with
-// selects.
+// exact 3x3 refinement (walk_refine) is due before it moves on.  The texel of the child cell
+// (one level down, holding the walk's pixel) is fetched in the same round trip, so a descent
+// and the step that follows it take one probe: the walk visits the same cells as one level per
+// probe would.  The outcome is applied with selects.
 __device__ inline int walk_probe(Walk& w, uint32_t* cap_hits) {
     if (w.it++ > w.cap) {
         atomicAdd(cap_hits, 1u);
         return kWalkOver;
     }
-    const int W = w.W, H = w.H, P = w.P, lv = w.level;
-    const int cx = w.ix >> lv, cy = w.iy >> lv;
+    const int W = w.W, H = w.H, P = w.P, lv = w.level, lc = max(lv - 1, 0);
+    const int cx = w.ix >> lv, cy = w.iy >> lv, cx2 = w.ix >> lc, cy2 = w.iy >> lc;
+    const float2 h = gld(w.hiz + hiz_offset(P, lv) + hiz_texel(P >> lv, cx, cy));
+    const float2 h2 = gld(w.hiz + hiz_offset(P, lc) + hiz_texel(P >> lc, cx2, cy2));
     const int xl = cx << lv, xh = min((cx + 1) << lv, W);
     const int yl = cy << lv, yh = min((cy + 1) << lv, H);
-    float sx, sy, se;
+    const int xl2 = cx2 << lc, xh2 = min((cx2 + 1) << lc, W);
+    const int yl2 = cy2 << lc, yh2 = min((cy2 + 1) << lc, H);
+    float sx, sy, se, sx2, sy2, se2;
     cell_exits(w, xl, xh, yl, yh, sx, sy, se);
-    const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz;
-    const float2 h = gld(w.hiz + hiz_offset(P, lv) + hiz_texel(P >> lv, cx, cy));
-    int nix, niy;
-    const bool ok = cell_next(w, sx, sy, se, xl, xh, yl, yh, nix, niy);
+    cell_exits(w, xl2, xh2, yl2, yh2, sx2, sy2, se2);
+    const float za = w.z0 + w.s * w.dz, zb = w.z0 + se * w.dz, zb2 = w.z0 + se2 * w.dz;
     const bool ov = (fmaxf(za, zb) + w.zpad >= h.x) & (fminf(za, zb) - w.zpad <= h.y);
-    const bool down = ov & (lv > 0), move = !ov & ok;
-    w.level = down ? lv - 1 : (move ? min(lv + 1, w.lp) : lv);
+    const bool ov2 = (fmaxf(za, zb2) + w.zpad >= h2.x) & (fminf(za, zb2) - w.zpad <= h2.y);
+    // an overlap above level 0 hands the decision to the child cell
+    const bool child = ov & (lv > 0);
+    const int ls = child ? lc : lv;
+    const bool ovs = child ? ov2 : ov;
+    int nix, niy;
+    const float Se = child ? se2 : se;
+    const bool ok = cell_next(w, child ? sx2 : sx, child ? sy2 : sy, Se, child ? xl2 : xl,
+                              child ? xh2 : xh, child ? yl2 : yl, child ? yh2 : yh, nix, niy);
+    const bool down = ovs & (ls > 0), move = !ovs & ok;
+    w.level = down ? ls - 1 : (move ? min(ls + 1, w.lp) : ls);
     w.ix = move ? nix : w.ix;
     w.iy = move ? niy : w.iy;
-    w.s = move ? se : w.s;
-    return (down | move) ? kWalkMoved : (ov ? kWalkRefine : kWalkOver);
+    w.s = move ? Se : w.s;
+    return (down | move) ? kWalkMoved : (ovs ? kWalkRefine : kWalkOver);
 }
 
 // The exact test of the 3x3 block around the walk's level-0 cell, then the move past the cell;
