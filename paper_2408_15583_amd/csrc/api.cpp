@@ -62,11 +62,30 @@ void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene) {
     }
 }
 
-int slots_per_batch(const pe_solve_desc* d) {
-    static const uint64_t target = [] {
+uint64_t batch_bytes_per_pixel(const pe_solve_desc* d) {
+    const uint64_t n_obs = d->obs_dir ? d->n_obs : 1;
+    const uint64_t seg = d->contrib == PE_CONTRIB_EVERY ? d->max_bounces : 1;
+    // ray state, depth, bounce count, hit index, three lists, alive flag, hit key, first-hit key,
+    // compaction counts, exit records
+    return RNCOMP * 4 + 8 + 1 + 4 + 12 + 1 + 8 + 8 + 8 + seg * n_obs * 40;
+}
+
+int slots_per_batch(pe_ctx ctx, const pe_solve_desc* d) {
+    static const uint64_t env = [] {
         const char* e = std::getenv("PE_BATCH_PIXELS");
-        return e ? std::strtoull(e, nullptr, 10) : (uint64_t)1 << 25;
+        return e ? std::strtoull(e, nullptr, 10) : (uint64_t)0;
     }();
+    uint64_t target = env;
+    if (target == 0) {
+        // As many pixels as half of the HBM budget left to this call holds (the default
+        // workspace's own buffers are reused), between 2^22 and 2^29: large batches keep the
+        // later bounces' launches full and amortise each launch's drain.
+        const uint64_t used = ctx->used.load(), held = ctx->ws->bytes();
+        const uint64_t avail = (ctx->budget > used ? ctx->budget - used : 0) + held;
+        target = avail / 2 / (batch_bytes_per_pixel(d) * 9 / 8);
+        target = std::min<uint64_t>(std::max<uint64_t>(target, (uint64_t)1 << 22),
+                                    (uint64_t)1 << 29);
+    }
     const uint64_t px = (uint64_t)d->screen_w * d->screen_h;
     uint64_t s = std::max<uint64_t>(1, target / px);
     s = std::min<uint64_t>(s, (uint64_t)kMaxSlots);
@@ -431,7 +450,7 @@ pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_res
         if (!g_densified_solve) return set_error(PE_EUNSUPPORTED, "densifier module unavailable");
         g_densified_solve(*ctx->ws, st, scene, desc, res->E, res->rcs_dbsm, &acc);
     } else {
-        const int per = slots_per_batch(desc);
+        const int per = slots_per_batch(ctx, desc);
         const int n_obs = desc->obs_dir ? desc->n_obs : 1;
         const uint64_t per_inc = (uint64_t)n_obs * desc->n_freq * 4;
         for (int i0 = 0; i0 < desc->n_inc; i0 += per) {

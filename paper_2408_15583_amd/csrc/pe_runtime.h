@@ -194,7 +194,10 @@ typedef void (*solve_fn)(Workspace& ws, hipStream_t st, pe_scene sc, const pe_so
                          double* E, double* rcs, pe_stats* acc);
 extern solve_fn g_densified_solve;
 void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene = true);
-int slots_per_batch(const pe_solve_desc* d);
+// Device bytes per pixel of a plain batch (before headroom), and the incidences per batch of a
+// synchronous solve.
+uint64_t batch_bytes_per_pixel(const pe_solve_desc* d);
+int slots_per_batch(pe_ctx ctx, const pe_solve_desc* d);
 std::vector<SlotSpec> make_slots(pe_scene sc, const pe_solve_desc* d, int i0, int count);
 void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>& slots,
                      int contrib, int precision, double* E_host, double* rcs_host,

@@ -241,9 +241,7 @@ struct Server {
 // keys, records, PO partials), times the slots it can occupy at once.
 static uint64_t request_footprint(const pe_solve_desc* d) {
     const uint64_t px = (uint64_t)d->screen_w * d->screen_h;
-    const uint64_t n_obs = d->obs_dir ? d->n_obs : 1;
-    const uint64_t seg = d->contrib == PE_CONTRIB_EVERY ? d->max_bounces : 1;
-    const uint64_t per_px = RNCOMP * 4 + 8 + 1 + 4 + 12 + 1 + 8 + 8 + 8 + seg * n_obs * 40;
+    const uint64_t per_px = batch_bytes_per_pixel(d);
     const uint64_t slots = std::min<uint64_t>(d->n_inc, std::max<uint64_t>(1, ((uint64_t)1 << 25) / px));
     return (slots * px * per_px + (64ull << 20)) / 8 * 9;
 }
