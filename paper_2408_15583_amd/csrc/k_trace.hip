@@ -484,16 +484,18 @@ __device__ inline uint32_t refine_mask(const Walk& w) {
 
 // A wavefront runs its pending refinements once kRefineBatch lanes wait for one, or once the
 // waiting lanes are at least 1 / kRefineRatio of its busy lanes.
+constexpr int kRefillIdleFirst = 56;  // idle lanes before a refill, second bounce
+constexpr int kRefillIdle = 48;       // the same for later bounces
 constexpr int kRefineBatch = 8;
 constexpr int kRefineRatio = 4;
 
 // One bounce, pass 1: the (view, ray) walks of the live list, view-major, each XCD taking a
 // contiguous eighth so that its L2 serves few views at a time (and then helping the other
 // XCDs once its own eighth is drained).  Lanes run walks independently: a lane that finishes
-// publishes its hit and, once three quarters of its wavefront are idle, the wavefront takes
-// the next walks with one atomic (consecutive rays of one view, so the new lanes are coherent
-// with each other; refilling earlier trades that coherence for fewer idle lanes and was
-// measured slower).  Each walk starts from the best hit already published
+// publishes its hit and, once most of its wavefront is idle (kRefillIdleFirst / kRefillIdle
+// lanes), the wavefront takes the next walks with one atomic (consecutive rays of one view, so
+// the new lanes are coherent with each other; refilling earlier trades that coherence for
+// fewer idle lanes and was measured slower).  Each walk starts from the best hit already published
 // for its ray and keeps only strictly better (t, index) hits, and the hits fold into the
 // ray's packed t|index key with a 64-bit atomic minimum: the result is the minimum over views
 // whatever the order in which walks run.
@@ -507,6 +509,10 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
     const uint32_t n = *n_live;
     const uint64_t total = (uint64_t)n * (uint32_t)max_views;
     const int lane = threadIdx.x & 63;
+    // Walks right after the primary hits are coherent (neighbouring pixels of one screen): a
+    // wavefront keeps them together by refilling only once most of its lanes are idle.  Later
+    // bounces have scattered directions and gain more from busier lanes than from coherence.
+    const int refill_idle = bounce <= 2 ? kRefillIdleFirst : kRefillIdle;
     // the XCD's own eighth first, then the other eighths in turn (work left at the end)
     uint32_t src = blockIdx.x % kNumXcd;
     int tried = 1;
@@ -524,7 +530,7 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int n_idle = __popcll(idle);
-        if (!exhausted && n_idle >= 48) {
+        if (!exhausted && n_idle >= refill_idle) {
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(queue + src, (uint32_t)n_idle);
             base = __shfl(base, 0);
