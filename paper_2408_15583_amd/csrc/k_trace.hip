@@ -459,11 +459,11 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
 // fold retained hits into the owner's packed (t, index) key with an LDS 64-bit minimum (t > 0,
 // so the key order is the order of t, then of the index: the same choice as the serial test).
 struct RefineWave {
-    float prm[64][12];             // x, k, tmin, a0, b0, da, db (owner lane)
-    int cell[64][4];               // ix, iy, W of the owner's view; unused
+    float prm[64][12];             // x, k, tmin, a0, b0, da, db, bits(ix | iy << 16) (owner)
+    uint32_t width[64];            // W of the owner's view
     const float4* pix[64];         // the owner's view pixel records
     unsigned long long key[64];    // the owner's best (t, index) so far
-    uint32_t cand[64 * 9];         // owner lane | (3x3 position << 6)
+    uint16_t cand[64 * 9];         // owner lane | (3x3 position << 6)
 };
 
 // The 3x3 positions (bit (dy + 1) * 3 + dx + 1) of the walk's block that are inside the view
@@ -610,9 +610,8 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                     pr[0] = x.x; pr[1] = x.y; pr[2] = x.z;
                     pr[3] = k.x; pr[4] = k.y; pr[5] = k.z;
                     pr[6] = w.tmin; pr[7] = w.a0; pr[8] = w.b0; pr[9] = w.da; pr[10] = w.db;
-                    R.cell[lane][0] = w.ix;
-                    R.cell[lane][1] = w.iy;
-                    R.cell[lane][2] = w.W;
+                    pr[11] = __uint_as_float((uint32_t)w.ix | ((uint32_t)w.iy << 16));
+                    R.width[lane] = (uint32_t)w.W;
                     R.pix[lane] = w.pix;
                     R.key[lane] = pack_hit(bt, bi);
                 }
@@ -629,7 +628,7 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                 while (m) {
                     const int b = __ffs(m) - 1;
                     m &= m - 1;
-                    R.cand[off++] = (uint32_t)lane | ((uint32_t)b << 6);
+                    R.cand[off++] = (uint16_t)(lane | (b << 6));
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -638,8 +637,10 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                     const uint32_t c = R.cand[j];
                     const int o = (int)(c & 63u), b = (int)(c >> 6);
                     const float* pr = R.prm[o];
-                    const int qx = R.cell[o][0] + b % 3 - 1, qy = R.cell[o][1] + b / 3 - 1;
-                    const int q = qy * R.cell[o][2] + qx;
+                    const uint32_t cell = __float_as_uint(pr[11]);
+                    const int qx = (int)(cell & 0xFFFFu) + b % 3 - 1;
+                    const int qy = (int)(cell >> 16) + b / 3 - 1;
+                    const int q = qy * (int)R.width[o] + qx;
                     const float4* pix = R.pix[o];
                     const float4 ra = gld(pix + 2 * q), rb = gld(pix + 2 * q + 1);
                     const uint32_t i = __float_as_uint(rb.w);
