@@ -73,13 +73,14 @@ void launch_po_tiles(const SlotDesc* d, const uint32_t* seg_cnt, int n_seg, int 
 
 // sin(x)/x.  The hardware sine is only defined for small arguments, and near-grazing facets
 // (area |u' x v'| = pitch^2 / |n . k|) have sinc arguments of 1e4 .. 1e6 rad, so the argument
-// is first reduced to [-1/2, 1/2) revolutions.
+// is first reduced to [-1/2, 1/2) revolutions.  The division is the hardware reciprocal (1 ulp),
+// well inside the error of the fp32 sine itself.
 __device__ inline float sinc_f(float x) {
     const float x2 = x * x;
     if (x2 < 1e-4f) return 1.f - x2 * (1.f / 6.f) + x2 * x2 * (1.f / 120.f);
     float r = x * 0.15915494309189535f;
     r -= rintf(r);
-    return __sinf(6.283185307179586f * r) / x;
+    return __sinf(6.283185307179586f * r) * __builtin_amdgcn_rcpf(x);
 }
 
 template <bool FP32>
