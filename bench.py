@@ -39,7 +39,7 @@ FP32_LANE_OPS = 256 * 128 * 2.4e9
 MARCH_TRAFFIC = dict(
     fetch_kib=12014653.8, write_kib=271926.8, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_trace.hip":
-             "0e31ac9b503d9c094fe5e06fffd8f8a360dd82b0df06f08dfa1e72c59b435c15",
+             "29d5a3ed46fcc6a9e8e3a31d52ad3cb4dccb09ca086581c56200e5d7259b3adc",
              "paper_2408_15583_amd/csrc/pe_device.h":
              "786a15ab8e5c679d9197e41692c2317faa24f153480d41b05948dd918664cb6c"})
 

@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
     bool pend = false;         // the walk waits for its level-0 refinement
     Walk w;
     __shared__ RefineWave rwave[4];
-    RefineWave& R = rwave[threadIdx.x >> 6];
+    RefineWave& rw = rwave[threadIdx.x >> 6];
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int n_idle = __popcll(idle);
@@ -606,14 +606,14 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                 uint32_t m = 0;
                 if (pend) {
                     m = refine_mask(w);
-                    float* pr = R.prm[lane];
+                    float* pr = rw.prm[lane];
                     pr[0] = x.x; pr[1] = x.y; pr[2] = x.z;
                     pr[3] = k.x; pr[4] = k.y; pr[5] = k.z;
                     pr[6] = w.tmin; pr[7] = w.a0; pr[8] = w.b0; pr[9] = w.da; pr[10] = w.db;
                     pr[11] = __uint_as_float((uint32_t)w.ix | ((uint32_t)w.iy << 16));
-                    R.width[lane] = (uint32_t)w.W;
-                    R.pix[lane] = w.pix;
-                    R.key[lane] = pack_hit(bt, bi);
+                    rw.width[lane] = (uint32_t)w.W;
+                    rw.pix[lane] = w.pix;
+                    rw.key[lane] = pack_hit(bt, bi);
                 }
                 // exclusive scan of the candidate counts over the wavefront
                 const int cnt = __popc(m);
@@ -628,20 +628,20 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                 while (m) {
                     const int b = __ffs(m) - 1;
                     m &= m - 1;
-                    R.cand[off++] = (uint16_t)(lane | (b << 6));
+                    rw.cand[off++] = (uint16_t)(lane | (b << 6));
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 for (int j = lane; j < n_cand; j += 64) {
-                    const uint32_t c = R.cand[j];
+                    const uint32_t c = rw.cand[j];
                     const int o = (int)(c & 63u), b = (int)(c >> 6);
-                    const float* pr = R.prm[o];
+                    const float* pr = rw.prm[o];
                     const uint32_t cell = __float_as_uint(pr[11]);
                     const int qx = (int)(cell & 0xFFFFu) + b % 3 - 1;
                     const int qy = (int)(cell >> 16) + b / 3 - 1;
-                    const int q = qy * (int)R.width[o] + qx;
-                    const float4* pix = R.pix[o];
+                    const int q = qy * (int)rw.width[o] + qx;
+                    const float4* pix = rw.pix[o];
                     const float4 ra = gld(pix + 2 * q), rb = gld(pix + 2 * q + 1);
                     const uint32_t i = __float_as_uint(rb.w);
                     float t;
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                         const int ha = (int)floorf(pr[7] + t * pr[9]);
                         const int hb = (int)floorf(pr[8] + t * pr[10]);
                         if (abs(ha - qx) <= 1 && abs(hb - qy) <= 1)
-                            atomicMin(&R.key[o], (unsigned long long)pack_hit(t, i));
+                            atomicMin(&rw.key[o], (unsigned long long)pack_hit(t, i));
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 if (pend) {
                     pend = false;
-                    const unsigned long long kk = R.key[lane];
+                    const unsigned long long kk = rw.key[lane];
                     bt = __uint_as_float((uint32_t)(kk >> 32));
                     bi = (uint32_t)(kk & 0xFFFFFFFFu);
                     const int xl = w.ix, xh = min(w.ix + 1, w.W), yl = w.iy,
