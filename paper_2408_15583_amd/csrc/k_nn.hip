@@ -39,12 +39,14 @@ union Frag {
 // K step covers 32 input channels of one tap: the block stages the A tile (128 pixels x 32
 // channels of the shifted input) and the B tile (BN channels x 32) in LDS, double-buffered, and
 // issues the next step's global loads before the current step's MFMAs.  A wavefront computes
-// 64 x BN/2 outputs as 4 x BN/32 tiles of v_mfma_f32_16x16x32_bf16.
+// BM/2 x BN/2 outputs as BM/32 x BN/32 tiles of v_mfma_f32_16x16x32_bf16.  Small layers take a
+// smaller BM so that the launch still has several workgroups per CU to hide load latency.
 // Requirements (checked by the host): Cin % 32 == 0.
-template <int BN>
+template <int BN, int BM>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
-    constexpr int BM = 128, LDS = 40;             // 32 k + 8 pad (bf16) per row
-    constexpr int TM = 4, TN = BN / 32;           // MFMA tiles per wavefront
+    constexpr int LDS = 40;                       // 32 k + 8 pad (bf16) per row
+    constexpr int TM = BM / 32, TN = BN / 32;     // MFMA tiles per wavefront
+    constexpr int ACH = BM * 4, AL = (ACH + 255) / 256;  // A chunks of 8 channels, per thread
     constexpr int TLD = BN + 8;                   // row of the bf16 output tile (epilogue)
     __shared__ __attribute__((aligned(16))) uint16_t smem[2 * BM * LDS + 2 * BN * LDS];
     static_assert(BM * TLD <= 2 * BM * LDS + 2 * BN * LDS, "output tile fits the staging LDS");
@@ -55,24 +57,24 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     const int HW = a.H * a.W, M = a.N * HW;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     const int pad = (a.K - 1) / 2, taps = a.K * a.K, kpt = a.Cin / 32, steps = taps * kpt;
-    // loader: A chunk c = tid + 256 i (i = 0, 1): row c >> 2, 8 channels at (c & 3) * 8
+    // loader: A chunk c = tid + 256 i (c < ACH): row c >> 2, 8 channels at (c & 3) * 8
     const int kc = (tid & 3) * 8;
-    int pn[2], py[2], px[2];
-    bool pv[2];
-    for (int i = 0; i < 2; i++) {
+    int pn[AL], py[AL], px[AL];
+    bool pv[AL];
+    for (int i = 0; i < AL; i++) {
         const int m = m0 + (tid >> 2) + 64 * i;
-        pv[i] = m < M;
+        pv[i] = m < M && tid + 256 * i < ACH;
         const int mm = pv[i] ? m : 0;
         pn[i] = mm / HW;
         py[i] = (mm % HW) / a.W;
         px[i] = mm % a.W;
     }
     constexpr int BCH = BN * 4;                  // B chunks of 8 channels
-    uint4 ra[2], rb[2];
+    uint4 ra[AL], rb[2];
     auto gload = [&](int step) {
         const int t = step / kpt, c0 = (step - t * kpt) * 32;
         const int dy = t / a.K - pad, dx = t % a.K - pad;
-        for (int i = 0; i < 2; i++) {
+        for (int i = 0; i < AL; i++) {
             const int y = py[i] + dy, x = px[i] + dx;
             const bool ok = pv[i] && y >= 0 && y < a.H && x >= 0 && x < a.W;
             ra[i] = ok ? *(const uint4*)(a.x + ((size_t)(pn[i] * a.H + y) * a.W + x) * a.ldx +
@@ -90,7 +92,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         }
     };
     auto sstore = [&](int buf) {
-        for (int i = 0; i < 2; i++) *(uint4*)&As[buf][(tid >> 2) + 64 * i][kc] = ra[i];
+        for (int i = 0; i < AL; i++)
+            if (tid + 256 * i < ACH) *(uint4*)&As[buf][(tid >> 2) + 64 * i][kc] = ra[i];
         for (int i = 0; i < 2; i++) {
             const int c = tid + 256 * i;
             if (c < BCH) *(uint4*)&Bs[buf][c >> 2][(c & 3) * 8] = rb[i];
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         if (step + 1 < steps) gload(step + 1);
         Frag fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; i++) fa[i].u = *(const uint4*)&As[buf][wm * 64 + i * 16 + r][kq];
+        for (int i = 0; i < TM; i++) fa[i].u = *(const uint4*)&As[buf][wm * (BM / 2) + i * 16 + r][kq];
 #pragma unroll
         for (int j = 0; j < TN; j++) fb[j].u = *(const uint4*)&Bs[buf][wn * (BN / 2) + j * 16 + r][kq];
 #pragma unroll
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
                 const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + q;
+                    const int m = m0 + wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + q;
                     if (cok && m < M) {
                         float v = acc[i][j][q] + bias;
                         if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
             const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int row = wm * 64 + i * 16 + (lane >> 4) * 4 + q, m = m0 + row;
+                const int row = wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + q, m = m0 + row;
                 float v = acc[i][j][q] + bias;
                 if (a.res && cok && m < M) v += bf2f(a.res[(size_t)m * a.ldres + co]);
                 if (a.z && cok && m < M) {
@@ -228,15 +231,24 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     }
 }
 
+template <int BN>
+static void launch_conv_fwd_bn(const ConvArgs& a, int M, unsigned gy, hipStream_t st) {
+    // 64-pixel tiles (measured faster than 128: half the registers, twice the workgroups per
+    // CU to hide load latency), 32-pixel tiles when even those give under four workgroups per CU
+    if ((uint64_t)((M + 63) / 64) * gy >= 1024)
+        hipLaunchKernelGGL((k_conv_fwd<BN, 64>), dim3((M + 63) / 64, gy), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_conv_fwd<BN, 32>), dim3((M + 31) / 32, gy), dim3(256), 0, st, a);
+}
+
 void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     const int M = a.N * a.H * a.W;
-    const unsigned gx = (unsigned)((M + 127) / 128);
     if (a.Cout > 64)
-        hipLaunchKernelGGL(k_conv_fwd<128>, dim3(gx, (a.Cout + 127) / 128), dim3(256), 0, st, a);
+        launch_conv_fwd_bn<128>(a, M, (unsigned)((a.Cout + 127) / 128), st);
     else if (a.Cout > 32)
-        hipLaunchKernelGGL(k_conv_fwd<64>, dim3(gx, 1), dim3(256), 0, st, a);
+        launch_conv_fwd_bn<64>(a, M, 1u, st);
     else
-        hipLaunchKernelGGL(k_conv_fwd<32>, dim3(gx, 1), dim3(256), 0, st, a);
+        launch_conv_fwd_bn<32>(a, M, 1u, st);
 }
 
 // Weight gradient: dW[co][t][ci] = sum_p dY[p][co] X[p + shift(t)][ci] over one chunk of
