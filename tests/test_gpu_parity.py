@@ -313,6 +313,25 @@ def test_invalid_inputs(pe, ctx):
     s.close()
 
 
+def test_batches_sized_by_budget(pe, ctx, dihedral):
+    """Synchronous solves size their batches from the HBM budget: 300 incidences at 128^2
+    (4.9M pixels) run as one batch under the default budget and as two under a 1.5 GiB budget
+    (half of it holds fewer than the 2^22-pixel floor, so 256 incidences per batch), with
+    bitwise-equal results."""
+    sc, _, _ = dihedral
+    inc = scenes.azimuth_sweep(np.linspace(0.0, 90.0, 300), 0.0)
+    big = pe.Scene.from_scene(ctx, sc, view_res=128)
+    E1 = pe.solve(ctx, big, inc, [10e9], 128, max_bounces=2, eps=0.5 * sc.radius)[0]
+    small = pe.Context(0, budget=3 << 29)
+    s2 = pe.Scene.from_scene(small, sc, view_res=128)
+    E2 = pe.solve(small, s2, inc, [10e9], 128, max_bounces=2, eps=0.5 * sc.radius)[0]
+    assert small.footprint()[0] < 3 << 29
+    assert np.array_equal(E1, E2)
+    s2.close()
+    small.close()
+    big.close()
+
+
 def test_budget_enomem(pe):
     from paper_2408_15583_amd import _native
     c = pe.Context(0, budget=1 << 20)
