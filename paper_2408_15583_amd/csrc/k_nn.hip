@@ -255,8 +255,12 @@ void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
 // 256 pixels per block (partials[chunk][co][t][ci], fp32), tiles 64 co x 64 ci, K = 32 pixels
 // per step staged through LDS transposed so each fragment is 8 contiguous bf16.
 __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
-    __shared__ uint16_t sdy[64][40];  // [co][pixel] (32 pixels + pad)
-    __shared__ uint16_t sx[64][40];   // [ci][pixel]
+    // [channel][pixel] staging rows (32 pixels + 8 pad = 20 dwords), filled with packed pixel
+    // pairs.  The x rows start 16 dwords past a multiple of 64 so that one store instruction's
+    // lanes (16 pixel pairs x 2 channel groups x 2 arrays) hit 64 different banks.
+    __shared__ __attribute__((aligned(16))) uint32_t stage[2 * 64 * 20 + 16];
+    uint32_t* const sdy = stage;
+    uint32_t* const sx = stage + 64 * 20 + 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int taps = a.K * a.K;
     const int t = blockIdx.z % taps, chunk = blockIdx.z / taps;
@@ -269,32 +273,43 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
     for (int i = 0; i < 2; i++)
         for (int j = 0; j < 2; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
     const int p_beg = chunk * a.chunk, p_end = min(M, p_beg + a.chunk);
-    // loader: thread -> (pixel lp = tid / 8, channel group cg = (tid % 8) * 8), 32 x 64 tile
-    const int lp = threadIdx.x >> 3, cg = (threadIdx.x & 7) * 8;
+    // loader: thread -> pixel pair pp, array arr (0: output gradient, 1: shifted input),
+    // 8 channels from cg; each thread stores 8 packed (pixel 2pp, 2pp + 1) dwords
+    const int pp = threadIdx.x & 15, arr = (threadIdx.x >> 4) & 1, cg = (threadIdx.x >> 5) * 8;
+    uint32_t* const dst = arr ? sx : sdy;
     for (int p0 = p_beg; p0 < p_end; p0 += 32) {
-        const int m = p0 + lp;
-        uint4 vy = make_uint4(0, 0, 0, 0), vx = make_uint4(0, 0, 0, 0);
-        if (m < p_end) {
-            const int n = m / HW, y = (m % HW) / a.W, x = m % a.W;
-            if (co0 + cg < a.Cout)
-                vy = *(const uint4*)(a.dy + ((size_t)(n * a.H + y) * a.W + x) * a.lddy + a.dyoff +
-                                     co0 + cg);
-            const int ys = y + dy, xs = x + dx;
-            if (ys >= 0 && ys < a.H && xs >= 0 && xs < a.W && ci0 + cg < a.Cin)
-                vx = *(const uint4*)(a.x + ((size_t)(n * a.H + ys) * a.W + xs) * a.ldx + a.xoff +
-                                     ci0 + cg);
+        uint4 v[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int m = p0 + 2 * pp + h;
+            v[h] = make_uint4(0, 0, 0, 0);
+            if (m < p_end) {
+                const int n = m / HW, y = (m % HW) / a.W, x = m % a.W;
+                if (arr == 0) {
+                    if (co0 + cg < a.Cout)
+                        v[h] = *(const uint4*)(a.dy + ((size_t)(n * a.H + y) * a.W + x) * a.lddy +
+                                               a.dyoff + co0 + cg);
+                } else {
+                    const int ys = y + dy, xs = x + dx;
+                    if (ys >= 0 && ys < a.H && xs >= 0 && xs < a.W && ci0 + cg < a.Cin)
+                        v[h] = *(const uint4*)(a.x + ((size_t)(n * a.H + ys) * a.W + xs) * a.ldx +
+                                               a.xoff + ci0 + cg);
+                }
+            }
         }
-        const uint16_t* hy = (const uint16_t*)&vy;
-        const uint16_t* hx = (const uint16_t*)&vx;
+        const uint32_t w0[4] = {v[0].x, v[0].y, v[0].z, v[0].w};
+        const uint32_t w1[4] = {v[1].x, v[1].y, v[1].z, v[1].w};
         __syncthreads();
-        for (int j = 0; j < 8; j++) {
-            sdy[cg + j][lp] = hy[j];
-            sx[cg + j][lp] = hx[j];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            // channels cg + 2e (low halves) and cg + 2e + 1 (high halves)
+            dst[(cg + 2 * e) * 20 + pp] = (w0[e] & 0xFFFFu) | (w1[e] << 16);
+            dst[(cg + 2 * e + 1) * 20 + pp] = (w0[e] >> 16) | (w1[e] & 0xFFFF0000u);
         }
         __syncthreads();
         Frag fa[2], fb[2];
-        for (int i = 0; i < 2; i++) fa[i].u = *(const uint4*)&sdy[wco + i * 16 + r][kq];
-        for (int j = 0; j < 2; j++) fb[j].u = *(const uint4*)&sx[wci + j * 16 + r][kq];
+        for (int i = 0; i < 2; i++) fa[i].u = *(const uint4*)&sdy[(wco + i * 16 + r) * 20 + kq / 2];
+        for (int j = 0; j < 2; j++) fb[j].u = *(const uint4*)&sx[(wci + j * 16 + r) * 20 + kq / 2];
         for (int i = 0; i < 2; i++)
             for (int j = 0; j < 2; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
