@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict
     }
     if (lane == 0) aabb[d.chunk_base + chunk] = make_int4(x0, y0, x1, y1);
     if (x0 > x1) return;
-    const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
+    const int tx0 = x0 / d.tile, tx1 = x1 / d.tile, ty0 = y0 / d.tile, ty1 = y1 / d.tile;
     const int ntx = tx1 - tx0 + 1, nt = ntx * (ty1 - ty0 + 1);
     for (int j = lane; j < nt; j += 64) {
         const int tx = tx0 + j % ntx, ty = ty0 + j / ntx;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const SlotDesc* __restrict
     if (chunk >= d.n_chunks) return;
     const int4 bb = aabb[d.chunk_base + chunk];
     if (bb.x > bb.z) return;
-    const int tx0 = bb.x / kTile, tx1 = bb.z / kTile, ty0 = bb.y / kTile, ty1 = bb.w / kTile;
+    const int tx0 = bb.x / d.tile, tx1 = bb.z / d.tile, ty0 = bb.y / d.tile, ty1 = bb.w / d.tile;
     for (int ty = ty0; ty <= ty1; ty++)
         for (int tx = tx0; tx <= tx1; tx++) {
             const uint32_t t = d.tile_base + ty * d.tiles_x + tx;
@@ -311,6 +311,7 @@ void launch_tile_scatter(const SlotDesc* d, int n_slots, int max_chunks, const i
                        d, aabb, tile_off, tile_cursor, list, capacity, overflow);
 }
 
+template <int TILE>
 __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
                                                 const uint32_t* __restrict__ tile_off,
                                                 const uint32_t* __restrict__ tile_count,
@@ -320,13 +321,13 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
     const SlotDesc& d = ds[blockIdx.y];
     const int tile = blockIdx.x;
     if (tile >= d.tiles_x * d.tiles_y) return;
-    __shared__ unsigned long long lk[kTile * kTile];
-    lk[threadIdx.x] = kEmptyKey;
+    __shared__ unsigned long long lk[TILE * TILE];
+    for (int q = threadIdx.x; q < TILE * TILE; q += 256) lk[q] = kEmptyKey;
     __syncthreads();
     const Screen s = screen_of(d);
     const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
-    const int px0 = tx * kTile, py0 = ty * kTile;
-    const int px1 = min(px0 + kTile, s.W) - 1, py1 = min(py0 + kTile, s.H) - 1;
+    const int px0 = tx * TILE, py0 = ty * TILE;
+    const int px1 = min(px0 + TILE, s.W) - 1, py1 = min(py0 + TILE, s.H) - 1;
     const uint32_t beg = tile_off[d.tile_base + tile];
     const uint32_t cnt = tile_count[d.tile_base + tile];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
                         const float t = tbase + dz;
                         if (t > 0.f) {
                             const uint64_t key = ((uint64_t)__float_as_uint(t) << 32) | idx;
-                            atomicMin(&lk[(y - py0) * kTile + (x - px0)],
+                            atomicMin(&lk[(y - py0) * TILE + (x - px0)],
                                       (unsigned long long)key);
                         }
                     }
@@ -372,23 +373,28 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
                     for (int x = x0; x <= x1; x++) {
                         const float du = (x + 0.5f - s.hw) * s.pitch - p.xa;
                         if (du * du + dv * dv < d2)
-                            atomicMin(&lk[(y - py0) * kTile + (x - px0)], (unsigned long long)key);
+                            atomicMin(&lk[(y - py0) * TILE + (x - px0)], (unsigned long long)key);
                     }
                 }
             }
         }
     }
     __syncthreads();
-    const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
-    const int x = px0 + lx, y = py0 + ly;
-    if (x < s.W && y < s.H) keys[d.pix_base + (uint64_t)y * s.W + x] = lk[threadIdx.x];
+    for (int q = threadIdx.x; q < TILE * TILE; q += 256) {
+        const int x = px0 + q % TILE, y = py0 + q / TILE;
+        if (x < s.W && y < s.H) keys[d.pix_base + (uint64_t)y * s.W + x] = lk[q];
+    }
 }
 
 void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
                    const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
-                   uint64_t* keys, hipStream_t st) {
-    hipLaunchKernelGGL(k_raster, dim3(max_tiles, n_slots), dim3(256), 0, st, d, tile_off,
-                       tile_count, list, capacity, keys);
+                   uint64_t* keys, int tile, hipStream_t st) {
+    if (tile == kTileWide)
+        hipLaunchKernelGGL(k_raster<kTileWide>, dim3(max_tiles, n_slots), dim3(256), 0, st, d,
+                           tile_off, tile_count, list, capacity, keys);
+    else
+        hipLaunchKernelGGL(k_raster<kTile>, dim3(max_tiles, n_slots), dim3(256), 0, st, d,
+                           tile_off, tile_count, list, capacity, keys);
 }
 
 // Algorithm 1 with a K-point heap (TUBE slots): per pixel, the K candidates nearest the central

@@ -7,7 +7,8 @@
 namespace pe {
 
 constexpr int kChunk = 64;          // points per spatial chunk (one wavefront)
-constexpr int kTile = 16;           // screen tile edge (pixels); one workgroup per tile
+constexpr int kTile = 16;           // screen tile edge (pixels) of the K-point-heap raster
+constexpr int kTileWide = 32;       // screen tile edge of the nearest-hit raster
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kEmptyKey = ~0ull;
 constexpr float kGraze = 1e-6f;     // |n.k| below this is a miss (grazing)
@@ -76,6 +77,7 @@ struct SlotDesc {
     float u[3], v[3], k[3];
     float pitch;
     int W, H, tiles_x, tiles_y;
+    int tile;                 // screen tile edge (kTile or kTileWide), one workgroup per tile
     int mode;                 // 0 disk, 1 tube
     float tube_r;
     // buffers
@@ -163,9 +165,10 @@ void launch_chunk_bounds(const SlotDesc* d, int n_slots, int max_chunks, int4* a
 void launch_tile_scatter(const SlotDesc* d, int n_slots, int max_chunks, const int4* aabb,
                          const uint32_t* tile_off, uint32_t* tile_cursor, uint32_t* list,
                          uint32_t capacity, uint32_t* overflow, hipStream_t st);
+// tile: the batch's screen tile edge (every slot's SlotDesc::tile; kTile or kTileWide).
 void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
                    const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
-                   uint64_t* keys, hipStream_t st);
+                   uint64_t* keys, int tile, hipStream_t st);
 void launch_resolve(const SlotDesc* d, const uint64_t* keys, float* depth, float* nrm,
                     uint32_t* idx, uint8_t* mask, int npix, hipStream_t st);
 void launch_view_level0(const SlotDesc* d, int slot, const uint64_t* keys, int W, int H, int P,

@@ -227,8 +227,11 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.pitch = (float)(2.0 * sc->R / std::max(sp.W, sp.H));
         d.W = sp.W;
         d.H = sp.H;
-        d.tiles_x = (sp.W + kTile - 1) / kTile;
-        d.tiles_y = (sp.H + kTile - 1) / kTile;
+        // the K-point heap keeps one pixel per thread (16 x 16 tiles); the nearest-hit raster
+        // takes 32 x 32 tiles, so each chunk of points overlaps fewer tiles
+        d.tile = topk > 0 ? kTile : kTileWide;
+        d.tiles_x = (sp.W + d.tile - 1) / d.tile;
+        d.tiles_y = (sp.H + d.tile - 1) / d.tile;
         d.mode = sp.mode;
         d.tube_r = (float)sp.tube_r;
         d.pix_base = tot_pix;
@@ -316,7 +319,7 @@ void Batch::splat() {
     if (topk > 0)
         launch_raster_topk(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, topk, keys, st);
     else
-        launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, st);
+        launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, hd[0].tile, st);
     prof_end("raster");
     HIPCHK(hipGetLastError());
 }
