@@ -171,7 +171,10 @@ pe_status pe_scene_info(pe_scene scene, double centre[3], double* R, double* r_m
 
 /* Synchronous solve: traces every incidence direction on a screen of central rays, bounces
  * up to max_bounces times and sums the PO field of Eq. (14) for every observation direction
- * and frequency.  Returns after the results are in the host buffers. */
+ * and frequency.  Returns after the results are in the host buffers.  Incidences run in
+ * batches sized to half of the context's unused HBM budget (2^22 .. 2^29 pixels; the
+ * PE_BATCH_PIXELS environment variable overrides); the context keeps the batch workspace for
+ * later calls, and results do not depend on the batching. */
 pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_result* res,
                    void* hip_stream);
 
