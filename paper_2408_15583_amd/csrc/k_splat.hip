@@ -244,12 +244,32 @@ __device__ inline void footprint(const Screen& s, const Proj& p, int& x0, int& y
     y1 = min(s.H - 1, (int)floorf(bc + ey));
 }
 
+// XCD-aware order of a (unit, slot) grid: workgroup b runs on XCD b % kNumXcd, and each XCD
+// takes a contiguous share of the unit-major, slot-minor order.  Consecutive workgroups of one
+// XCD then project the same chunks for neighbouring incidences of the batch, reading those
+// points from that XCD's L2.
+__host__ __device__ inline uint32_t xcd_grid(uint32_t n_units, uint32_t n_slots) {
+    return (n_units * n_slots + kNumXcd - 1) / kNumXcd * kNumXcd;
+}
+__device__ inline bool xcd_unit_slot(uint32_t b, uint32_t n_units, uint32_t n_slots,
+                                     uint32_t& unit, uint32_t& slot) {
+    const uint32_t total = n_units * n_slots, per = (total + kNumXcd - 1) / kNumXcd;
+    const uint32_t pos = (b % kNumXcd) * per + b / kNumXcd;
+    if (pos >= total) return false;
+    unit = pos / n_slots;
+    slot = pos % n_slots;
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict__ ds,
                                                       int4* __restrict__ aabb,
-                                                      uint32_t* __restrict__ tile_count) {
-    const SlotDesc& d = ds[blockIdx.y];
+                                                      uint32_t* __restrict__ tile_count,
+                                                      uint32_t n_groups, uint32_t n_slots) {
+    uint32_t group, slot;
+    if (!xcd_unit_slot(blockIdx.x, n_groups, n_slots, group, slot)) return;
+    const SlotDesc& d = ds[slot];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t chunk = blockIdx.x * 4 + wave;
+    const uint32_t chunk = group * 4 + wave;
     if (chunk >= d.n_chunks) return;
     const Screen s = screen_of(d);
     const uint32_t i = chunk * kChunk + lane;
@@ -278,8 +298,9 @@ __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict
 
 void launch_chunk_bounds(const SlotDesc* d, int n_slots, int max_chunks, int4* aabb,
                          uint32_t* tile_count, hipStream_t st) {
-    hipLaunchKernelGGL(k_chunk_bounds, dim3((max_chunks + 3) / 4, n_slots), dim3(256), 0, st, d,
-                       aabb, tile_count);
+    const uint32_t groups = (uint32_t)(max_chunks + 3) / 4;
+    hipLaunchKernelGGL(k_chunk_bounds, dim3(xcd_grid(groups, (uint32_t)n_slots)), dim3(256), 0, st,
+                       d, aabb, tile_count, groups, (uint32_t)n_slots);
 }
 
 __global__ __launch_bounds__(256) void k_tile_scatter(const SlotDesc* __restrict__ ds,
@@ -389,6 +410,8 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
 void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
                    const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
                    uint64_t* keys, int tile, hipStream_t st) {
+    // (tiles keep the slot-major order: an XCD-aware order would give each XCD one region of
+    // the screen for every incidence, and the regions' point counts differ widely)
     if (tile == kTileWide)
         hipLaunchKernelGGL(k_raster<kTileWide>, dim3(max_tiles, n_slots), dim3(256), 0, st, d,
                            tile_off, tile_count, list, capacity, keys);
