@@ -261,6 +261,20 @@ __device__ inline bool xcd_unit_slot(uint32_t b, uint32_t n_units, uint32_t n_sl
     return true;
 }
 
+// The raster's order: XCD x takes the tiles t = x (mod kNumXcd), each for every incidence in
+// turn, so one XCD's L2 serves a tile's points to neighbouring incidences while the XCDs share
+// every region of the screen (whose point counts differ widely) evenly.
+__host__ __device__ inline uint32_t xcd_tile_grid(uint32_t n_tiles, uint32_t n_slots) {
+    return (n_tiles + kNumXcd - 1) / kNumXcd * kNumXcd * n_slots;
+}
+__device__ inline bool xcd_tile_slot(uint32_t b, uint32_t n_tiles, uint32_t n_slots,
+                                     uint32_t& tile, uint32_t& slot) {
+    const uint32_t x = b % kNumXcd, q = b / kNumXcd;
+    tile = (q / n_slots) * kNumXcd + x;
+    slot = q % n_slots;
+    return tile < n_tiles;
+}
+
 __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict__ ds,
                                                       int4* __restrict__ aabb,
                                                       uint32_t* __restrict__ tile_count,
@@ -338,9 +352,12 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
                                                 const uint32_t* __restrict__ tile_count,
                                                 const uint32_t* __restrict__ list,
                                                 uint32_t capacity,
-                                                uint64_t* __restrict__ keys) {
-    const SlotDesc& d = ds[blockIdx.y];
-    const int tile = blockIdx.x;
+                                                uint64_t* __restrict__ keys, uint32_t n_tiles,
+                                                uint32_t n_slots) {
+    uint32_t utile, slot;
+    if (!xcd_tile_slot(blockIdx.x, n_tiles, n_slots, utile, slot)) return;
+    const SlotDesc& d = ds[slot];
+    const int tile = (int)utile;
     if (tile >= d.tiles_x * d.tiles_y) return;
     __shared__ unsigned long long lk[TILE * TILE];
     for (int q = threadIdx.x; q < TILE * TILE; q += 256) lk[q] = kEmptyKey;
@@ -410,14 +427,13 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
 void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
                    const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
                    uint64_t* keys, int tile, hipStream_t st) {
-    // (tiles keep the slot-major order: an XCD-aware order would give each XCD one region of
-    // the screen for every incidence, and the regions' point counts differ widely)
+    const dim3 grid(xcd_tile_grid((uint32_t)max_tiles, (uint32_t)n_slots));
     if (tile == kTileWide)
-        hipLaunchKernelGGL(k_raster<kTileWide>, dim3(max_tiles, n_slots), dim3(256), 0, st, d,
-                           tile_off, tile_count, list, capacity, keys);
+        hipLaunchKernelGGL(k_raster<kTileWide>, grid, dim3(256), 0, st, d, tile_off, tile_count,
+                           list, capacity, keys, (uint32_t)max_tiles, (uint32_t)n_slots);
     else
-        hipLaunchKernelGGL(k_raster<kTile>, dim3(max_tiles, n_slots), dim3(256), 0, st, d,
-                           tile_off, tile_count, list, capacity, keys);
+        hipLaunchKernelGGL(k_raster<kTile>, grid, dim3(256), 0, st, d, tile_off, tile_count, list,
+                           capacity, keys, (uint32_t)max_tiles, (uint32_t)n_slots);
 }
 
 // Algorithm 1 with a K-point heap (TUBE slots): per pixel, the K candidates nearest the central
