@@ -75,48 +75,82 @@ void launch_po_tiles(const SlotDesc* d, const uint32_t* seg_cnt, int n_seg, int 
 // (area |u' x v'| = pitch^2 / |n . k|) have sinc arguments of 1e4 .. 1e6 rad, so the argument
 // is first reduced to [-1/2, 1/2) revolutions.  The division is the hardware reciprocal (1 ulp),
 // well inside the error of the fp32 sine itself.
+// Both branches are evaluated and one is selected (lanes of a wavefront hold different
+// arguments; the small-argument series costs three operations).
 __device__ inline float sinc_f(float x) {
     const float x2 = x * x;
-    if (x2 < 1e-4f) return 1.f - x2 * (1.f / 6.f) + x2 * x2 * (1.f / 120.f);
+    const float series = 1.f - x2 * (1.f / 6.f) + x2 * x2 * (1.f / 120.f);
     float r = x * 0.15915494309189535f;
     r -= rintf(r);
-    return __sinf(6.283185307179586f * r) * __builtin_amdgcn_rcpf(x);
+    const float full = __sinf(6.283185307179586f * r) * __builtin_amdgcn_rcpf(x);
+    return x2 < 1e-4f ? series : full;
+}
+
+// One exit record's fields.
+struct PoRec {
+    double D;
+    float al, be, a[4];
+};
+
+__device__ inline PoRec po_rec(const ExitRecs& er, uint64_t i) {
+    PoRec q;
+    q.D = er.D[i];
+    q.al = er.al[i];
+    q.be = er.be[i];
+#pragma unroll
+    for (int pq = 0; pq < 4; pq++) q.a[pq] = er.A[pq][i];
+    return q;
 }
 
 template <bool FP32>
 __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, int rl, int RL,
                         const double* __restrict__ freq, const ExitRecs& er, double acc[8]) {
-    if (f >= d.n_freq) return;
+    if (f >= d.n_freq || (uint32_t)rl >= rn) return;
     const double fr = freq[d.freq_base + f];
     const float kf = (float)(kTwoPi * fr / kC0);
     const double rev = fr / kC0;
     const float revf = (float)rev;
     float facc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t r = rl; r < rn; r += RL) {
-        const uint64_t i = base + r;
-        const double D = er.D[i];
-        const float S = sinc_f(kf * er.al[i]) * sinc_f(kf * er.be[i]);
-        float rf;
-        if (FP32) {
-            const float ph = (float)D * revf;
-            rf = ph - floorf(ph);
-        } else {
-            const double ph = D * rev;
-            rf = (float)(ph - floor(ph));
-        }
-        if (rf >= 0.5f) rf -= 1.f;
-        const float ang = (float)kTwoPi * rf;
-        const float cs = __cosf(ang), sn = __sinf(ang);
-        const float wr = S * cs, wi = -S * sn;  // S exp(-j phase)
+    // Records are fetched four at a time, all before any is used: one memory round trip per
+    // four records instead of three per record (the loads of one record would otherwise wait
+    // for each other's uses).  The summation order is the plain r = rl, rl + RL, ... order.
+    constexpr int kU = 4;
+    for (uint32_t r0 = rl; r0 < rn; r0 += kU * RL) {
+        PoRec q[kU];
 #pragma unroll
-        for (int pq = 0; pq < 4; pq++) {
-            const float a = er.A[pq][i];
+        for (int u = 0; u < kU; u++) {
+            const uint32_t r = r0 + u * RL;
+            q[u] = po_rec(er, base + (r < rn ? r : r0));  // past the end: re-read (in range)
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const PoRec& cur = q[u];
+            // a re-read record past the end adds a zero (no branch, so that the compiler does
+            // not sink the loads back to their uses)
+            const float live = r0 + u * RL < rn ? 1.f : 0.f;
+            const float S = sinc_f(kf * cur.al) * sinc_f(kf * cur.be) * live;
+            float rf;
             if (FP32) {
-                facc[2 * pq] += a * wr;
-                facc[2 * pq + 1] += a * wi;
+                const float ph = (float)cur.D * revf;
+                rf = ph - floorf(ph);
             } else {
-                acc[2 * pq] += (double)(a * wr);
-                acc[2 * pq + 1] += (double)(a * wi);
+                const double ph = cur.D * rev;
+                rf = (float)(ph - floor(ph));
+            }
+            if (rf >= 0.5f) rf -= 1.f;
+            const float ang = (float)kTwoPi * rf;
+            const float cs = __cosf(ang), sn = __sinf(ang);
+            const float wr = S * cs, wi = -S * sn;  // S exp(-j phase)
+#pragma unroll
+            for (int pq = 0; pq < 4; pq++) {
+                const float a = cur.a[pq];
+                if (FP32) {
+                    facc[2 * pq] += a * wr;
+                    facc[2 * pq + 1] += a * wi;
+                } else {
+                    acc[2 * pq] += (double)(a * wr);
+                    acc[2 * pq + 1] += (double)(a * wi);
+                }
             }
         }
     }
