@@ -92,42 +92,70 @@ struct PoRec {
     float al, be, a[4];
 };
 
-__device__ inline PoRec po_rec(const ExitRecs& er, uint64_t i) {
-    PoRec q;
-    q.D = er.D[i];
-    q.al = er.al[i];
-    q.be = er.be[i];
+// A tile's records: the arrays offset to the tile's first record, so that a record is a
+// 32-bit index from a wave-uniform base (the loads take the base from scalar registers).
+struct PoTileRecs {
+    const double* D;
+    const float *al, *be, *A[4];
+};
+
+__device__ inline PoTileRecs po_tile_recs(const ExitRecs& er, uint64_t base) {
+    PoTileRecs t;
+    t.D = er.D + base;
+    t.al = er.al + base;
+    t.be = er.be + base;
 #pragma unroll
-    for (int pq = 0; pq < 4; pq++) q.a[pq] = er.A[pq][i];
+    for (int pq = 0; pq < 4; pq++) t.A[pq] = er.A[pq] + base;
+    return t;
+}
+
+// r < kRT: the byte offsets fit 32 bits, which lets the loads add them to a scalar base.
+__device__ inline PoRec po_rec(const PoTileRecs& t, uint32_t r) {
+    typedef const __attribute__((address_space(1))) char GC;
+    typedef const __attribute__((address_space(1))) double GD;
+    typedef const __attribute__((address_space(1))) float GF;
+    const uint32_t o4 = r * 4u, o8 = r * 8u;
+    PoRec q;
+    q.D = *(GD*)((GC*)t.D + o8);
+    q.al = *(GF*)((GC*)t.al + o4);
+    q.be = *(GF*)((GC*)t.be + o4);
+#pragma unroll
+    for (int pq = 0; pq < 4; pq++) q.a[pq] = *(GF*)((GC*)t.A[pq] + o4);
     return q;
 }
 
 template <bool FP32>
 __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, int rl, int RL,
                         const double* __restrict__ freq, const ExitRecs& er, double acc[8]) {
-    if (f >= d.n_freq || (uint32_t)rl >= rn) return;
+    if (f >= d.n_freq || (uint32_t)rl * 4u >= rn) return;
     const double fr = freq[d.freq_base + f];
     const float kf = (float)(kTwoPi * fr / kC0);
     const double rev = fr / kC0;
     const float revf = (float)rev;
     float facc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // Records are fetched four at a time, all before any is used: one memory round trip per
-    // four records instead of three per record (the loads of one record would otherwise wait
-    // for each other's uses).  The summation order is the plain r = rl, rl + RL, ... order.
+    // Records go in aligned groups of four consecutive ones, each group's loads all issued
+    // before any is used (one memory round trip per group instead of three per record).  In
+    // the fp64-phase mode a group's four terms are summed in fp32 and the group sums in fp64:
+    // the groups are the same whatever the lane layout (ft), so each frequency's result does
+    // not depend on the other frequencies of its slot.
     constexpr int kU = 4;
-    for (uint32_t r0 = rl; r0 < rn; r0 += kU * RL) {
+    const PoTileRecs tr = po_tile_recs(er, base);
+    const uint32_t n_grp = (rn + kU - 1) / kU;
+    for (uint32_t gi = rl; gi < n_grp; gi += RL) {
+        const uint32_t r0 = gi * kU;
+        float blk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         PoRec q[kU];
 #pragma unroll
         for (int u = 0; u < kU; u++) {
-            const uint32_t r = r0 + u * RL;
-            q[u] = po_rec(er, base + (r < rn ? r : r0));  // past the end: re-read (in range)
+            const uint32_t r = r0 + u;
+            q[u] = po_rec(tr, r < rn ? r : r0);  // past the end: re-read (in range)
         }
 #pragma unroll
         for (int u = 0; u < kU; u++) {
             const PoRec& cur = q[u];
             // a re-read record past the end adds a zero (no branch, so that the compiler does
             // not sink the loads back to their uses)
-            const float live = r0 + u * RL < rn ? 1.f : 0.f;
+            const float live = r0 + u < rn ? 1.f : 0.f;
             const float S = sinc_f(kf * cur.al) * sinc_f(kf * cur.be) * live;
             float rf;
             if (FP32) {
@@ -148,11 +176,13 @@ __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, in
                     facc[2 * pq] += a * wr;
                     facc[2 * pq + 1] += a * wi;
                 } else {
-                    acc[2 * pq] += (double)(a * wr);
-                    acc[2 * pq + 1] += (double)(a * wi);
+                    blk[2 * pq] += a * wr;
+                    blk[2 * pq + 1] += a * wi;
                 }
             }
         }
+        if (!FP32)
+            for (int c = 0; c < 8; c++) acc[c] += (double)blk[c];
     }
     if (FP32)
         for (int c = 0; c < 8; c++) acc[c] = facc[c];
