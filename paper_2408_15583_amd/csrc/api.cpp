@@ -325,6 +325,8 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
                         counts, st);
     launch_scan(counts, offs, ncell, nullptr, 1, offs + ncell, st);
     launch_morton_scatter(sc->pa, sc->pb, n, cell_of, offs, cursor, sc->pa_s, sc->pb_s, st);
+    sc->cbox = (float4*)sc->alloc(((n + kChunk - 1) / kChunk) * 32);
+    launch_chunk_box(sc->pa_s, n, sc->cbox, st);
     HIPCHK(hipGetLastError());
 
     // aggregation views

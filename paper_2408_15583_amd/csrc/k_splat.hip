@@ -275,6 +275,61 @@ __device__ inline bool xcd_tile_slot(uint32_t b, uint32_t n_tiles, uint32_t n_sl
     return tile < n_tiles;
 }
 
+// One wavefront per chunk: the box of the chunk's disk centres and its largest radius.
+__global__ __launch_bounds__(256) void k_chunk_box(const float4* __restrict__ pa_s, uint64_t n,
+                                                   float4* __restrict__ cbox) {
+    const uint64_t chunk = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (chunk >= (n + kChunk - 1) / kChunk) return;
+    const uint64_t i = chunk * kChunk + lane;
+    float lx = FLT_MAX, ly = FLT_MAX, lz = FLT_MAX, hx = -FLT_MAX, hy = -FLT_MAX, hz = -FLT_MAX;
+    float r = 0.f;
+    if (i < n) {
+        const float4 a = gld(pa_s + i);
+        lx = hx = a.x;
+        ly = hy = a.y;
+        lz = hz = a.z;
+        r = a.w;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lx = fminf(lx, __shfl_xor(lx, o));
+        ly = fminf(ly, __shfl_xor(ly, o));
+        lz = fminf(lz, __shfl_xor(lz, o));
+        hx = fmaxf(hx, __shfl_xor(hx, o));
+        hy = fmaxf(hy, __shfl_xor(hy, o));
+        hz = fmaxf(hz, __shfl_xor(hz, o));
+        r = fmaxf(r, __shfl_xor(r, o));
+    }
+    if (lane == 0) {
+        cbox[2 * chunk] = make_float4(lx, ly, lz, r);
+        cbox[2 * chunk + 1] = make_float4(hx, hy, hz, 0.f);
+    }
+}
+
+void launch_chunk_box(const float4* pa_s, uint64_t n, float4* cbox, hipStream_t st) {
+    const uint64_t n_chunks = (n + kChunk - 1) / kChunk;
+    if (n_chunks == 0) return;
+    hipLaunchKernelGGL(k_chunk_box, dim3((uint32_t)((n_chunks + 3) / 4)), dim3(256), 0, st, pa_s,
+                       n, cbox);
+}
+
+// Pixel range of a chunk on one screen, from its box: the box's orthographic shadow widened by
+// the largest disk (or the tube) radius.  It contains the footprint of every point of the
+// chunk (the slack covers the rounding of the per-point projection), so the tiles it
+// reaches hold every pixel the chunk can cover; the raster tests each point exactly.  One
+// thread per (chunk, slot) reads 32 bytes, where projecting the chunk's points read 2 KiB.
+constexpr float kBoxSlack = 1e-2f;  // pixels
+
+__device__ inline void box_span(float4 lo, float4 hi, float e0, float e1, float e2, float& a,
+                                float& b) {
+    a = fminf(lo.x * e0, hi.x * e0) + fminf(lo.y * e1, hi.y * e1) + fminf(lo.z * e2, hi.z * e2);
+    b = fmaxf(lo.x * e0, hi.x * e0) + fmaxf(lo.y * e1, hi.y * e1) + fmaxf(lo.z * e2, hi.z * e2);
+}
+
+__device__ inline int pix_floor(float x) { return (int)floorf(fminf(fmaxf(x, -1e8f), 1e8f)); }
+__device__ inline int pix_ceil(float x) { return (int)ceilf(fminf(fmaxf(x, -1e8f), 1e8f)); }
+
 __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict__ ds,
                                                       int4* __restrict__ aabb,
                                                       uint32_t* __restrict__ tile_count,
@@ -282,37 +337,30 @@ __global__ __launch_bounds__(256) void k_chunk_bounds(const SlotDesc* __restrict
     uint32_t group, slot;
     if (!xcd_unit_slot(blockIdx.x, n_groups, n_slots, group, slot)) return;
     const SlotDesc& d = ds[slot];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t chunk = group * 4 + wave;
+    const uint32_t chunk = group * 256 + threadIdx.x;
     if (chunk >= d.n_chunks) return;
     const Screen s = screen_of(d);
-    const uint32_t i = chunk * kChunk + lane;
-    int x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
-    if (i < d.n_pts) {
-        const Proj p = project(s, gld(d.pa_s + i), gld(d.pb_s + i));
-        footprint(s, p, x0, y0, x1, y1);
-        if (x0 > x1 || y0 > y1) { x0 = y0 = INT_MAX; x1 = y1 = INT_MIN; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        x0 = min(x0, __shfl_xor(x0, o));
-        y0 = min(y0, __shfl_xor(y0, o));
-        x1 = max(x1, __shfl_xor(x1, o));
-        y1 = max(y1, __shfl_xor(y1, o));
-    }
-    if (lane == 0) aabb[d.chunk_base + chunk] = make_int4(x0, y0, x1, y1);
+    const float4 lo = gld(d.cbox + 2 * (uint64_t)chunk), hi = gld(d.cbox + 2 * (uint64_t)chunk + 1);
+    float ua, ub, va, vb;
+    box_span(lo, hi, s.u0, s.u1, s.u2, ua, ub);
+    box_span(lo, hi, s.v0, s.v1, s.v2, va, vb);
+    const float e = (s.mode == 0 ? lo.w : s.tube_r) * s.ipitch + 1e-3f + kBoxSlack;
+    int x0 = max(0, pix_ceil(ua * s.ipitch + s.hw - 0.5f - e));
+    int x1 = min(s.W - 1, pix_floor(ub * s.ipitch + s.hw - 0.5f + e));
+    int y0 = max(0, pix_ceil(va * s.ipitch + s.hh - 0.5f - e));
+    int y1 = min(s.H - 1, pix_floor(vb * s.ipitch + s.hh - 0.5f + e));
+    if (x0 > x1 || y0 > y1) { x0 = y0 = INT_MAX; x1 = y1 = INT_MIN; }
+    aabb[d.chunk_base + chunk] = make_int4(x0, y0, x1, y1);
     if (x0 > x1) return;
     const int tx0 = x0 / d.tile, tx1 = x1 / d.tile, ty0 = y0 / d.tile, ty1 = y1 / d.tile;
-    const int ntx = tx1 - tx0 + 1, nt = ntx * (ty1 - ty0 + 1);
-    for (int j = lane; j < nt; j += 64) {
-        const int tx = tx0 + j % ntx, ty = ty0 + j / ntx;
-        atomicAdd(&tile_count[d.tile_base + ty * d.tiles_x + tx], 1u);
-    }
+    for (int ty = ty0; ty <= ty1; ty++)
+        for (int tx = tx0; tx <= tx1; tx++)
+            atomicAdd(&tile_count[d.tile_base + ty * d.tiles_x + tx], 1u);
 }
 
 void launch_chunk_bounds(const SlotDesc* d, int n_slots, int max_chunks, int4* aabb,
                          uint32_t* tile_count, hipStream_t st) {
-    const uint32_t groups = (uint32_t)(max_chunks + 3) / 4;
+    const uint32_t groups = (uint32_t)(max_chunks + 255) / 256;
     hipLaunchKernelGGL(k_chunk_bounds, dim3(xcd_grid(groups, (uint32_t)n_slots)), dim3(256), 0, st,
                        d, aabb, tile_count, groups, (uint32_t)n_slots);
 }

@@ -67,6 +67,7 @@ struct SlotDesc {
     // scene
     const float4* pa_s;       // spatially ordered (x, y, z, r)
     const float4* pb_s;       // spatially ordered (nx, ny, nz, bits(original index))
+    const float4* cbox;       // per chunk of pa_s: (lo x, y, z, max r), (hi x, y, z, 0)
     const float4* pa;         // original order (x, y, z, r)
     const float4* pb;         // original order (nx, ny, nz, material)
     const ViewDesc* views;
@@ -158,6 +159,9 @@ void launch_morton_count(const float4* pa, uint64_t n, float lo_x, float lo_y, f
 void launch_morton_scatter(const float4* pa, const float4* pb, uint64_t n,
                            const uint32_t* cell_of, const uint32_t* offsets, uint32_t* cursor,
                            float4* pa_s, float4* pb_s, hipStream_t st);
+
+// Bounding box of each kChunk-point chunk of pa_s (2 float4 per chunk, see SlotDesc::cbox).
+void launch_chunk_box(const float4* pa_s, uint64_t n, float4* cbox, hipStream_t st);
 
 // splat pipeline for a batch of slots
 void launch_chunk_bounds(const SlotDesc* d, int n_slots, int max_chunks, int4* aabb,

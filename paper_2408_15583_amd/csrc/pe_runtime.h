@@ -154,6 +154,7 @@ struct pe_scene_s {
     double c[3] = {0, 0, 0};
     double R = 0, r_max = 0;
     float4 *pa = nullptr, *pb = nullptr, *pa_s = nullptr, *pb_s = nullptr;
+    float4* cbox = nullptr;  // per-chunk bounding boxes of pa_s
     std::vector<pe::ViewDesc> views;
     pe::ViewDesc* views_dev = nullptr;
     float blend_r = 0.f, bl_h = 0.f;  // Eq. (23) refinement radius and centre-grid cell edge

@@ -202,6 +202,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
             throw Error{PE_EINVAL, "screen must hold 1 .. 2^22 pixels"};
         d.pa_s = sc->pa_s;
         d.pb_s = sc->pb_s;
+        d.cbox = sc->cbox;
         d.pa = sc->pa;
         d.pb = sc->pb;
         d.blend_r = sc->blend_r;
