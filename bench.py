@@ -37,11 +37,11 @@ FP32_LANE_OPS = 256 * 128 * 2.4e9
 # (FETCH_SIZE reads 524302 KiB for 1 GiB: factor 2.0; WRITE_SIZE 1048576 KiB: factor 1.0).
 # Valid only for the sources they were taken on; any edit of those files reports null.
 MARCH_TRAFFIC = dict(
-    fetch_kib=11963133.2, write_kib=271679.7, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=11981593.3, write_kib=271382.7, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_trace.hip":
              "29d5a3ed46fcc6a9e8e3a31d52ad3cb4dccb09ca086581c56200e5d7259b3adc",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "510c4a3b187a5e9c9358b7477adad1ab261b245c805ea8681477ec61470c2e39"})
+             "5ab2f46976353d190730f103bb20eaf4ada3ee477be42a771582ea965be68715"})
 
 
 def march_traffic():
@@ -57,10 +57,12 @@ def march_traffic():
 
 def po_slots_per_term():
     """Issue slots (fp32 lane-op equivalents) one PO term needs: fp64 ops count twice (half
-    rate), transcendentals four times (quarter rate)."""
-    fp64 = 1 + 2 + 1 + 8 + 8      # D*rev, floor+sub, cvt f64->f32, 8 cvt f32->f64, 8 adds
-    fp32 = 2 + 2 * 5 + 2 + 4 + 8  # k*al, k*be, two sinc (mul, rcp, mul, cmp, sel), S, 2pi*rf, 8 mul
-    trans = 4                     # sin, cos, two sinc sines
+    rate), transcendentals four times (quarter rate).  The 8 fp64 conversions and adds of the
+    accumulators run once per aligned group of four terms."""
+    fp64 = 1 + 2 + 1 + 1 + (8 + 8) / 4  # D*rev, floor+sub, cvt f64->f32, cmp, accumulators
+    fp32 = 2 + 2 * 11 + 2 + 3 + 2 + 2 + 8  # k*al, k*be, two sinc (series and full, select),
+    #                                        S and tail mask, half-turn fold, angle, wr/wi, 8 fma
+    trans = 4 + 2                          # sin, cos, two sinc sines, two reciprocals
     return 2 * fp64 + fp32 + 4 * trans
 
 
