@@ -310,21 +310,17 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
         sc->r_max = std::max(sc->r_max, hp[2 * b + 1]);
     }
 
-    // spatial order: counting sort by the Morton code of a 64^3 grid over the bounding box
-    const int ncell = 64 * 64 * 64;
+    // spatial order: stable radix sort by the Morton code of a 1024^3 grid over the bounding box
     double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
     if (!(ext > 0)) ext = 1.0;
-    uint32_t* cell_of = (uint32_t*)tmp.get(n * 4);
-    uint32_t* counts = (uint32_t*)tmp.get(4 * (ncell + 1));
-    uint32_t* offs = (uint32_t*)tmp.get(4 * (ncell + 1));
-    uint32_t* cursor = (uint32_t*)tmp.get(4 * ncell);
-    launch_fill_u32(counts, 0u, ncell, st);
-    launch_fill_u32(cursor, 0u, ncell, st);
-    launch_morton_count(sc->pa, n, (float)(lo[0] - sc->c[0]), (float)(lo[1] - sc->c[1]),
-                        (float)(lo[2] - sc->c[2]), (float)(64.0 / (ext * (1 + 1e-6))), cell_of,
-                        counts, st);
-    launch_scan(counts, offs, ncell, nullptr, 1, offs + ncell, st);
-    launch_morton_scatter(sc->pa, sc->pb, n, cell_of, offs, cursor, sc->pa_s, sc->pb_s, st);
+    const size_t sort_bytes = morton_sort_temp_bytes(n);
+    if (sort_bytes == 0) return set_error(PE_EDEVICE, "radix sort size query failed");
+    uint32_t* sort_keys = (uint32_t*)tmp.get(n * 16);
+    void* sort_tmp = tmp.get(sort_bytes);
+    HIPCHK(launch_morton_sort(sc->pa, sc->pb, n, (float)(lo[0] - sc->c[0]),
+                              (float)(lo[1] - sc->c[1]), (float)(lo[2] - sc->c[2]),
+                              (float)(1024.0 / (ext * (1 + 1e-6))), sort_keys, sort_tmp, sort_bytes,
+                              sc->pa_s, sc->pb_s, st));
     sc->cbox = (float4*)sc->alloc(((n + kChunk - 1) / kChunk) * 32);
     launch_chunk_box(sc->pa_s, n, sc->cbox, st);
     HIPCHK(hipGetLastError());

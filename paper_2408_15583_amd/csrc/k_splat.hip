@@ -2,9 +2,10 @@
 // pixel's central ray keeps the nearest disk it crosses (DISK mode) or the nearest point within
 // the tube radius of the central ray (TUBE mode, Algorithm 1 with an unbounded Top-K).
 //
-// MI355X design: points are bucketed once per scene in Morton order of a 64^3 grid so that a
-// wavefront of 64 consecutive points is a compact surface patch; per view, each patch's screen
-// footprint is binned into 16x16-pixel tiles; one workgroup per tile rasterises its patches
+// MI355X design: points are sorted once per scene in Morton order of a 1024^3 grid
+// (k_sort.hip) so that a wavefront of 64 consecutive points is a compact surface patch; per
+// view, each patch's screen rectangle (from its 3D box) is binned into 32x32-pixel tiles
+// (16x16 for the K-point heap); one workgroup per tile rasterises its patches
 // into an LDS tile of packed 64-bit keys (fp32 depth bits << 32 | point index) with ds_min_u64,
 // then writes the tile once.  The minimum key is the nearest hit with ties going to the lowest
 // index, independent of the order in which patches arrive.
@@ -131,59 +132,6 @@ void launch_ingest_pack(const void* xyz, int is_f64, const float* nrm, const uin
                         hipStream_t st) {
     hipLaunchKernelGGL(k_ingest_pack, dim3(n_blocks), dim3(256), 0, st, xyz, is_f64, nrm, mat,
                        rad, rad_scalar, n, cx, cy, cz, pa, pb, partial);
-}
-
-__device__ inline uint32_t spread3(uint32_t v) {  // 6 bits -> every third bit
-    uint32_t r = 0;
-#pragma unroll
-    for (int b = 0; b < 6; b++) r |= ((v >> b) & 1u) << (3 * b);
-    return r;
-}
-
-__global__ void k_morton_count(const float4* __restrict__ pa, uint64_t n, float lx, float ly,
-                               float lz, float inv, uint32_t* __restrict__ cell_of,
-                               uint32_t* __restrict__ counts) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const float4 a = pa[i];
-        int cx = (int)((a.x - lx) * inv), cy = (int)((a.y - ly) * inv), cz = (int)((a.z - lz) * inv);
-        cx = min(max(cx, 0), 63); cy = min(max(cy, 0), 63); cz = min(max(cz, 0), 63);
-        const uint32_t code = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
-        cell_of[i] = code;
-        atomicAdd(&counts[code], 1u);
-    }
-}
-
-void launch_morton_count(const float4* pa, uint64_t n, float lo_x, float lo_y, float lo_z,
-                         float inv_cell, uint32_t* cell_of, uint32_t* counts, hipStream_t st) {
-    int b = (int)((n + 255) / 256);
-    if (b > 8192) b = 8192;
-    hipLaunchKernelGGL(k_morton_count, dim3(b), dim3(256), 0, st, pa, n, lo_x, lo_y, lo_z,
-                       inv_cell, cell_of, counts);
-}
-
-__global__ void k_morton_scatter(const float4* __restrict__ pa, const float4* __restrict__ pb,
-                                 uint64_t n, const uint32_t* __restrict__ cell_of,
-                                 const uint32_t* __restrict__ offsets,
-                                 uint32_t* __restrict__ cursor, float4* __restrict__ pa_s,
-                                 float4* __restrict__ pb_s) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = cell_of[i];
-        const uint32_t pos = offsets[c] + atomicAdd(&cursor[c], 1u);
-        const float4 b = pb[i];
-        pa_s[pos] = pa[i];
-        pb_s[pos] = make_float4(b.x, b.y, b.z, __uint_as_float((uint32_t)i));
-    }
-}
-
-void launch_morton_scatter(const float4* pa, const float4* pb, uint64_t n,
-                           const uint32_t* cell_of, const uint32_t* offsets, uint32_t* cursor,
-                           float4* pa_s, float4* pb_s, hipStream_t st) {
-    int b = (int)((n + 255) / 256);
-    if (b > 8192) b = 8192;
-    hipLaunchKernelGGL(k_morton_scatter, dim3(b), dim3(256), 0, st, pa, pb, n, cell_of, offsets,
-                       cursor, pa_s, pb_s);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -154,11 +154,15 @@ void launch_ingest_pack(const void* xyz, int is_f64, const float* nrm, const uin
                         const float* rad, float rad_scalar, uint64_t n, double cx, double cy,
                         double cz, float4* pa, float4* pb, double* partial, int n_blocks,
                         hipStream_t st);
-void launch_morton_count(const float4* pa, uint64_t n, float lo_x, float lo_y, float lo_z,
-                         float inv_cell, uint32_t* cell_of, uint32_t* counts, hipStream_t st);
-void launch_morton_scatter(const float4* pa, const float4* pb, uint64_t n,
-                           const uint32_t* cell_of, const uint32_t* offsets, uint32_t* cursor,
-                           float4* pa_s, float4* pb_s, hipStream_t st);
+// Spatial order of a scene (k_sort.hip): sorts the points by the Morton code of a 1024^3 grid
+// whose cells have edge 1 / inv_cell from (lo_x, lo_y, lo_z), writing pa_s / pb_s (original
+// index in pb_s.w).  keys: 4 n u32 of scratch; temp: morton_sort_temp_bytes(n) bytes (0 when
+// the size query fails).
+size_t morton_sort_temp_bytes(uint64_t n);
+hipError_t launch_morton_sort(const float4* pa, const float4* pb, uint64_t n, float lo_x,
+                              float lo_y, float lo_z, float inv_cell, uint32_t* keys,
+                              void* temp, size_t temp_bytes, float4* pa_s, float4* pb_s,
+                              hipStream_t st);
 
 // Bounding box of each kChunk-point chunk of pa_s (2 float4 per chunk, see SlotDesc::cbox).
 void launch_chunk_box(const float4* pa_s, uint64_t n, float4* cbox, hipStream_t st);
