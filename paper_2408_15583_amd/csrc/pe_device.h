@@ -145,6 +145,12 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st);
 // exclusive scan of n items (n = n_static, or ceil(*n_dev / div) if n_dev); writes total.
 void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n_static, const uint32_t* n_dev,
                  uint32_t div, uint32_t* total, hipStream_t st);
+// The same scan by one workgroup per 16 Ki items, for large n: n = n_max, or
+// min(n_max, ceil(*n_dev / div)) if n_dev (n_max sizes the grid).  scratch holds
+// scan_wide_scratch(n_max) u32 (per-tile totals).
+uint32_t scan_wide_scratch(uint32_t n_max);
+void launch_scan_wide(const uint32_t* in, uint32_t* out, uint32_t n_max, const uint32_t* n_dev,
+                      uint32_t div, uint32_t* total, uint32_t* scratch, hipStream_t st);
 
 // ingest
 void launch_ingest_stats(const void* xyz, int is_f64, const float* nrm, const uint8_t* mat,

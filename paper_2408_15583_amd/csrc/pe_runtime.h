@@ -75,6 +75,7 @@ struct Batch {
     ObsDesc* dobs = nullptr;
     double* dfreq = nullptr;
     uint32_t* cnt = nullptr;
+    uint32_t* scan_ws = nullptr;  // per-tile totals of the wide scans
     int n = 0, contrib = 0, precision = 0, n_seg = 1, ft = 1, max_b = 1;
     int topk = 0;  // > 0: TUBE slots keep a K-point heap (Algorithm 1) instead of K unbounded
     bool blend = false;  // some slot's scene refines hits by Eq. (23)

@@ -161,7 +161,7 @@ enum BufId {
     B_SLOTS, B_OBS, B_FREQ, B_AABB, B_TCOUNT, B_TCURSOR, B_TOFF, B_TLIST, B_KEYS, B_RSF,
     B_RSD, B_RSM, B_RSH, B_LIST0, B_LIST1, B_LIST2, B_ALIVE, B_CCOUNT, B_COFF, B_WGC, B_WGO,
     B_RECD, B_RECF, B_SEGB, B_SEGC, B_TPRE, B_TTMP, B_PART, B_EOUT, B_ROUT, B_CNT, B_HITKEY,
-    B_MQUEUE, B_NUMBUF
+    B_MQUEUE, B_SCAN, B_NUMBUF
 };
 static_assert(B_NUMBUF <= 34, "workspace ids 34..39 belong to the densified solve");
 
@@ -290,6 +290,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
     dobs = ws.get<ObsDesc>(B_OBS, ho.size());
     dfreq = ws.get<double>(B_FREQ, hf.size());
     cnt = ws.get<uint32_t>(B_CNT, C_NCOUNT);
+    scan_ws = ws.get<uint32_t>(B_SCAN, scan_wide_scratch(0xFFFFFFFFu));  // 1 MiB, any scan size
     HIPCHK(hipMemcpyAsync(dd, hd.data(), sizeof(SlotDesc) * n, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(dobs, ho.data(), sizeof(ObsDesc) * ho.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(dfreq, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice, st));
@@ -310,7 +311,8 @@ void Batch::splat() {
     launch_chunk_bounds(dd, n, max_chunks, aabb, tcount, st);
     prof_end("chunk_bounds");
     prof_begin();
-    launch_scan(tcount, toff, tot_tiles, nullptr, 1, cnt + C_TILES, st);
+    launch_scan_wide(tcount, toff, tot_tiles, nullptr, 1, cnt + C_TILES,
+                     scan_ws, st);
     prof_end("tile_scan");
     prof_begin();
     launch_tile_scatter(dd, n, max_chunks, aabb, toff, tcursor, tlist, tlist_cap,
@@ -351,7 +353,8 @@ void Batch::raygen() {
     launch_raygen_count(dd, n, max_pix, keys, wgc, st);
     prof_end("raygen_count");
     prof_begin();
-    launch_scan(wgc, wgo, (uint32_t)(gx * n), nullptr, 1, cnt + C_N0, st);
+    launch_scan_wide(wgc, wgo, (uint32_t)(gx * n), nullptr, 1, cnt + C_N0,
+                     scan_ws, st);
     prof_end("raygen_scan");
     prof_begin();
     launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, hitkey, st);
@@ -420,7 +423,9 @@ void Batch::trace(bool with_records) {
         launch_bounce_apply(dd, cur, ncur, rs, hitkey, alive, ccount, b, persistent_blocks(), st);
         prof_end("bounce_apply");
         prof_begin();
-        launch_scan(ccount, coff, 0, ncur, kWaveChunk, nout, st);
+        const uint32_t max_chunks = (uint32_t)((tot_pix + kWaveChunk - 1) / kWaveChunk);
+        launch_scan_wide(ccount, coff, max_chunks, ncur, kWaveChunk, nout,
+                         scan_ws, st);
         prof_end("compact_scan");
         prof_begin();
         launch_compact(cur, ncur, alive, coff, out, persistent_blocks(), st);
