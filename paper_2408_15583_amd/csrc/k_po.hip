@@ -188,7 +188,8 @@ __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, in
         for (int c = 0; c < 8; c++) acc[c] = facc[c];
 }
 
-__global__ __launch_bounds__(256) void k_po_sum(const SlotDesc* __restrict__ ds,
+// Six waves per SIMD (77 VGPRs, no spills) rather than the four its 98 registers allow.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_po_sum(const SlotDesc* __restrict__ ds,
                                                 const uint32_t* __restrict__ seg_beg,
                                                 const uint32_t* __restrict__ seg_cnt, int n_seg,
                                                 int n_slots, const double* __restrict__ freq,
