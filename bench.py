@@ -231,6 +231,67 @@ def densifier_bench(pe, ctx, batch=8, h=256, steps=10, log=None):
                 note="dense-conv flops of the network / wall time (whole pass incl. VALU layers)")
 
 
+def next_rows(pe, ctx, sc, xyz_dev, nrm_dev, view_res, log=None):
+    """One timed call of each extension row beside the hot path (GPU wall time, the device
+    synchronised on both sides; one untimed call first): learned-GFB fusion on the synthetic
+    OctAR (eight 512^2 sensor views of first-hit buffers, 256^3 grid), the fused splats traced
+    with and without the Eq. (23) normal blending, the OctAR 3-bounce monostatic sweep, a
+    bistatic sweep, the finite-K tube raster and PCA normals on the composite."""
+    import numpy as np
+    import torch
+    import scenes
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    out = {}
+    oc = scenes.octar()
+    views = scenes.octar_views()
+    os_ = pe.Scene.from_scene(ctx, oc, view_res=512, view_dirs=views)
+    info = os_.info()
+    _, dg, ng, mg = pe.make_pair(ctx, os_, views, 256, 256)
+    side = 2.0 * float(oc.meta["half"])
+    fz, ms = timed(lambda: pe.fuse_gfbs(ctx, views, dg, ng, mg, info["centre"], info["R"],
+                                        grid=256, grid_side=side))
+    out["fusion"] = dict(views=8, res=512, grid=256, splats=int(fz["xyz"].shape[0]), ms=ms)
+    eps = 0.5 * float(oc.radius)
+    inc = scenes.azimuth_sweep(np.arange(0.0, 360.0, 10.0), 30.0)
+    for name, blend in (("fused_sweep", 0.0), ("fused_sweep_eq23", side / 256)):
+        fs = pe.Scene(ctx, fz["xyz"], fz["nrm"], fz["radius"], view_dirs=views, view_res=512,
+                      blend_radius=blend)
+        (_, _, st), ms = timed(lambda: pe.solve(ctx, fs, inc, [5e9], 512, max_bounces=3, eps=eps))
+        out[name] = dict(incidences=len(inc), screen=512, bounces=3, blend_radius=blend, ms=ms,
+                         ray_bounces_per_s=st["ray_queries"] / (ms * 1e-3))
+        fs.close()
+    (_, _, st), ms = timed(lambda: pe.solve(ctx, os_, inc, [5e9], 512, max_bounces=3, eps=eps))
+    out["octar_sweep"] = dict(points=int(oc.n), incidences=len(inc), screen=512, bounces=3, ms=ms,
+                              ray_bounces_per_s=st["ray_queries"] / (ms * 1e-3))
+    binc = scenes.azimuth_sweep([40.0, 130.0], 30.0)
+    obs = -scenes.azimuth_sweep(np.arange(0.0, 360.0, 22.5), 20.0)
+    (_, _, st), ms = timed(lambda: pe.solve(ctx, os_, binc, [3e9, 5e9], 512, max_bounces=3,
+                                            eps=eps, obs_dir=obs))
+    out["bistatic"] = dict(incidences=2, observations=len(obs), freqs=2, bounces=3, ms=ms,
+                           rcs_samples_per_s=2 * len(obs) * 2 / (ms * 1e-3))
+    os_.close()
+    s = pe.Scene(ctx, xyz_dev, nrm_dev, sc.radius, view_res=view_res)
+    d = np.array([0.3, -0.4, -0.866])
+    _, ms = timed(lambda: pe.render_tube_topk(ctx, s, d / np.linalg.norm(d), 1024, 1024,
+                                              2.0 * float(sc.radius), 4))
+    out["topk_raster"] = dict(screen=1024, K=4, points=int(sc.n), ms=ms)
+    s.close()
+    xyz = torch.from_numpy(np.ascontiguousarray(sc.xyz, dtype=np.float32)).cuda()
+    _, ms = timed(lambda: pe.estimate_normals(ctx, xyz, 16))
+    out["pca_normals"] = dict(points=int(sc.n), k=16, ms=ms)
+    if log:
+        log("next rows: " + ", ".join(f"{k} {v['ms']:.1f} ms" for k, v in out.items()))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +310,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="Poisson serving window (0 = skip the serving measurement)")
     ap.add_argument("--no-densifier", action="store_true")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the fusion / OctAR / bistatic / finite-K / PCA-normals timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path shards by "
@@ -378,6 +441,8 @@ def main():
                                                                         key=lambda kv: -kv[1][0])},
     }
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    out["next_rows"] = None if args.no_next_rows else next_rows(pe, ctx, sc, xyz, nrm, sw.view_res,
+                                                                      log=log)
     out["densifier"] = None if args.no_densifier else densifier_bench(pe, ctx, log=log)
     out["serving"] = serving(pe, ctx, args.serve_seconds, log=log) if args.serve_seconds > 0 else None
     if args.cpu_sample > 0:

@@ -137,8 +137,9 @@ pe_status pe_fuse_gfbs(pe_ctx ctx, const pe_gfb_set* g, const pe_fuse_desc* f, d
     uint32_t* flag = (uint32_t*)s.get(ncell * sizeof(uint32_t));
     uint32_t* off = (uint32_t*)s.get(ncell * sizeof(uint32_t));
     uint32_t* total = (uint32_t*)s.get(sizeof(uint32_t));
+    uint32_t* scan_ws = (uint32_t*)s.get(scan_wide_scratch((uint32_t)ncell) * sizeof(uint32_t));
     launch_fuse_flag(acc, ncell, flag, st);
-    launch_scan(flag, off, (uint32_t)ncell, nullptr, 1u, total, st);
+    launch_scan_wide(flag, off, (uint32_t)ncell, nullptr, 1u, total, scan_ws, st);
     uint32_t nt = 0;
     HIPCHK(hipMemcpyAsync(&nt, total, sizeof(nt), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
