@@ -229,11 +229,11 @@ __global__ __launch_bounds__(256) void k_gfb_write(const SlotDesc* __restrict__ 
 void launch_gfb_raygen(const SlotDesc* d, int n_slots, int max_pix, const float* depth,
                        const float* nrm, const float* prob, const uint8_t* use, float thresh,
                        uint32_t* wg_count, uint32_t* wg_off, uint32_t* list, RayState rs,
-                       uint64_t* hitkey, uint32_t* n_out, hipStream_t st) {
+                       uint64_t* hitkey, uint32_t* n_out, uint32_t* scan_ws, hipStream_t st) {
     const int gx = (max_pix + 255) / 256;
     hipLaunchKernelGGL(k_gfb_count, dim3(gx, n_slots), dim3(256), 0, st, d, prob, nrm, use,
                        thresh, wg_count);
-    launch_scan(wg_count, wg_off, (uint32_t)(gx * n_slots), nullptr, 1, n_out, st);
+    launch_scan_wide(wg_count, wg_off, (uint32_t)(gx * n_slots), nullptr, 1, n_out, scan_ws, st);
     hipLaunchKernelGGL(k_gfb_write, dim3(gx, n_slots), dim3(256), 0, st, d, depth, nrm, prob, use,
                        thresh, wg_off, list, rs, hitkey);
 }

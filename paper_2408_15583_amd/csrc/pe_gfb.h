@@ -16,7 +16,7 @@ void launch_gfb_uncertain(const SlotDesc* d, int n_slots, int max_pix, const flo
 void launch_gfb_raygen(const SlotDesc* d, int n_slots, int max_pix, const float* depth,
                        const float* nrm, const float* prob, const uint8_t* use, float thresh,
                        uint32_t* wg_count, uint32_t* wg_off, uint32_t* list, RayState rs,
-                       uint64_t* hitkey, uint32_t* n_out, hipStream_t st);
+                       uint64_t* hitkey, uint32_t* n_out, uint32_t* scan_ws, hipStream_t st);
 // Algorithm 1 with a K-point heap over TUBE slots (binned like the TUBE raster); keys hold the
 // Euclidean depth |p - o| of the chosen point.
 void launch_raster_topk(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,

@@ -375,7 +375,7 @@ void Batch::raygen_gfb(const float* depth, const float* nrm, const float* prob,
     uint32_t* wgo = ws.get<uint32_t>(B_WGO, (uint64_t)gx * n + 1);
     prof_begin();
     launch_gfb_raygen(dd, n, max_pix, depth, nrm, prob, use, thresh, wgc, wgo, lists[0], rs,
-                      hitkey, cnt + C_N0, st);
+                      hitkey, cnt + C_N0, scan_ws, st);
     prof_end("gfb_raygen");
     HIPCHK(hipGetLastError());
 }
