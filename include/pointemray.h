@@ -38,7 +38,7 @@ typedef int32_t pe_status;
 #define PE_ENOMEM (-2)       /* footprint above the context's HBM budget (nothing allocated) */
 #define PE_EDEVICE (-3)      /* HIP runtime error; the context stays usable */
 #define PE_EUNSUPPORTED (-4) /* valid but not implemented combination */
-#define PE_EBUSY (-5)        /* serving queue full */
+#define PE_EBUSY (-5)        /* resource still in use (a scene held by unfinished requests) */
 #define PE_ECANCELED (-6)    /* request cancelled before completion */
 #define PE_ETIMEOUT (-7)     /* pe_wait timed out; the request is still pending */
 
@@ -161,6 +161,10 @@ pe_status pe_ctx_kernel_stats(pe_ctx ctx, int32_t cap, const char** names, doubl
  * pyramids; the scene is immutable afterwards and may be shared by concurrent solves.
  * Errors: PE_EINVAL (bad desc or bad point data), PE_ENOMEM (footprint above budget). */
 pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_stream, pe_scene* out);
+/* Frees the scene's device memory.  Every request submitted with the scene (pe_submit) holds it
+ * until the request finishes (completed, failed or cancelled); while any does, the call returns
+ * PE_EBUSY and frees nothing.  Serialised with the context's other calls, so a synchronous
+ * solve on another thread never sees the scene disappear mid-launch. */
 pe_status pe_scene_destroy(pe_scene scene);
 /* Scene frame: centre c (bounding-box centre, m), radius R = max |x_i - c| + r_i, r_max, and
  * the device bytes the scene holds. */
@@ -179,8 +183,11 @@ pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_res
                    void* hip_stream);
 
 /* Asynchronous solve through the context's continuous-batching server.  The desc's host
- * arrays are copied during the call; res buffers must stay valid until pe_wait returns
- * PE_OK/PE_ECANCELED.  Admission waits until the request's HBM footprint fits the budget.
+ * arrays are copied during the call; the res buffers (E, rcs_dbsm, stats) are written by the
+ * server thread and must stay valid until pe_wait has returned the request's final status
+ * (anything but PE_ETIMEOUT): to give them up early, pe_cancel and then pe_wait.  The request
+ * holds the scene until it finishes (pe_scene_destroy returns PE_EBUSY meanwhile).  Admission
+ * waits until the request's HBM footprint fits the budget.
  * Errors at submit: PE_EINVAL, PE_ENOMEM (request larger than the whole budget). */
 pe_status pe_submit(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_result* res,
                     pe_ticket* ticket);

@@ -163,6 +163,7 @@ class Scene:
         return dict(centre=np.array(list(c)), R=R.value, r_max=rm.value, bytes=b.value)
 
     def close(self):
+        """Frees the scene; raises PEError (PE_EBUSY) while submitted requests still use it."""
         if self.h:
             check(lib().pe_scene_destroy(self.h))
             self.h = None
@@ -434,11 +435,16 @@ def fuse_gfbs(ctx: Context, view_dirs, depth, nrm, hit, centre, R, grid=256, gri
 
 
 class Ticket:
-    """A request submitted to the context's continuous-batching server."""
+    """A request submitted to the context's continuous-batching server.
+
+    The server writes the request's result into buffers this object owns, so they must outlive
+    the request: a Ticket dropped before its request finished cancels it and waits for the
+    server to let go of the buffers (finalizer)."""
 
     def __init__(self, ctx, ticket, E, rcs, st, res, keep):
         self.ctx, self.id, self._E, self._rcs, self._st = ctx, ticket, E, rcs, st
         self._res, self._keep = res, keep
+        self._final = False  # pe_wait returned the request's final status
 
     def wait(self, timeout_s=None):
         """Blocks until the request finishes; returns (E complex, rcs_dbsm, stats).  Raises
@@ -447,12 +453,23 @@ class Ticket:
         s = lib().pe_wait(self.ctx.h, self.id, us)
         if s == _native.PE_ETIMEOUT:
             raise TimeoutError(f"request {self.id} still pending")
+        self._final = True
         check(s)
         stats = {f: getattr(self._st, f) for f, _ in _native.pe_stats._fields_}
         return self._E[..., 0] + 1j * self._E[..., 1], self._rcs, stats
 
     def cancel(self):
         check(lib().pe_cancel(self.ctx.h, self.id))
+
+    def __del__(self):
+        # A closed context has already finished (cancelled) every request of its server.
+        if getattr(self, "_final", True) or not getattr(self.ctx, "h", None):
+            return
+        try:
+            lib().pe_cancel(self.ctx.h, self.id)
+            lib().pe_wait(self.ctx.h, self.id, -1)
+        except Exception:
+            pass
 
 
 def submit(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,

@@ -412,7 +412,16 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
 pe_status pe_scene_destroy(pe_scene scene) {
     API_BEGIN
     if (!scene) return PE_OK;
-    (void)hipSetDevice(scene->ctx->device);
+    pe_ctx ctx = scene->ctx;
+    // Serialised with the synchronous calls (which hold ctx->mu while they launch) and with
+    // the server's batches (which take ctx->mu too); a scene still held by a submitted request
+    // is refused instead of freed under it.
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int held = scene->refs.load();
+    if (held > 0)
+        return set_error(PE_EBUSY, "scene is held by " + std::to_string(held) +
+                                       " unfinished server request(s); wait or cancel them first");
+    (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     delete scene;
     return PE_OK;

@@ -151,6 +151,7 @@ struct pe_ctx_s {
 
 struct pe_scene_s {
     pe_ctx ctx = nullptr;
+    std::atomic<int> refs{0};  // server requests holding this scene until they finish
     uint64_t n = 0;
     double c[3] = {0, 0, 0};
     double R = 0, r_max = 0;

@@ -72,6 +72,10 @@ struct Server {
 
     void finish(const std::shared_ptr<Request>& r, pe_status s) {
         r->status = s;
+        if (r->sc) {
+            r->sc->refs--;  // the scene may be destroyed from here on
+            r->sc = nullptr;
+        }
         if (r->admitted) active_bytes -= r->footprint;
         r->admitted = false;
         if (s == PE_OK) {
@@ -294,6 +298,7 @@ pe_status pe_submit(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_re
     Server* s = get_server(ctx);
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        scene->refs++;  // released by Server::finish
         r->id = s->next_id++;
         s->all[r->id] = r;
         s->pending.push_back(r);

@@ -126,3 +126,28 @@ def test_submit_errors(pe, ctx, two_scenes):
         pe.submit(ctx, s, inc, [-1.0], 64)
     with pytest.raises(pe.PEError):
         pe.submit(ctx, s, inc, [1e9], 64, max_bounces=0)
+
+
+def test_scene_destroy_refused_while_requests_hold_it(pe, ctx):
+    """A scene used by an unfinished request cannot be freed (PE_EBUSY); once the request has
+    finished (here: cancelled), it can.  A Ticket dropped early cancels and waits for the server
+    to let go of its result buffers."""
+    sc = scenes.dihedral()
+    s = pe.Scene.from_scene(ctx, sc, view_res=128)
+    many = scenes.azimuth_sweep(np.arange(0, 360, 0.5), 10.0)
+    f = np.linspace(2e9, 12e9, 16)
+    t = pe.submit(ctx, s, many, f, 512, max_bounces=2, eps=0.5 * sc.radius)
+    with pytest.raises(pe.PEError) as e:
+        s.close()
+    assert "PE_EBUSY" in str(e.value)
+    assert s.h  # nothing was freed
+    t.cancel()
+    with pytest.raises(pe.PEError):
+        t.wait(timeout_s=120)
+    s.close()
+    assert not s.h
+    # dropped ticket: the finalizer cancels and waits, then the scene can go
+    s2 = pe.Scene.from_scene(ctx, sc, view_res=128)
+    t2 = pe.submit(ctx, s2, many, f, 512, max_bounces=2, eps=0.5 * sc.radius)
+    del t2
+    s2.close()
