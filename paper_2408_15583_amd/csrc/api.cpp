@@ -413,14 +413,19 @@ pe_status pe_scene_destroy(pe_scene scene) {
     API_BEGIN
     if (!scene) return PE_OK;
     pe_ctx ctx = scene->ctx;
-    // Serialised with the synchronous calls (which hold ctx->mu while they launch) and with
-    // the server's batches (which take ctx->mu too); a scene still held by a submitted request
-    // is refused instead of freed under it.
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    const int held = scene->refs.load();
-    if (held > 0)
+    // A scene still held by a submitted request is refused at once (before waiting for the
+    // device lock, which the server may hold for many batches in a row); the check is repeated
+    // under the lock, which also serialises the free with the synchronous calls that launch
+    // with this scene.
+    auto busy = [&]() -> pe_status {
+        const int held = scene->refs.load();
+        if (held <= 0) return PE_OK;
         return set_error(PE_EBUSY, "scene is held by " + std::to_string(held) +
                                        " unfinished server request(s); wait or cancel them first");
+    };
+    if (busy() != PE_OK) return PE_EBUSY;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (busy() != PE_OK) return PE_EBUSY;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     delete scene;
