@@ -182,6 +182,26 @@ pe_status pe_scene_info(pe_scene scene, double centre[3], double* R, double* r_m
 pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_result* res,
                    void* hip_stream);
 
+/* Size of the fixed per-device array behind pe_solve_noalloc (128 MiB). */
+#define PE_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
+/* pe_solve for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, semantics, results (bitwise)
+ * and errors as pe_solve with geometry PE_GEOM_PLAIN, but no device or pinned memory is
+ * allocated or freed and no HIP event is created: every transient buffer is carved from one
+ * fixed array of PE_NOALLOC_SCRATCH_BYTES bytes that the library's code object holds on each
+ * device (for the process lifetime; its address is looked up by pe_ctx_create).  Incidences run
+ * in batches that fit the array.  The scene, the desc and the result buffers are the caller's,
+ * as for pe_solve.  Limits: one incidence's batch must fit the array (about 180 bytes per screen
+ * pixel, 40 more per observation direction and, with PE_CONTRIB_EVERY, per bounce: screens up to
+ * 512 x 512 fit, 1024 x 1024 do not); a larger screen returns PE_ENOMEM before anything is
+ * launched, and a single incidence that still outgrows the array returns PE_ENOMEM before the
+ * kernel that would use the missing bytes.  Other geometries return PE_EUNSUPPORTED.  All calls on one device share the
+ * array, so the library runs them one at a time (a second caller blocks until the first
+ * returns); stats->time_ms is host wall time. */
+pe_status pe_solve_noalloc(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc,
+                           pe_result* res, void* hip_stream);
+
 /* Asynchronous solve through the context's continuous-batching server.  The desc's host
  * arrays are copied during the call; the res buffers (E, rcs_dbsm, stats) are written by the
  * server thread and must stay valid until pe_wait has returned the request's final status

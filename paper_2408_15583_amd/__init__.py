@@ -14,7 +14,8 @@ from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM
                       PE_GEOM_DENSIFIED, PE_GEOM_PLAIN, PE_MEM_DEVICE, PE_MEM_HOST, PE_PREC_FP32,
                       PE_PREC_FP64PHASE, PE_SPLAT_DISK, PE_SPLAT_TUBE, PEError, check, lib)
 
-__all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "submit", "server_stats",
+__all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "solve_noalloc", "submit",
+           "server_stats",
            "render_gfb", "render_tube_topk", "trace_pixels", "make_pair", "fuse_gfbs",
            "estimate_normals",
            "PEError", "lib", "check"]
@@ -223,6 +224,25 @@ def solve(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, e
                             rcs.ctypes.data_as(_native.c_double_p), ctypes.pointer(st))
     s = current_stream() if stream is None else stream
     check(lib().pe_solve(ctx.h, scene.h, ctypes.byref(d), ctypes.byref(res), s))
+    del keep
+    stats = {f: getattr(st, f) for f, _ in _native.pe_stats._fields_}
+    return E[..., 0] + 1j * E[..., 1], rcs, stats
+
+
+def solve_noalloc(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
+                  obs_dir=None, contrib="last", precision="fp64phase", stream=None):
+    """pe_solve_noalloc: the plain solve with every transient buffer in the library's fixed
+    per-device scratch array (no device allocation).  Same returns as solve()."""
+    d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
+                              precision)
+    no = 1 if obs_dir is None else d.n_obs
+    E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
+    rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))
+    st = _native.pe_stats()
+    res = _native.pe_result(E.ctypes.data_as(_native.c_double_p),
+                            rcs.ctypes.data_as(_native.c_double_p), ctypes.pointer(st))
+    s = current_stream() if stream is None else stream
+    check(lib().pe_solve_noalloc(ctx.h, scene.h, ctypes.byref(d), ctypes.byref(res), s))
     del keep
     stats = {f: getattr(st, f) for f, _ in _native.pe_stats._fields_}
     return E[..., 0] + 1j * E[..., 1], rcs, stats

@@ -98,6 +98,8 @@ _SIGS = {
     "pe_scene_info": [pe_scene, c_double_p, c_double_p, c_double_p, c_u64_p],
     "pe_solve": [pe_ctx, pe_scene, ctypes.POINTER(pe_solve_desc), ctypes.POINTER(pe_result),
                  ctypes.c_void_p],
+    "pe_solve_noalloc": [pe_ctx, pe_scene, ctypes.POINTER(pe_solve_desc),
+                         ctypes.POINTER(pe_result), ctypes.c_void_p],
     "pe_submit": [pe_ctx, pe_scene, ctypes.POINTER(pe_solve_desc), ctypes.POINTER(pe_result),
                   ctypes.POINTER(pe_ticket)],
     "pe_wait": [pe_ctx, pe_ticket, ctypes.c_int64],

@@ -117,6 +117,7 @@ void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>&
                      int contrib, int precision, double* E_host, double* rcs_host,
                      pe_stats* acc) {
     Batch b(ws, st);
+    ws.begin_batch();
     b.setup(slots, contrib, precision);
     uint32_t c[kNumCounters];
     for (int attempt = 0;; attempt++) {
@@ -127,6 +128,7 @@ void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>&
         b.read_counters(c);
         if (!b.overflowed(c)) break;
         if (attempt > 3) throw Error{PE_EDEVICE, "tile list overflow persists"};
+        ws.begin_batch();
         b.setup(slots, contrib, precision);
     }
     if (acc) {
@@ -161,6 +163,7 @@ pe_status pe_ctx_create(int32_t device, uint64_t hbm_budget, pe_ctx* out) {
     ctx->device = device;
     ctx->budget = hbm_budget ? hbm_budget : (uint64_t)(0.9 * (double)free_b);
     ctx->ws = new Workspace(ctx.get());
+    scratch_init(device);
     *out = ctx.release();
     return PE_OK;
     API_END

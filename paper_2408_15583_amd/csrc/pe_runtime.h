@@ -30,7 +30,9 @@ void pol_basis(const double s[3], double th[3], double ph[3]);
 void* ctx_alloc(pe_ctx ctx, size_t bytes);
 void ctx_free(pe_ctx ctx, void* p, size_t bytes);
 
-// Growable set of device buffers charged to a context's budget.
+// Growable set of device buffers charged to a context's budget.  In arena mode (arena !=
+// nullptr) nothing is allocated: buffers are carved in request order from a fixed device
+// region owned by someone else, and running past its end throws PE_ENOMEM.
 struct Workspace {
     struct Buf {
         void* p = nullptr;
@@ -38,7 +40,11 @@ struct Workspace {
     };
     pe_ctx ctx = nullptr;
     Buf bufs[40];
+    uint8_t* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     explicit Workspace(pe_ctx c) : ctx(c) {}
+    Workspace(pe_ctx c, void* region, size_t cap)
+        : ctx(c), arena((uint8_t*)region), arena_cap(cap) {}
     ~Workspace() { release(); }
     void* raw(int id, size_t bytes);
     template <class T>
@@ -46,6 +52,9 @@ struct Workspace {
         return (T*)raw(id, (size_t)count * sizeof(T));
     }
     void release();
+    // Arena mode: forgets every buffer so that the next batch carves its own from the start
+    // (no-op for allocated workspaces, whose buffers are kept and grown).
+    void begin_batch();
     uint64_t bytes() const;
 };
 
@@ -134,6 +143,12 @@ constexpr int kMaxBounces = 16;
 struct Server;
 struct Densifier;
 
+}  // namespace pe
+
+namespace pe {
+// Fixed per-device scratch of the no-allocation solve (noalloc.hip): looked up once per device
+// by pe_ctx_create with the device current.
+void scratch_init(int device);
 }  // namespace pe
 
 struct pe_ctx_s {

@@ -77,6 +77,18 @@ void ctx_free(pe_ctx ctx, void* p, size_t bytes) {
 void* Workspace::raw(int id, size_t bytes) {
     Buf& b = bufs[id];
     if (bytes == 0) bytes = 16;
+    if (arena) {
+        if (b.cap >= bytes) return b.p;
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        if (want > arena_cap - arena_used)
+            throw Error{PE_ENOMEM, "solve needs more than the fixed scratch of " +
+                                       std::to_string(arena_cap) + " bytes (" +
+                                       std::to_string(arena_used + want) + " requested)"};
+        b.p = arena + arena_used;
+        b.cap = want;
+        arena_used += want;
+        return b.p;
+    }
     if (b.cap < bytes) {
         if (b.p) ctx_free(ctx, b.p, b.cap);
         b.p = nullptr;
@@ -91,10 +103,15 @@ void* Workspace::raw(int id, size_t bytes) {
 
 void Workspace::release() {
     for (auto& b : bufs) {
-        if (b.p) ctx_free(ctx, b.p, b.cap);
+        if (b.p && !arena) ctx_free(ctx, b.p, b.cap);
         b.p = nullptr;
         b.cap = 0;
     }
+    arena_used = 0;
+}
+
+void Workspace::begin_batch() {
+    if (arena) release();
 }
 
 uint64_t Workspace::bytes() const {
@@ -477,7 +494,7 @@ void Batch::read_counters(uint32_t* host) {
 
 // Per-kernel HIP-event timers on the launch stream (enabled per context).
 void Batch::prof_begin() {
-    if (!ws.ctx->profile) return;
+    if (!ws.ctx->profile || ws.arena) return;  // the no-allocation path records no events
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(e, st));
@@ -485,7 +502,7 @@ void Batch::prof_begin() {
 }
 
 void Batch::prof_end(const char* name) {
-    if (!ws.ctx->profile) return;
+    if (!ws.ctx->profile || ws.arena) return;
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(e, st));
