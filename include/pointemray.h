@@ -54,6 +54,7 @@ enum { PE_CONTRIB_LAST = 0, PE_CONTRIB_EVERY = 1 };
 enum { PE_PREC_FP64PHASE = 0, PE_PREC_FP32 = 1 };
 enum { PE_GEOM_PLAIN = 0, PE_GEOM_DENSIFIED = 1, PE_GEOM_COARSE = 2 };
 enum { PE_SPLAT_DISK = 0, PE_SPLAT_TUBE = 1 };
+enum { PE_SECONDARY_VIEWS = 0, PE_SECONDARY_SPLATS = 1 };
 
 /* Scene description (input P of Algorithm 1, with normals and a material flag per point). */
 typedef struct {
@@ -111,6 +112,17 @@ typedef struct {
     int32_t tube_k;          /* DENSIFIED/COARSE: heap size K of Algorithm 1 for the coarse
                                 buffer, 1 .. 1024 (see pe_render_tube_topk); 0 = unbounded K
                                 (the front-most point in the tube, depth along the ray) */
+    int32_t secondary;       /* geometry the bounces and the visibility Psi of Eq. (14) see:
+                                PE_SECONDARY_VIEWS (0): what the scene's aggregation views
+                                retain (Sec. III-B): a secondary hit on disk i at p counts iff a
+                                view stores i within one pixel of p's projection; monostatic
+                                Psi from the incidence first-hit buffer, bistatic Psi by a march
+                                through the views.
+                                PE_SECONDARY_SPLATS (1): every splat of the scene, through an
+                                object-space hierarchy over them (Algorithm 3's acceleration
+                                structure over splats): the nearest disk hit beyond eps, and Psi
+                                = 0 iff any disk is hit from the facet toward k_s beyond eps
+                                (monostatic first-bounce facets are visible). */
 } pe_solve_desc;
 
 /* Counters of one solve. */
@@ -249,9 +261,11 @@ pe_status pe_render_tube_topk(pe_ctx ctx, pe_scene scene, const double dir[3], i
 /* Per-pixel bounce records of one incidence (what the PO sum consumes), device outputs,
  * row-major h x w: n_bounce (0 = no hit), last_x (x3, scene frame: add the centre for world),
  * last_n (x3, oriented), path (image-method path length to last_x in the scene frame), last_idx
- * (point index of the last facet).  Any output may be NULL. */
+ * (point index of the last facet).  Any output may be NULL.  secondary: PE_SECONDARY_VIEWS or
+ * PE_SECONDARY_SPLATS, as in pe_solve_desc. */
 pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], int32_t w,
-                          int32_t h, int32_t max_bounces, double eps, int32_t* n_bounce,
+                          int32_t h, int32_t max_bounces, double eps, int32_t secondary,
+                          int32_t* n_bounce,
                           float* last_x, float* last_n, double* path, uint32_t* last_idx,
                           void* hip_stream);
 

@@ -12,7 +12,8 @@ import numpy as np
 from . import _native
 from ._native import (PE_CONTRIB_EVERY, PE_CONTRIB_LAST, PE_F32, PE_F64, PE_GEOM_COARSE,
                       PE_GEOM_DENSIFIED, PE_GEOM_PLAIN, PE_MEM_DEVICE, PE_MEM_HOST, PE_PREC_FP32,
-                      PE_PREC_FP64PHASE, PE_SPLAT_DISK, PE_SPLAT_TUBE, PEError, check, lib)
+                      PE_PREC_FP64PHASE, PE_SECONDARY_SPLATS, PE_SECONDARY_VIEWS, PE_SPLAT_DISK,
+                      PE_SPLAT_TUBE, PEError, check, lib)
 
 __all__ = ["Context", "Scene", "Densifier", "Ticket", "solve", "solve_noalloc", "submit",
            "server_stats",
@@ -172,11 +173,12 @@ class Scene:
 
 _CONTRIB = {"last": PE_CONTRIB_LAST, "every": PE_CONTRIB_EVERY}
 _PREC = {"fp64phase": PE_PREC_FP64PHASE, "fp32": PE_PREC_FP32}
+_SECONDARY = {"views": PE_SECONDARY_VIEWS, "splats": PE_SECONDARY_SPLATS}
 
 
 def make_solve_desc(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=None,
                     contrib="last", precision="fp64phase", densifier=None, geometry=None,
-                    tube_px=0.0, max_uncertain=0.0, tube_k=0):
+                    tube_px=0.0, max_uncertain=0.0, tube_k=0, secondary="views"):
     inc = np.ascontiguousarray(inc_dir, dtype=np.float64).reshape(-1, 3)
     fr = np.ascontiguousarray(freq_hz, dtype=np.float64).ravel()
     d = _native.pe_solve_desc()
@@ -205,17 +207,20 @@ def make_solve_desc(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=No
     d.tube_px = float(tube_px)
     d.max_uncertain = float(max_uncertain)
     d.tube_k = int(tube_k)
+    d.secondary = _SECONDARY[secondary]
     return d, keep
 
 
 def solve(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
           obs_dir=None, contrib="last", precision="fp64phase", densifier=None, stream=None,
-          geometry=None, tube_px=0.0, max_uncertain=0.0, tube_k=0):
+          geometry=None, tube_px=0.0, max_uncertain=0.0, tube_k=0, secondary="views"):
     """Synchronous pe_solve.  Returns (E complex [inc, obs, freq, rx, tx], rcs_dbsm, stats).
     geometry: "plain" (default), "densified" (needs densifier) or "coarse"; tube_k: heap size
-    of the coarse buffer (0 = unbounded)."""
+    of the coarse buffer (0 = unbounded); secondary: "views" (what the aggregation views
+    retain) or "splats" (every splat, through the object-space hierarchy)."""
     d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
-                              precision, densifier, geometry, tube_px, max_uncertain, tube_k)
+                              precision, densifier, geometry, tube_px, max_uncertain, tube_k,
+                              secondary)
     no = 1 if obs_dir is None else d.n_obs
     E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
     rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))
@@ -230,11 +235,12 @@ def solve(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, e
 
 
 def solve_noalloc(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
-                  obs_dir=None, contrib="last", precision="fp64phase", stream=None):
+                  obs_dir=None, contrib="last", precision="fp64phase", stream=None,
+                  secondary="views"):
     """pe_solve_noalloc: the plain solve with every transient buffer in the library's fixed
     per-device scratch array (no device allocation).  Same returns as solve()."""
     d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
-                              precision)
+                              precision, secondary=secondary)
     no = 1 if obs_dir is None else d.n_obs
     E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
     rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))
@@ -282,7 +288,8 @@ def render_tube_topk(ctx: Context, scene: Scene, direction, w, h, tube_radius, K
     return dict(depth=depth, nrm=nrm, idx=idx, mask=mask)
 
 
-def trace_pixels(ctx: Context, scene: Scene, inc_dir, w, h, max_bounces, eps, stream=None):
+def trace_pixels(ctx: Context, scene: Scene, inc_dir, w, h, max_bounces, eps, stream=None,
+                 secondary="views"):
     """Per-pixel last bounce records of one incidence as torch CUDA tensors."""
     torch = _torch()
     dev = torch.device("cuda")
@@ -294,7 +301,8 @@ def trace_pixels(ctx: Context, scene: Scene, inc_dir, w, h, max_bounces, eps, st
     dr = (ctypes.c_double * 3)(*[float(x) for x in inc_dir])
     s = current_stream() if stream is None else stream
     check(lib().pe_trace_pixels(ctx.h, scene.h, dr, w, h, int(max_bounces), float(eps),
-                                _dptr(nb), _dptr(lx), _dptr(ln), _dptr(path), _dptr(li), s))
+                                _SECONDARY[secondary], _dptr(nb), _dptr(lx), _dptr(ln),
+                                _dptr(path), _dptr(li), s))
     return dict(n_bounce=nb, last_x=lx, last_n=ln, path=path, last_idx=li)
 
 
@@ -493,10 +501,10 @@ class Ticket:
 
 
 def submit(ctx: Context, scene: Scene, inc_dir, freq_hz, screen, max_bounces=1, eps=0.0,
-           obs_dir=None, contrib="last", precision="fp64phase"):
+           obs_dir=None, contrib="last", precision="fp64phase", secondary="views"):
     """Asynchronous solve through the server (pe_submit); returns a Ticket."""
     d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
-                              precision)
+                              precision, secondary=secondary)
     no = 1 if obs_dir is None else d.n_obs
     E = np.zeros((d.n_inc, no, d.n_freq, 2, 2, 2))
     rcs = np.zeros((d.n_inc, no, d.n_freq, 2, 2))

@@ -29,6 +29,7 @@ PE_CONTRIB_LAST, PE_CONTRIB_EVERY = 0, 1
 PE_PREC_FP64PHASE, PE_PREC_FP32 = 0, 1
 PE_GEOM_PLAIN, PE_GEOM_DENSIFIED, PE_GEOM_COARSE = 0, 1, 2
 PE_SPLAT_DISK, PE_SPLAT_TUBE = 0, 1
+PE_SECONDARY_VIEWS, PE_SECONDARY_SPLATS = 0, 1
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -58,7 +59,8 @@ class pe_solve_desc(ctypes.Structure):
                 ("contrib", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("geometry", ctypes.c_int32), ("densifier", pe_densifier),
                 ("seed", ctypes.c_uint64), ("tube_px", ctypes.c_double),
-                ("max_uncertain", ctypes.c_double), ("tube_k", ctypes.c_int32)]
+                ("max_uncertain", ctypes.c_double), ("tube_k", ctypes.c_int32),
+                ("secondary", ctypes.c_int32)]
 
 
 class pe_stats(ctypes.Structure):
@@ -113,8 +115,9 @@ _SIGS = {
                             ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "pe_trace_pixels": [pe_ctx, pe_scene, c_double_p, ctypes.c_int32, ctypes.c_int32,
-                        ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
-                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                        ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p],
     "pe_estimate_normals": [pe_ctx, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int32,
                             ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
     "pe_fuse_gfbs": [pe_ctx, ctypes.POINTER(pe_gfb_set), ctypes.POINTER(pe_fuse_desc),

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "pe_bvh.h"
 #include "pe_device.h"
 #include "pe_runtime.h"
 #include "pointemray.h"
@@ -49,6 +50,8 @@ void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene) {
     if (!(d->eps >= 0) || !std::isfinite(d->eps)) throw Error{PE_EINVAL, "eps must be finite and >= 0"};
     if (d->contrib != PE_CONTRIB_LAST && d->contrib != PE_CONTRIB_EVERY) throw Error{PE_EINVAL, "bad contrib flag"};
     if (d->precision != PE_PREC_FP64PHASE && d->precision != PE_PREC_FP32) throw Error{PE_EINVAL, "bad precision flag"};
+    if (d->secondary != PE_SECONDARY_VIEWS && d->secondary != PE_SECONDARY_SPLATS)
+        throw Error{PE_EINVAL, "bad secondary flag"};
     if (d->geometry != PE_GEOM_PLAIN && d->geometry != PE_GEOM_DENSIFIED && d->geometry != PE_GEOM_COARSE)
         throw Error{PE_EINVAL, "bad geometry flag"};
     if (d->geometry != PE_GEOM_PLAIN) {
@@ -115,8 +118,9 @@ std::vector<SlotSpec> make_slots(pe_scene sc, const pe_solve_desc* d, int i0, in
 // Runs one batch to completion (re-running with a larger tile list if it overflowed).
 void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>& slots,
                      int contrib, int precision, double* E_host, double* rcs_host,
-                     pe_stats* acc) {
+                     pe_stats* acc, int secondary) {
     Batch b(ws, st);
+    b.secondary = secondary;
     ws.begin_batch();
     b.setup(slots, contrib, precision);
     uint32_t c[kNumCounters];
@@ -328,6 +332,46 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
     launch_chunk_box(sc->pa_s, n, sc->cbox, st);
     HIPCHK(hipGetLastError());
 
+    // object-space hierarchy over the ordered points: an octree of their sorted Morton codes,
+    // built top-down one level at a time (each level's node count comes back to the host to
+    // size the next), then its boxes bottom-up into one node array
+    {
+        const uint32_t* codes = sort_keys + n;  // sorted keys of launch_morton_sort
+        std::vector<uint2*> rng{(uint2*)tmp.get(8)}, finfo;
+        std::vector<uint32_t> cnt{1u}, base{0u};
+        launch_fill_u32((uint32_t*)rng[0], 0u, 1, st);
+        launch_fill_u32((uint32_t*)rng[0] + 1, (uint32_t)n, 1, st);
+        uint32_t* d_total = (uint32_t*)tmp.get(4);
+        for (int level = 0;; level++) {
+            const uint32_t m = cnt[level];
+            uint32_t* ccount = (uint32_t*)tmp.get(4ull * m);
+            uint32_t* coff = (uint32_t*)tmp.get(4ull * m + 4);
+            uint32_t* scr = (uint32_t*)tmp.get(4ull * scan_wide_scratch(m));
+            finfo.push_back((uint2*)tmp.get(8ull * m));
+            launch_bvh_count(rng[level], m, level, codes, ccount, st);
+            launch_scan_wide(ccount, coff, m, nullptr, 1, d_total, scr, st);
+            uint32_t next = 0;
+            HIPCHK(hipMemcpyAsync(&next, d_total, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            uint2* rng_next = next ? (uint2*)tmp.get(8ull * next) : nullptr;
+            launch_bvh_emit(rng[level], m, level, codes, coff, base[level] + m, rng_next,
+                            finfo[level], st);
+            if (next == 0) break;
+            if (level + 1 > 11) return set_error(PE_EDEVICE, "hierarchy deeper than its codes");
+            rng.push_back(rng_next);
+            cnt.push_back(next);
+            base.push_back(base[level] + m);
+        }
+        const int L = (int)cnt.size();
+        sc->bvh_nodes = (uint64_t)base[L - 1] + cnt[L - 1];
+        sc->bvh = (float4*)sc->alloc(sc->bvh_nodes * 32);
+        // slack: fp32 rounding of the disk test's hit point at scene scale (a few ulps of R)
+        const float pad = (float)(4e-6 * sc->R);
+        for (int l = L - 1; l >= 0; l--)
+            launch_bvh_box(finfo[l], cnt[l], base[l], sc->pa_s, sc->pb_s, pad, sc->bvh, st);
+        HIPCHK(hipGetLastError());
+    }
+
     // aggregation views
     std::vector<double> dirs;
     if (d.n_views > 0) {
@@ -472,7 +516,8 @@ pe_status pe_solve(pe_ctx ctx, pe_scene scene, const pe_solve_desc* desc, pe_res
             const int cnt = std::min(per, desc->n_inc - i0);
             run_field_batch(*ctx->ws, st, make_slots(scene, desc, i0, cnt), desc->contrib,
                             desc->precision, res->E + i0 * per_inc * 2,
-                            res->rcs_dbsm ? res->rcs_dbsm + i0 * per_inc : nullptr, &acc);
+                            res->rcs_dbsm ? res->rcs_dbsm + i0 * per_inc : nullptr, &acc,
+                            desc->secondary);
         }
     }
     HIPCHK(hipEventRecord(e1, st));
@@ -557,7 +602,8 @@ static pe_status render_gfb(pe_ctx ctx, pe_scene scene, const double dir[3], int
 extern "C" {
 
 pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], int32_t w,
-                          int32_t h, int32_t max_bounces, double eps, int32_t* n_bounce,
+                          int32_t h, int32_t max_bounces, double eps, int32_t secondary,
+                          int32_t* n_bounce,
                           float* last_x, float* last_n, double* path, uint32_t* last_idx,
                           void* hip_stream) {
     API_BEGIN
@@ -566,6 +612,8 @@ pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], i
     if (w < 1 || h < 1 || (uint64_t)w * h > (1u << kPixBits)) return set_error(PE_EINVAL, "bad screen size");
     if (max_bounces < 1 || max_bounces > kMaxBounces) return set_error(PE_EINVAL, "max_bounces must be 1..16");
     if (!(eps >= 0) || !std::isfinite(eps)) return set_error(PE_EINVAL, "eps must be >= 0");
+    if (secondary != PE_SECONDARY_VIEWS && secondary != PE_SECONDARY_SPLATS)
+        return set_error(PE_EINVAL, "bad secondary flag");
     HIPCHK(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)hip_stream;
@@ -577,6 +625,7 @@ pe_status pe_trace_pixels(pe_ctx ctx, pe_scene scene, const double inc_dir[3], i
     s[0].max_b = max_bounces;
     s[0].eps = eps;
     Batch b(*ctx->ws, st);
+    b.secondary = secondary;
     b.setup(s, PE_CONTRIB_LAST, PE_PREC_FP64PHASE);
     uint32_t c[kNumCounters];
     for (int attempt = 0;; attempt++) {

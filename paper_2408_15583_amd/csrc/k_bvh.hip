@@ -1,0 +1,261 @@
+// Object-space hierarchy over a scene's splats and the secondary-hit pass that traverses it.
+//
+// Algorithm 3 builds an acceleration structure over the splats and traverses it for every ray
+// and bounce.  Here the splats are the scene's points, already sorted by their 30-bit Morton
+// codes, so an octree needs no sorting or splitting search: the points sharing a 3 l-bit code
+// prefix form a node of level l, and its children (the occupied octants of the next 3 bits) are
+// contiguous runs found by binary search in the sorted codes.  The tree is built one level at a
+// time (count, scan, emit), then its boxes bottom-up; a leaf's box is the union of its disks'
+// exact boxes (centre +- r sqrt(1 - n_a^2) per axis), widened by a scene-relative slack so that
+// any hit the fp32 disk test accepts lies inside it.
+#include <float.h>
+
+#include <algorithm>
+
+#include "pe_bvh.h"
+#include "pe_device.h"
+#include "pe_geom.h"
+
+namespace pe {
+
+// First index i in [a, b) whose octant ((codes[i] >> s) & 7) is >= o (codes of [a, b) share
+// their bits above s + 2, so the octants are non-decreasing there).
+__device__ inline uint32_t octant_bound(const uint32_t* codes, uint32_t a, uint32_t b, int s,
+                                        uint32_t o) {
+    while (a < b) {
+        const uint32_t mid = a + (b - a) / 2;
+        if (((codes[mid] >> s) & 7u) < o)
+            a = mid + 1;
+        else
+            b = mid;
+    }
+    return a;
+}
+
+// Children of node (a, b) at `level`: octant boundaries bnd[0..8] (level < 10), or a count
+// split into k chunks (level 10); returns the child count (0 = leaf).
+__device__ inline int node_children(const uint32_t* codes, uint32_t a, uint32_t b, int level,
+                                    uint32_t bnd[9], uint32_t& split_len) {
+    const uint32_t cnt = b - a;
+    if (cnt <= (uint32_t)kBvhLeaf || level > 10) return 0;
+    if (level == 10) {
+        const uint32_t k = min(8u, (cnt + kBvhLeaf - 1) / kBvhLeaf);
+        split_len = (cnt + k - 1) / k;
+        return (int)k;
+    }
+    const int s = 27 - 3 * level;
+    bnd[0] = a;
+    bnd[8] = b;
+    int nc = 0;
+    for (uint32_t o = 1; o < 8; o++) bnd[o] = octant_bound(codes, bnd[o - 1], b, s, o);
+    for (int o = 0; o < 8; o++) nc += bnd[o] < bnd[o + 1];
+    return nc;
+}
+
+__global__ __launch_bounds__(256) void k_bvh_count(const uint2* __restrict__ rng, uint32_t n_nodes,
+                                                   int level, const uint32_t* __restrict__ codes,
+                                                   uint32_t* __restrict__ ccount) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
+         j += gridDim.x * blockDim.x) {
+        uint32_t bnd[9], len = 0;
+        ccount[j] = (uint32_t)node_children(codes, rng[j].x, rng[j].y, level, bnd, len);
+    }
+}
+
+void launch_bvh_count(const uint2* rng, uint32_t n_nodes, int level, const uint32_t* codes,
+                      uint32_t* ccount, hipStream_t st) {
+    const uint32_t b = std::min<uint32_t>(65535u, (n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_bvh_count, dim3(b), dim3(256), 0, st, rng, n_nodes, level, codes,
+                       ccount);
+}
+
+__global__ __launch_bounds__(256) void k_bvh_emit(const uint2* __restrict__ rng, uint32_t n_nodes,
+                                                  int level, const uint32_t* __restrict__ codes,
+                                                  const uint32_t* __restrict__ coff,
+                                                  uint32_t cbase, uint2* __restrict__ rng_next,
+                                                  uint2* __restrict__ finfo) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
+         j += gridDim.x * blockDim.x) {
+        const uint32_t a = rng[j].x, b = rng[j].y;
+        uint32_t bnd[9], len = 0;
+        const int nc = node_children(codes, a, b, level, bnd, len);
+        if (nc == 0) {
+            finfo[j] = make_uint2(a, kBvhLeafBit | (b - a));
+            continue;
+        }
+        uint2* out = rng_next + coff[j];
+        uint32_t occ = 0;
+        if (level == 10) {
+            for (int c = 0; c < nc; c++)
+                out[c] = make_uint2(a + c * len, min(a + (c + 1) * len, b));
+            occ = (1u << nc) - 1u;
+        } else {
+            int c = 0;
+            for (int o = 0; o < 8; o++)
+                if (bnd[o] < bnd[o + 1]) {
+                    out[c++] = make_uint2(bnd[o], bnd[o + 1]);
+                    occ |= 1u << o;
+                }
+        }
+        finfo[j] = make_uint2(cbase + coff[j], occ);
+    }
+}
+
+void launch_bvh_emit(const uint2* rng, uint32_t n_nodes, int level, const uint32_t* codes,
+                     const uint32_t* coff, uint32_t cbase, uint2* rng_next, uint2* finfo,
+                     hipStream_t st) {
+    const uint32_t b = std::min<uint32_t>(65535u, (n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_bvh_emit, dim3(b), dim3(256), 0, st, rng, n_nodes, level, codes, coff,
+                       cbase, rng_next, finfo);
+}
+
+__global__ __launch_bounds__(256) void k_bvh_box(const uint2* __restrict__ finfo, uint32_t n_nodes,
+                                                 uint32_t base, const float4* __restrict__ pa_s,
+                                                 const float4* __restrict__ pb_s, float pad,
+                                                 float4* __restrict__ nodes) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
+         j += gridDim.x * blockDim.x) {
+        const uint32_t first = finfo[j].x, info = finfo[j].y;
+        float4 lo = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, 0.f);
+        float4 hi = make_float4(-FLT_MAX, -FLT_MAX, -FLT_MAX, 0.f);
+        if (info & kBvhLeafBit) {
+            const uint32_t p1 = first + (info & 0xFFFFFFu);
+            for (uint32_t p = first; p < p1; p++) {
+                const float4 a = pa_s[p], b = pb_s[p];
+                const float ex = a.w * sqrtf(fmaxf(0.f, 1.f - b.x * b.x));
+                const float ey = a.w * sqrtf(fmaxf(0.f, 1.f - b.y * b.y));
+                const float ez = a.w * sqrtf(fmaxf(0.f, 1.f - b.z * b.z));
+                lo.x = fminf(lo.x, a.x - ex);
+                lo.y = fminf(lo.y, a.y - ey);
+                lo.z = fminf(lo.z, a.z - ez);
+                hi.x = fmaxf(hi.x, a.x + ex);
+                hi.y = fmaxf(hi.y, a.y + ey);
+                hi.z = fmaxf(hi.z, a.z + ez);
+            }
+            lo.x -= pad;
+            lo.y -= pad;
+            lo.z -= pad;
+            hi.x += pad;
+            hi.y += pad;
+            hi.z += pad;
+        } else {
+            const uint32_t nc = __popc(info & 0xFFu);
+            for (uint32_t c = 0; c < nc; c++) {
+                const float4 a = nodes[2 * ((uint64_t)first + c)];
+                const float4 b = nodes[2 * ((uint64_t)first + c) + 1];
+                lo.x = fminf(lo.x, a.x);
+                lo.y = fminf(lo.y, a.y);
+                lo.z = fminf(lo.z, a.z);
+                hi.x = fmaxf(hi.x, b.x);
+                hi.y = fmaxf(hi.y, b.y);
+                hi.z = fmaxf(hi.z, b.z);
+            }
+        }
+        lo.w = __uint_as_float(first);
+        hi.w = __uint_as_float(info);
+        nodes[2 * ((uint64_t)base + j)] = lo;
+        nodes[2 * ((uint64_t)base + j) + 1] = hi;
+    }
+}
+
+void launch_bvh_box(const uint2* finfo, uint32_t n_nodes, uint32_t base, const float4* pa_s,
+                    const float4* pb_s, float pad, float4* nodes, hipStream_t st) {
+    const uint32_t b = std::min<uint32_t>(65535u, (n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_bvh_box, dim3(b), dim3(256), 0, st, finfo, n_nodes, base, pa_s, pb_s,
+                       pad, nodes);
+}
+
+// One bounce, pass 1 with every splat as bounce geometry: each live ray (one lane) leaves its
+// facet along the Eq. (4) reflection and takes the nearest disk hit beyond eps over the whole
+// scene; the packed (t, index) key goes to hitkey[entry] for the apply pass.
+__global__ __launch_bounds__(256) void k_trace_bvh(const SlotDesc* __restrict__ ds,
+                                                   const uint32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ n_live,
+                                                   RayState rs, uint64_t* __restrict__ hitkey,
+                                                   int bounce) {
+    extern __shared__ uint64_t stk[];
+    const uint32_t n = *n_live;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const uint32_t entry = list[e];
+        const SlotDesc& d = ds[entry_slot(entry)];
+        uint64_t key = kEmptyKey;
+        if (bounce <= d.max_b) {
+            const uint64_t g = d.pix_base + entry_pix(entry);
+            const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+            key = bvh_trace<false>(d, x, leave_dir(kin, nn), d.eps, stk + threadIdx.x,
+                                   blockDim.x);
+        }
+        hitkey[e] = key;
+    }
+}
+
+void launch_trace_bvh(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
+                      RayState rs, uint64_t* hitkey, int bounce, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_trace_bvh, dim3(n_blocks), dim3(256),
+                       (size_t)kBvhMaxStack * 256 * sizeof(uint64_t), st, d, list, n_live, rs,
+                       hitkey, bounce);
+}
+
+// Monostatic visibility, pass 1: which entries need a traced Psi (later-bounce facets of
+// monostatic slots), with per-chunk survivor counts for the compaction.
+__global__ __launch_bounds__(256) void k_psi_mark(const SlotDesc* __restrict__ ds,
+                                                  const uint32_t* __restrict__ list,
+                                                  const uint32_t* __restrict__ n_list,
+                                                  RayState rs, uint8_t* __restrict__ alive,
+                                                  uint32_t* __restrict__ chunk_count) {
+    const uint32_t n = *n_list;
+    const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const uint32_t nw = gridDim.x * 4;
+    for (uint32_t c = wid; c < n_chunks; c += nw) {
+        const uint32_t e = c * kWaveChunk + lane;
+        bool need = false;
+        if (e < n) {
+            const uint32_t entry = list[e];
+            const SlotDesc& d = ds[entry_slot(entry)];
+            need = d.mono && rs.m[d.pix_base + entry_pix(entry)] >= 2;
+            alive[e] = need ? 1 : 0;
+        }
+        const uint64_t bal = __ballot(need);
+        if (lane == 0) chunk_count[c] = (uint32_t)__popcll(bal);
+    }
+}
+
+void launch_psi_mark(const SlotDesc* d, const uint32_t* list, const uint32_t* n_list,
+                     RayState rs, uint8_t* alive, uint32_t* chunk_count, int n_blocks,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_psi_mark, dim3(n_blocks), dim3(256), 0, st, d, list, n_list, rs, alive,
+                       chunk_count);
+}
+
+// Monostatic visibility, pass 2: one lane per compacted facet, any hit toward k_s beyond eps.
+__global__ __launch_bounds__(256) void k_psi_trace(const SlotDesc* __restrict__ ds,
+                                                   const ObsDesc* __restrict__ obs,
+                                                   const uint32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ n_list,
+                                                   RayState rs, uint8_t* __restrict__ vis) {
+    extern __shared__ uint64_t stk[];
+    const uint32_t n = *n_list;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const uint32_t entry = list[e];
+        const SlotDesc& d = ds[entry_slot(entry)];
+        const uint64_t g = d.pix_base + entry_pix(entry);
+        const ObsDesc& O = obs[d.obs_base];
+        const f3 ks = mk3(O.ks[0], O.ks[1], O.ks[2]);
+        vis[g] = bvh_trace<true>(d, ld3(rs, RX, g), ks, d.eps, stk + threadIdx.x, blockDim.x) ==
+                         kEmptyKey
+                     ? 1
+                     : 0;
+    }
+}
+
+void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
+                      const uint32_t* n_list, RayState rs, uint8_t* vis, int n_blocks,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_psi_trace, dim3(n_blocks), dim3(256),
+                       (size_t)kBvhMaxStack * 256 * sizeof(uint64_t), st, d, obs, list, n_list,
+                       rs, vis);
+}
+
+}  // namespace pe

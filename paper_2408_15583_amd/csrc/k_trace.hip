@@ -14,43 +14,11 @@
 // exclusive scan, so the order (and every downstream sum) is deterministic.
 #include <float.h>
 
+#include "pe_bvh.h"
 #include "pe_device.h"
+#include "pe_geom.h"
 
 namespace pe {
-
-struct f3 {
-    float x, y, z;
-};
-__device__ inline f3 mk3(float x, float y, float z) { return {x, y, z}; }
-__device__ inline f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ inline f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ inline f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
-__device__ inline float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ inline f3 mirror(f3 a, f3 n) { return a - n * (2.f * dot(n, a)); }
-__device__ inline f3 ld3(const RayState& rs, int c, uint64_t g) {
-    return {rs.f[c][g], rs.f[c + 1][g], rs.f[c + 2][g]};
-}
-__device__ inline void st3(const RayState& rs, int c, uint64_t g, f3 v) {
-    rs.f[c][g] = v.x;
-    rs.f[c + 1][g] = v.y;
-    rs.f[c + 2][g] = v.z;
-}
-
-// Exact ray-disk test in the scene frame (two-sided; grazing |n.k| < 1e-6 misses; t > tmin;
-// inclusive boundary).
-__device__ inline bool disk_test(float4 a, float4 b, f3 o, f3 k, float tmin, float& t) {
-    const float den = b.x * k.x + b.y * k.y + b.z * k.z;
-    if (fabsf(den) < kGraze) return false;
-    const f3 w = mk3(a.x - o.x, a.y - o.y, a.z - o.z);
-    const float tt = (b.x * w.x + b.y * w.y + b.z * w.z) / den;
-    if (!(tt > tmin)) return false;
-    const f3 q = k * tt - w;
-    if (dot(q, q) <= a.w * a.w) {
-        t = tt;
-        return true;
-    }
-    return false;
-}
 
 // ------------------------------------------------------------------------------------------
 // Ray generation from the first-hit buffer
@@ -417,10 +385,6 @@ __device__ inline void march_all(const SlotDesc& d, f3 x, f3 k, float tmin, floa
         march_view(d.views[v], x, k, tmin, smax, tol, best_t, best_i, cap_hits);
 }
 
-__device__ inline uint64_t pack_hit(float t, uint32_t i) {
-    return ((uint64_t)__float_as_uint(t) << 32) | i;
-}
-
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
     const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
@@ -571,8 +535,7 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                         const ViewFields vf = view_fields(views[v]);
                         __builtin_amdgcn_sched_barrier(0);  // issue these before waiting above
                         x = xs;
-                        k = mirror(kin, nn);
-                        k = k * rsqrtf(dot(k, k));
+                        k = leave_dir(kin, nn);
                         active = walk_init(vf, x, k, eps, march_smax(R, r_max, x, k),
                                            march_tol(R), bt, w);
                     }
@@ -718,8 +681,7 @@ __global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict
             if (bounce <= d.max_b) {
                 const uint64_t g = d.pix_base + entry_pix(entry);
                 const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
-                f3 k = mirror(kin, nn);
-                k = k * rsqrtf(dot(k, k));
+                const f3 k = leave_dir(kin, nn);
                 live = apply_bounce(d, g, rs, x, nn, k, key, bounce);
             }
             alive[e] = live ? 1 : 0;
@@ -844,7 +806,9 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
                                                  const uint32_t* __restrict__ n_list,
                                                  RayState rs, const uint64_t* __restrict__ keys,
                                                  ExitRecs er, uint32_t rec_stride, int seg,
-                                                 int n_seg, uint32_t* cap_hits) {
+                                                 int n_seg, uint32_t* cap_hits, int splats,
+                                                 const uint8_t* __restrict__ vis_mono) {
+    extern __shared__ uint64_t stk[];
     const uint32_t n = *n_list;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const uint32_t entry = list[e];
@@ -866,7 +830,15 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
             const ObsDesc& O = obs[d.obs_base + o];
             const f3 ks = mk3(O.ks[0], O.ks[1], O.ks[2]);
             bool vis = true;
-            if (d.mono) {
+            if (splats) {
+                // every splat can hide the facet; a monostatic first-bounce facet is the nearest
+                // hit along its own reversed ray and is visible; later ones were traced densely
+                if (!d.mono)
+                    vis = bvh_trace<true>(d, x, ks, d.eps, stk + threadIdx.x, blockDim.x) ==
+                          kEmptyKey;
+                else if (m >= 2)
+                    vis = vis_mono[g] != 0;
+            } else if (d.mono) {
                 if (m >= 2) vis = visible_primary(d, keys, x, ks);
             } else {
                 vis = visible_views(d, x, ks, cap_hits);
@@ -889,10 +861,11 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
 
 void launch_po_prep(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
                     const uint32_t* n_list, RayState rs, const uint64_t* keys, ExitRecs er,
-                    uint32_t rec_stride, int seg, int n_seg, uint32_t* cap_hits, int n_blocks,
-                    hipStream_t st) {
-    hipLaunchKernelGGL(k_po_prep, dim3(n_blocks), dim3(256), 0, st, d, obs, list, n_list, rs,
-                       keys, er, rec_stride, seg, n_seg, cap_hits);
+                    uint32_t rec_stride, int seg, int n_seg, uint32_t* cap_hits, int splats,
+                    const uint8_t* vis, int n_blocks, hipStream_t st) {
+    const size_t lds = splats ? (size_t)kBvhMaxStack * 256 * sizeof(uint64_t) : 0;
+    hipLaunchKernelGGL(k_po_prep, dim3(n_blocks), dim3(256), lds, st, d, obs, list, n_list, rs,
+                       keys, er, rec_stride, seg, n_seg, cap_hits, splats, vis);
 }
 
 }  // namespace pe

@@ -105,7 +105,8 @@ extern "C" pe_status pe_solve_noalloc(pe_ctx ctx, pe_scene scene, const pe_solve
         try {
             run_field_batch(ws, st, make_slots(scene, desc, i0, cnt), desc->contrib,
                             desc->precision, res->E + i0 * per_inc * 2,
-                            res->rcs_dbsm ? res->rcs_dbsm + i0 * per_inc : nullptr, &acc);
+                            res->rcs_dbsm ? res->rcs_dbsm + i0 * per_inc : nullptr, &acc,
+                            desc->secondary);
         } catch (const Error& err) {
             if (err.status != PE_ENOMEM || cnt == 1) throw;
             HIPCHK(hipStreamSynchronize(st));

@@ -39,7 +39,7 @@ struct Workspace {
         size_t cap = 0;
     };
     pe_ctx ctx = nullptr;
-    Buf bufs[40];
+    Buf bufs[44];
     uint8_t* arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
     explicit Workspace(pe_ctx c) : ctx(c) {}
@@ -87,6 +87,9 @@ struct Batch {
     uint32_t* scan_ws = nullptr;  // per-tile totals of the wide scans
     int n = 0, contrib = 0, precision = 0, n_seg = 1, ft = 1, max_b = 1;
     int topk = 0;  // > 0: TUBE slots keep a K-point heap (Algorithm 1) instead of K unbounded
+    // PE_SECONDARY_SPLATS: bounces and visibility against every splat through the scene's
+    // object-space hierarchy; PE_SECONDARY_VIEWS: through the aggregation views
+    int secondary = 0;
     bool blend = false;  // some slot's scene refines hits by Eq. (23)
     int max_chunks = 0, max_tiles = 0, max_pix = 0, max_obs = 1, max_freq = 1, tot_out = 0;
     uint64_t tot_pix = 0;
@@ -174,6 +177,8 @@ struct pe_scene_s {
     float4* cbox = nullptr;  // per-chunk bounding boxes of pa_s
     std::vector<pe::ViewDesc> views;
     pe::ViewDesc* views_dev = nullptr;
+    float4* bvh = nullptr;  // object-space hierarchy over pa_s (node records at pe::kBvhLeaf)
+    uint64_t bvh_nodes = 0;
     float blend_r = 0.f, bl_h = 0.f;  // Eq. (23) refinement radius and centre-grid cell edge
     int bl_G = 0;
     uint32_t *bl_start = nullptr, *bl_items = nullptr;
@@ -219,5 +224,5 @@ int slots_per_batch(pe_ctx ctx, const pe_solve_desc* d);
 std::vector<SlotSpec> make_slots(pe_scene sc, const pe_solve_desc* d, int i0, int count);
 void run_field_batch(Workspace& ws, hipStream_t st, const std::vector<SlotSpec>& slots,
                      int contrib, int precision, double* E_host, double* rcs_host,
-                     pe_stats* acc);
+                     pe_stats* acc, int secondary = PE_SECONDARY_VIEWS);
 }  // namespace pe

@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "pe_bvh.h"
 #include "pe_device.h"
 #include "pe_gfb.h"
 #include "pe_runtime.h"
@@ -181,10 +182,12 @@ enum BufId {
     B_MQUEUE, B_SCAN, B_NUMBUF
 };
 static_assert(B_NUMBUF <= 34, "workspace ids 34..39 belong to the densified solve");
+constexpr int B_PSILIST = 40, B_VIS = 41;  // monostatic visibility pass (secondary = splats)
 
 enum Counter : int {
     C_TILES = 0, C_OVERFLOW, C_N0, C_N1, C_N2, C_WORK, C_CAP, C_BOUNCE0, C_NCOUNT = C_BOUNCE0 + 64
 };
+constexpr int C_PSI = C_BOUNCE0 + 63;  // facets of the monostatic visibility pass
 
 static int pow2_at_least(int x) {
     int p = 1;
@@ -227,6 +230,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.bl_G = sc->bl_G;
         d.bl_start = sc->bl_start;
         d.bl_items = sc->bl_items;
+        d.bvh = sc->bvh;
         if (sc->blend_r > 0.f) blend = true;
         d.views = sc->views_dev;
         d.n_views = (int)sc->views.size();
@@ -410,9 +414,26 @@ void Batch::alloc_records() {
 }
 
 void Batch::records(int seg, const uint32_t* list, const uint32_t* n_list) {
+    const bool splats = secondary == PE_SECONDARY_SPLATS;
+    uint8_t* vis = nullptr;
+    if (splats) {
+        // dense any-hit pass over the monostatic later-bounce facets (most facets are first
+        // bounces, which are visible, so tracing inside po_prep would idle most lanes)
+        uint32_t* plist = ws.get<uint32_t>(B_PSILIST, tot_pix);
+        vis = ws.get<uint8_t>(B_VIS, tot_pix);
+        const uint32_t max_chunks = (uint32_t)((tot_pix + kWaveChunk - 1) / kWaveChunk);
+        prof_begin();
+        launch_psi_mark(dd, list, n_list, rs, alive, ccount, persistent_blocks(), st);
+        launch_scan_wide(ccount, coff, max_chunks, n_list, kWaveChunk, cnt + C_PSI, scan_ws, st);
+        launch_compact(list, n_list, alive, coff, plist, persistent_blocks(), st);
+        prof_end("psi_compact");
+        prof_begin();
+        launch_psi_trace(dd, dobs, plist, cnt + C_PSI, rs, vis, persistent_blocks(), st);
+        prof_end("psi_bvh");
+    }
     prof_begin();
     launch_po_prep(dd, dobs, list, n_list, rs, keys, er, rec_stride, seg, n_seg, cnt + C_CAP,
-                   persistent_blocks(), st);
+                   splats, vis, persistent_blocks(), st);
     prof_end("po_prep");
     prof_begin();
     launch_slot_ranges(list, n_list, n, seg_beg + (uint64_t)seg * n, seg_cnt + (uint64_t)seg * n,
@@ -431,11 +452,18 @@ void Batch::trace(bool with_records) {
         uint32_t* out = lists[b % 2 == 0 ? 1 : 2];
         uint32_t* nout = cnt + (b % 2 == 0 ? C_N1 : C_N2);
         prof_begin();
-        launch_march(dd, cur, ncur, rs, hitkey, b, max_views, cnt + C_CAP,
-                     ws.get<uint32_t>(B_MQUEUE, kNumXcd), persistent_blocks(), st);
-        static const char* names[] = {"march_b2", "march_b3", "march_b4", "march_b5", "march_b6",
-                                      "march_b7", "march_b8", "march_b9+"};
-        prof_end(names[std::min(b - 2, 7)]);
+        if (secondary == PE_SECONDARY_SPLATS) {
+            launch_trace_bvh(dd, cur, ncur, rs, hitkey, b, persistent_blocks(), st);
+            static const char* names[] = {"bvh_b2", "bvh_b3", "bvh_b4", "bvh_b5", "bvh_b6",
+                                          "bvh_b7", "bvh_b8", "bvh_b9+"};
+            prof_end(names[std::min(b - 2, 7)]);
+        } else {
+            launch_march(dd, cur, ncur, rs, hitkey, b, max_views, cnt + C_CAP,
+                         ws.get<uint32_t>(B_MQUEUE, kNumXcd), persistent_blocks(), st);
+            static const char* names[] = {"march_b2", "march_b3", "march_b4", "march_b5",
+                                          "march_b6", "march_b7", "march_b8", "march_b9+"};
+            prof_end(names[std::min(b - 2, 7)]);
+        }
         prof_begin();
         launch_bounce_apply(dd, cur, ncur, rs, hitkey, alive, ccount, b, persistent_blocks(), st);
         prof_end("bounce_apply");

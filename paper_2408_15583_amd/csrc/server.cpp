@@ -122,7 +122,7 @@ struct Server {
                 int inc;
             };
             std::vector<Item> items;
-            int contrib = 0, precision = 0;
+            int contrib = 0, precision = 0, secondary = 0;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
@@ -146,12 +146,15 @@ struct Server {
                 // round-robin over admitted requests sharing the first one's flags
                 contrib = active.front()->d.contrib;
                 precision = active.front()->d.precision;
+                secondary = active.front()->d.secondary;
                 uint64_t px = 0;
                 bool progress = true;
                 while (progress && (int)items.size() < kMaxSlots) {
                     progress = false;
                     for (auto& r : active) {
-                        if (r->d.contrib != contrib || r->d.precision != precision) continue;
+                        if (r->d.contrib != contrib || r->d.precision != precision ||
+                            r->d.secondary != secondary)
+                            continue;
                         if (r->next >= r->d.n_inc) continue;
                         const uint64_t p = (uint64_t)r->d.screen_w * r->d.screen_h;
                         if (!items.empty() && px + p > px_budget) continue;
@@ -182,7 +185,8 @@ struct Server {
             std::string err;
             try {
                 std::lock_guard<std::mutex> dev(ctx->mu);
-                run_field_batch(ws, st, slots, contrib, precision, E.data(), R.data(), &acc);
+                run_field_batch(ws, st, slots, contrib, precision, E.data(), R.data(), &acc,
+                                secondary);
                 HIPCHK(hipStreamSynchronize(st));
             } catch (const Error& e) {
                 s = e.status;
