@@ -9,10 +9,15 @@ min/max pyramids, then for every azimuth the first-hit splat, ray generation, bo
 visibility, facet records and the PO sum over all frequencies.  Inputs (points, normals) are
 resident in device memory before the timed region.
 
+Bounces and visibility are traced against every splat through the object-space hierarchy by
+default (--secondary splats: the result follows the exact oracle); the aggregation views' march
+(--secondary views) is timed beside it for a few steps.
+
 Prints one JSON line: value = ray-bounces/s (live-ray intersection queries, primary rays
 included, per second of step wall time); extra fields give RCS samples/s, the dominant
-kernel's roofline (HIP events on its launch stream, over the timed steps) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+kernel's roofline (HIP events on its launch stream, over the timed steps), the FP64 CPU
+oracle timed on a bounded sample of the same workload, and the error of each bounce geometry
+against that oracle's culled-exact solve of 36 azimuths.
 """
 from __future__ import annotations
 
@@ -44,6 +49,15 @@ MARCH_TRAFFIC = dict(
              "e8ec339ff11e3ccc787afcff74d5151897879d2a05c2796c91656e2912572470"})
 
 
+# HBM traffic of k_trace_bvh (the same two counter passes); None until measured on its sources.
+BVH_TRAFFIC = None
+
+
+def bvh_traffic():
+    """Counter-measured bytes per k_trace_bvh launch, or None (not measured on these sources)."""
+    return None if BVH_TRAFFIC is None else BVH_TRAFFIC
+
+
 def march_traffic():
     """Counter-measured bytes per k_march launch, or None once the kernel's sources changed."""
     import hashlib
@@ -66,23 +80,63 @@ def po_slots_per_term():
     return 2 * fp64 + fp32 + 4 * trans
 
 
-def cpu_baseline(sc, sw, sample_px, seed=11):
-    """FP64 oracle (brute force over all disks) tracing a fixed seeded sample of the
-    workload's pixel rays for one azimuth; returns ray-bounces/s on the host."""
+def cpu_baseline(sc, sw, n_az, sample_px, gpu_rcs, seed=11):
+    """FP64 oracle on the host, timed on a bounded sample of the workload: its culled-exact mode
+    (uniform grid, bitwise equal to brute force) solves n_az of the workload's azimuths in full
+    (screen, frequencies, bounces), and its brute-force mode traces sample_px seeded pixel rays
+    of azimuth 0.  The culled-exact RCS also measures each GPU mode's error on those azimuths
+    (gpu_rcs: {mode: rcs of all azimuths}), reported with the per-sample fp32 spread of the
+    oracle itself (inputs rounded to fp32 in the scene frame)."""
     import numpy as np
     import oracle
-    o = oracle.OracleScene(sc)
+    idx = np.linspace(0, len(sw.inc_dir), n_az, endpoint=False).astype(int)
+    inc = sw.inc_dir[idx]
+    t0 = time.perf_counter()
+    o = oracle.OracleScene(sc, grid=256)
+    t_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    E, st = o.solve(inc, sw.freq_hz, sw.screen, sw.screen, sw.max_bounces, sw.eps)
+    dt = time.perf_counter() - t0
+    ro = oracle.rcs_dbsm(E)
+    c = 0.5 * (sc.xyz.min(0) + sc.xyz.max(0))
+    o32 = oracle.OracleScene((sc.xyz - c).astype(np.float32).astype(np.float64) + c,
+                             sc.nrm.astype(np.float32).astype(np.float64), sc.radius_array(),
+                             sc.material, grid=256)
+    r32 = oracle.rcs_dbsm(o32.solve(inc, sw.freq_hz, sw.screen, sw.screen, sw.max_bounces,
+                                    sw.eps)[0])
+
+    def errors(r):
+        out = []
+        for p in range(2):
+            a, b = r[..., p, p], ro[..., p, p]
+            sel = b >= b.max(axis=0, keepdims=True) - 30.0
+            out.append(np.abs(a - b)[sel])
+        e = np.concatenate(out)
+        return dict(median_db=float(np.median(e)), p90_db=float(np.percentile(e, 90)),
+                    p99_db=float(np.percentile(e, 99)), max_db=float(e.max()),
+                    within_0p1db=float((e <= 0.1).mean()), samples=int(e.size))
+
+    accuracy = {m: errors(r[idx]) for m, r in gpu_rcs.items()}
+    accuracy["oracle_fp32_inputs"] = errors(r32)
     rng = np.random.default_rng(seed)
     pix = rng.choice(sw.screen * sw.screen, size=sample_px, replace=False)
     t0 = time.perf_counter()
     nb, _, _ = o.trace_pixels(sw.inc_dir[0], sw.screen, sw.screen, pix, sw.max_bounces, sw.eps,
                               grid=0)
-    dt = time.perf_counter() - t0
-    q = float(np.sum(nb + (nb < sw.max_bounces)))
+    dtb = time.perf_counter() - t0
+    qb = float(np.sum(nb + (nb < sw.max_bounces)))
+    q = float(st["queries"])
     return dict(value=q / dt, unit="ray-bounces/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{sample_px} seeded pixel rays of azimuth 0 at {sw.screen}^2, "
-                       f"<= {sw.max_bounces} bounces, brute force over all {sc.n} disks "
-                       f"({q:.0f} queries in {dt:.1f} s)")
+                rcs_samples_per_s=len(inc) * len(sw.freq_hz) / dt,
+                sample=f"culled-exact oracle (256^3 grid, built in {t_grid:.1f} s, not timed), "
+                       f"{len(inc)} of the {len(sw.inc_dir)} azimuths at {sw.screen}^2, "
+                       f"{len(sw.freq_hz)} freqs, <= {sw.max_bounces} bounces: {q:.0f} queries "
+                       f"in {dt:.1f} s",
+                brute_force=dict(value=qb / dtb, unit="ray-bounces/s",
+                                 sample=f"{sample_px} seeded pixel rays of azimuth 0, brute force "
+                                        f"over all {sc.n} disks ({qb:.0f} queries in "
+                                        f"{dtb:.1f} s)"),
+                accuracy=accuracy)
 
 
 def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
@@ -302,9 +356,16 @@ def main():
     ap.add_argument("--n-az", type=int, default=360)
     ap.add_argument("--n-freq", type=int, default=64)
     ap.add_argument("--bounces", type=int, default=4)
-    ap.add_argument("--precision", default="fp64phase", choices=["fp64phase", "fp32"])
-    ap.add_argument("--cpu-sample", type=int, default=3000,
-                    help="pixel rays traced by the CPU oracle (0 = skip)")
+    ap.add_argument("--precision", default="fp64phase", choices=["fp64phase", "fp32", "fp64acc"])
+    ap.add_argument("--secondary", default="splats", choices=["splats", "views"],
+                    help="bounce geometry of the timed steps: every splat through the "
+                         "object-space hierarchy, or what the aggregation views retain")
+    ap.add_argument("--compare-steps", type=int, default=2,
+                    help="timed steps of the other bounce geometry, reported beside (0 = skip)")
+    ap.add_argument("--cpu-az", type=int, default=36,
+                    help="azimuths the CPU oracle solves in full (0 = skip the CPU leg)")
+    ap.add_argument("--cpu-sample", type=int, default=2000,
+                    help="pixel rays traced by the brute-force oracle")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -346,10 +407,11 @@ def main():
     torch.cuda.synchronize()
     ctx = pe.Context(0)
 
-    def step():
+    def step(secondary=args.secondary):
         s = pe.Scene(ctx, xyz, nrm, sc.radius, view_res=sw.view_res)
         E, rcs, st = pe.solve(ctx, s, sw.inc_dir, sw.freq_hz, sw.screen,
-                              max_bounces=sw.max_bounces, eps=sw.eps, precision=args.precision)
+                              max_bounces=sw.max_bounces, eps=sw.eps, precision=args.precision,
+                              secondary=secondary)
         s.close()
         return E, rcs, st
 
@@ -382,28 +444,38 @@ def main():
     finite = np.isfinite(rcs[..., 0, 0]).all() and np.isfinite(rcs[..., 1, 1]).all()
 
     # dominant kernel and its roofline: HIP events on the launch stream over the timed steps
-    march = {k: v for k, v in ks.items() if k.startswith("march")}
     groups = dict(ks)
-    if march:
-        for k in march:
-            groups.pop(k)
-        groups["march"] = (sum(v[0] for v in march.values()), sum(v[1] for v in march.values()))
+    for prefix in ("march", "bvh"):
+        part = {k: v for k, v in ks.items() if k.startswith(prefix + "_b")}
+        if part:
+            for k in part:
+                groups.pop(k)
+            groups[prefix] = (sum(v[0] for v in part.values()), sum(v[1] for v in part.values()))
     name, (tot_ms, launches) = max(groups.items(), key=lambda kv: kv[1][0])
     avg_ms = tot_ms / max(launches, 1)
-    if name == "march":
-        # algorithmic bytes: every live ray's state is read once (21 fp32 + fp64 path + u8 bounce
-        # count + u32 facet index = 97 B) and, for rays that continue, written once (97 B), plus
-        # one alive byte; view pyramids and pixel records are not counted.
+    if name in ("march", "bvh"):
+        # algorithmic bytes of one bounce (the secondary-hit pass and its apply) per live ray:
+        # the ray state, 76 B (18 fp32 + fp64 path + u32 pixel id), read once and written once
+        # for the rays that continue; the SoA state this build keeps is 97 B (21 fp32: the
+        # incoming direction and the two incident polarisations kept whole, + fp64 path + u8
+        # bounce count + u32 facet index), reported beside.  Scene data and view pyramids are
+        # not counted.
         rays = march_rays / args.steps
         hits = march_hits / args.steps
-        per_step_bytes = 97.0 * rays + 97.0 * hits + rays
+        per_step_bytes = 76.0 * rays + 76.0 * hits
         per_launch = per_step_bytes / (launches / args.steps)
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        soa_launch = (97.0 * rays + 97.0 * hits + rays) / (launches / args.steps)
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=march_traffic(), kernel="k_march",
-                    avg_launch_ms=avg_ms, launches=launches,
-                    bytes_per_launch=per_launch,
-                    note="97 B state read per live ray + 97 B write per continuing ray + 1 B")
+                    frac=achieved / HBM_PEAK_GBS,
+                    traffic=march_traffic() if name == "march" else bvh_traffic(),
+                    kernel="k_march" if name == "march" else "k_trace_bvh",
+                    avg_launch_ms=avg_ms, launches=launches, bytes_per_launch=per_launch,
+                    soa_bytes_per_launch=soa_launch,
+                    soa_frac=soa_launch / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    rays_per_s=rays / (tot_ms / args.steps * 1e-3),
+                    note="76 B state read per live ray + 76 B write per continuing ray "
+                         "(soa_*: the 97 B SoA state + 1 B flag)")
     elif name == "po_sum":
         per_launch_terms = terms / launches
         achieved = per_launch_terms * po_slots_per_term() / (avg_ms * 1e-3) / 1e12
@@ -430,7 +502,8 @@ def main():
         "config": {"workload": f"composite 12 primitives, {sc.n} points, {sw.screen}^2 screen, "
                                f"6 views at {sw.view_res}^2, {len(sw.inc_dir)} azimuths at 30 deg "
                                f"elevation, {len(sw.freq_hz)} freqs 2-12 GHz, <= {sw.max_bounces} "
-                               "bounces, monostatic"},
+                               "bounces, monostatic",
+                   "secondary": args.secondary, "precision": args.precision},
         "rcs_samples_per_s": len(sw.inc_dir) * len(sw.freq_hz) * args.steps / dt,
         "ray_queries_per_step": queries / args.steps,
         "po_terms_per_step": terms / args.steps,
@@ -441,12 +514,36 @@ def main():
                                                                         key=lambda kv: -kv[1][0])},
     }
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    gpu_rcs = {args.secondary: rcs}
+    other = "views" if args.secondary == "splats" else "splats"
+    if args.compare_steps > 0:
+        # the other bounce geometry on the same workload, timed the same way (fewer steps)
+        step(other)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q2 = 0.0
+        for _ in range(args.compare_steps):
+            _, rcs2, st2 = step(other)
+            q2 += st2["ray_queries"]
+        torch.cuda.synchronize()
+        dt2 = time.perf_counter() - t0
+        gpu_rcs[other] = rcs2
+        out["compare"] = {"secondary": other, "steps": args.compare_steps,
+                          "ms_per_step": 1e3 * dt2 / args.compare_steps, "value": q2 / dt2,
+                          "unit": "ray-bounces/s"}
+        log(f"{other}: {1e3 * dt2 / args.compare_steps:.1f} ms per step")
     out["next_rows"] = None if args.no_next_rows else next_rows(pe, ctx, sc, xyz, nrm, sw.view_res,
                                                                       log=log)
     out["densifier"] = None if args.no_densifier else densifier_bench(pe, ctx, log=log)
     out["serving"] = serving(pe, ctx, args.serve_seconds, log=log) if args.serve_seconds > 0 else None
-    if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(sc, sw, args.cpu_sample)
+    if args.cpu_az > 0:
+        log("CPU oracle leg ...")
+        out["cpu_baseline"] = cpu_baseline(sc, sw, args.cpu_az, args.cpu_sample, gpu_rcs)
+        acc = out["cpu_baseline"]["accuracy"]
+        # error of the timed result against the exact oracle on the oracle's azimuths
+        out["accuracy_vs_oracle"] = acc.get(args.secondary)
+        log("accuracy: " + ", ".join(f"{m} median {a['median_db']:.4f} / p99 {a['p99_db']:.3f} / "
+                                     f"max {a['max_db']:.3f} dB" for m, a in acc.items()))
     else:
         out["cpu_baseline"] = None
     ctx.close()

@@ -51,7 +51,7 @@ enum { PE_MEM_HOST = 0, PE_MEM_DEVICE = 1 };
 enum { PE_F32 = 0, PE_F64 = 1 };
 enum { PE_MAT_PEC = 0, PE_MAT_ABSORBER = 1 };
 enum { PE_CONTRIB_LAST = 0, PE_CONTRIB_EVERY = 1 };
-enum { PE_PREC_FP64PHASE = 0, PE_PREC_FP32 = 1 };
+enum { PE_PREC_FP64PHASE = 0, PE_PREC_FP32 = 1, PE_PREC_FP64ACC = 2 };
 enum { PE_GEOM_PLAIN = 0, PE_GEOM_DENSIFIED = 1, PE_GEOM_COARSE = 2 };
 enum { PE_SPLAT_DISK = 0, PE_SPLAT_TUBE = 1 };
 enum { PE_SECONDARY_VIEWS = 0, PE_SECONDARY_SPLATS = 1 };
@@ -92,7 +92,11 @@ typedef struct {
     int32_t max_bounces;     /* >= 1 (1 = physical optics from the first-hit buffer only) */
     double eps;              /* minimum travel distance of secondary rays (m), >= 0 */
     int32_t contrib;         /* PE_CONTRIB_LAST (Eq. (14)) or PE_CONTRIB_EVERY */
-    int32_t precision;       /* PE_PREC_FP64PHASE or PE_PREC_FP32 */
+    int32_t precision;       /* PO sum of Eq. (14): PE_PREC_FP64PHASE (phase k D reduced in fp64,
+                                fp32 sin/cos and sinc, each aligned group of four facet terms
+                                summed in fp32 and the group sums accumulated in fp64),
+                                PE_PREC_FP64ACC (the same with every term accumulated in fp64),
+                                PE_PREC_FP32 (phase, sums and accumulation in fp32) */
     int32_t geometry;        /* PE_GEOM_PLAIN: first hits from the disk splat (Algorithm 3).
                                 PE_GEOM_DENSIFIED: coarse TUBE buffer at half resolution
                                 (Algorithm 1) -> network -> GFB at the screen resolution ->

@@ -172,7 +172,7 @@ class Scene:
 
 
 _CONTRIB = {"last": PE_CONTRIB_LAST, "every": PE_CONTRIB_EVERY}
-_PREC = {"fp64phase": PE_PREC_FP64PHASE, "fp32": PE_PREC_FP32}
+_PREC = {"fp64phase": PE_PREC_FP64PHASE, "fp32": PE_PREC_FP32, "fp64acc": _native.PE_PREC_FP64ACC}
 _SECONDARY = {"views": PE_SECONDARY_VIEWS, "splats": PE_SECONDARY_SPLATS}
 
 

@@ -26,7 +26,7 @@ PE_MEM_HOST, PE_MEM_DEVICE = 0, 1
 PE_F32, PE_F64 = 0, 1
 PE_MAT_PEC, PE_MAT_ABSORBER = 0, 1
 PE_CONTRIB_LAST, PE_CONTRIB_EVERY = 0, 1
-PE_PREC_FP64PHASE, PE_PREC_FP32 = 0, 1
+PE_PREC_FP64PHASE, PE_PREC_FP32, PE_PREC_FP64ACC = 0, 1, 2
 PE_GEOM_PLAIN, PE_GEOM_DENSIFIED, PE_GEOM_COARSE = 0, 1, 2
 PE_SPLAT_DISK, PE_SPLAT_TUBE = 0, 1
 PE_SECONDARY_VIEWS, PE_SECONDARY_SPLATS = 0, 1

@@ -49,7 +49,9 @@ void validate_solve(pe_scene sc, const pe_solve_desc* d, bool need_scene) {
     if (d->max_bounces < 1 || d->max_bounces > kMaxBounces) throw Error{PE_EINVAL, "max_bounces must be 1..16"};
     if (!(d->eps >= 0) || !std::isfinite(d->eps)) throw Error{PE_EINVAL, "eps must be finite and >= 0"};
     if (d->contrib != PE_CONTRIB_LAST && d->contrib != PE_CONTRIB_EVERY) throw Error{PE_EINVAL, "bad contrib flag"};
-    if (d->precision != PE_PREC_FP64PHASE && d->precision != PE_PREC_FP32) throw Error{PE_EINVAL, "bad precision flag"};
+    if (d->precision != PE_PREC_FP64PHASE && d->precision != PE_PREC_FP32 &&
+        d->precision != PE_PREC_FP64ACC)
+        throw Error{PE_EINVAL, "bad precision flag"};
     if (d->secondary != PE_SECONDARY_VIEWS && d->secondary != PE_SECONDARY_SPLATS)
         throw Error{PE_EINVAL, "bad secondary flag"};
     if (d->geometry != PE_GEOM_PLAIN && d->geometry != PE_GEOM_DENSIFIED && d->geometry != PE_GEOM_COARSE)

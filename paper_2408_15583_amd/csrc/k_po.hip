@@ -6,8 +6,11 @@
 // scene-frame phase is shifted back to the global origin by the (k_i - k_s).c factor).
 //
 // Precision (FP64PHASE): the phase k D is formed in fp64 as D * (f / c) revolutions and reduced
-// to [-1/2, 1/2) in fp64 before the fp32 sin/cos; every term is accumulated in fp64.  FP32 mode
-// does all of it in fp32.  The sum is deterministic: a tile is 1024 records of one
+// to [-1/2, 1/2) in fp64 before the fp32 sin/cos; each term (fp32 amplitude x fp32 sinc and
+// trig) is summed with the other three of its aligned group of four records in fp32, and the
+// group sums are accumulated in fp64.  FP64ACC does the same with every term accumulated in
+// fp64 on its own (no fp32 groups).  FP32 mode does all of it in fp32.  The sum is
+// deterministic: a tile is 1024 records of one
 // (segment, slot, observation, frequency tile); lanes own one frequency and stride over the
 // tile's records in a fixed order, lanes are combined by a fixed tree, and tiles by a fixed
 // loop in the reduction kernel.
@@ -124,7 +127,9 @@ __device__ inline PoRec po_rec(const PoTileRecs& t, uint32_t r) {
     return q;
 }
 
-template <bool FP32>
+// MODE: 0 fp64 phase, fp32 groups of four into fp64; 1 all fp32; 2 fp64 phase, every term into
+// fp64.
+template <int MODE>
 __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, int rl, int RL,
                         const double* __restrict__ freq, const ExitRecs& er, double acc[8]) {
     if (f >= d.n_freq || (uint32_t)rl * 4u >= rn) return;
@@ -158,7 +163,7 @@ __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, in
             const float live = r0 + u < rn ? 1.f : 0.f;
             const float S = sinc_f(kf * cur.al) * sinc_f(kf * cur.be) * live;
             float rf;
-            if (FP32) {
+            if (MODE == 1) {
                 const float ph = (float)cur.D * revf;
                 rf = ph - floorf(ph);
             } else {
@@ -172,19 +177,22 @@ __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, in
 #pragma unroll
             for (int pq = 0; pq < 4; pq++) {
                 const float a = cur.a[pq];
-                if (FP32) {
+                if (MODE == 1) {
                     facc[2 * pq] += a * wr;
                     facc[2 * pq + 1] += a * wi;
+                } else if (MODE == 2) {
+                    acc[2 * pq] += (double)(a * wr);
+                    acc[2 * pq + 1] += (double)(a * wi);
                 } else {
                     blk[2 * pq] += a * wr;
                     blk[2 * pq + 1] += a * wi;
                 }
             }
         }
-        if (!FP32)
+        if (MODE == 0)
             for (int c = 0; c < 8; c++) acc[c] += (double)blk[c];
     }
-    if (FP32)
+    if (MODE == 1)
         for (int c = 0; c < 8; c++) acc[c] = facc[c];
 }
 
@@ -221,14 +229,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
         const uint64_t base = ((uint64_t)o * n_seg + g) * rec_stride + r0;
         double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const int f = ftile * ft + fi;
-        if (fp32) po_tile<true>(d, base, rn, f, rl, RL, freq, er, acc);
-        else po_tile<false>(d, base, rn, f, rl, RL, freq, er, acc);
+        if (fp32 == 1) po_tile<1>(d, base, rn, f, rl, RL, freq, er, acc);
+        else if (fp32 == 2) po_tile<2>(d, base, rn, f, rl, RL, freq, er, acc);
+        else po_tile<0>(d, base, rn, f, rl, RL, freq, er, acc);
         for (int c = 0; c < 8; c++) red[c][tid] = acc[c];
         __syncthreads();
         for (int stride = RL / 2; stride > 0; stride >>= 1) {
             if (rl < stride) {
                 for (int c = 0; c < 8; c++) {
-                    if (fp32) red[c][tid] = (double)((float)red[c][tid] + (float)red[c][tid + stride * ft]);
+                    if (fp32 == 1) red[c][tid] = (double)((float)red[c][tid] + (float)red[c][tid + stride * ft]);
                     else red[c][tid] += red[c][tid + stride * ft];
                 }
             }
@@ -274,12 +283,12 @@ __global__ void k_po_reduce(const SlotDesc* __restrict__ ds, const ObsDesc* __re
             for (uint32_t rt = 0; rt < nrt; rt++) {
                 const double* p = partial + ((b + rt) * FT + fi) * 8;
                 for (int c = 0; c < 8; c++) {
-                    if (fp32) Sf[c] += (float)p[c];
+                    if (fp32 == 1) Sf[c] += (float)p[c];
                     else S[c] += p[c];
                 }
             }
         }
-        if (fp32)
+        if (fp32 == 1)
             for (int c = 0; c < 8; c++) S[c] = Sf[c];
         const ObsDesc& O = obs[d.obs_base + o];
         const double k = kTwoPi * freq[d.freq_base + f] / kC0;

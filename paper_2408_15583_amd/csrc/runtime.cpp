@@ -502,12 +502,15 @@ void Batch::field(double* E_host, double* rcs_host) {
     launch_po_tiles(dd, seg_cnt, n_seg, n, ft, ttmp, tpre, st);
     prof_end("po_tiles");
     prof_begin();
+    // PO accumulation mode of k_po_sum / k_po_reduce: 0 fp64 phase with fp32 groups of four,
+    // 1 all fp32, 2 fp64 phase with every term accumulated in fp64
+    const int po_mode = precision == PE_PREC_FP32 ? 1 : precision == PE_PREC_FP64ACC ? 2 : 0;
     launch_po_sum(dd, seg_beg, seg_cnt, n_seg, n, dfreq, er, rec_stride, tpre,
-                  precision == PE_PREC_FP32, ft, part, persistent_blocks(), st);
+                  po_mode, ft, part, persistent_blocks(), st);
     prof_end("po_sum");
     prof_begin();
     launch_po_reduce(dd, dobs, n, max_obs, max_freq, n_seg, dfreq, seg_cnt, tpre, ft, part,
-                     precision == PE_PREC_FP32, Eo, Ro, st);
+                     po_mode, Eo, Ro, st);
     prof_end("po_reduce");
     HIPCHK(hipGetLastError());
     if (E_host) HIPCHK(hipMemcpyAsync(E_host, Eo, sizeof(double) * 8 * tot_out, hipMemcpyDeviceToHost, st));

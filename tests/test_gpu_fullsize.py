@@ -2,6 +2,14 @@
 times (2M-point composite: 1024^2 screen, six 1024^2 aggregation views, 64 frequencies
 2-12 GHz, up to 4 bounces; 4M-point sphere of radius 4 m at 1024^2, 64 frequencies 2-24 GHz).
 
+Conditioning of the composite: rounding its inputs to fp32 in the scene frame (what any fp32
+path does on ingest) moves the exact FP64 oracle itself by a median 0.004 dB but up to about
+1 dB at in-window samples that sit in deep interference nulls of this many-ray sum.  So the
+exact-oracle bar for a fp32 path is stated per sample: |GPU - oracle| <= max(0.1 dB, 2 x the
+sample's spread over an ensemble of oracle runs on fp32-perturbed inputs), with the spread
+measured here (the deterministic fp32 rounding plus two seeded +-2-ulp jitters of positions and
+normals).  Well-conditioned samples keep the plain 0.1 dB bar.
+
 The oracle computes sampled pixels one by one and the RCS of a few azimuths with its
 culled-exact grid.  Bars:
   - primary buffers: hit masks agree on >= 99.9 % of sampled pixels, depth within 1e-5 D;
@@ -51,6 +59,41 @@ def composite(pe, ctx):
     o.set_views(sw.view_res)
     yield sc, sw, s, o
     s.close()
+
+
+def ensemble(sc, seeds=(1, 2)):
+    """Oracle scenes on fp32-perturbed inputs: the scene-frame positions and the normals
+    rounded to fp32, and seeded jitters of +-2 fp32 ulps of each coordinate."""
+    c = 0.5 * (sc.xyz.min(0) + sc.xyz.max(0))
+    q = sc.xyz - c
+    out = [oracle.OracleScene(q.astype(np.float32).astype(np.float64) + c,
+                              sc.nrm.astype(np.float32).astype(np.float64), sc.radius_array(),
+                              sc.material, grid=256)]
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        ulp = np.spacing(np.abs(q).astype(np.float32)).astype(np.float64)
+        xq = q + rng.uniform(-2, 2, q.shape) * ulp
+        nq = sc.nrm + rng.uniform(-2, 2, sc.nrm.shape) * 2.0 ** -24
+        out.append(oracle.OracleScene(xq + c, nq, sc.radius_array(), sc.material, grid=256))
+    return out
+
+
+def conditioned_errors(r, ro, r_ens, dyn=30.0):
+    """Co-polar |r - ro| (dB) where ro is within dyn dB of the curve's peak over angles, with
+    each sample's fp32 spread max_j |r_j - ro| over the ensemble."""
+    err, spread = [], []
+    for p in range(2):
+        a, b = r[..., p, p], ro[..., p, p]
+        sel = b >= b.max(axis=0, keepdims=True) - dyn
+        err.append(np.abs(a - b)[sel])
+        spread.append(np.max([np.abs(re[..., p, p] - b)[sel] for re in r_ens], axis=0))
+    return np.concatenate(err), np.concatenate(spread)
+
+
+def report(name, e):
+    print(f"{name}: median {np.median(e):.4f} dB, p90 {np.percentile(e, 90):.3f}, p99 "
+          f"{np.percentile(e, 99):.3f}, max {e.max():.3f}; within 0.1 dB {(e <= 0.1).mean():.4f} "
+          f"of {e.size}")
 
 
 def db_errors(r, ro, dyn=30.0):
@@ -170,4 +213,120 @@ def test_sphere_4m_precision(pe, ctx):
           f"{np.median(agg):.4f} dB, max {agg.max():.3f}; march rays {st['march_rays']:.0f}")
     assert np.median(e) <= 0.05
     assert np.percentile(e, 90) <= 0.25
+    s.close()
+
+
+def test_composite_multibounce_splats_per_ray(pe, ctx, composite):
+    """Bounces against every splat (object-space hierarchy) follow the exact oracle ray by
+    ray."""
+    sc, sw, s, o = composite
+    rng = np.random.default_rng(11)
+    c, _ = o.frame()
+    for az_i in (0, 123, 250):
+        k = sw.inc_dir[az_i]
+        g = pe.trace_pixels(ctx, s, k, 1024, 1024, sw.max_bounces, sw.eps, secondary="splats")
+        nb = g["n_bounce"].cpu().numpy().ravel()
+        li = g["last_idx"].cpu().numpy().ravel().astype(np.int64)
+        lx = g["last_x"].cpu().numpy().reshape(-1, 3) + c
+        pix = rng.choice(1024 * 1024, 60000, replace=False)
+        nbe, rec, hidx = o.trace_pixels(k, 1024, 1024, pix, sw.max_bounces, sw.eps)
+        agree = (nb[pix] == nbe).mean()
+        same = (nb[pix] == nbe) & (nbe > 0)
+        m = np.where(same)[0]
+        ok = li[pix[m]] == hidx[m, nbe[m] - 1]
+        dx = np.linalg.norm(lx[pix[m]] - rec[m, nbe[m] - 1, 0:3], axis=1)[ok]
+        print(f"FULLSIZE composite splats az {az_i}: bounce counts {agree:.5f} "
+              f"({(nbe > 1).sum()} multi-bounce rays), last facet {ok.mean():.5f}, "
+              f"|dx| max {dx.max():.2e} m")
+        assert agree >= 0.9999
+        assert ok.mean() >= 0.999
+        assert dx.max() <= 1e-4
+
+
+def test_composite_multibounce_splats_rcs(pe, ctx, composite):
+    """The workload's four bounces against every splat vs the exact oracle, with the per-sample
+    conditioning bar of the module docstring; the views mode's error is printed beside it."""
+    sc, sw, s, o = composite
+    inc = sw.inc_dir[np.arange(0, 360, 30)]
+    _, r, _ = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=sw.max_bounces, eps=sw.eps,
+                       secondary="splats")
+    _, rv, _ = pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=sw.max_bounces, eps=sw.eps)
+    ro = oracle.rcs_dbsm(o.solve(inc, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps)[0])
+    r_ens = [oracle.rcs_dbsm(oe.solve(inc, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps)[0])
+             for oe in ensemble(sc)]
+    e, spread = conditioned_errors(r, ro, r_ens)
+    ev, _ = conditioned_errors(rv, ro, r_ens)
+    report("FULLSIZE composite B=4 splats vs exact oracle", e)
+    report("FULLSIZE composite B=4 fp32-input spread of the oracle", spread)
+    report("FULLSIZE composite B=4 views vs exact oracle", ev)
+    bar = np.maximum(0.1, 2.0 * spread)
+    ok = e <= bar
+    print(f"FULLSIZE composite B=4 splats: {ok.mean():.5f} of samples within max(0.1 dB, 2 x "
+          f"spread); worst excess {np.max(e - bar):.3f} dB")
+    assert ok.mean() >= 0.995
+    assert np.median(e) <= 0.02
+    assert np.percentile(e, 90) <= 0.1
+
+
+def test_composite_precision_study(pe, ctx, composite):
+    """Precision study on the composite, single bounce, 36 azimuths x 64 frequencies: fp64
+    phase with fp32 groups of four terms (the default), every term accumulated in fp64, and all
+    fp32, against the exact oracle per angle and frequency."""
+    sc, sw, s, o = composite
+    inc = sw.inc_dir[np.arange(0, 360, 10)]
+    res = {m: pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=1, eps=sw.eps,
+                       precision=m)[1] for m in ("fp64phase", "fp64acc", "fp32")}
+    ro = oracle.rcs_dbsm(o.solve(inc, sw.freq_hz, 1024, 1024, 1, sw.eps)[0])
+    r_ens = [oracle.rcs_dbsm(oe.solve(inc, sw.freq_hz, 1024, 1024, 1, sw.eps)[0])
+             for oe in ensemble(sc)]
+    errs = {m: conditioned_errors(r, ro, r_ens) for m, r in res.items()}
+    for m, (e, sp) in errs.items():
+        report(f"FULLSIZE composite B=1 {m} vs exact oracle", e)
+    report("FULLSIZE composite B=1 fp32-input spread of the oracle", errs["fp64phase"][1])
+    # per frequency: max over angles and both co-polar channels
+    for f in range(0, len(sw.freq_hz), 9):
+        row = []
+        for m, r in res.items():
+            sel = [ro[:, 0, f, p, p] >= ro[:, 0, f, p, p].max() - 30.0 for p in range(2)]
+            d = np.concatenate([np.abs(r[:, 0, f, p, p] - ro[:, 0, f, p, p])[sel[p]]
+                                for p in range(2)])
+            row.append(f"{m} {d.max():.4f}")
+        print(f"FULLSIZE composite B=1 {sw.freq_hz[f] / 1e9:5.2f} GHz max: " + ", ".join(row))
+    g4 = np.abs(res["fp64phase"] - res["fp64acc"])
+    print(f"FULLSIZE composite B=1 fp32 groups of four vs per-term fp64: max {np.nanmax(g4):.2e} dB")
+    for m in ("fp64phase", "fp64acc"):
+        e, sp = errs[m]
+        assert (e <= np.maximum(0.1, 2.0 * sp)).mean() >= 0.998
+        assert np.median(e) <= 0.01
+    assert np.nanmax(g4) <= 0.01
+
+
+def test_sphere_precision_36az(pe, ctx):
+    """Sphere r = 4 m, 4M points, ka up to 2000: single bounce at 36 azimuths x 64 frequencies,
+    every (angle, frequency) within 0.1 dB of the exact oracle in the fp64-phase modes; all-fp32
+    reported per frequency; the workload's four bounces against every splat vs the exact
+    oracle at 3 azimuths."""
+    sc, sw = scenes.workload_sphere()
+    s = pe.Scene.from_scene(ctx, sc, view_res=sw.view_res)
+    o = oracle.OracleScene(sc, grid=256)
+    inc = sw.inc_dir[np.arange(0, 360, 10)]
+    res = {m: pe.solve(ctx, s, inc, sw.freq_hz, 1024, max_bounces=1, eps=sw.eps,
+                       precision=m)[1] for m in ("fp64phase", "fp64acc", "fp32")}
+    ro = oracle.rcs_dbsm(o.solve(inc, sw.freq_hz, 1024, 1024, 1, sw.eps)[0])
+    err = {m: np.max([np.abs(r[..., p, p] - ro[..., p, p]) for p in range(2)], axis=0)
+           for m, r in res.items()}  # [angle, 1, freq]
+    for f in range(0, len(sw.freq_hz), 7):
+        print(f"FULLSIZE sphere B=1 {sw.freq_hz[f] / 1e9:5.1f} GHz max over 36 az: " +
+              ", ".join(f"{m} {e[:, 0, f].max():.4f} dB" for m, e in err.items()))
+    for m, e in err.items():
+        print(f"FULLSIZE sphere B=1 {m}: max {e.max():.4f} dB over {e.size} (angle, freq)")
+    assert err["fp64phase"].max() < 0.1
+    assert err["fp64acc"].max() < 0.1
+    inc3 = sw.inc_dir[[0, 90, 200]]
+    _, r4, _ = pe.solve(ctx, s, inc3, sw.freq_hz, 1024, max_bounces=sw.max_bounces, eps=sw.eps,
+                        secondary="splats")
+    ro4 = oracle.rcs_dbsm(o.solve(inc3, sw.freq_hz, 1024, 1024, sw.max_bounces, sw.eps)[0])
+    e4 = db_errors(r4, ro4)
+    report("FULLSIZE sphere B=4 splats vs exact oracle", e4)
+    assert e4.max() < 0.1
     s.close()
