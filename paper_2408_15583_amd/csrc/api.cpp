@@ -359,12 +359,14 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
             launch_bvh_emit(rng[level], m, level, codes, coff, base[level] + m, rng_next,
                             finfo[level], st);
             if (next == 0) break;
-            if (level + 1 > 11) return set_error(PE_EDEVICE, "hierarchy deeper than its codes");
+            if (level + 1 >= kBvhMaxLevels)
+                return set_error(PE_EINVAL, "point cloud too dense for the hierarchy");
             rng.push_back(rng_next);
             cnt.push_back(next);
             base.push_back(base[level] + m);
         }
         const int L = (int)cnt.size();
+        sc->bvh_levels = L;
         sc->bvh_nodes = (uint64_t)base[L - 1] + cnt[L - 1];
         sc->bvh = (float4*)sc->alloc(sc->bvh_nodes * 32);
         // slack: fp32 rounding of the disk test's hit point at scene scale (a few ulps of R)

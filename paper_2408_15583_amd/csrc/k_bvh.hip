@@ -33,12 +33,12 @@ __device__ inline uint32_t octant_bound(const uint32_t* codes, uint32_t a, uint3
 }
 
 // Children of node (a, b) at `level`: octant boundaries bnd[0..8] (level < 10), or a count
-// split into k chunks (level 10); returns the child count (0 = leaf).
+// split into k chunks (level >= 10, all 30 code bits shared); returns the child count (0 = leaf).
 __device__ inline int node_children(const uint32_t* codes, uint32_t a, uint32_t b, int level,
                                     uint32_t bnd[9], uint32_t& split_len) {
     const uint32_t cnt = b - a;
-    if (cnt <= (uint32_t)kBvhLeaf || level > 10) return 0;
-    if (level == 10) {
+    if (cnt <= (uint32_t)kBvhLeaf) return 0;
+    if (level >= 10) {
         const uint32_t k = min(8u, (cnt + kBvhLeaf - 1) / kBvhLeaf);
         split_len = (cnt + k - 1) / k;
         return (int)k;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_bvh_emit(const uint2* __restrict__ rng,
         }
         uint2* out = rng_next + coff[j];
         uint32_t occ = 0;
-        if (level == 10) {
+        if (level >= 10) {
             for (int c = 0; c < nc; c++)
                 out[c] = make_uint2(a + c * len, min(a + (c + 1) * len, b));
             occ = (1u << nc) - 1u;
@@ -165,39 +165,87 @@ void launch_bvh_box(const uint2* finfo, uint32_t n_nodes, uint32_t base, const f
                        pad, nodes);
 }
 
-// One bounce, pass 1 with every splat as bounce geometry: each live ray (one lane) leaves its
-// facet along the Eq. (4) reflection and takes the nearest disk hit beyond eps over the whole
-// scene; the packed (t, index) key goes to hitkey[entry] for the apply pass.
+// Persistent traversal loop shared by the two passes: every lane holds one ray; a wavefront
+// takes new work items for its idle lanes from a global counter once at least `refill` of its
+// lanes are idle (all from one atomic, so the lanes of a batch are neighbouring items), and
+// advances its busy lanes one node expansion per iteration.  The loop indices and the exit
+// test are wave-uniform (ballots, the shuffled counter value), so every lane leaves together.
+// start(j, s): set up item j (returns false when it needs no traversal, after writing its
+// result); finish(j, s): write the result of a finished item.
+template <bool any, class Start, class Finish>
+__device__ inline void bvh_persistent(const SlotDesc* __restrict__ ds, uint64_t n_items,
+                                      uint32_t* __restrict__ queue, int refill, Start start,
+                                      Finish finish) {
+    extern __shared__ uint64_t stk[];
+    uint64_t* my = stk + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool active = false, exhausted = n_items == 0;
+    uint64_t item = 0;
+    const SlotDesc* dp = ds;
+    BvhState s;
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        const int n_idle = __popcll(idle);
+        if (!exhausted && n_idle >= refill) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(queue, (uint32_t)n_idle);
+            base = __shfl(base, 0);
+            if ((uint64_t)base + (uint64_t)n_idle >= n_items) exhausted = true;
+            if (!active) {
+                const uint64_t j = (uint64_t)base + __popcll(idle & ((1ull << lane) - 1ull));
+                if (j < n_items) {
+                    item = j;
+                    active = start(j, dp, s);
+                }
+            }
+        }
+        if (__ballot(active) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        if (active && bvh_step<any>(*dp, s, my, blockDim.x)) {
+            finish(item, s);
+            active = false;
+        }
+    }
+}
+
+// One bounce, pass 1 with every splat as bounce geometry: each live ray leaves its facet along
+// the Eq. (4) reflection and takes the nearest disk hit beyond eps over the whole scene; the
+// packed (t, index) key goes to hitkey[entry] for the apply pass.
 __global__ __launch_bounds__(256) void k_trace_bvh(const SlotDesc* __restrict__ ds,
                                                    const uint32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ n_live,
                                                    RayState rs, uint64_t* __restrict__ hitkey,
-                                                   int bounce) {
-    extern __shared__ uint64_t stk[];
-    const uint32_t n = *n_live;
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const uint32_t entry = list[e];
-        const SlotDesc& d = ds[entry_slot(entry)];
-        uint64_t key = kEmptyKey;
-        if (bounce <= d.max_b) {
-            const uint64_t g = d.pix_base + entry_pix(entry);
-            const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
-            key = bvh_trace<false>(d, x, leave_dir(kin, nn), d.eps, stk + threadIdx.x,
-                                   blockDim.x);
-        }
-        hitkey[e] = key;
-    }
+                                                   int bounce, uint32_t* __restrict__ queue,
+                                                   int refill) {
+    bvh_persistent<false>(
+        ds, *n_live, queue, refill,
+        [&](uint64_t j, const SlotDesc*& dp, BvhState& s) {
+            const uint32_t entry = list[j];
+            dp = ds + entry_slot(entry);
+            if (bounce <= dp->max_b) {
+                const uint64_t g = dp->pix_base + entry_pix(entry);
+                const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                if (bvh_begin(*dp, x, leave_dir(kin, nn), dp->eps, s)) return true;
+            }
+            hitkey[j] = kEmptyKey;
+            return false;
+        },
+        [&](uint64_t j, const BvhState& s) { hitkey[j] = s.key; });
 }
 
 void launch_trace_bvh(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
-                      RayState rs, uint64_t* hitkey, int bounce, int n_blocks, hipStream_t st) {
+                      RayState rs, uint64_t* hitkey, int bounce, int stack_depth,
+                      uint32_t* queue, int refill, int n_blocks, hipStream_t st) {
+    launch_fill_u32(queue, 0u, 1, st);
     hipLaunchKernelGGL(k_trace_bvh, dim3(n_blocks), dim3(256),
-                       (size_t)kBvhMaxStack * 256 * sizeof(uint64_t), st, d, list, n_live, rs,
-                       hitkey, bounce);
+                       (size_t)stack_depth * 256 * sizeof(uint64_t), st, d, list, n_live, rs,
+                       hitkey, bounce, queue, std::min(64, std::max(1, refill)));
 }
 
-// Monostatic visibility, pass 1: which entries need a traced Psi (later-bounce facets of
-// monostatic slots), with per-chunk survivor counts for the compaction.
+// Visibility, pass 1: which entries need a traced Psi (every facet of a bistatic slot, the
+// later-bounce facets of a monostatic one), with per-chunk survivor counts for the compaction.
 __global__ __launch_bounds__(256) void k_psi_mark(const SlotDesc* __restrict__ ds,
                                                   const uint32_t* __restrict__ list,
                                                   const uint32_t* __restrict__ n_list,
@@ -214,7 +262,7 @@ __global__ __launch_bounds__(256) void k_psi_mark(const SlotDesc* __restrict__ d
         if (e < n) {
             const uint32_t entry = list[e];
             const SlotDesc& d = ds[entry_slot(entry)];
-            need = d.mono && rs.m[d.pix_base + entry_pix(entry)] >= 2;
+            need = !d.mono || rs.m[d.pix_base + entry_pix(entry)] >= 2;
             alive[e] = need ? 1 : 0;
         }
         const uint64_t bal = __ballot(need);
@@ -229,33 +277,49 @@ void launch_psi_mark(const SlotDesc* d, const uint32_t* list, const uint32_t* n_
                        chunk_count);
 }
 
-// Monostatic visibility, pass 2: one lane per compacted facet, any hit toward k_s beyond eps.
+// Visibility, pass 2: one lane per (compacted facet, observation direction): any hit toward
+// k_s beyond eps.
 __global__ __launch_bounds__(256) void k_psi_trace(const SlotDesc* __restrict__ ds,
                                                    const ObsDesc* __restrict__ obs,
                                                    const uint32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ n_list,
-                                                   RayState rs, uint8_t* __restrict__ vis) {
-    extern __shared__ uint64_t stk[];
-    const uint32_t n = *n_list;
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const uint32_t entry = list[e];
-        const SlotDesc& d = ds[entry_slot(entry)];
-        const uint64_t g = d.pix_base + entry_pix(entry);
-        const ObsDesc& O = obs[d.obs_base];
-        const f3 ks = mk3(O.ks[0], O.ks[1], O.ks[2]);
-        vis[g] = bvh_trace<true>(d, ld3(rs, RX, g), ks, d.eps, stk + threadIdx.x, blockDim.x) ==
-                         kEmptyKey
-                     ? 1
-                     : 0;
-    }
+                                                   int max_obs, RayState rs,
+                                                   uint8_t* __restrict__ vis, uint64_t vis_stride,
+                                                   uint32_t* __restrict__ queue, int refill) {
+    auto where = [&](uint64_t w, uint64_t& g) {
+        const uint32_t entry = list[w / (uint32_t)max_obs];
+        const SlotDesc* dp = ds + entry_slot(entry);
+        g = dp->pix_base + entry_pix(entry);
+        return dp;
+    };
+    bvh_persistent<true>(
+        ds, (uint64_t)*n_list * (uint32_t)max_obs, queue, refill,
+        [&](uint64_t w, const SlotDesc*& dp, BvhState& s) {
+            const uint32_t o = (uint32_t)(w % (uint32_t)max_obs);
+            uint64_t g;
+            dp = where(w, g);
+            if ((int)o >= dp->n_obs) return false;
+            const ObsDesc& O = obs[dp->obs_base + o];
+            if (bvh_begin(*dp, ld3(rs, RX, g), mk3(O.ks[0], O.ks[1], O.ks[2]), dp->eps, s))
+                return true;
+            vis[o * vis_stride + g] = 1;
+            return false;
+        },
+        [&](uint64_t w, const BvhState& s) {
+            uint64_t g;
+            where(w, g);
+            vis[(w % (uint32_t)max_obs) * vis_stride + g] = s.key == kEmptyKey ? 1 : 0;
+        });
 }
 
 void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
-                      const uint32_t* n_list, RayState rs, uint8_t* vis, int n_blocks,
-                      hipStream_t st) {
+                      const uint32_t* n_list, int max_obs, RayState rs, uint8_t* vis,
+                      uint64_t vis_stride, int stack_depth, uint32_t* queue, int refill,
+                      int n_blocks, hipStream_t st) {
+    launch_fill_u32(queue, 0u, 1, st);
     hipLaunchKernelGGL(k_psi_trace, dim3(n_blocks), dim3(256),
-                       (size_t)kBvhMaxStack * 256 * sizeof(uint64_t), st, d, obs, list, n_list,
-                       rs, vis);
+                       (size_t)stack_depth * 256 * sizeof(uint64_t), st, d, obs, list, n_list,
+                       max_obs, rs, vis, vis_stride, queue, std::min(64, std::max(1, refill)));
 }
 
 }  // namespace pe

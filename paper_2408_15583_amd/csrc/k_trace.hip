@@ -14,7 +14,6 @@
 // exclusive scan, so the order (and every downstream sum) is deterministic.
 #include <float.h>
 
-#include "pe_bvh.h"
 #include "pe_device.h"
 #include "pe_geom.h"
 
@@ -807,8 +806,8 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
                                                  RayState rs, const uint64_t* __restrict__ keys,
                                                  ExitRecs er, uint32_t rec_stride, int seg,
                                                  int n_seg, uint32_t* cap_hits, int splats,
-                                                 const uint8_t* __restrict__ vis_mono) {
-    extern __shared__ uint64_t stk[];
+                                                 const uint8_t* __restrict__ vis_splats,
+                                                 uint64_t vis_stride) {
     const uint32_t n = *n_list;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const uint32_t entry = list[e];
@@ -831,13 +830,9 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
             const f3 ks = mk3(O.ks[0], O.ks[1], O.ks[2]);
             bool vis = true;
             if (splats) {
-                // every splat can hide the facet; a monostatic first-bounce facet is the nearest
-                // hit along its own reversed ray and is visible; later ones were traced densely
-                if (!d.mono)
-                    vis = bvh_trace<true>(d, x, ks, d.eps, stk + threadIdx.x, blockDim.x) ==
-                          kEmptyKey;
-                else if (m >= 2)
-                    vis = vis_mono[g] != 0;
+                // every splat can hide the facet (traced by the visibility pass); a monostatic
+                // first-bounce facet is the nearest hit along its own reversed ray: visible
+                if (!d.mono || m >= 2) vis = vis_splats[(uint64_t)o * vis_stride + g] != 0;
             } else if (d.mono) {
                 if (m >= 2) vis = visible_primary(d, keys, x, ks);
             } else {
@@ -862,10 +857,9 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
 void launch_po_prep(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
                     const uint32_t* n_list, RayState rs, const uint64_t* keys, ExitRecs er,
                     uint32_t rec_stride, int seg, int n_seg, uint32_t* cap_hits, int splats,
-                    const uint8_t* vis, int n_blocks, hipStream_t st) {
-    const size_t lds = splats ? (size_t)kBvhMaxStack * 256 * sizeof(uint64_t) : 0;
-    hipLaunchKernelGGL(k_po_prep, dim3(n_blocks), dim3(256), lds, st, d, obs, list, n_list, rs,
-                       keys, er, rec_stride, seg, n_seg, cap_hits, splats, vis);
+                    const uint8_t* vis, uint64_t vis_stride, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_po_prep, dim3(n_blocks), dim3(256), 0, st, d, obs, list, n_list, rs,
+                       keys, er, rec_stride, seg, n_seg, cap_hits, splats, vis, vis_stride);
 }
 
 }  // namespace pe

@@ -64,14 +64,16 @@ constexpr int kNumXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCD
 
 // Object-space hierarchy over a scene's points in Morton order (an octree of their 30-bit codes):
 // node = the points sharing a code prefix of 3 l bits at level l; a node of at most kBvhLeaf
-// points is a leaf; a finest-cell node of more is split by count into at most 8 leaves.
-// Node record: 2 float4, (lo xyz, bits(first)), (hi xyz, bits(info)); info bit 31 = leaf with
-// (info & 0xFFFFFF) points from pa_s[first]; else children nodes first .. first + popc(occ) - 1
-// for the occupied octants occ = info & 0xFF (octant = the 3 code bits below the prefix, x in
-// bit 0), stored in increasing octant order.  The root is node 0.
+// points is a leaf; past the 30 bits (level 10) a node of more points is split by count into
+// up to 8 chunks, again and again.  Node record: 2 float4, (lo xyz, bits(first)), (hi xyz,
+// bits(info)); info bit 31 = leaf with (info & 0xFFFFFF) points from pa_s[first]; else children
+// nodes first .. first + popc(occ) - 1 for the occupied octants occ = info & 0xFF (octant = the
+// 3 code bits below the prefix, x in bit 0; chunk number past the code), stored in increasing
+// octant order.  The root is node 0.
 constexpr int kBvhLeaf = 8;
 constexpr uint32_t kBvhLeafBit = 0x80000000u;
-constexpr int kBvhMaxStack = 12;  // internal levels 0 .. 10: one stack entry per level
+constexpr int kBvhMaxLevels = 20;  // 10 code levels + count splits of up to 2^31 points
+constexpr int kBvhMaxStack = kBvhMaxLevels;  // one stack entry per level
 
 // One work item of a batched launch: one screen (one incidence) on one scene.
 struct SlotDesc {
@@ -223,20 +225,27 @@ void launch_bvh_emit(const uint2* rng, uint32_t n_nodes, int level, const uint32
                      hipStream_t st);
 void launch_bvh_box(const uint2* finfo, uint32_t n_nodes, uint32_t base, const float4* pa_s,
                     const float4* pb_s, float pad, float4* nodes, hipStream_t st);
-// Visibility of the monostatic later-bounce facets against every splat, as a dense pass: mark
-// the entries of list whose slot is monostatic and whose facet is a later bounce (alive[e], and
-// per-64-entry chunk counts for the order-preserving compaction); then, over the compacted
-// list, vis[pixel] = 1 iff no disk is hit from the facet toward k_s beyond eps.
+
+// Visibility of facets against every splat, as a dense pass: mark the entries of list whose
+// facet needs a traced Psi (every facet of a bistatic slot, the later-bounce facets of a
+// monostatic one; alive[e], and per-64-entry chunk counts for the order-preserving compaction);
+// then, over the compacted list x the slot's observation directions, vis[o * vis_stride +
+// pixel] = 1 iff no disk is hit from the facet toward k_s(o) beyond eps.
 void launch_psi_mark(const SlotDesc* d, const uint32_t* list, const uint32_t* n_list,
                      RayState rs, uint8_t* alive, uint32_t* chunk_count, int n_blocks,
                      hipStream_t st);
 void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
-                      const uint32_t* n_list, RayState rs, uint8_t* vis, int n_blocks,
-                      hipStream_t st);
+                      const uint32_t* n_list, int max_obs, RayState rs, uint8_t* vis,
+                      uint64_t vis_stride, int stack_depth, uint32_t* queue, int refill,
+                      int n_blocks, hipStream_t st);
 // Nearest hit beyond eps of every live ray against all of its scene's splats (the hierarchy
-// above), written to hitkey[entry] (kEmptyKey when none); kBvhMaxStack u64 of LDS per thread.
+// above), written to hitkey[entry] (kEmptyKey when none).  stack_depth: the batch's largest
+// octree level count (<= kBvhMaxStack), u64 LDS entries per thread.  Both traversal passes are
+// persistent: queue is one u32 work counter (cleared by the launcher), and a wavefront refills
+// its idle lanes once `refill` (1 .. 64) of them are idle.
 void launch_trace_bvh(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
-                      RayState rs, uint64_t* hitkey, int bounce, int n_blocks, hipStream_t st);
+                      RayState rs, uint64_t* hitkey, int bounce, int stack_depth,
+                      uint32_t* queue, int refill, int n_blocks, hipStream_t st);
 void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
                   uint64_t* hitkey, int bounce, int max_views, uint32_t* cap_hits, uint32_t* queue,
                   int n_blocks, hipStream_t st);
@@ -267,13 +276,12 @@ void launch_trace_out(const SlotDesc* d, const uint32_t* list, const uint32_t* n
 
 // physical optics
 constexpr int kRT = 1024;  // facet records per PO tile
-// splats != 0: visibility against every splat: monostatic later-bounce facets read vis[pixel]
-// (launch_psi_trace), bistatic facets traverse the object-space hierarchy (kBvhMaxStack u64 of
-// LDS per thread); else through the aggregation views / incidence first-hit buffer.
+// splats != 0: visibility against every splat from the visibility pass (vis, see
+// launch_psi_trace); else through the aggregation views / incidence first-hit buffer.
 void launch_po_prep(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,
                     const uint32_t* n_list, RayState rs, const uint64_t* keys, ExitRecs er,
                     uint32_t rec_stride, int seg, int n_seg, uint32_t* cap_hits, int splats,
-                    const uint8_t* vis, int n_blocks, hipStream_t st);
+                    const uint8_t* vis, uint64_t vis_stride, int n_blocks, hipStream_t st);
 void launch_slot_ranges(const uint32_t* list, const uint32_t* n_list, int n_slots,
                         uint32_t* beg, uint32_t* cnt, hipStream_t st);
 // tile_prefix gets n_seg*n_slots+1 entries (exclusive prefix, total last); tmp same size.

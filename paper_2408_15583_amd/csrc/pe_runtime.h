@@ -90,6 +90,7 @@ struct Batch {
     // PE_SECONDARY_SPLATS: bounces and visibility against every splat through the scene's
     // object-space hierarchy; PE_SECONDARY_VIEWS: through the aggregation views
     int secondary = 0;
+    int bvh_depth = 1;  // LDS stack entries per lane of the hierarchy traversals
     bool blend = false;  // some slot's scene refines hits by Eq. (23)
     int max_chunks = 0, max_tiles = 0, max_pix = 0, max_obs = 1, max_freq = 1, tot_out = 0;
     uint64_t tot_pix = 0;
@@ -179,6 +180,7 @@ struct pe_scene_s {
     pe::ViewDesc* views_dev = nullptr;
     float4* bvh = nullptr;  // object-space hierarchy over pa_s (node records at pe::kBvhLeaf)
     uint64_t bvh_nodes = 0;
+    int bvh_levels = 1;  // octree levels: the traversal's stack holds at most one entry each
     float blend_r = 0.f, bl_h = 0.f;  // Eq. (23) refinement radius and centre-grid cell edge
     int bl_G = 0;
     uint32_t *bl_start = nullptr, *bl_items = nullptr;

@@ -11,6 +11,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -214,6 +215,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
     tot_out = 0;
     max_b = 1;
     max_views = 0;
+    bvh_depth = 1;
     for (int i = 0; i < n; i++) {
         const SlotSpec& sp = slots[i];
         const pe_scene sc = sp.sc;
@@ -231,6 +233,7 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.bl_start = sc->bl_start;
         d.bl_items = sc->bl_items;
         d.bvh = sc->bvh;
+        bvh_depth = std::max(bvh_depth, sc->bvh_levels);
         if (sc->blend_r > 0.f) blend = true;
         d.views = sc->views_dev;
         d.n_views = (int)sc->views.size();
@@ -365,6 +368,15 @@ void Batch::alloc_rays() {
 
 static int persistent_blocks() { return 2048; }
 
+// Idle lanes at which a traversal wavefront takes new rays (PE_BVH_REFILL overrides).
+static int bvh_refill() {
+    static const int v = [] {
+        const char* e = std::getenv("PE_BVH_REFILL");
+        return e ? std::atoi(e) : 16;
+    }();
+    return v;
+}
+
 void Batch::raygen() {
     alloc_rays();
     const int gx = (max_pix + 255) / 256;
@@ -417,10 +429,10 @@ void Batch::records(int seg, const uint32_t* list, const uint32_t* n_list) {
     const bool splats = secondary == PE_SECONDARY_SPLATS;
     uint8_t* vis = nullptr;
     if (splats) {
-        // dense any-hit pass over the monostatic later-bounce facets (most facets are first
-        // bounces, which are visible, so tracing inside po_prep would idle most lanes)
+        // dense any-hit pass over the facets that need a traced Psi (monostatic first bounces
+        // are visible and are most facets, so tracing inside po_prep would idle most lanes)
         uint32_t* plist = ws.get<uint32_t>(B_PSILIST, tot_pix);
-        vis = ws.get<uint8_t>(B_VIS, tot_pix);
+        vis = ws.get<uint8_t>(B_VIS, (uint64_t)max_obs * tot_pix);
         const uint32_t max_chunks = (uint32_t)((tot_pix + kWaveChunk - 1) / kWaveChunk);
         prof_begin();
         launch_psi_mark(dd, list, n_list, rs, alive, ccount, persistent_blocks(), st);
@@ -428,12 +440,14 @@ void Batch::records(int seg, const uint32_t* list, const uint32_t* n_list) {
         launch_compact(list, n_list, alive, coff, plist, persistent_blocks(), st);
         prof_end("psi_compact");
         prof_begin();
-        launch_psi_trace(dd, dobs, plist, cnt + C_PSI, rs, vis, persistent_blocks(), st);
+        launch_psi_trace(dd, dobs, plist, cnt + C_PSI, max_obs, rs, vis, tot_pix, bvh_depth,
+                         ws.get<uint32_t>(B_MQUEUE, kNumXcd), bvh_refill(), persistent_blocks(),
+                         st);
         prof_end("psi_bvh");
     }
     prof_begin();
     launch_po_prep(dd, dobs, list, n_list, rs, keys, er, rec_stride, seg, n_seg, cnt + C_CAP,
-                   splats, vis, persistent_blocks(), st);
+                   splats, vis, tot_pix, persistent_blocks(), st);
     prof_end("po_prep");
     prof_begin();
     launch_slot_ranges(list, n_list, n, seg_beg + (uint64_t)seg * n, seg_cnt + (uint64_t)seg * n,
@@ -453,7 +467,9 @@ void Batch::trace(bool with_records) {
         uint32_t* nout = cnt + (b % 2 == 0 ? C_N1 : C_N2);
         prof_begin();
         if (secondary == PE_SECONDARY_SPLATS) {
-            launch_trace_bvh(dd, cur, ncur, rs, hitkey, b, persistent_blocks(), st);
+            launch_trace_bvh(dd, cur, ncur, rs, hitkey, b, bvh_depth,
+                             ws.get<uint32_t>(B_MQUEUE, kNumXcd), bvh_refill(), persistent_blocks(),
+                             st);
             static const char* names[] = {"bvh_b2", "bvh_b3", "bvh_b4", "bvh_b5", "bvh_b6",
                                           "bvh_b7", "bvh_b8", "bvh_b9+"};
             prof_end(names[std::min(b - 2, 7)]);
