@@ -49,24 +49,38 @@ MARCH_TRAFFIC = dict(
              "e8ec339ff11e3ccc787afcff74d5151897879d2a05c2796c91656e2912572470"})
 
 
-# HBM traffic of k_trace_bvh (the same two counter passes); None until measured on its sources.
-BVH_TRAFFIC = None
+# L2-to-fabric traffic of k_trace_bvh from the same two counter passes over one step (mean KiB
+# per dispatch over its three bounces), scaled by the same copy calibration; null once any of
+# the traversal's sources changes.
+BVH_TRAFFIC = dict(
+    fetch_kib=35881835.6, write_kib=774523.2, fetch_factor=2.0, write_factor=1.0,
+    sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
+             "b40848c6218fe01a57cd275435f63f859b16299b115fe838138caa4d60f62c1f",
+             "paper_2408_15583_amd/csrc/pe_bvh.h":
+             "9e21bb4cadb3863febcfb3f17bc533a65ca461bc029f3bb0c045505bb25c7e6b",
+             "paper_2408_15583_amd/csrc/pe_device.h":
+             "6a6a681705cbb92a166f4fd6dddb0fd1133a03859207d45171ab968568f9e60e",
+             "paper_2408_15583_amd/csrc/pe_geom.h":
+             "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
+
+
+def _counter_traffic(t):
+    import hashlib
+    for rel, digest in t["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
 
 
 def bvh_traffic():
-    """Counter-measured bytes per k_trace_bvh launch, or None (not measured on these sources)."""
-    return None if BVH_TRAFFIC is None else BVH_TRAFFIC
+    """Counter-measured bytes per k_trace_bvh launch, or None once its sources changed."""
+    return _counter_traffic(BVH_TRAFFIC)
 
 
 def march_traffic():
     """Counter-measured bytes per k_march launch, or None once the kernel's sources changed."""
-    import hashlib
-    for rel, digest in MARCH_TRAFFIC["sources"].items():
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != digest:
-                return None
-    t = MARCH_TRAFFIC
-    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+    return _counter_traffic(MARCH_TRAFFIC)
 
 
 def po_slots_per_term():
