@@ -19,9 +19,18 @@ Readings of the paper (it names the operator, the grid and Eq. (22), not their d
     projection direction of a contributing view, and the splat takes the smallest radius over
     its contributing views.
 
-Every decision that turns floating point into an integer or a branch (edge classes, the grid
-cell of a point, the side a normal is turned to) is taken in fp32 with each operation rounded on
-its own, as the GPU kernels do; the fused values themselves are fp64.
+Everything is computed in fp64 from the buffers' values.  Decisions that turn floating point
+into an integer or a branch (edge classes, the grid cell of a point, the side a normal is
+turned to) are reported with an ambiguity flag where their fp64 margin is within reach of fp32
+rounding: a fp32 implementation may take those the other way, and the tests bound where such
+flips may appear.  The reach is stated with generous factors on the fp32 unit roundoff u:
+  - Canny: every gradient component within 256 u D of its fp64 value (25 blur taps of depths up
+    to D = 2R, then 8 Sobel terms), so m = gx^2 + gy^2 moves by up to 2 e (|g| + |g'|) + e^2;
+  - cells: a point's grid coordinate within 32 u R / L (the point is two products and sums of
+    size R on fp32-rounded screen axes, about 17 u R, then shifted by half the side and divided
+    by L, about 4 u R / L more in grid units); such a point may land in the neighbouring cell
+    across each face within reach, and every cell it may land in is reported;
+  - normal side: the largest and second largest |component| of the turned normal within 1e-5.
 """
 from __future__ import annotations
 
@@ -30,7 +39,7 @@ import math
 import numpy as np
 from scipy import ndimage
 
-f32 = np.float32
+U32 = 2.0 ** -24  # fp32 unit roundoff
 
 
 def screen_basis(k):
@@ -47,38 +56,40 @@ def screen_basis(k):
 
 
 def gaussian_taps():
-    """Weights of the 5-tap Gaussian, sigma = 1 pixel, at offsets 0, 1, 2 (fp32)."""
+    """Weights of the 5-tap Gaussian, sigma = 1 pixel, at offsets 0, 1, 2."""
     e = [math.exp(-0.5 * d * d) for d in range(3)]
     s = e[0] + 2.0 * (e[1] + e[2])
-    return [f32(x / s) for x in e]
+    return [x / s for x in e]
 
 
-def canny(depth, hit, R, lo, hi):
-    """Edge map (bool, n x h x w) of depth buffers (t / 2R) per the readings above."""
-    depth = np.asarray(depth, f32)
+def canny(depth, hit, R, lo, hi, ambiguity=False):
+    """Edge map (bool, n x h x w) of depth buffers (t / 2R) per the readings above; with
+    ambiguity=True also the map of pixels whose class (strong / weak / none after non-maximum
+    suppression, or the suppression direction) is within fp32 reach of changing, and the map of
+    candidates (strong or weak, or ambiguous) through which hysteresis can carry a change."""
+    depth = np.asarray(depth, np.float64)
     n, h, w = depth.shape
-    D = f32(2.0) * f32(R)
-    d = np.where(np.asarray(hit, f32) >= f32(0.5), depth * D, D).astype(f32)
+    D = 2.0 * float(R)
+    d = np.where(np.asarray(hit, np.float64) >= 0.5, depth * D, D)
     g = gaussian_taps()
     gw = [g[2], g[1], g[0], g[1], g[2]]
     dp = np.pad(d, ((0, 0), (2, 2), (2, 2)), mode="edge")
     blur = np.zeros_like(d)
     for dy in range(5):
         for dx in range(5):
-            blur = blur + f32(gw[dy] * gw[dx]) * dp[:, dy:dy + h, dx:dx + w]
+            blur = blur + gw[dy] * gw[dx] * dp[:, dy:dy + h, dx:dx + w]
     # Sobel sums at every pixel and one ring outside (clamped reads = edge padding)
     bp = np.pad(blur, ((0, 0), (2, 2), (2, 2)), mode="edge")
 
     def B(ox, oy):  # blurred value at (x + ox, y + oy) for x in -1..w, y in -1..h
         return bp[:, 1 + oy:1 + oy + h + 2, 1 + ox:1 + ox + w + 2]
 
-    two = f32(2.0)
-    gx = ((B(1, -1) + two * B(1, 0)) + B(1, 1)) - ((B(-1, -1) + two * B(-1, 0)) + B(-1, 1))
-    gy = ((B(-1, 1) + two * B(0, 1)) + B(1, 1)) - ((B(-1, -1) + two * B(0, -1)) + B(1, -1))
+    gx = (B(1, -1) + 2.0 * B(1, 0) + B(1, 1)) - (B(-1, -1) + 2.0 * B(-1, 0) + B(-1, 1))
+    gy = (B(-1, 1) + 2.0 * B(0, 1) + B(1, 1)) - (B(-1, -1) + 2.0 * B(0, -1) + B(1, -1))
     m2 = gx * gx + gy * gy  # indexed [v, y + 1, x + 1]
     tl, th = lo * 16.0 * R / w, hi * 16.0 * R / w
-    t2lo, t2hi = f32(tl * tl), f32(th * th)
-    tan22 = f32(math.sqrt(2.0) - 1.0)
+    t2lo, t2hi = tl * tl, th * th
+    tan22 = math.sqrt(2.0) - 1.0
     m = m2[:, 1:h + 1, 1:w + 1]
     gxc, gyc = gx[:, 1:h + 1, 1:w + 1], gy[:, 1:h + 1, 1:w + 1]
     ax, ay = np.abs(gxc), np.abs(gyc)
@@ -93,7 +104,21 @@ def canny(depth, hit, R, lo, hi):
     keep = (m >= t2lo) & (m >= m1) & (m >= mm)
     strong = keep & (m >= t2hi)
     weak = keep & ~strong
-    return np.stack([hysteresis(strong[v], weak[v]) for v in range(n)])
+    edges = np.stack([hysteresis(strong[v], weak[v]) for v in range(n)])
+    if not ambiguity:
+        return edges
+    e = 256.0 * U32 * D  # reach of a gradient component
+
+    def near_sq(a, b):  # squared magnitudes a, b within reach of each other
+        return np.abs(a - b) <= 2.0 * e * (np.sqrt(a) + np.sqrt(b)) + e * e
+
+    relevant = (m >= t2lo) | near_sq(m, t2lo)  # below it a pixel is no edge either way
+    amb = (near_sq(m, t2lo) | near_sq(m, t2hi) |
+           (relevant & (near_sq(m, m1) | near_sq(m, mm) |
+                        (np.abs(ay - tan22 * ax) <= 2.0 * e) |
+                        (np.abs(ax - tan22 * ay) <= 2.0 * e) |
+                        (np.minimum(ax, ay) <= e))))
+    return edges, amb, keep | amb
 
 
 def hysteresis(strong, weak):
@@ -114,52 +139,68 @@ def eq22_radius(cos_np, L):
 
 
 def fuse(view_dirs, depth, nrm, hit, centre, R, grid=256, side=0.0, lo=2.0, hi=4.0, dilate=1):
-    """Splats from GFBs: dict of xyz (world, fp64), nrm, radius, count (pixels per splat), cell
-    (flat index, x fastest) and edge (the Canny map), splats in cell order; coherence and
-    best_cos (the |n.p| the radius was taken at) describe each splat's conditioning."""
-    depth = np.asarray(depth, f32)
-    nrm = np.asarray(nrm, f32)
-    hit = np.asarray(hit, f32)
+    """Splats from GFBs: dict of xyz (world), nrm, radius, count (pixels per splat), cell (flat
+    index, x fastest) and edge (the Canny map), splats in cell order; coherence and best_cos
+    (the |n.p| the radius was taken at) describe each splat's conditioning.  Per pixel: edge_amb
+    (the Canny decision is ambiguous), edge_cand (see canny), pix_cell (grid cell of each hit
+    pixel, -1 elsewhere) and pix_amb (its cell or its normal's side is ambiguous); amb_cells
+    lists every cell that a pixel with an ambiguous cell decision may land in."""
+    depth = np.asarray(depth, np.float64)
+    nrm = np.asarray(nrm, np.float64)
+    hit = np.asarray(hit, np.float64)
     n, h, w = depth.shape
     G = int(grid)
     side = float(side) if side > 0 else 2.0 * R
-    edge = canny(depth, hit, R, lo, hi)
+    edge, edge_amb, edge_cand = canny(depth, hit, R, lo, hi, ambiguity=True)
     if dilate > 0:
         st = np.ones((1, 2 * dilate + 1, 2 * dilate + 1), bool)
         drop = ndimage.binary_dilation(edge, structure=st)
     else:
         drop = edge
-    keep = (hit >= f32(0.5)) & ~drop
-    half32, L32 = f32(0.5 * side), f32(side / G)
-    D = f32(2.0) * f32(R)
-    pitch = D / f32(w)
-    P_all, N_all, C_all, V_all = [], [], [], []
+    is_hit = hit >= 0.5
+    keep = is_hit & ~drop
+    half, L = 0.5 * side, side / G
+    reach_cell = 32.0 * U32 * R / L
+    pix_cell = np.full((n, h, w), -1, np.int64)
+    pix_amb = np.zeros((n, h, w), bool)
+    P_all, N_all, C_all, V_all, A_all = [], [], [], [], []
     for v in range(n):
         u, vv, k = screen_basis(view_dirs[v])
-        ys, xs = np.nonzero(keep[v])
+        ys, xs = np.nonzero(is_hit[v])
         dep, nv3 = depth[v, ys, xs], nrm[v, ys, xs]
-        # fp32 decisions
-        b = [np.asarray(a, np.float64).astype(f32) for a in (u, vv, k)]
-        ou = ((xs.astype(f32) + f32(0.5)) - f32(0.5) * f32(w)) * pitch
-        ov = ((ys.astype(f32) + f32(0.5)) - f32(0.5) * f32(h)) * pitch
-        t = dep * D - f32(R)
-        P32 = np.stack([(b[0][c] * ou + b[1][c] * ov) + b[2][c] * t for c in range(3)], 1)
-        N32 = np.stack([(b[0][c] * nv3[:, 0] + b[1][c] * nv3[:, 1]) - b[2][c] * nv3[:, 2]
-                        for c in range(3)], 1)
-        q = np.floor((P32 + half32) / L32).astype(np.int64)
-        q[q == -1] = 0
-        q[q == G] = G - 1
-        ok = np.all((q >= 0) & (q < G), 1) & np.any(N32 != 0, 1)
-        am = np.argmax(np.abs(N32), 1)
-        sgn = np.where(N32[np.arange(len(am)), am] < 0, -1.0, 1.0)
-        # fp64 values
-        tt = dep.astype(np.float64) * 2.0 * R - R
+        tt = dep * 2.0 * R - R
         pu = (xs + 0.5 - 0.5 * w) * (2.0 * R / w)
         pv = (ys + 0.5 - 0.5 * h) * (2.0 * R / w)
         P = pu[:, None] * u + pv[:, None] * vv + tt[:, None] * k
-        N = nv3[:, 0:1].astype(np.float64) * u + nv3[:, 1:2] * vv - nv3[:, 2:3].astype(np.float64) * k
+        N = nv3[:, 0:1] * u + nv3[:, 1:2] * vv - nv3[:, 2:3] * k
+        g = (P + half) / L
+        q = np.floor(g).astype(np.int64)
+        q[q == -1] = 0
+        q[q == G] = G - 1
+        fr = g - np.floor(g)
+        amb_cell = np.any(np.minimum(fr, 1 - fr) <= reach_cell, 1)
+        qa, fa = np.floor(g[amb_cell]).astype(np.int64), fr[amb_cell]
+        for off in np.ndindex(3, 3, 3):  # the cell itself and its neighbours across near faces
+            o3 = np.array(off) - 1
+            ok_o = np.all(((o3 != -1) | (fa <= reach_cell)) & ((o3 != 1) | (1 - fa <= reach_cell)),
+                          1)
+            qo = qa + o3
+            qo[qo == -1] = 0
+            qo[qo == G] = G - 1
+            ok_o &= np.all((qo >= 0) & (qo < G), 1)
+            A_all.append(((qo[:, 2] * G + qo[:, 1]) * G + qo[:, 0])[ok_o])
+        inside = np.all((q >= 0) & (q < G), 1) & np.any(N != 0, 1)
+        aN = np.abs(N)
+        am = np.argmax(aN, 1)
+        top = aN[np.arange(len(am)), am]
+        second = np.sort(aN, 1)[:, 1]
+        amb_sign = (top - second <= 1e-5) | (top <= 1e-5)
+        sgn = np.where(N[np.arange(len(am)), am] < 0, -1.0, 1.0)
         N = N / np.linalg.norm(N, axis=1, keepdims=True).clip(1e-300) * sgn[:, None]
         cell = (q[:, 2] * G + q[:, 1]) * G + q[:, 0]
+        pix_cell[v, ys[inside], xs[inside]] = cell[inside]
+        pix_amb[v, ys, xs] = amb_cell | amb_sign
+        ok = inside & keep[v, ys, xs]
         P_all.append(P[ok]); N_all.append(N[ok]); C_all.append(cell[ok])
         V_all.append(np.full(int(ok.sum()), v))
     P, N, C, V = (np.concatenate(a) for a in (P_all, N_all, C_all, V_all))
@@ -181,4 +222,5 @@ def fuse(view_dirs, depth, nrm, hit, centre, R, grid=256, side=0.0, lo=2.0, hi=4
     # conditioning of each splat's normal: |sum of unit normals| / count (near 0 when they
     # nearly cancel, where any rounding in the inputs is amplified by 1 / coherence)
     return dict(xyz=xyz, nrm=nf, radius=radius, count=cnt, cell=cells, edge=edge,
-                coherence=nl[:, 0] / cnt, best_cos=best)
+                coherence=nl[:, 0] / cnt, best_cos=best, edge_amb=edge_amb, edge_cand=edge_cand,
+                pix_cell=pix_cell, pix_amb=pix_amb, amb_cells=np.unique(np.concatenate(A_all)))

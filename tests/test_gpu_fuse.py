@@ -1,15 +1,22 @@
 """GPU parity of GFB edge filtering and fusion (pe_fuse_gfbs) against oracle/fuse.py, and the
 fused-splat geometry driving a three-bounce OctAR sweep.
 
-Inputs are seeded synthetic GFB stacks (scenes.synthetic_gfbs) shared by both sides.  Bars:
-  - Canny edge maps identical (both sides take every edge decision in fp32 with each
-    operation rounded on its own);
-  - the same occupied cells in the same order with the same pixel counts (cell indices and
-    normal sides are fp32 decisions too);
-  - fused positions within 1e-5 R; normals within 1e-6 / coherence (coherence = |sum of the
-    cell's unit normals| / count: nearly cancelling normals amplify input rounding) and Eq. (22)
-    radii within 1e-6 / (coherence |n.p|) relative (fp32 point/normal arithmetic on the GPU
-    against fp64 values in the oracle).
+Inputs are seeded synthetic GFB stacks (scenes.synthetic_gfbs) shared by both sides.  The
+oracle takes every decision in fp64 and flags those within fp32 reach of flipping (its module
+docstring states the reach).  Bars:
+  - Canny edge maps: every pixel where the GPU differs lies in an 8-connected component of the
+    oracle's candidates (strong, weak or ambiguous pixels) that holds an ambiguous pixel (a
+    flipped decision there can carry along the hysteresis chain), and flips are at most 1 % of
+    the edge pixels;
+  - cells: a cell whose pixels can change (a hit pixel within the dilation of a flipped edge
+    pixel, or with an ambiguous cell or normal-side decision, or a cell that a pixel with an
+    ambiguous cell decision may land in) is "affected"; every cell present on one side only is
+    affected, affected cells are at most 1 % of the cells, and every other cell has the same
+    pixel count on both sides;
+  - on unaffected cells, fused positions within 1e-5 R; normals within 1e-6 / coherence
+    (coherence = |sum of the cell's unit normals| / count: nearly cancelling normals amplify input
+    rounding) and Eq. (22) radii within 1e-6 / (coherence |n.p|) relative (fp32 point/normal
+    arithmetic on the GPU against fp64 values in the oracle).
 Sizes: 3 views of 96^2 on a 64^3 grid (tiles and ragged tails), soft hit probabilities,
 dilation 0..2, a clipped grid, and 8 views of 512^2 on the paper's 256^3 grid.
 """
@@ -49,22 +56,51 @@ def run_both(pe, ctx, g, centre, R, grid, side=0.0, dilate=1, lo=2.0, hi=4.0):
     gpu = {k: v.cpu().numpy() for k, v in r.items()}
     o = ofuse.fuse(g["view_dirs"], g["depth"], g["nrm"], g["hit"], centre, R, grid=grid, side=side,
                    lo=lo, hi=hi, dilate=dilate)
-    return gpu, o
+    side = side if side > 0 else 2.0 * R
+    return gpu, o, dict(centre=np.asarray(centre, float), side=side, grid=grid, dilate=dilate,
+                        hit=g["hit"] >= 0.5)
 
 
-def check(gpu, o, R, tag):
-    ne = int((gpu["edge"].astype(bool) != o["edge"]).sum())
-    print(f"{tag}: {len(o['xyz'])} splats, {int(o['edge'].sum())} edge pixels, edge mismatches {ne}")
-    assert ne == 0
-    assert len(gpu["xyz"]) == len(o["xyz"])
-    np.testing.assert_array_equal(gpu["count"], o["count"])
-    dx = np.abs(gpu["xyz"] - o["xyz"]).max() / R
+def check(gpu, o, R, tag, geo):
+    from scipy import ndimage
+    ge, oe = gpu["edge"].astype(bool), o["edge"]
+    diff = ge ^ oe
+    allowed = np.zeros_like(diff)
+    for v in range(oe.shape[0]):
+        lab, _ = ndimage.label(o["edge_cand"][v] | ge[v], structure=np.ones((3, 3), bool))
+        ids = np.unique(lab[o["edge_amb"][v]])
+        allowed[v] = np.isin(lab, ids[ids > 0])
+    n_flip = int(diff.sum())
+    print(f"{tag}: {len(o['xyz'])} splats, {int(oe.sum())} edge pixels, {n_flip} flipped "
+          f"({int(o['edge_amb'].sum())} ambiguous edge decisions)")
+    assert not (diff & ~allowed).any(), "edge flip away from any ambiguous decision"
+    assert n_flip <= 0.01 * max(1, int(oe.sum()))
+    # cells whose pixel sets can differ
+    d = geo["dilate"]
+    grown = diff if d <= 0 else ndimage.binary_dilation(
+        diff, structure=np.ones((1, 2 * d + 1, 2 * d + 1), bool))
+    touch = ((grown & geo["hit"]) | o["pix_amb"]) & (o["pix_cell"] >= 0)
+    affected = set(np.unique(o["pix_cell"][touch]).tolist()) | set(o["amb_cells"].tolist())
+    G, L = geo["grid"], geo["side"] / geo["grid"]
+    q = np.clip(np.floor((gpu["xyz"] - geo["centre"] + 0.5 * geo["side"]) / L), 0, G - 1)
+    q = q.astype(np.int64)
+    gcell = (q[:, 2] * G + q[:, 1]) * G + q[:, 0]
+    ocell = o["cell"]
+    only = set(np.setxor1d(gcell, ocell).tolist())
+    print(f"{tag}: {len(affected)} affected cells, {len(only)} cells on one side only")
+    assert only <= affected
+    assert len(affected) <= 0.01 * len(ocell)
+    common, gi, oi = np.intersect1d(gcell, ocell, return_indices=True)
+    free = ~np.isin(common, np.array(sorted(affected), dtype=np.int64))
+    gi, oi = gi[free], oi[free]
+    np.testing.assert_array_equal(gpu["count"][gi], o["count"][oi])
+    dx = np.abs(gpu["xyz"][gi] - o["xyz"][oi]).max() / R
     # normals and radii: 1e-6 scaled by the splat's conditioning (1 / coherence of its unit
     # normals; the radius moves by half the relative change of |n.p|)
-    en = np.abs(gpu["nrm"] - o["nrm"]).max(axis=1) * o["coherence"]
-    er = np.abs(gpu["radius"] - o["radius"]) / o["radius"] * o["coherence"] * o["best_cos"]
-    print(f"{tag}: max |dx|/R {dx:.2e}, scaled |dn| {en.max():.2e}, scaled radius {er.max():.2e}, "
-          f"raw |dn| {np.abs(gpu['nrm'] - o['nrm']).max():.2e}")
+    en = np.abs(gpu["nrm"][gi] - o["nrm"][oi]).max(axis=1) * o["coherence"][oi]
+    er = (np.abs(gpu["radius"][gi] - o["radius"][oi]) / o["radius"][oi] * o["coherence"][oi] *
+          o["best_cos"][oi])
+    print(f"{tag}: max |dx|/R {dx:.2e}, scaled |dn| {en.max():.2e}, scaled radius {er.max():.2e}")
     assert dx < 1e-5 and en.max() < 1e-6 and er.max() < 1e-6
 
 
@@ -72,22 +108,22 @@ def check(gpu, o, R, tag):
 def test_fuse_parity_small(pe, ctx, soft, dilate):
     g = scenes.synthetic_gfbs(11, 3, 96, soft_hit=soft)
     centre, R = np.array([0.5, -1.0, 2.0]), 1.3
-    gpu, o = run_both(pe, ctx, g, centre, R, 64, dilate=dilate)
-    check(gpu, o, R, f"96^2 x3 soft={soft} dilate={dilate}")
+    gpu, o, geo = run_both(pe, ctx, g, centre, R, 64, dilate=dilate)
+    check(gpu, o, R, f"96^2 x3 soft={soft} dilate={dilate}", geo)
 
 
 def test_fuse_parity_clipped_grid(pe, ctx):
     """A grid smaller than the screens: points beyond one cell outside are ignored, those
     within one cell go to the boundary cells."""
     g = scenes.synthetic_gfbs(12, 2, 80)
-    gpu, o = run_both(pe, ctx, g, np.zeros(3), 1.0, 40, side=1.1)
-    check(gpu, o, 1.0, "clipped grid")
+    gpu, o, geo = run_both(pe, ctx, g, np.zeros(3), 1.0, 40, side=1.1)
+    check(gpu, o, 1.0, "clipped grid", geo)
 
 
 def test_fuse_parity_full_size(pe, ctx):
     g = scenes.synthetic_gfbs(13, 8, 512, n_regions=6)
-    gpu, o = run_both(pe, ctx, g, np.zeros(3), 10.0, 256)
-    check(gpu, o, 10.0, "512^2 x8, 256^3")
+    gpu, o, geo = run_both(pe, ctx, g, np.zeros(3), 10.0, 256)
+    check(gpu, o, 10.0, "512^2 x8, 256^3", geo)
 
 
 def test_fuse_cap_and_count_only(pe, ctx):

@@ -11,13 +11,15 @@ formulas:
     weak one only when joined to a strong edge), above it the crest column; a depth step gives
     an edge beside it in every row;
   - hysteresis == brute-force propagation on random tiny maps;
-  - empty pixels count as far depth, so a hit square's border is an edge all round.
+  - empty pixels count as far depth, so a hit square's border is an edge all round;
+  - the fp32-reach flags cover what a few ulps of input rounding actually change.
 """
 import math
 
 import numpy as np
 import pytest
 
+import scenes
 from oracle import fuse
 
 
@@ -178,3 +180,32 @@ def test_hysteresis_matches_brute_force():
         strong, weak = u > 0.93, (u > 0.55) & (u <= 0.93)
         np.testing.assert_array_equal(fuse.hysteresis(strong, weak),
                                       brute_hysteresis(strong, weak))
+
+
+def test_ambiguity_flags_cover_ulp_perturbations():
+    """The fp32 reach the oracle flags is wide enough: perturbing every depth and normal by up to
+    4 fp32 ulps (the size of the GPU kernels' own rounding) changes edge decisions only inside
+    candidate components that hold a flagged pixel, and moves only flagged pixels across cell
+    faces, into cells the oracle lists as reachable."""
+    from scipy import ndimage
+    g = scenes.synthetic_gfbs(13, 4, 512, n_regions=6)
+    centre, R = np.zeros(3), 10.0
+    r0 = fuse.fuse(g["view_dirs"], g["depth"], g["nrm"], g["hit"], centre, R, grid=256)
+    rng = np.random.default_rng(5)
+    d32 = g["depth"].astype(np.float32)
+    dp = d32 + rng.integers(-4, 5, d32.shape) * np.spacing(d32)
+    n32 = g["nrm"].astype(np.float32)
+    npert = n32 + rng.integers(-4, 5, n32.shape) * np.spacing(n32)
+    r1 = fuse.fuse(g["view_dirs"], dp, npert, g["hit"], centre, R, grid=256)
+    diff = r0["edge"] ^ r1["edge"]
+    allowed = np.zeros_like(diff)
+    for v in range(diff.shape[0]):
+        lab, _ = ndimage.label(r0["edge_cand"][v] | r1["edge"][v], structure=np.ones((3, 3), bool))
+        ids = np.unique(lab[r0["edge_amb"][v]])
+        allowed[v] = np.isin(lab, ids[ids > 0])
+    assert not (diff & ~allowed).any()
+    hit = g["hit"] >= 0.5
+    moved = (r0["pix_cell"] != r1["pix_cell"]) & hit
+    assert moved.sum() > 0  # the perturbation does move some points across cell faces
+    assert not (moved & ~r0["pix_amb"]).any()
+    assert np.isin(r1["pix_cell"][moved], r0["amb_cells"]).all()
