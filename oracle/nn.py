@@ -30,6 +30,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+from scipy import special
 
 LAMBDAS = (1.0, 0.5, 1.0, 0.5)   # Eq. (21)
 FOCAL_ALPHA = 0.5                # Eq. (19)
@@ -51,8 +52,9 @@ def conv2d(x, w, b=None):
     xp = _pad(x, p)
     y = np.zeros((N, H, W, Co))
     for a in range(KH):
-        for c in range(KW):
-            y += np.einsum("nhwi,oi->nhwo", xp[:, a:a + H, c:c + W, :], w[:, a, c, :])
+        for c in range(KW):  # one tap: a (pixels x Ci) by (Ci x Co) product
+            xs = xp[:, a:a + H, c:c + W, :].reshape(-1, Ci)
+            y += (xs @ w[:, a, c, :].T).reshape(N, H, W, Co)
     if b is not None:
         y += b
     return y
@@ -65,10 +67,11 @@ def conv2d_backward(x, w, dy):
     xp = _pad(x, p)
     dxp = np.zeros_like(xp)
     dw = np.zeros_like(w)
+    d2 = dy.reshape(-1, Co)
     for a in range(KH):
         for c in range(KW):
-            dw[:, a, c, :] = np.einsum("nhwo,nhwi->oi", dy, xp[:, a:a + H, c:c + W, :])
-            dxp[:, a:a + H, c:c + W, :] += np.einsum("nhwo,oi->nhwi", dy, w[:, a, c, :])
+            dw[:, a, c, :] = d2.T @ xp[:, a:a + H, c:c + W, :].reshape(-1, Ci)
+            dxp[:, a:a + H, c:c + W, :] += (d2 @ w[:, a, c, :]).reshape(N, H, W, Ci)
     dx = dxp[:, p:p + H, p:p + W, :]
     db = dy.sum(axis=(0, 1, 2))
     return dx, dw, db
@@ -122,7 +125,7 @@ def layernorm_backward(cache, g, dy):
 
 # ---------------------------------------------------------------------------- activations --
 
-_erf = np.vectorize(math.erf)
+_erf = special.erf
 
 
 def gelu(x):
@@ -137,7 +140,7 @@ def gelu_backward(x, dy):
 
 
 def sigmoid(x):
-    return 1.0 / (1.0 + np.exp(-x))
+    return special.expit(x)
 
 
 # ------------------------------------------------------------------------ resampling --
@@ -196,17 +199,19 @@ def losses(depth, nrm, logit, depth_gt, nrm_gt, mask_gt):
     dcrn_dp = np.cross(nrm_gt, u)  # d|p x g|/dp = g x (c/|c|)
     ds_dp = dcrn_dp / den[..., None] - (s / np.maximum(npn, 1e-30) ** 2)[..., None] * nrm
     g_nrm = (m / nv)[..., None] * ds_dp
-    # L3: alpha-balanced focal loss over all pixels
-    h = sigmoid(logit)
+    # L3: alpha-balanced focal loss over all pixels (Eq. (19)), with h, 1 - h and their logs
+    # taken from the logit itself so that saturated logits keep their exact value
+    h, hb = sigmoid(logit), sigmoid(-logit)
+    lh, l1h = -np.logaddexp(0.0, -logit), -np.logaddexp(0.0, logit)  # log h, log(1 - h)
     a, gm = FOCAL_ALPHA, FOCAL_GAMMA
-    eps = 1e-12
-    pos = -a * (1 - h) ** gm * np.log(np.maximum(h, eps))
-    neg = -(1 - a) * h ** gm * np.log(np.maximum(1 - h, eps))
+    pos = -a * hb ** gm * lh
+    neg = -(1 - a) * h ** gm * l1h
     l3 = np.where(mask_gt > 0, pos, neg)
     L3 = l3.mean()
-    dpos = a * gm * (1 - h) ** (gm - 1) * np.log(np.maximum(h, eps)) - a * (1 - h) ** gm / np.maximum(h, eps)
-    dneg = -(1 - a) * gm * h ** (gm - 1) * np.log(np.maximum(1 - h, eps)) + (1 - a) * h ** gm / np.maximum(1 - h, eps)
-    g_logit = np.where(mask_gt > 0, dpos, dneg) * h * (1 - h) / l3.size
+    # d/dlogit, using dh/dlogit = h (1 - h)
+    dpos = a * hb ** gm * (gm * h * lh - hb)
+    dneg = (1 - a) * h ** gm * (h - gm * hb * l1h)
+    g_logit = np.where(mask_gt > 0, dpos, dneg) / l3.size
     # L4: depth-gradient normals (-du, -dv, 1), forward differences, pixels whose right and
     # lower neighbours are also target hits
     N, H, W = depth.shape
@@ -275,41 +280,51 @@ def init_params(base=8, seed=0, in_ch=1):
     return P
 
 
-def _block_fwd(P, name, x):
+def _same(t):
+    return t
+
+
+def _block_fwd(P, name, x, q=_same):
     c = {}
     c["x"] = x
-    c["dw"] = dwconv(x, P[name + ".dw.w"], P[name + ".dw.b"])
-    c["ln"], c["lnc"] = layernorm(c["dw"], P[name + ".ln.g"], P[name + ".ln.b"])
-    c["z1"] = conv2d(c["ln"], P[name + ".pw1.w"], P[name + ".pw1.b"])
-    c["a1"] = gelu(c["z1"])
-    y = x + conv2d(c["a1"], P[name + ".pw2.w"], P[name + ".pw2.b"])
+    c["dw"] = q(dwconv(x, P[name + ".dw.w"], P[name + ".dw.b"]))
+    ln, c["lnc"] = layernorm(c["dw"], P[name + ".ln.g"], P[name + ".ln.b"])
+    c["ln"] = q(ln)
+    c["z1"] = q(conv2d(c["ln"], P[name + ".pw1.w"], P[name + ".pw1.b"]))
+    c["a1"] = q(gelu(c["z1"]))
+    y = q(x + conv2d(c["a1"], P[name + ".pw2.w"], P[name + ".pw2.b"]))
     return y, c
 
 
-def _block_bwd(P, name, c, dy, G):
+def _block_bwd(P, name, c, dy, G, q=_same):
     da1, G[name + ".pw2.w"], G[name + ".pw2.b"] = conv2d_backward(c["a1"], P[name + ".pw2.w"], dy)
-    dz1 = gelu_backward(c["z1"], da1)
+    dz1 = q(gelu_backward(c["z1"], q(da1)))
     dln, G[name + ".pw1.w"], G[name + ".pw1.b"] = conv2d_backward(c["ln"], P[name + ".pw1.w"], dz1)
-    ddw, G[name + ".ln.g"], G[name + ".ln.b"] = layernorm_backward(c["lnc"], P[name + ".ln.g"], dln)
-    dx, G[name + ".dw.w"], G[name + ".dw.b"] = dwconv_backward(c["x"], P[name + ".dw.w"], ddw)
-    return dx + dy
+    ddw, G[name + ".ln.g"], G[name + ".ln.b"] = layernorm_backward(c["lnc"], P[name + ".ln.g"],
+                                                                   q(dln))
+    dx, G[name + ".dw.w"], G[name + ".dw.b"] = dwconv_backward(c["x"], P[name + ".dw.w"], q(ddw))
+    return q(q(dx) + dy)
 
 
-def forward(P, x):
-    """x [N,H,W,in_ch] -> (depth [N,2H,2W], nrm [N,2H,2W,3], logit [N,2H,2W]), cache."""
+def forward(P, x, q=_same):
+    """x [N,H,W,in_ch] -> (depth [N,2H,2W], nrm [N,2H,2W,3], logit [N,2H,2W]), cache.
+
+    q is applied to every intermediate tensor (identity by default): a test passes a random
+    relative perturbation of rounding size to measure how each output responds to rounding at
+    every layer (the conditioning of the network at that input)."""
     cache = {}
-    z = conv2d(x, P["stem.w"], P["stem.b"])
+    z = q(conv2d(x, P["stem.w"], P["stem.b"]))
     cache["x"] = x
     cache["stem_z"] = z
-    a = gelu(z)
+    a = q(gelu(z))
     skips = []
-    h, cache["enc0"] = _block_fwd(P, "enc0", a)
+    h, cache["enc0"] = _block_fwd(P, "enc0", a, q)
     skips.append(h)
     for l in range(1, 4):
         p, arg = maxpool2(h)
         cache[f"pool{l}"] = (arg, h.shape, p)
-        d = conv2d(p, P[f"down{l}.w"], P[f"down{l}.b"])
-        h, cache[f"enc{l}"] = _block_fwd(P, f"enc{l}", d)
+        d = q(conv2d(p, P[f"down{l}.w"], P[f"down{l}.b"]))
+        h, cache[f"enc{l}"] = _block_fwd(P, f"enc{l}", d, q)
         cache[f"down{l}_in"] = p
         skips.append(h)
     outs = {}
@@ -317,13 +332,13 @@ def forward(P, x):
         hc = {}
         u = skips[3]
         for l in (3, 2, 1):
-            zu = conv2d(u, P[f"{head}.up{l}.w"], P[f"{head}.up{l}.b"])
+            zu = q(conv2d(u, P[f"{head}.up{l}.w"], P[f"{head}.up{l}.b"]))
             sh = pixel_shuffle(zu)
             cat = np.concatenate([sh, skips[l - 1]], axis=-1)
-            zf = conv2d(cat, P[f"{head}.fuse{l}.w"], P[f"{head}.fuse{l}.b"])
+            zf = q(conv2d(cat, P[f"{head}.fuse{l}.w"], P[f"{head}.fuse{l}.b"]))
             hc[l] = (u, cat, zf)
-            u = gelu(zf)
-        zo = conv2d(u, P[f"{head}.out.w"], P[f"{head}.out.b"])
+            u = q(gelu(zf))
+        zo = q(conv2d(u, P[f"{head}.out.w"], P[f"{head}.out.b"]))
         hc["out_in"] = u
         outs[head] = pixel_shuffle(zo)
         cache["head_" + head] = hc
@@ -341,7 +356,9 @@ def depth_scale(x):
     return 1.0 / max(x.shape[1], x.shape[2])
 
 
-def backward(P, cache, d_depth, d_nrm, d_logit):
+def backward(P, cache, d_depth, d_nrm, d_logit, q=_same):
+    """Parameter gradients from the output gradients; q as in forward, on every intermediate
+    gradient (not on the parameter gradients themselves)."""
     G = {}
     skips = cache["skips"]
     dskips = [np.zeros_like(s) for s in skips]
@@ -349,26 +366,27 @@ def backward(P, cache, d_depth, d_nrm, d_logit):
     for head, dout in (("depth", sc * d_depth[..., None]), ("nrm", d_nrm),
                        ("mask", d_logit[..., None])):
         hc = cache["head_" + head]
-        dzo = pixel_unshuffle(dout)
+        dzo = q(pixel_unshuffle(dout))
         du, G[f"{head}.out.w"], G[f"{head}.out.b"] = conv2d_backward(hc["out_in"], P[f"{head}.out.w"], dzo)
         for l in (1, 2, 3):
             u_in, cat, zf = hc[l]
-            dzf = gelu_backward(zf, du)
+            dzf = q(gelu_backward(zf, q(du)))
             dcat, G[f"{head}.fuse{l}.w"], G[f"{head}.fuse{l}.b"] = conv2d_backward(cat, P[f"{head}.fuse{l}.w"], dzf)
+            dcat = q(dcat)
             cs = dcat.shape[-1] // 2
             dsh, dskip = dcat[..., :cs], dcat[..., cs:]
             dskips[l - 1] += dskip
             dzu = pixel_unshuffle(dsh)
             du, G[f"{head}.up{l}.w"], G[f"{head}.up{l}.b"] = conv2d_backward(u_in, P[f"{head}.up{l}.w"], dzu)
-        dskips[3] += du
-    dh = dskips[3]
+        dskips[3] += q(du)
+    dh = q(dskips[3])
     for l in (3, 2, 1):
-        dd = _block_bwd(P, f"enc{l}", cache[f"enc{l}"], dh, G)
+        dd = _block_bwd(P, f"enc{l}", cache[f"enc{l}"], dh, G, q)
         dp, G[f"down{l}.w"], G[f"down{l}.b"] = conv2d_backward(cache[f"down{l}_in"], P[f"down{l}.w"], dd)
         arg, shape, _ = cache[f"pool{l}"]
-        dh = maxpool2_backward(arg, dp, shape) + dskips[l - 1]
-    da = _block_bwd(P, "enc0", cache["enc0"], dh, G)
-    dz = gelu_backward(cache["stem_z"], da)
+        dh = q(maxpool2_backward(arg, q(dp), shape) + dskips[l - 1])
+    da = _block_bwd(P, "enc0", cache["enc0"], dh, G, q)
+    dz = q(gelu_backward(cache["stem_z"], da))
     _, G["stem.w"], G["stem.b"] = conv2d_backward(cache["x"], P["stem.w"], dz)
     return G
 

@@ -1136,19 +1136,26 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
         a.gn[3 * i] = m * ((gy * uz - gz * uy) / den - s * ip2 * px);
         a.gn[3 * i + 1] = m * ((gz * ux - gx * uz) / den - s * ip2 * py);
         a.gn[3 * i + 2] = m * ((gx * uy - gy * ux) / den - s * ip2 * pz);
-        // L3 focal
-        const float h = 1.f / (1.f + __expf(-a.logit[i]));
-        const float al = 0.5f, lh = logf(fmaxf(h, 1e-12f)), l1h = logf(fmaxf(1.f - h, 1e-12f));
-        float l3, dl;
+        // L3 focal (Eq. (19), gamma = 2): h, 1 - h and their logs from the logit itself
+        // (log h = -softplus(-l), log(1 - h) = -softplus(l)), exact for saturated logits where
+        // 1 - h computed as a difference would round to 0
+        const float lg = a.logit[i];
+        const float e = expf(-fabsf(lg));                  // in (0, 1]
+        const float sp = log1pf(e);                         // softplus(-|l|)
+        const float h = lg >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+        const float hb = lg >= 0.f ? e / (1.f + e) : 1.f / (1.f + e);
+        const float lh = -(fmaxf(-lg, 0.f) + sp), l1h = -(fmaxf(lg, 0.f) + sp);
+        const float al = 0.5f;
+        float l3, gl;
         if (m > 0.f) {
-            l3 = -al * (1.f - h) * (1.f - h) * lh;
-            dl = al * 2.f * (1.f - h) * lh - al * (1.f - h) * (1.f - h) / fmaxf(h, 1e-12f);
+            l3 = -al * hb * hb * lh;
+            gl = al * hb * hb * (2.f * h * lh - hb);
         } else {
             l3 = -(1.f - al) * h * h * l1h;
-            dl = -(1.f - al) * 2.f * h * l1h + (1.f - al) * h * h / fmaxf(1.f - h, 1e-12f);
+            gl = (1.f - al) * h * h * (h - 2.f * hb * l1h);
         }
         acc[2] = l3;
-        a.gl[i] = dl * h * (1.f - h);
+        a.gl[i] = gl;
         // L4 contribution of the quad at (y, x): needs (y, x+1), (y+1, x) hits
         if (x + 1 < a.W && y + 1 < a.H) {
             const float mr = a.mask_gt[i + 1], md = a.mask_gt[i + a.W];

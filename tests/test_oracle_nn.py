@@ -166,11 +166,25 @@ def test_losses_special_cases():
     try:
         N.FOCAL_GAMMA = 0.0
         _, parts, _ = N.losses(d, n, lg, dg, ng, mg)
-        h = N.sigmoid(lg)
+        h = 1.0 / (1.0 + np.exp(-lg))
         bce = -(mg * np.log(h) + (1 - mg) * np.log(1 - h)).mean()
         assert abs(parts[2] - 0.5 * bce) < 1e-12
     finally:
         N.FOCAL_GAMMA = old
+
+
+def test_focal_loss_saturated_logits():
+    """Eq. (19) at logits far beyond where 1 - h underflows: the loss of a wrong confident
+    prediction grows like (1 - alpha) |logit| (and alpha |logit| for a missed hit), with slope
+    1 - alpha (alpha); a right confident prediction costs nothing."""
+    one = np.ones((1, 1, 1))
+    z = np.zeros((1, 1, 1))
+    nrm, ng = np.ones((1, 1, 1, 3)), np.ones((1, 1, 1, 3))
+    for lg, m, loss, slope in ((40.0, 0.0, 0.5 * 40.0, 0.5), (-60.0, 1.0, 0.5 * 60.0, -0.5),
+                               (40.0, 1.0, 0.0, 0.0), (-60.0, 0.0, 0.0, 0.0)):
+        _, parts, (_, _, gl) = N.losses(0.5 * one, nrm, lg * one, 0.5 * one, ng, m * one)
+        assert abs(parts[2] - loss) < 1e-12, (lg, m, parts[2])
+        assert abs(gl[0, 0, 0] - slope) < 1e-12, (lg, m, gl[0, 0, 0])
 
 
 def test_network_backward_fd():
