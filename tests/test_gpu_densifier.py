@@ -3,13 +3,24 @@ oracle/nn.py, through the C ABI on a HIP device.
 
 The oracle runs on the same parameters, with the weights the GPU reads in bf16 (the MFMA
 convolutions) rounded to bf16 first, so the comparison measures only the kernels' arithmetic:
-bf16 activations and gradients (unit roundoff 2^-9) through about 30 layers forward and as many
-backward.  Bars: relative L2 error <= 2 % on the forward outputs and the loss terms; for every
-parameter gradient tensor, cosine similarity >= 0.995 and relative L2 error <= 6 % plus the
-sensitivity of the exact gradient to the forward's own error (the oracle's gradient recomputed
-from the GPU's forward outputs: the normal sine loss of Eq. (18) is not differentiable where
-predicted and target normals align, so a 1 % forward error moves its gradient by several %);
-AdamW's update to fp32 rounding.
+bf16 activations and gradients through about 30 layers forward and as many backward.
+
+Element-wise bar, from bf16's unit roundoff u = 2^-9 and the network's depth: the oracle is run
+again K times with every intermediate tensor of the forward and the backward multiplied by
+(1 + delta), delta uniform in [-u, u] per element (oracle forward/backward's q hook).  The
+per-element RMS deviation s of those runs is how much each output moves under rounding of bf16
+size at every layer; depth and conditioning (LayerNorm, the non-differentiable point of the
+normal sine loss, saturated sigmoids) enter through the network itself.  Every element of the
+forward outputs, the loss terms and every parameter gradient must satisfy
+|gpu - oracle| <= 32 (s + 0.1 rms(s)), and each tensor rms|gpu - oracle| <= 6 rms(s).  The factor
+covers that the GPU's rounding is deterministic (equal values round alike, so sums of many equal
+terms, such as a bias gradient over saturated pixels, accumulate it coherently) and the sampling
+error of s from K runs; measured, the bulk sits at err ~ s (median ratio ~1).
+
+Shapes: 2 images of 16^2 (ragged 32-pixel tiles, flat chunk sums), and 256^2 -> 512^2 (the
+densifier's configured resolution): 64-pixel k_conv_fwd tiles with 128- and 32-channel output
+tiles, k_conv_wgrad chunks of 576 pixels (18 K steps per block) with the tree reduction over
+114 chunks; 4 images of 256^2 forward adds the 64 x 64 tile.
 """
 import numpy as np
 import pytest
@@ -54,12 +65,6 @@ def oracle_params(net):
     return P
 
 
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
-
-
 def batch(seed, n=2, h=16, w=16):
     rng = np.random.default_rng(seed)
     x = rng.uniform(0.2, 1.0, (n, h, w)) * (rng.uniform(size=(n, h, w)) < 0.8)
@@ -86,51 +91,86 @@ def test_registry_matches_oracle(pe, ctx):
     net.close()
 
 
-def test_forward_and_gradients_match_oracle(pe, ctx):
+U_BF16 = 2.0 ** -9
+Z_ELEM, Z_RMS = 32.0, 6.0
+
+
+def oracle_outputs(P, x, dg, ng, mg, q=N._same, grads=True):
+    """Forward outputs (depth, unit normal, hit probability), loss terms and gradients."""
+    (dp, npr, lp), cache = N.forward(P, x[..., None], q)
+    out = dict(d=dp, n=npr / np.linalg.norm(npr, axis=-1, keepdims=True), p=N.sigmoid(lp))
+    if grads:
+        L, parts, (gd, gn, gl) = N.losses(dp, npr, lp, dg, ng, mg)
+        out["loss"] = np.array([L] + list(parts))
+        out.update({"G_" + k: v for k, v in N.backward(P, cache, gd, gn, gl, q).items()})
+    return out
+
+
+def rounding_spread(P, x, dg, ng, mg, nom, K, seed, grads=True):
+    """Per-element RMS deviation of K oracle runs under bf16-sized relative perturbations of
+    every intermediate tensor."""
+    rng = np.random.default_rng(seed)
+
+    def q(t):
+        return t * (1.0 + rng.uniform(-U_BF16, U_BF16, t.shape))
+
+    acc = {k: np.zeros_like(v) for k, v in nom.items()}
+    for _ in range(K):
+        e = oracle_outputs(P, x, dg, ng, mg, q, grads)
+        for k in acc:
+            acc[k] += (e[k] - nom[k]) ** 2
+    return {k: np.sqrt(v / K) for k, v in acc.items()}
+
+
+def check_elementwise(gpu, nom, s, tag):
+    worst = []
+    for k, o in nom.items():
+        g = np.asarray(gpu[k], np.float64).reshape(o.shape)
+        err = np.abs(g - o)
+        rs = float(np.sqrt((s[k] ** 2).mean()))
+        ratio = float((err / (s[k] + 0.1 * rs)).max())
+        rms_ratio = float(np.sqrt((err ** 2).mean()) / rs)
+        worst.append((ratio, rms_ratio, k))
+    worst.sort(reverse=True)
+    for r, rr, k in worst[:8]:
+        print(f"{tag} {k:18s} max err/(s + 0.1 rms s) {r:6.2f}  rms err / rms s {rr:5.2f}")
+    bad = [(k, r, rr) for r, rr, k in worst if not (r <= Z_ELEM and rr <= Z_RMS)]
+    assert not bad, bad
+
+
+def gpu_outputs(net, x, dg, ng, mg, grads=True):
+    xd, dgd, ngd, mgd = to_dev(x, dg, ng, mg)
+    d, n, p = [t.cpu().numpy() for t in net.infer(xd)]
+    out = dict(d=d, n=n, p=p)
+    if grads:
+        p_before = net.get("params")
+        out["loss"] = np.array(net.train_step(xd, dgd, ngd, mgd, lr=0.0))
+        out.update({"G_" + k: v for k, v in net.get_dict("grads").items()})
+        assert np.array_equal(net.get("params"), p_before)  # lr = 0 leaves them untouched
+    return out
+
+
+@pytest.mark.parametrize("n,h", [(2, 16), (1, 256)])
+def test_forward_and_gradients_elementwise(pe, ctx, n, h):
     net = pe.Densifier(ctx, base=32, seed=3)
     P = oracle_params(net)
-    x, dg, ng, mg = batch(5)
-    xd, dgd, ngd, mgd = to_dev(x, dg, ng, mg)
-    # forward (inference outputs)
-    d_gpu, n_gpu, p_gpu = [t.cpu().numpy() for t in net.infer(xd)]
-    (dp, npr, lp), cache = N.forward(P, x[..., None])
-    assert rel(d_gpu, dp) < 0.02
-    nref = npr / np.linalg.norm(npr, axis=-1, keepdims=True)
-    assert rel(n_gpu, nref) < 0.02
-    assert rel(p_gpu, N.sigmoid(lp)) < 0.02
-    # loss terms and every gradient (lr = 0: parameters unchanged)
-    p_before = net.get("params")
-    losses = net.train_step(xd, dgd, ngd, mgd, lr=0.0)
-    L, parts, (gd, gn, gl) = N.losses(dp, npr, lp, dg, ng, mg)
-    assert abs(losses[0] - L) <= 0.02 * abs(L)
-    for a, b in zip(losses[1:], parts):
-        assert abs(a - b) <= 0.02 * abs(b) + 1e-6, (losses, parts)
-    G = N.backward(P, cache, gd, gn, gl)
-    Gb = N.backward(P, cache, bf16(gd), bf16(gn), bf16(gl))
-    Gg = net.get_dict("grads")
-    errs = {k: rel(Gg[k], G[k]) for k in G}
-    errs_b = {k: rel(Gg[k], Gb[k]) for k in G}
-    floor = {k: rel(Gb[k], G[k]) for k in G}
-    cos = {k: float(np.dot(Gg[k].ravel(), G[k].ravel()) /
-                    max(np.linalg.norm(Gg[k]) * np.linalg.norm(G[k]), 1e-30)) for k in G}
-    for k in sorted(errs, key=errs.get, reverse=True):
-        print(f"GRAD {k:18s} rel {errs[k]:.4f} rel_vs_bf16grad {errs_b[k]:.4f} "
-              f"floor {floor[k]:.4f} cos {cos[k]:.5f}")
-    # sensitivity of the oracle's own gradient to the forward error: oracle gradients from the
-    # GPU's forward outputs (normal directions and probabilities as the GPU produced them)
-    n_pert = n_gpu * np.linalg.norm(npr, axis=-1, keepdims=True)
-    l_pert = np.log(np.clip(p_gpu, 1e-7, 1 - 1e-7) / np.clip(1 - p_gpu, 1e-7, 1))
-    _, _, (gd2, gn2, gl2) = N.losses(d_gpu.astype(np.float64), n_pert, l_pert, dg, ng, mg)
-    Gs = N.backward(P, cache, gd2, gn2, gl2)
-    sens = {k: rel(Gs[k], G[k]) for k in G}
-    for k in sorted(errs, key=errs.get, reverse=True)[:20]:
-        print(f"SENS {k:18s} rel {errs[k]:.4f} oracle-from-gpu-forward {sens[k]:.4f}")
-    bad = {k: (errs[k], sens[k], cos[k]) for k in G
-           if not (errs[k] <= 0.06 + sens[k] and cos[k] >= 0.995)}
-    assert not bad, bad
-    # parameters untouched at lr = 0
-    assert np.array_equal(net.get("params"), p_before)
+    x, dg, ng, mg = batch(5, n=n, h=h, w=h)
+    gpu = gpu_outputs(net, x, dg, ng, mg)
     net.close()
+    nom = oracle_outputs(P, x, dg, ng, mg)
+    s = rounding_spread(P, x, dg, ng, mg, nom, K=8, seed=11)
+    check_elementwise(gpu, nom, s, f"{n}x{h}^2")
+
+
+def test_forward_batch4_full_size_elementwise(pe, ctx):
+    net = pe.Densifier(ctx, base=32, seed=3)
+    P = oracle_params(net)
+    x, dg, ng, mg = batch(6, n=4, h=256, w=256)
+    gpu = gpu_outputs(net, x, dg, ng, mg, grads=False)
+    net.close()
+    nom = oracle_outputs(P, x, dg, ng, mg, grads=False)
+    s = rounding_spread(P, x, dg, ng, mg, nom, K=6, seed=12, grads=False)
+    check_elementwise(gpu, nom, s, "4x256^2 forward")
 
 
 def test_adamw_step_matches_oracle(pe, ctx):
