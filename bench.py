@@ -153,99 +153,151 @@ def cpu_baseline(sc, sw, n_az, sample_px, gpu_rcs, seed=11):
                 accuracy=accuracy)
 
 
-def serving(pe, ctx, seconds, n_scenes=8, seed=5, log=None):
-    """Continuous-batching server under the request mix of the serving workload: scenes drawn
-    from a resident pool (composite generator, N log-uniform in [5e4, 4e6]), screens uniform in
-    {256, 512, 1024, 2048}^2, angle counts log-uniform in [1, 720], frequency counts log-uniform
-    in [1, 128] (2-12 GHz), 1-5 bounces.  Phase 1 submits a closed batch of requests at once
-    (saturation: solves/s and work/s the GPU sustains); phase 2 offers Poisson arrivals for
-    `seconds` at 70 % of the saturated work rate and reports latency percentiles from submit
-    to completion.  Work per request follows a cost model, pixels x angles x (bounces +
-    frequencies / 16), whose mean over the mix is estimated from 20000 draws; the request
-    sizes span five orders of magnitude, so a rate set from request counts alone would offer a
-    load that depends on which few large requests the saturation sample happened to hold."""
+def _latency_classes(done):
+    """p50 / p99 / count of submit-to-completion latency per screen-size class and overall;
+    done: list of (screen, latency ms)."""
     import numpy as np
+    out = {}
+    for cls in scenes_mod().SERVING_SCREENS + (None,):
+        v = np.array([ms for sc, ms in done if cls is None or sc == cls])
+        if len(v):
+            out["all" if cls is None else f"{cls}^2"] = dict(
+                n=int(len(v)), p50_ms=float(np.percentile(v, 50)),
+                p99_ms=float(np.percentile(v, 99)))
+    return out
+
+
+def scenes_mod():
     import scenes
+    return scenes
+
+
+def serving(pe, ctx, seconds, n_scenes=64, seed=5, log=None, budget_8gb_seconds=0.0):
+    """Continuous-batching server under the serving workload's request mix: a resident pool of
+    n_scenes composite scenes (N log-uniform in [5e4, 4e6]), screens uniform in {256, 512, 1024,
+    2048}^2, angle counts log-uniform in [1, 720], frequency counts log-uniform in [1, 128]
+    (2-12 GHz), 1-5 bounces, every request traced against every splat.  Phase 1 submits a closed
+    batch of 64 requests at once (saturation: solves/s and work/s the GPU sustains); phase 2
+    offers Poisson arrivals for `seconds` at 70 % of the saturated work rate and reports latency
+    percentiles from submit to completion, overall and per screen-size class.  Phase 3 (when
+    budget_8gb_seconds > 0) repeats phase 2's offered load in a context limited to 8 GiB with the
+    part of the pool that fits in 1.5 GiB, so admission by footprint serialises the large
+    requests.  Work per request follows a cost model, pixels x angles x (bounces + frequencies
+    / 16), whose mean over the mix is estimated from 20000 draws; the request sizes span five
+    orders of magnitude, so a rate set from request counts alone would offer a load that
+    depends on which few large requests the saturation sample happened to hold."""
+    import numpy as np
+    scenes = scenes_mod()
     rng = np.random.default_rng(seed)
-    pool = []
-    for i in range(n_scenes):
-        n = int(np.exp(rng.uniform(np.log(5e4), np.log(4e6))))
-        sc = scenes.composite(seed=1000 + i, n_points=n)
-        pool.append((sc, pe.Scene.from_scene(ctx, sc, view_res=1024)))
+    t_pool = time.perf_counter()
+    sizes = scenes.serving_pool_sizes(n_scenes, seed)
+    pool_sc, pool = [], []
+    for i, n in enumerate(sizes):
+        sc = scenes.serving_scene(i, n)
+        pool_sc.append(sc)
+        pool.append(pe.Scene.from_scene(ctx, sc, view_res=1024))
+    pool_bytes = ctx.footprint()[0]
+    t_pool = time.perf_counter() - t_pool
     if log:
-        log(f"serving pool: {[sc.n for sc, _ in pool]} points")
+        log(f"serving pool: {len(pool)} scenes, {sum(sizes) / 1e6:.1f}M points, "
+            f"{pool_bytes / 2**30:.2f} GiB resident ({t_pool:.1f} s)")
 
-    def request():
-        sc, s = pool[int(rng.integers(len(pool)))]
-        screen = int(rng.choice([256, 512, 1024, 2048]))
-        n_ang = int(np.exp(rng.uniform(0.0, np.log(720.0))))
-        n_f = int(np.exp(rng.uniform(0.0, np.log(128.0))))
-        az = (rng.uniform(0, 360) + np.arange(n_ang) * (360.0 / n_ang)) % 360.0
-        inc = scenes.azimuth_sweep(az, 30.0)
-        freq = np.linspace(2e9, 12e9, n_f)
-        eps = max(0.5 * float(sc.radius), 6.0 * sc.noise_sigma)
-        B = int(rng.integers(1, 6))
-        return s, inc, freq, screen, B, eps
+    def submit(c, scene_list, r):
+        return pe.submit(c, scene_list[r["scene"]], r["inc_dir"], r["freq_hz"], r["screen"],
+                         max_bounces=r["max_bounces"], eps=r["eps"], secondary="splats")
 
-    def submit(r):
-        s, inc, freq, screen, B, eps = r
-        return pe.submit(ctx, s, inc, freq, screen, max_bounces=B, eps=eps)
-
-    def work(screen, n_ang, n_f, B):
-        return float(screen) ** 2 * n_ang * (B + n_f / 16.0)
+    def work(r):
+        return float(r["screen"]) ** 2 * len(r["inc_dir"]) * (r["max_bounces"] +
+                                                              len(r["freq_hz"]) / 16.0)
 
     mrng = np.random.default_rng(seed + 1)
-    mean_work = float(np.mean([work(mrng.choice([256, 512, 1024, 2048]),
-                                    int(np.exp(mrng.uniform(0.0, np.log(720.0)))),
-                                    int(np.exp(mrng.uniform(0.0, np.log(128.0)))),
-                                    int(mrng.integers(1, 6))) for _ in range(20000)]))
+    mean_work = float(np.mean([work(scenes.serving_request(mrng, pool_sc))
+                               for _ in range(20000)]))
 
     # phase 1: saturation
-    reqs = [request() for _ in range(64)]
+    reqs = [scenes.serving_request(rng, pool_sc) for _ in range(64)]
     pe.server_stats(ctx, reset=True)
     t0 = time.perf_counter()
-    ts = [submit(r) for r in reqs]
+    ts = [submit(ctx, pool, r) for r in reqs]
     samples = 0
     for t, r in zip(ts, reqs):
         t.wait()
-        samples += len(r[1]) * len(r[2])
+        samples += len(r["inc_dir"]) * len(r["freq_hz"])
     dt = time.perf_counter() - t0
     cap = len(reqs) / dt
-    work_rate = sum(work(r[3], len(r[1]), len(r[2]), r[4]) for r in reqs) / dt
+    work_rate = sum(work(r) for r in reqs) / dt
     sat = pe.server_stats(ctx, reset=True)
     if log:
         log(f"serving saturation: {len(reqs)} requests in {dt:.2f} s ({cap:.2f} solves/s)")
+
+    def poisson(c, scene_list, draw, rate, window, tag):
+        arrivals = []
+        t = 0.0
+        while t < window:
+            t += rng.exponential(1.0 / rate)
+            arrivals.append(t)
+        rs = [draw() for _ in arrivals]
+        pe.server_stats(c, reset=True)
+        t0 = time.perf_counter()
+        ts = []
+        next_log = 15.0
+        for a, r in zip(arrivals, rs):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            ts.append(submit(c, scene_list, r))
+            if log and now > next_log:
+                log(f"serving {tag}: {len(ts)} submitted at {now:.0f} s")
+                next_log += 15.0
+        done = []
+        for t, r in zip(ts, rs):
+            _, _, st = t.wait()
+            done.append((r["screen"], st["time_ms"]))
+        st = pe.server_stats(c, reset=True)
+        return dict(offered_rate_per_s=rate, requests=len(ts), completed=st["completed"],
+                    window_s=time.perf_counter() - t0, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                    mean_ms=st["mean_ms"], max_concurrent=st["max_concurrent"],
+                    reqs_per_batch=st["reqs_per_batch"], by_screen=_latency_classes(done))
+
     # phase 2: Poisson arrivals offering 70 % of the saturated work rate
     rate = 0.7 * work_rate / mean_work
-    arrivals = []
-    t = 0.0
-    while t < seconds:
-        t += rng.exponential(1.0 / rate)
-        arrivals.append(t)
-    reqs = [request() for _ in arrivals]
-    t0 = time.perf_counter()
-    ts = []
-    for a, r in zip(arrivals, reqs):
-        now = time.perf_counter() - t0
-        if a > now:
-            time.sleep(a - now)
-        ts.append(submit(r))
-    for t in ts:
-        t.wait()
-    dt2 = time.perf_counter() - t0
-    st = pe.server_stats(ctx, reset=True)
-    for _, s in pool:
+    full = poisson(ctx, pool, lambda: scenes.serving_request(rng, pool_sc), rate, seconds,
+                   "full HBM")
+    if log:
+        log(f"serving full HBM: {full['requests']} requests, p50 {full['p50_ms']:.0f} ms, "
+            f"p99 {full['p99_ms']:.0f} ms")
+    for s in pool:
         s.close()
-    return dict(saturation_solves_per_s=cap, saturation_rcs_samples_per_s=samples / dt,
-                saturation_reqs_per_batch=sat["reqs_per_batch"],
-                offered_rate_per_s=rate, requests=len(ts), completed=st["completed"],
-                p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
-                max_concurrent=st["max_concurrent"], reqs_per_batch=st["reqs_per_batch"],
-                window_s=dt2, capacity_for_mix_per_s=work_rate / mean_work,
-                note="workload request mix (scene pool of %d); Poisson arrivals offering 70%% of "
-                     "the saturated work rate (cost model pixels x angles x (bounces + freqs/16)); "
-                     "200 req/s of this mix is %.0fx one GPU's capacity"
-                     % (len(pool), 200.0 * mean_work / work_rate))
+    out = dict(pool_scenes=len(pool), pool_points=int(sum(sizes)), pool_gib=pool_bytes / 2**30,
+               saturation_solves_per_s=cap, saturation_rcs_samples_per_s=samples / dt,
+               saturation_reqs_per_batch=sat["reqs_per_batch"],
+               capacity_for_mix_per_s=work_rate / mean_work, full_hbm=full)
+    # phase 3: the same offered load under an 8 GiB budget
+    if budget_8gb_seconds > 0:
+        c8 = pe.Context(0, budget=8 << 30)
+        sub_sc, sub = [], []
+        for sc in pool_sc:
+            s = pe.Scene.from_scene(c8, sc, view_res=1024)
+            if c8.footprint()[0] > 1.5 * 2**30:
+                s.close()
+                continue
+            sub_sc.append(sc)
+            sub.append(s)
+        b8 = poisson(c8, sub, lambda: scenes.serving_request(rng, sub_sc), rate,
+                     budget_8gb_seconds, "8 GiB")
+        b8["pool_scenes"] = len(sub)
+        if log:
+            log(f"serving 8 GiB: {b8['requests']} requests, p50 {b8['p50_ms']:.0f} ms, "
+                f"p99 {b8['p99_ms']:.0f} ms, max concurrent {b8['max_concurrent']:.0f}")
+        for s in sub:
+            s.close()
+        c8.close()
+        out["budget_8gib"] = b8
+    out["note"] = ("serving request mix (scene pool of %d); Poisson arrivals offering 70%% of the "
+                   "saturated work rate (cost model pixels x angles x (bounces + freqs/16)); "
+                   "200 req/s of this mix is %.0fx one GPU's capacity"
+                   % (len(pool), 200.0 * mean_work / work_rate))
+    return out
 
 
 # Dense MFMA flops of one densifier forward pass at base 32 from a coarse h x w input
@@ -382,8 +434,11 @@ def main():
                     help="pixel rays traced by the brute-force oracle")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="Poisson serving window (0 = skip the serving measurement)")
+    ap.add_argument("--serve-8gb-seconds", type=float, default=20.0,
+                    help="Poisson window of the same load under an 8 GiB budget (0 = skip)")
+    ap.add_argument("--serve-scenes", type=int, default=64, help="serving scene pool size")
     ap.add_argument("--no-densifier", action="store_true")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the fusion / OctAR / bistatic / finite-K / PCA-normals timings")
@@ -549,7 +604,9 @@ def main():
     out["next_rows"] = None if args.no_next_rows else next_rows(pe, ctx, sc, xyz, nrm, sw.view_res,
                                                                       log=log)
     out["densifier"] = None if args.no_densifier else densifier_bench(pe, ctx, log=log)
-    out["serving"] = serving(pe, ctx, args.serve_seconds, log=log) if args.serve_seconds > 0 else None
+    out["serving"] = (serving(pe, ctx, args.serve_seconds, n_scenes=args.serve_scenes, log=log,
+                              budget_8gb_seconds=args.serve_8gb_seconds)
+                      if args.serve_seconds > 0 else None)
     if args.cpu_az > 0:
         log("CPU oracle leg ...")
         out["cpu_baseline"] = cpu_baseline(sc, sw, args.cpu_az, args.cpu_sample, gpu_rcs)

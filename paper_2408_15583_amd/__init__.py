@@ -526,10 +526,10 @@ def server_stats(ctx: Context, reset=False):
 
 
 def request_footprint(inc_dir, freq_hz, screen, max_bounces=1, eps=0.0, obs_dir=None,
-                      contrib="last", precision="fp64phase"):
+                      contrib="last", precision="fp64phase", secondary="views"):
     """HBM bytes the server charges a request for admission."""
     d, keep = make_solve_desc(inc_dir, freq_hz, screen, max_bounces, eps, obs_dir, contrib,
-                              precision)
+                              precision, secondary=secondary)
     b = ctypes.c_uint64()
     check(lib().pe_request_footprint(ctypes.byref(d), ctypes.byref(b)))
     del keep

@@ -71,8 +71,10 @@ uint64_t batch_bytes_per_pixel(const pe_solve_desc* d) {
     const uint64_t n_obs = d->obs_dir ? d->n_obs : 1;
     const uint64_t seg = d->contrib == PE_CONTRIB_EVERY ? d->max_bounces : 1;
     // ray state, depth, bounce count, hit index, three lists, alive flag, hit key, first-hit key,
-    // compaction counts, exit records
-    return RNCOMP * 4 + 8 + 1 + 4 + 12 + 1 + 8 + 8 + 8 + seg * n_obs * 40;
+    // compaction counts, exit records; against every splat also the visibility pass's facet
+    // list and its per-observation flags
+    const uint64_t vis = d->secondary == PE_SECONDARY_SPLATS ? 4 + n_obs : 0;
+    return RNCOMP * 4 + 8 + 1 + 4 + 12 + 1 + 8 + 8 + 8 + seg * n_obs * 40 + vis;
 }
 
 int slots_per_batch(pe_ctx ctx, const pe_solve_desc* d) {

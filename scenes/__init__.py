@@ -511,3 +511,38 @@ def workload_sphere(n_points: int = 4_000_000, n_az: int = 360, screen: int = 10
     sw = Sweep(inc_dir=azimuth_sweep(az, 0.0), freq_hz=np.linspace(2e9, 24e9, n_freq),
                screen=screen, max_bounces=4, eps=eps, view_res=screen, az_deg=az, el_deg=0.0)
     return sc, sw
+
+
+# ------------------------------------------------------------------------------ serving mix --
+
+SERVING_SCREENS = (256, 512, 1024, 2048)
+
+
+def serving_pool_sizes(n_scenes: int = 64, seed: int = 5) -> list[int]:
+    """Point counts of the serving workload's scene pool, log-uniform in [5e4, 4e6]."""
+    rng = _rng(seed)
+    return [int(np.exp(rng.uniform(np.log(5e4), np.log(4e6)))) for _ in range(n_scenes)]
+
+
+def serving_scene(i: int, n_points: int) -> Scene:
+    """Scene i of the serving pool: the composite generator at n_points."""
+    return composite(seed=1000 + i, n_points=n_points)
+
+
+def serving_request(rng: np.random.Generator, pool: list, screens=SERVING_SCREENS,
+                    max_angles: int = 720, max_freqs: int = 128) -> dict:
+    """One request of the serving mix: a scene index into `pool` (a list of Scene), a screen
+    uniform over `screens`, an angle count log-uniform in [1, 720] (monostatic azimuths at 30
+    deg elevation, evenly spaced from a random start), a frequency count log-uniform in [1, 128]
+    (2-12 GHz) and 1-5 bounces.  max_angles / max_freqs cap the counts after they are drawn, so
+    the same rng yields the same scenes, screens and bounce limits with or without a cap."""
+    i = int(rng.integers(len(pool)))
+    sc = pool[i]
+    screen = int(rng.choice(screens))
+    n_ang = int(np.exp(rng.uniform(0.0, np.log(720.0))))
+    n_f = int(np.exp(rng.uniform(0.0, np.log(128.0))))
+    az = (rng.uniform(0, 360) + np.arange(min(n_ang, max_angles)) * (360.0 / n_ang)) % 360.0
+    return dict(scene=i, inc_dir=azimuth_sweep(az, 30.0),
+                freq_hz=np.linspace(2e9, 12e9, min(n_f, max_freqs)), screen=screen,
+                max_bounces=int(rng.integers(1, 6)),
+                eps=max(0.5 * float(sc.radius), 6.0 * sc.noise_sigma))

@@ -3,7 +3,12 @@
 A request's field must be bitwise identical whether solved alone (pe_solve) or packed into
 shared launches with other requests (different scenes, screens, frequency sets, bounce
 limits); admission must respect the context's HBM budget; cancellation and time-outs are
-forced from the host.
+forced from the host.  On the serving mix itself (scenes.serving_request: composite scenes of
+5e4-4e6 points, 256^2-2048^2 screens, 1-5 bounces, every splat as bounce geometry): two requests
+served inside a mixed batch match the exact oracle (0.1 dB in the 30 dB window, or twice the
+sample's spread under fp32 rounding of the oracle's inputs where that is larger), and under an
+8 GiB budget every request completes, the context never holds more than its budget, and the
+results are those of the unconstrained context.
 """
 import numpy as np
 import pytest
@@ -151,3 +156,121 @@ def test_scene_destroy_refused_while_requests_hold_it(pe, ctx):
     t2 = pe.submit(ctx, s2, many, f, 512, max_bounces=2, eps=0.5 * sc.radius)
     del t2
     s2.close()
+
+
+def test_mixed_batch_vs_exact_oracle(pe, ctx):
+    """Two requests on the serving generator's smallest scenes (24 azimuths, 8 frequencies, 2
+    and 3 bounces, 256^2) submitted among four other serving-mix requests so that they share
+    launches, each against the exact oracle, and bitwise equal to the same request solved alone."""
+    import oracle
+    from rcs_bars import conditioned_errors, ensemble, report
+    pool_sc = [scenes.serving_scene(0, 50_000), scenes.serving_scene(1, 80_000)]
+    pool = [pe.Scene.from_scene(ctx, sc, view_res=1024) for sc in pool_sc]
+    rng = np.random.default_rng(17)
+    mates = [scenes.serving_request(rng, pool_sc, screens=(256, 512), max_angles=16,
+                                    max_freqs=16) for _ in range(4)]
+    checked = []
+    for i, B in ((0, 3), (1, 2)):
+        sc = pool_sc[i]
+        checked.append(dict(scene=i, inc_dir=scenes.azimuth_sweep(np.arange(24) * 15.0 + 3.0, 30.0),
+                            freq_hz=np.linspace(2e9, 12e9, 8), screen=256, max_bounces=B,
+                            eps=max(0.5 * float(sc.radius), 6.0 * sc.noise_sigma)))
+    reqs = [mates[0], checked[0], mates[1], mates[2], checked[1], mates[3]]
+
+    def args(r):
+        return (pool[r["scene"]], r["inc_dir"], r["freq_hz"], r["screen"])
+
+    def kw(r):
+        return dict(max_bounces=r["max_bounces"], eps=r["eps"], secondary="splats")
+
+    pe.server_stats(ctx, reset=True)
+    ts = [pe.submit(ctx, *args(r), **kw(r)) for r in reqs]
+    res = [t.wait(timeout_s=300) for t in ts]
+    st = pe.server_stats(ctx, reset=True)
+    assert st["reqs_per_batch"] > 1.0
+    for r, (E, rcs, _) in zip(reqs, res):
+        if not any(r is c for c in checked):
+            assert np.isfinite(E).all()
+            continue
+        E0, r0, _ = pe.solve(ctx, *args(r), **kw(r))
+        assert np.array_equal(E, E0) and np.array_equal(rcs, r0)
+        sc = pool_sc[r["scene"]]
+        o = oracle.OracleScene(sc, grid=256)
+        a = (r["inc_dir"], r["freq_hz"], r["screen"], r["screen"], r["max_bounces"], r["eps"])
+        ro = oracle.rcs_dbsm(o.solve(*a)[0])
+        r_ens = [oracle.rcs_dbsm(oe.solve(*a)[0]) for oe in ensemble(sc, seeds=range(1, 9))]
+        e, spread = conditioned_errors(rcs, ro, r_ens)
+        tag = f"SERVE mixed batch, {sc.n} points, B={r['max_bounces']}"
+        report(tag + " vs exact oracle", e)
+        report(tag + " fp32-input spread of the oracle", spread)
+        bar = np.maximum(0.1, 2.0 * spread)
+        for j in np.nonzero(e > bar)[0]:
+            print(f"{tag}: sample {j} error {e[j]:.3f} dB, spread {spread[j]:.3f} dB")
+        assert (e <= bar).all()
+    for s in pool:
+        s.close()
+
+
+def test_admission_8gib_serving_mix(pe, ctx):
+    """Serving-mix requests (angle counts capped at 12 to bound the run) on the first pool scenes
+    that fit 1.5 GiB, in a context limited to 8 GiB: the largest requests cannot share the budget
+    with each other, the small ones can; all complete, the context's footprint (polled while they
+    run) never exceeds the budget, and three results equal solves in the unconstrained context."""
+    import threading
+    import time
+    budget = 8 << 30
+    c8 = pe.Context(0, budget=budget)
+    pool_sc, pool = [], []
+    for i, n in enumerate(scenes.serving_pool_sizes(64, 5)[:8]):
+        sc = scenes.serving_scene(i, n)
+        s = pe.Scene.from_scene(c8, sc, view_res=1024)
+        if c8.footprint()[0] > 1.5 * 2**30:
+            s.close()
+            continue
+        pool_sc.append(sc)
+        pool.append(s)
+    assert len(pool) >= 2
+    rng = np.random.default_rng(23)
+    reqs = [scenes.serving_request(rng, pool_sc, max_angles=12, max_freqs=32) for _ in range(16)]
+    fps = [pe.request_footprint(r["inc_dir"], r["freq_hz"], r["screen"],
+                                max_bounces=r["max_bounces"], eps=r["eps"], secondary="splats")
+           for r in reqs]
+    free = budget - c8.footprint()[0]
+    big = sorted(fps)[-2:]
+    print(f"SERVE 8 GiB: {len(pool)} scenes ({(budget - free) / 2**30:.2f} GiB), request "
+          f"footprints {min(fps) / 2**20:.0f} .. {max(fps) / 2**20:.0f} MiB")
+    assert big[0] + big[1] > free and 2 * min(fps) < free
+    peak = [0]
+    stop = threading.Event()
+
+    def poll():
+        while not stop.is_set():
+            peak[0] = max(peak[0], c8.footprint()[0])
+            time.sleep(0.001)
+
+    th = threading.Thread(target=poll)
+    th.start()
+    pe.server_stats(c8, reset=True)
+    try:
+        ts = [pe.submit(c8, pool[r["scene"]], r["inc_dir"], r["freq_hz"], r["screen"],
+                        max_bounces=r["max_bounces"], eps=r["eps"], secondary="splats")
+              for r in reqs]
+        res = [t.wait(timeout_s=600) for t in ts]
+    finally:
+        stop.set()
+        th.join()
+    st = pe.server_stats(c8, reset=True)
+    print(f"SERVE 8 GiB: peak footprint {peak[0] / 2**30:.2f} GiB, max concurrent "
+          f"{st['max_concurrent']:.0f}, p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms")
+    assert st["completed"] == len(reqs)
+    assert peak[0] <= budget
+    assert st["max_concurrent"] >= 2
+    for r, (E, _, _) in list(zip(reqs, res))[:3]:
+        s_full = pe.Scene.from_scene(ctx, pool_sc[r["scene"]], view_res=1024)
+        E0, _, _ = pe.solve(ctx, s_full, r["inc_dir"], r["freq_hz"], r["screen"],
+                            max_bounces=r["max_bounces"], eps=r["eps"], secondary="splats")
+        s_full.close()
+        assert np.array_equal(E, E0)
+    for s in pool:
+        s.close()
+    c8.close()
