@@ -190,13 +190,14 @@ def serving(pe, ctx, seconds, n_scenes=64, seed=5, log=None, budget_8gb_seconds=
     scenes = scenes_mod()
     rng = np.random.default_rng(seed)
     t_pool = time.perf_counter()
+    held0 = ctx.footprint()[0]
     sizes = scenes.serving_pool_sizes(n_scenes, seed)
     pool_sc, pool = [], []
     for i, n in enumerate(sizes):
         sc = scenes.serving_scene(i, n)
         pool_sc.append(sc)
         pool.append(pe.Scene.from_scene(ctx, sc, view_res=1024))
-    pool_bytes = ctx.footprint()[0]
+    pool_bytes = ctx.footprint()[0] - held0
     t_pool = time.perf_counter() - t_pool
     if log:
         log(f"serving pool: {len(pool)} scenes, {sum(sizes) / 1e6:.1f}M points, "
