@@ -352,6 +352,86 @@ def densifier_bench(pe, ctx, batch=8, h=256, steps=10, log=None):
                 note="dense-conv flops of the network / wall time (whole pass incl. VALU layers)")
 
 
+def densifier_claim(pe, ctx, train_steps=1500, log=None):
+    """Densified against plain solves at the densifier workload (coarse 256^2 -> 512^2,
+    composite scenes of 1e5-5e5 points): a network trained here for a short schedule on
+    8 x 48 GPU-made pairs, then, on two held-out scenes (18 azimuths at 30 deg x 16 frequencies,
+    single bounce), the RCS error of each solve form against the plain 512^2 first-hit trace
+    (RMSE in dB of the co-polar channels within 30 dB of each curve's peak) and its solves/s.
+    Forms: densified (network alone, no fallback), plain at 512^2 in fp32 phase and sum (the
+    mixed-precision form), and plain at 256^2 and 128^2 (cheaper plain solves whose error
+    brackets the densified one)."""
+    import numpy as np
+    import torch
+    import scenes
+    from paper_2408_15583_amd import train_densifier as T
+    t0 = time.perf_counter()
+    data = T.make_dataset(pe, ctx, n_scenes=8, views=48, h=256, seed=11, n_lo=100_000,
+                          n_hi=500_000)
+    net = pe.Densifier(ctx, base=32, seed=5)
+    hist = T.train(net, data, steps=train_steps, batch=8, lr0=1e-3, decay_every=500, seed=5)
+    del data
+    t_train = time.perf_counter() - t0
+    if log:
+        log(f"densifier claim: trained {train_steps} steps in {t_train:.1f} s, loss "
+            f"{np.mean([h[0] for h in hist[:50]]):.3f} -> {np.mean([h[0] for h in hist[-50:]]):.3f}")
+    rng = np.random.default_rng(1234)
+    az = np.arange(0, 360, 20.0)
+    freqs = np.linspace(2e9, 12e9, 16)
+    forms = {"densified_512": dict(screen=512, densifier=net, max_uncertain=1.0),
+             "plain_512_fp32": dict(screen=512, precision="fp32"),
+             "plain_256": dict(screen=256), "plain_128": dict(screen=128)}
+    err = {k: [] for k in forms}
+    ms = {k: [] for k in list(forms) + ["plain_512"]}
+
+    def timed(s, inc, kw):
+        kw = dict(kw)
+        screen = kw.pop("screen")
+        pe.solve(ctx, s, inc, freqs, screen, **kw)  # untimed first call
+        best = 1e30
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = pe.solve(ctx, s, inc, freqs, screen, **kw)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return out[1], best * 1e3
+
+    for i in range(2):
+        n = int(rng.integers(100_000, 500_001))
+        sc = scenes.composite(seed=int(rng.integers(1 << 30)), n_points=n)
+        s = pe.Scene.from_scene(ctx, sc, view_res=256)
+        inc = scenes.azimuth_sweep(az, 30.0)
+        ref, t_ref = timed(s, inc, dict(screen=512))
+        ms["plain_512"].append(t_ref)
+        for k, kw in forms.items():
+            r, t = timed(s, inc, kw)
+            err[k].append(T.rmse_db(r, ref))
+            ms[k].append(t)
+        s.close()
+    net.close()
+    out = {"plain_512": dict(rmse_db=0.0, ms=float(np.mean(ms["plain_512"])),
+                             solves_per_s=1e3 / float(np.mean(ms["plain_512"])))}
+    for k in forms:
+        out[k] = dict(rmse_db=float(np.mean(err[k])), ms=float(np.mean(ms[k])),
+                      solves_per_s=1e3 / float(np.mean(ms[k])))
+    d = out["densified_512"]
+    cheaper = [k for k in ("plain_128", "plain_256", "plain_512_fp32", "plain_512")
+               if out[k]["rmse_db"] <= d["rmse_db"] and out[k]["solves_per_s"] >= d["solves_per_s"]]
+    out["densified_beats_plain_at_equal_error"] = not cheaper
+    out["plain_forms_at_least_as_accurate_and_fast"] = cheaper
+    out["fp32_beats_plain_at_equal_error"] = bool(
+        out["plain_512_fp32"]["rmse_db"] <= 0.01 and
+        out["plain_512_fp32"]["solves_per_s"] > out["plain_512"]["solves_per_s"])
+    out["train_s"] = t_train
+    out["note"] = ("solve = 18 incidences x 16 frequencies, single bounce, on held-out scenes; "
+                   "errors vs the plain 512^2 trace")
+    if log:
+        log("densifier claim: " + ", ".join(f"{k} {v['rmse_db']:.2f} dB {v['solves_per_s']:.0f}/s"
+                                            for k, v in out.items() if isinstance(v, dict)))
+    return out
+
+
 def next_rows(pe, ctx, sc, xyz_dev, nrm_dev, view_res, log=None):
     """One timed call of each extension row beside the hot path (GPU wall time, the device
     synchronised on both sides; one untimed call first): learned-GFB fusion on the synthetic
@@ -441,6 +521,8 @@ def main():
                     help="Poisson window of the same load under an 8 GiB budget (0 = skip)")
     ap.add_argument("--serve-scenes", type=int, default=64, help="serving scene pool size")
     ap.add_argument("--no-densifier", action="store_true")
+    ap.add_argument("--claim-steps", type=int, default=1500,
+                    help="training steps of the densified-vs-plain comparison (0 = skip)")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the fusion / OctAR / bistatic / finite-K / PCA-normals timings")
     args = ap.parse_args()
@@ -605,6 +687,9 @@ def main():
     out["next_rows"] = None if args.no_next_rows else next_rows(pe, ctx, sc, xyz, nrm, sw.view_res,
                                                                       log=log)
     out["densifier"] = None if args.no_densifier else densifier_bench(pe, ctx, log=log)
+    if not args.no_densifier and args.claim_steps > 0:
+        out["densifier"]["vs_plain"] = densifier_claim(pe, ctx, train_steps=args.claim_steps,
+                                                       log=log)
     out["serving"] = (serving(pe, ctx, args.serve_seconds, n_scenes=args.serve_scenes, log=log,
                               budget_8gb_seconds=args.serve_8gb_seconds)
                       if args.serve_seconds > 0 else None)
