@@ -376,6 +376,24 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
         for (int l = L - 1; l >= 0; l--)
             launch_bvh_box(finfo[l], cnt[l], base[l], sc->pa_s, sc->pb_s, pad, sc->bvh, st);
         HIPCHK(hipGetLastError());
+        // wide records: internal nodes numbered in node order, leaf points in record order
+        const uint32_t nn = (uint32_t)sc->bvh_nodes;
+        uint32_t* is_int = (uint32_t*)tmp.get(4ull * nn);
+        uint32_t* leafpts = (uint32_t*)tmp.get(4ull * nn);
+        uint32_t* rec = (uint32_t*)tmp.get(4ull * nn + 4);
+        uint32_t* lbase = (uint32_t*)tmp.get(4ull * nn + 4);
+        uint32_t* scr = (uint32_t*)tmp.get(4ull * scan_wide_scratch(nn));
+        launch_wide_count(sc->bvh, nn, is_int, leafpts, st);
+        launch_scan_wide(is_int, rec, nn, nullptr, 1, rec + nn, scr, st);
+        launch_scan_wide(leafpts, lbase, nn, nullptr, 1, lbase + nn, scr, st);
+        uint32_t n_rec = 0;
+        HIPCHK(hipMemcpyAsync(&n_rec, rec + nn, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        sc->w_root_pts = n_rec == 0 ? (uint32_t)n : 0u;  // no internal node: the root is a leaf
+        sc->wrec = (uint4*)sc->alloc(std::max<uint64_t>(n_rec, 1) * kWideRec * 16);
+        sc->wpts = (float4*)sc->alloc(n * 32);
+        launch_wide_emit(sc->bvh, nn, rec, lbase, sc->pa_s, sc->pb_s, sc->wrec, sc->wpts, st);
+        HIPCHK(hipGetLastError());
     }
 
     // aggregation views

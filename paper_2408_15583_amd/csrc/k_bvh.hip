@@ -165,6 +165,130 @@ void launch_bvh_box(const uint2* finfo, uint32_t n_nodes, uint32_t base, const f
                        pad, nodes);
 }
 
+__global__ __launch_bounds__(256) void k_wide_count(const float4* __restrict__ nodes,
+                                                    uint32_t n_nodes, uint32_t* __restrict__ is_int,
+                                                    uint32_t* __restrict__ leafpts) {
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes;
+         g += gridDim.x * blockDim.x) {
+        const uint32_t first = __float_as_uint(nodes[2 * (uint64_t)g].w);
+        const uint32_t info = __float_as_uint(nodes[2 * (uint64_t)g + 1].w);
+        uint32_t pts = 0;
+        if (!(info & kBvhLeafBit)) {
+            const uint32_t nc = __popc(info & 0xFFu);
+            for (uint32_t c = 0; c < nc; c++) {
+                const uint32_t ci = __float_as_uint(nodes[2 * ((uint64_t)first + c) + 1].w);
+                if (ci & kBvhLeafBit) pts += ci & 0xFFFFFFu;
+            }
+        }
+        is_int[g] = (info & kBvhLeafBit) ? 0u : 1u;
+        leafpts[g] = pts;
+    }
+}
+
+void launch_wide_count(const float4* nodes, uint32_t n_nodes, uint32_t* is_int,
+                       uint32_t* leafpts, hipStream_t st) {
+    const uint32_t b = std::min<uint32_t>(65535u, (n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_wide_count, dim3(b), dim3(256), 0, st, nodes, n_nodes, is_int, leafpts);
+}
+
+// Outward 8-bit quantisation of one axis of a child box [clo, chi] in the frame (org, scale):
+// the planes org + q scale, evaluated in fp32 as the traversal evaluates them, enclose it.
+__device__ inline void quantise_axis(float org, float scale, float clo, float chi, uint32_t& qlo,
+                                     uint32_t& qhi) {
+    int a = (int)floorf((clo - org) / scale), b = (int)ceilf((chi - org) / scale);
+    a = min(max(a, 0), 255);
+    b = min(max(b, 0), 255);
+    while (a > 0 && org + (float)a * scale > clo) a--;
+    while (b < 255 && org + (float)b * scale < chi) b++;
+    qlo = (uint32_t)a;
+    qhi = (uint32_t)b;
+}
+
+__device__ inline void copy_points(const float4* __restrict__ pa_s,
+                                   const float4* __restrict__ pb_s, uint32_t first, uint32_t cnt,
+                                   float4* __restrict__ wpts, uint32_t dst) {
+    for (uint32_t i = 0; i < cnt; i++) {
+        wpts[2 * ((uint64_t)dst + i)] = pa_s[first + i];
+        wpts[2 * ((uint64_t)dst + i) + 1] = pb_s[first + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wide_emit(const float4* __restrict__ nodes,
+                                                   uint32_t n_nodes,
+                                                   const uint32_t* __restrict__ rec,
+                                                   const uint32_t* __restrict__ lbase,
+                                                   const float4* __restrict__ pa_s,
+                                                   const float4* __restrict__ pb_s,
+                                                   uint4* __restrict__ wrec,
+                                                   float4* __restrict__ wpts) {
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes;
+         g += gridDim.x * blockDim.x) {
+        const float4 lo = nodes[2 * (uint64_t)g], hi = nodes[2 * (uint64_t)g + 1];
+        const uint32_t first = __float_as_uint(lo.w), info = __float_as_uint(hi.w);
+        if (info & kBvhLeafBit) {
+            if (g == 0) copy_points(pa_s, pb_s, first, info & 0xFFFFFFu, wpts, 0);
+            continue;
+        }
+        // per-axis scale 2^e, the smallest power of two whose 255 steps from the low corner
+        // reach the high corner in fp32
+        const float org[3] = {lo.x, lo.y, lo.z}, top[3] = {hi.x, hi.y, hi.z};
+        float scale[3];
+        uint32_t eb[3];
+        for (int a = 0; a < 3; a++) {
+            const float ext = fmaxf(top[a] - org[a], 0.f);
+            int e = -100;
+            if (ext > 0.f) {
+                frexpf(ext / 255.f, &e);
+                e = max(e, -100);
+            }
+            while (e < 120 && org[a] + 255.f * ldexpf(1.f, e) < top[a]) e++;
+            scale[a] = ldexpf(1.f, e);
+            eb[a] = (uint32_t)(e + 127);
+        }
+        const uint32_t occ = info & 0xFFu, nc = __popc(occ);
+        uint32_t iocc = 0, counts = 0, off = 0, m = occ;
+        uint32_t q[6][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        for (uint32_t c = 0; c < nc; c++) {
+            const uint32_t o = __builtin_ctz(m);
+            m &= m - 1u;
+            const float4 clo = nodes[2 * ((uint64_t)first + c)];
+            const float4 chi = nodes[2 * ((uint64_t)first + c) + 1];
+            const uint32_t cinfo = __float_as_uint(chi.w);
+            if (cinfo & kBvhLeafBit) {
+                const uint32_t cnt = cinfo & 0xFFFFFFu;
+                counts |= cnt << (4 * o);
+                copy_points(pa_s, pb_s, __float_as_uint(clo.w), cnt, wpts, lbase[g] + off);
+                off += cnt;
+            } else {
+                iocc |= 1u << o;
+            }
+            const float cl[3] = {clo.x, clo.y, clo.z}, ch[3] = {chi.x, chi.y, chi.z};
+            const int w = o >> 2, sh = 8 * (o & 3);
+            for (int a = 0; a < 3; a++) {
+                uint32_t ql, qh;
+                quantise_axis(org[a], scale[a], cl[a], ch[a], ql, qh);
+                q[a][w] |= ql << sh;
+                q[3 + a][w] |= qh << sh;
+            }
+        }
+        uint4* r = wrec + (uint64_t)kWideRec * rec[g];
+        r[0] = make_uint4(__float_as_uint(org[0]), __float_as_uint(org[1]),
+                          __float_as_uint(org[2]), eb[0] | (eb[1] << 8) | (eb[2] << 16) | (occ << 24));
+        r[1] = make_uint4(rec[first], lbase[g], iocc, counts);
+        r[2] = make_uint4(q[0][0], q[0][1], q[1][0], q[1][1]);
+        r[3] = make_uint4(q[2][0], q[2][1], q[3][0], q[3][1]);
+        r[4] = make_uint4(q[4][0], q[4][1], q[5][0], q[5][1]);
+    }
+}
+
+void launch_wide_emit(const float4* nodes, uint32_t n_nodes, const uint32_t* rec,
+                      const uint32_t* lbase, const float4* pa_s, const float4* pb_s,
+                      uint4* wrec, float4* wpts, hipStream_t st) {
+    const uint32_t b = std::min<uint32_t>(65535u, (n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_wide_emit, dim3(b), dim3(256), 0, st, nodes, n_nodes, rec, lbase, pa_s,
+                       pb_s, wrec, wpts);
+}
+
 // Persistent traversal loop shared by the two passes: every lane holds one ray; a wavefront
 // takes new work items for its idle lanes from a global counter once at least `refill` of its
 // lanes are idle (all from one atomic, so the lanes of a batch are neighbouring items), and

@@ -3,12 +3,20 @@
 // lane.  Every point of the scene is reachable, so the result is the exact first hit of the
 // fp32 disk test over all disks (ties: lowest index), independent of traversal order.
 //
-// The hierarchy is an octree of the points' Morton codes (node records at kBvhLeaf in
-// pe_device.h).  Expanding a node tests its children's boxes and pushes ONE stack entry: the
-// first child's index, the octant mask and the mask of children still to visit, so the stack
-// holds at most one entry per level.  Children are visited front to back for the ray's
-// direction signs (octant order XOR the sign mask); once a hit is known, a popped child's box
-// is tested again against it.  Each lane's stack lives in LDS, laid out [depth][thread].
+// The hierarchy is the octree of the points' Morton codes (kBvhLeaf in pe_device.h), traversed
+// through its wide records (kWideRec): one 80-byte record per internal node holds the boxes of
+// all its children, quantised to 8 bits per plane relative to the node's own box and rounded
+// outward, so expanding a node is one memory round trip however many children it has.  Leaf
+// children are not records: their points sit consecutively in a leaf-ordered copy of the scene
+// (wpts), and the points of every hit leaf child of a node form one point group, tested four
+// points per round trip before the traversal descends further.
+//
+// Per lane the traversal keeps a node group (the record base of a node's internal children,
+// the mask of hit children still to visit in front-to-back rank order = octant XOR the ray's
+// sign mask, the octant mask of internal children) and a point group (base and 64-bit mask).
+// Descending into a child pushes the rest of the current node group, so the LDS stack holds at
+// most one u64 per level; a popped group is not culled again (its boxes were tested when its
+// parent was expanded, and the child's own children are tested against the current hit).
 #pragma once
 #include <float.h>
 
@@ -17,147 +25,176 @@
 
 namespace pe {
 
-struct BvhRay {
-    f3 o, inv;  // origin and reciprocal direction (components kept away from 0)
-    float tmin;
-};
-
 __device__ inline float safe_inv(float k) {
     return 1.f / (fabsf(k) > 1e-20f ? k : copysignf(1e-20f, k));
-}
-
-__device__ inline BvhRay bvh_ray(f3 o, f3 k, float tmin) {
-    return {o, mk3(safe_inv(k.x), safe_inv(k.y), safe_inv(k.z)), tmin};
-}
-
-// Slab test: near and far planes picked by the direction's sign.  Returns the entry parameter,
-// or FLT_MAX when the box misses [tmin, tmax].
-__device__ inline float box_enter(const BvhRay& r, float4 lo, float4 hi, float tmax) {
-    const float ax = ((r.inv.x >= 0.f ? lo.x : hi.x) - r.o.x) * r.inv.x;
-    const float bx = ((r.inv.x >= 0.f ? hi.x : lo.x) - r.o.x) * r.inv.x;
-    const float ay = ((r.inv.y >= 0.f ? lo.y : hi.y) - r.o.y) * r.inv.y;
-    const float by = ((r.inv.y >= 0.f ? hi.y : lo.y) - r.o.y) * r.inv.y;
-    const float az = ((r.inv.z >= 0.f ? lo.z : hi.z) - r.o.z) * r.inv.z;
-    const float bz = ((r.inv.z >= 0.f ? hi.z : lo.z) - r.o.z) * r.inv.z;
-    const float tn = fmaxf(fmaxf(ax, ay), az);
-    const float tf = fminf(fminf(bx, by), bz);
-    return (tn <= tf && tf >= r.tmin && tn <= tmax) ? tn : FLT_MAX;
 }
 
 __device__ inline float key_t(uint64_t key) {
     return key == kEmptyKey ? FLT_MAX : __uint_as_float((uint32_t)(key >> 32));
 }
 
-// Traversal state of one ray (one lane), advanced one node expansion per step so that a
-// wavefront can give finished lanes new rays while the others go on.
+__device__ inline uint4 gld(const uint4* p) {
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const v4u r = *(const __attribute__((address_space(1))) v4u*)p;
+    return make_uint4(r.x, r.y, r.z, r.w);
+}
+
+// Disk test of the traversal, written without early exits so that a batch of points can be
+// requested before the first test: the same arithmetic as disk_test (IEEE division, grazing
+// |n.k| < kGraze misses, t > tmin, inclusive boundary); FLT_MAX when the disk is missed.
+__device__ inline float disk_t(float4 a, float4 b, f3 o, f3 k, float tmin) {
+    const float den = b.x * k.x + b.y * k.y + b.z * k.z;
+    const f3 w = mk3(a.x - o.x, a.y - o.y, a.z - o.z);
+    const float tt = (b.x * w.x + b.y * w.y + b.z * w.z) / den;
+    const f3 q = k * tt - w;
+    const bool hit = fabsf(den) >= kGraze && tt > tmin && dot(q, q) <= a.w * a.w;
+    return hit ? tt : FLT_MAX;
+}
+
+// Traversal state of one ray (one lane), advanced one round trip per step so that a wavefront
+// can give finished lanes new rays while the others go on.
 struct BvhState {
-    BvhRay r;
-    f3 o, k;
+    f3 o, k, inv;          // origin, direction, reciprocal direction (kept away from 0)
+    float tmin;
     uint32_t dmask;        // octant bits of the negative direction components
     uint64_t key;          // best hit so far (packed t, index); any-hit: 0 once hit
     int sp;                // stack entries in use
-    uint32_t first, info;  // record fields of the node to expand next
+    uint32_t gbase, ghits, giocc;  // node group
+    uint32_t pbase;                // point group: wpts index of its first point
+    uint64_t pmask;                //   and the points still to test
 };
 
 // Starts a ray; false when it misses the root's box (nothing to trace).
 __device__ inline bool bvh_begin(const SlotDesc& d, f3 o, f3 k, float tmin, BvhState& s) {
-    s.r = bvh_ray(o, k, tmin);
     s.o = o;
     s.k = k;
+    s.inv = mk3(safe_inv(k.x), safe_inv(k.y), safe_inv(k.z));
+    s.tmin = tmin;
     s.dmask = (k.x < 0.f ? 1u : 0u) | (k.y < 0.f ? 2u : 0u) | (k.z < 0.f ? 4u : 0u);
     s.key = kEmptyKey;
     s.sp = 0;
+    // the root's exact box (slab test with the near and far planes picked by the signs)
     const float4 lo = gld(d.bvh), hi = gld(d.bvh + 1);
-    s.first = __float_as_uint(lo.w);
-    s.info = __float_as_uint(hi.w);
-    return box_enter(s.r, lo, hi, FLT_MAX) != FLT_MAX;
-}
-
-// One step: expands the current node (a leaf's points, or an internal node's children boxes),
-// then picks the next node: the front-most hit child (its record came with its box), else the
-// front-most waiting child of the deepest stack entry.  Returns true when the ray is done
-// (any-hit: at the first hit, with key = 0).  stk: this lane's stack base, entries stride apart.
-template <bool any>
-__device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, int stride) {
-    if (s.info & kBvhLeafBit) {
-        const uint32_t p1 = s.first + (s.info & 0xFFFFFFu);
-        for (uint32_t p = s.first; p < p1; p++) {
-            const float4 a = gld(d.pa_s + p), b = gld(d.pb_s + p);
-            float t;
-            if (disk_test(a, b, s.o, s.k, s.r.tmin, t)) {
-                if (any) {
-                    s.key = 0;
-                    return true;
-                }
-                const uint64_t c = pack_hit(t, __float_as_uint(b.w));
-                s.key = c < s.key ? c : s.key;
-            }
-        }
-    } else {
-        const uint32_t occ = s.info & 0xFFu;
-        const float tmax = any ? FLT_MAX : key_t(s.key);
-        uint32_t pending = 0, m = occ, bj = 8u, bf = 0u, bi = 0u;
-#pragma unroll
-        for (int c = 0; c < 8; c++) {
-            if (m == 0) break;
-            const uint32_t oct = __builtin_ctz(m);
-            m &= m - 1u;
-            const float4* cn = d.bvh + 2 * ((uint64_t)s.first + c);
-            const float4 lo = gld(cn), hi = gld(cn + 1);
-            if (box_enter(s.r, lo, hi, tmax) != FLT_MAX) {
-                const uint32_t rank = oct ^ s.dmask;
-                pending |= 1u << rank;
-                if (rank < bj) {
-                    bj = rank;
-                    bf = __float_as_uint(lo.w);
-                    bi = __float_as_uint(hi.w);
-                }
-            }
-        }
-        if (pending) {
-            pending &= ~(1u << bj);
-            if (pending) {
-                stk[s.sp * stride] =
-                    (uint64_t)s.first | ((uint64_t)occ << 32) | ((uint64_t)pending << 40);
-                s.sp++;
-            }
-            s.first = bf;
-            s.info = bi;
-            return false;
-        }
-    }
-    while (s.sp > 0) {
-        const uint64_t e = stk[(s.sp - 1) * stride];
-        uint32_t pend = (uint32_t)(e >> 40) & 0xFFu;
-        const uint32_t j = __builtin_ctz(pend);
-        pend &= pend - 1u;
-        if (pend)
-            stk[(s.sp - 1) * stride] = (e & 0xFFFFFFFFFFull) | ((uint64_t)pend << 40);
-        else
-            s.sp--;
-        const uint32_t occ = (uint32_t)(e >> 32) & 0xFFu, oct = j ^ s.dmask;
-        const float4* cn = d.bvh + 2 * ((uint64_t)(uint32_t)e + __popc(occ & ((1u << oct) - 1u)));
-        const float4 lo = gld(cn), hi = gld(cn + 1);
-        // once a hit is known, a waiting child entered beyond it is skipped
-        if (!any && s.key != kEmptyKey && box_enter(s.r, lo, hi, key_t(s.key)) == FLT_MAX)
-            continue;
-        s.first = __float_as_uint(lo.w);
-        s.info = __float_as_uint(hi.w);
-        return false;
+    const float ax = ((s.inv.x >= 0.f ? lo.x : hi.x) - o.x) * s.inv.x;
+    const float bx = ((s.inv.x >= 0.f ? hi.x : lo.x) - o.x) * s.inv.x;
+    const float ay = ((s.inv.y >= 0.f ? lo.y : hi.y) - o.y) * s.inv.y;
+    const float by = ((s.inv.y >= 0.f ? hi.y : lo.y) - o.y) * s.inv.y;
+    const float az = ((s.inv.z >= 0.f ? lo.z : hi.z) - o.z) * s.inv.z;
+    const float bz = ((s.inv.z >= 0.f ? hi.z : lo.z) - o.z) * s.inv.z;
+    const float tn = fmaxf(fmaxf(ax, ay), az), tf = fminf(fminf(bx, by), bz);
+    if (!(tn <= tf && tf >= tmin)) return false;
+    if (d.w_root_pts) {  // the whole scene is one leaf
+        s.pbase = 0;
+        s.pmask = (1ull << d.w_root_pts) - 1ull;
+        s.ghits = 0;
+    } else {  // a node group holding the root record alone (octant 0, internal)
+        s.pmask = 0;
+        s.gbase = 0;
+        s.giocc = 1u;
+        s.ghits = 1u << s.dmask;
     }
     return true;
 }
 
-// Whole traversal of one ray on one lane: nearest hit (any = false: packed key, kEmptyKey when
-// none) or any hit (any = true: 0 when something is hit, kEmptyKey otherwise).
+// Points tested per round trip of a point group.
+constexpr int kBvhBatch = 4;
+
+// One step: tests up to kBvhBatch points of the point group, or expands the front-most child
+// of the node group (popping a group when the current one is spent).  Returns true when the
+// ray is done (any-hit: at the first hit, with key = 0).  stk: this lane's stack base, entries
+// stride apart.
 template <bool any>
-__device__ inline uint64_t bvh_trace(const SlotDesc& d, f3 o, f3 k, float tmin, uint64_t* stk,
-                                     int stride) {
-    BvhState s;
-    if (!bvh_begin(d, o, k, tmin, s)) return kEmptyKey;
-    while (!bvh_step<any>(d, s, stk, stride)) {
+__device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, int stride) {
+    if (s.pmask) {
+        uint64_t mm = s.pmask;
+        uint32_t p[kBvhBatch];
+        bool ok[kBvhBatch];
+#pragma unroll
+        for (int i = 0; i < kBvhBatch; i++) {
+            ok[i] = mm != 0;
+            p[i] = ok[i] ? s.pbase + (uint32_t)__builtin_ctzll(mm) : p[0];
+            mm &= mm - 1ull;
+        }
+        s.pmask = mm;
+        float4 pa[kBvhBatch], pb[kBvhBatch];
+#pragma unroll
+        for (int i = 0; i < kBvhBatch; i++) {
+            pa[i] = gld(d.wpts + 2 * (uint64_t)p[i]);
+            pb[i] = gld(d.wpts + 2 * (uint64_t)p[i] + 1);
+        }
+#pragma unroll
+        for (int i = 0; i < kBvhBatch; i++) {
+            const float t = disk_t(pa[i], pb[i], s.o, s.k, s.tmin);
+            if (ok[i] && t != FLT_MAX) {
+                if (any) {
+                    s.key = 0;
+                    return true;
+                }
+                const uint64_t c = pack_hit(t, __float_as_uint(pb[i].w));
+                s.key = c < s.key ? c : s.key;
+            }
+        }
+        return s.pmask == 0 && s.ghits == 0 && s.sp == 0;
     }
-    return s.key;
+    if (s.ghits == 0) {
+        if (s.sp == 0) return true;
+        const uint64_t e = stk[(--s.sp) * stride];
+        s.gbase = (uint32_t)e;
+        s.ghits = (uint32_t)(e >> 32) & 0xFFu;
+        s.giocc = (uint32_t)(e >> 40) & 0xFFu;
+    }
+    const uint32_t r = __builtin_ctz(s.ghits), oct = r ^ s.dmask;
+    s.ghits &= s.ghits - 1u;
+    const uint32_t idx = s.gbase + __popc(s.giocc & ((1u << oct) - 1u));
+    if (s.ghits) {
+        stk[s.sp * stride] =
+            (uint64_t)s.gbase | ((uint64_t)s.ghits << 32) | ((uint64_t)s.giocc << 40);
+        s.sp++;
+    }
+    const uint4* rec = d.wrec + (uint64_t)kWideRec * idx;
+    const uint4 q0 = gld(rec), q1 = gld(rec + 1), q2 = gld(rec + 2), q3 = gld(rec + 3),
+                q4 = gld(rec + 4);
+    // plane parameter of quantised coordinate q on axis a: (org + q scale - o) / k, as
+    // q (scale / k) + (org - o) / k
+    const float sx = __uint_as_float((q0.w & 0xFFu) << 23) * s.inv.x;
+    const float sy = __uint_as_float(((q0.w >> 8) & 0xFFu) << 23) * s.inv.y;
+    const float sz = __uint_as_float(((q0.w >> 16) & 0xFFu) << 23) * s.inv.z;
+    const float ax = (__uint_as_float(q0.x) - s.o.x) * s.inv.x;
+    const float ay = (__uint_as_float(q0.y) - s.o.y) * s.inv.y;
+    const float az = (__uint_as_float(q0.z) - s.o.z) * s.inv.z;
+    const uint32_t occ = q0.w >> 24, iocc = q1.z, counts = q1.w;
+    const float tmax = any ? FLT_MAX : key_t(s.key);
+    const uint32_t lox[2] = {q2.x, q2.y}, loy[2] = {q2.z, q2.w}, loz[2] = {q3.x, q3.y},
+                   hix[2] = {q3.z, q3.w}, hiy[2] = {q4.x, q4.y}, hiz[2] = {q4.z, q4.w};
+    uint32_t nh = 0, off = 0;
+    uint64_t pm = 0;
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
+        const int w = o >> 2, sh = 8 * (o & 3);
+        const float x0 = fmaf((float)((lox[w] >> sh) & 0xFFu), sx, ax);
+        const float x1 = fmaf((float)((hix[w] >> sh) & 0xFFu), sx, ax);
+        const float y0 = fmaf((float)((loy[w] >> sh) & 0xFFu), sy, ay);
+        const float y1 = fmaf((float)((hiy[w] >> sh) & 0xFFu), sy, ay);
+        const float z0 = fmaf((float)((loz[w] >> sh) & 0xFFu), sz, az);
+        const float z1 = fmaf((float)((hiz[w] >> sh) & 0xFFu), sz, az);
+        const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fminf(z0, z1));
+        const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
+        const bool hit = ((occ >> o) & 1u) && tn <= tf && tf >= s.tmin && tn <= tmax;
+        const uint32_t cnt = (counts >> (4 * o)) & 0xFu;
+        if (hit) {
+            if ((iocc >> o) & 1u)
+                nh |= 1u << (o ^ s.dmask);
+            else
+                pm |= ((1ull << cnt) - 1ull) << off;
+        }
+        off += cnt;
+    }
+    s.gbase = q1.x;
+    s.giocc = iocc;
+    s.ghits = nh;
+    s.pbase = q1.y;
+    s.pmask = pm;
+    return nh == 0 && pm == 0 && s.sp == 0;
 }
 
 }  // namespace pe

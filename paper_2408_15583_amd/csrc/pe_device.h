@@ -70,8 +70,24 @@ constexpr int kNumXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCD
 // nodes first .. first + popc(occ) - 1 for the occupied octants occ = info & 0xFF (octant = the
 // 3 code bits below the prefix, x in bit 0; chunk number past the code), stored in increasing
 // octant order.  The root is node 0.
+//
+// Wide records (what the traversal reads): one record of kWideRec uint4 per internal node, in
+// node order (so the internal children of a node have consecutive record indices):
+//   [0] origin x, y, z (the node's box low corner, fp32 bits); w = e_x | e_y << 8 | e_z << 16 |
+//       occ << 24, with the per-axis scale 2^(e - 127) (biased fp32 exponent) and occ the
+//       octant mask of the children;
+//   [1] x = record index of the first internal child, y = wpts index of the first point of the
+//       leaf children, z = octant mask of the internal children, w = 4-bit point count of the
+//       leaf child in each octant (0 for internal or empty octants);
+//   [2..4] child boxes by octant, 8-bit coordinates q (plane = origin + q scale, rounded
+//       outward so each contains the child's exact box): low x[8], low y[8], low z[8], high
+//       x[8], high y[8], high z[8] bytes.
+// wpts holds every point once (2 float4 as pa_s / pb_s), the leaf children of each node
+// consecutively in octant order; when the root is itself a leaf its points come first and
+// there is no record.
 constexpr int kBvhLeaf = 8;
 constexpr uint32_t kBvhLeafBit = 0x80000000u;
+constexpr int kWideRec = 5;
 constexpr int kBvhMaxLevels = 20;  // 10 code levels + count splits of up to 2^31 points
 constexpr int kBvhMaxStack = kBvhMaxLevels;  // one stack entry per level
 
@@ -113,8 +129,11 @@ struct SlotDesc {
     const uint32_t* bl_start;
     const uint32_t* bl_items;
     // object-space hierarchy over pa_s (secondary hits and visibility against every splat),
-    // node records as described at kBvhLeaf
+    // node records and wide records as described at kBvhLeaf
     const float4* bvh;
+    const uint4* wrec;
+    const float4* wpts;
+    uint32_t w_root_pts;  // points of the root when it is a leaf, else 0
 };
 
 struct ObsDesc {
@@ -178,8 +197,8 @@ void launch_ingest_pack(const void* xyz, int is_f64, const float* nrm, const uin
                         hipStream_t st);
 // Spatial order of a scene (k_sort.hip): sorts the points by the Morton code of a 1024^3 grid
 // whose cells have edge 1 / inv_cell from (lo_x, lo_y, lo_z), writing pa_s / pb_s (original
-// index in pb_s.w).  keys: 4 n u32 of scratch; temp: morton_sort_temp_bytes(n) bytes (0 when
-// the size query fails).
+// index in pb_s.w).  keys: 4 n u32 of scratch, the sorted codes end in keys[n .. 2n); temp:
+// morton_sort_temp_bytes(n) bytes (digit counts, their offsets and the scan's tile totals).
 size_t morton_sort_temp_bytes(uint64_t n);
 hipError_t launch_morton_sort(const float4* pa, const float4* pb, uint64_t n, float lo_x,
                               float lo_y, float lo_z, float inv_cell, uint32_t* keys,
@@ -225,6 +244,15 @@ void launch_bvh_emit(const uint2* rng, uint32_t n_nodes, int level, const uint32
                      hipStream_t st);
 void launch_bvh_box(const uint2* finfo, uint32_t n_nodes, uint32_t base, const float4* pa_s,
                     const float4* pb_s, float pad, float4* nodes, hipStream_t st);
+// Wide records from the finished node records: count pass (is_int[g] = node g is internal,
+// leafpts[g] = points of its leaf children), then, after exclusive scans of both into rec and
+// lbase, the emit pass writes each internal node's record at rec[g] and copies its leaf
+// children's points to wpts from lbase[g] (a leaf root copies its points to wpts[0..]).
+void launch_wide_count(const float4* nodes, uint32_t n_nodes, uint32_t* is_int,
+                       uint32_t* leafpts, hipStream_t st);
+void launch_wide_emit(const float4* nodes, uint32_t n_nodes, const uint32_t* rec,
+                      const uint32_t* lbase, const float4* pa_s, const float4* pb_s,
+                      uint4* wrec, float4* wpts, hipStream_t st);
 
 // Visibility of facets against every splat, as a dense pass: mark the entries of list whose
 // facet needs a traced Psi (every facet of a bistatic slot, the later-bounce facets of a

@@ -181,6 +181,9 @@ struct pe_scene_s {
     float4* bvh = nullptr;  // object-space hierarchy over pa_s (node records at pe::kBvhLeaf)
     uint64_t bvh_nodes = 0;
     int bvh_levels = 1;  // octree levels: the traversal's stack holds at most one entry each
+    uint4* wrec = nullptr;     // wide records of the internal nodes (pe::kWideRec)
+    float4* wpts = nullptr;    // the points in leaf order, 2 float4 each
+    uint32_t w_root_pts = 0;   // points of the root when it is a leaf
     float blend_r = 0.f, bl_h = 0.f;  // Eq. (23) refinement radius and centre-grid cell edge
     int bl_G = 0;
     uint32_t *bl_start = nullptr, *bl_items = nullptr;

@@ -233,6 +233,9 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.bl_start = sc->bl_start;
         d.bl_items = sc->bl_items;
         d.bvh = sc->bvh;
+        d.wrec = sc->wrec;
+        d.wpts = sc->wpts;
+        d.w_root_pts = sc->w_root_pts;
         bvh_depth = std::max(bvh_depth, sc->bvh_levels);
         if (sc->blend_r > 0.f) blend = true;
         d.views = sc->views_dev;

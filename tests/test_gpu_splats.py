@@ -91,6 +91,27 @@ def test_trace_random_clouds_splats(pe, ctx, seed):
     s.close()
 
 
+@pytest.mark.parametrize("n", [1, 6, 8, 9, 70])
+def test_trace_tiny_clouds_splats(pe, ctx, n):
+    """Clouds of a handful of disks: a root that is itself a leaf (n <= 8), a root with leaf
+    children only, and two levels; every pixel's bounces agree with the oracle's brute force."""
+    sc = scenes.random_disks(900 + n, n, extent=0.3, r_lo=0.05, r_hi=0.15, absorber_frac=0.0)
+    s = pe.Scene.from_scene(ctx, sc, view_res=32)
+    o = oracle.OracleScene(sc)
+    rng = np.random.default_rng(n)
+    multi = 0
+    for _ in range(6):
+        k = rng.standard_normal(3)
+        k /= np.linalg.norm(k)
+        agree, dx, idx, nbo = trace_agreement(pe, ctx, s, o, k, 64, 4, 0.01)
+        multi += int((nbo >= 2).sum())
+        assert agree == 1.0, (n, agree)
+        assert idx == 1.0 and dx <= 1e-4, (n, idx, dx)
+    s.close()
+    print(f"tiny cloud of {n}: {multi} rays with secondary hits")
+    assert n == 1 or multi > 0
+
+
 def test_dihedral_workload_splats(pe, ctx):
     sc, sw = scenes.workload_dihedral()
     s = pe.Scene.from_scene(ctx, sc, view_res=sw.view_res)
