@@ -53,13 +53,13 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=35881835.6, write_kib=774523.2, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=20275437.2, write_kib=887990.3, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
-             "b40848c6218fe01a57cd275435f63f859b16299b115fe838138caa4d60f62c1f",
+             "e08ecdbc431ee1c8fd4c0ae1ded5e49703737b2d84afa9329f32f62033ff9194",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
-             "9e21bb4cadb3863febcfb3f17bc533a65ca461bc029f3bb0c045505bb25c7e6b",
+             "71f9e0279725ea611dcdbc18a192e61d2662ba203d639825c1a1237fdef37eca",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "6a6a681705cbb92a166f4fd6dddb0fd1133a03859207d45171ab968568f9e60e",
+             "893b4a1556de12b39e1d4bce3c3e5729b02b79ccf6637280312394ca4e76c01c",
              "paper_2408_15583_amd/csrc/pe_geom.h":
              "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
 
@@ -181,8 +181,8 @@ def serving(pe, ctx, seconds, n_scenes=64, seed=5, log=None, budget_8gb_seconds=
     offers Poisson arrivals for `seconds` at 70 % of the saturated work rate and reports latency
     percentiles from submit to completion, overall and per screen-size class.  Phase 3 (when
     budget_8gb_seconds > 0) repeats phase 2's offered load in a context limited to 8 GiB with the
-    part of the pool that fits in 1.5 GiB, so admission by footprint serialises the large
-    requests.  Work per request follows a cost model, pixels x angles x (bounces + frequencies
+    part of the pool that fits in 1.25 GiB, so admission by footprint serialises the large
+    requests (a request larger than the budget left by the scenes is refused and counted).  Work per request follows a cost model, pixels x angles x (bounces + frequencies
     / 16), whose mean over the mix is estimated from 20000 draws; the request sizes span five
     orders of magnitude, so a rate set from request counts alone would offer a load that
     depends on which few large requests the saturation sample happened to hold."""
@@ -251,11 +251,21 @@ def serving(pe, ctx, seconds, n_scenes=64, seed=5, log=None, budget_8gb_seconds=
                 log(f"serving {tag}: {len(ts)} submitted at {now:.0f} s")
                 next_log += 15.0
         done = []
+        rejected = 0
         for t, r in zip(ts, rs):
-            _, _, st = t.wait()
+            try:
+                _, _, st = t.wait()
+            except pe.PEError as e:
+                # admission by footprint: a request larger than the budget the resident scenes
+                # leave is refused at once
+                if e.status != pe._native.PE_ENOMEM:
+                    raise
+                rejected += 1
+                continue
             done.append((r["screen"], st["time_ms"]))
         st = pe.server_stats(c, reset=True)
         return dict(offered_rate_per_s=rate, requests=len(ts), completed=st["completed"],
+                    rejected_over_budget=rejected,
                     window_s=time.perf_counter() - t0, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
                     mean_ms=st["mean_ms"], max_concurrent=st["max_concurrent"],
                     reqs_per_batch=st["reqs_per_batch"], by_screen=_latency_classes(done))
@@ -279,7 +289,7 @@ def serving(pe, ctx, seconds, n_scenes=64, seed=5, log=None, budget_8gb_seconds=
         sub_sc, sub = [], []
         for sc in pool_sc:
             s = pe.Scene.from_scene(c8, sc, view_res=1024)
-            if c8.footprint()[0] > 1.5 * 2**30:
+            if c8.footprint()[0] > 1.25 * 2**30:
                 s.close()
                 continue
             sub_sc.append(sc)

@@ -62,6 +62,8 @@ struct BvhState {
     uint32_t gbase, ghits, giocc;  // node group
     uint32_t pbase;                // point group: wpts index of its first point
     uint64_t pmask;                //   and the points still to test
+    const uint4* wrec;             // the ray's scene (kept per lane: a launch may mix scenes)
+    const float4* wpts;
 };
 
 // Starts a ray; false when it misses the root's box (nothing to trace).
@@ -73,6 +75,8 @@ __device__ inline bool bvh_begin(const SlotDesc& d, f3 o, f3 k, float tmin, BvhS
     s.dmask = (k.x < 0.f ? 1u : 0u) | (k.y < 0.f ? 2u : 0u) | (k.z < 0.f ? 4u : 0u);
     s.key = kEmptyKey;
     s.sp = 0;
+    s.wrec = d.wrec;
+    s.wpts = d.wpts;
     // the root's exact box (slab test with the near and far planes picked by the signs)
     const float4 lo = gld(d.bvh), hi = gld(d.bvh + 1);
     const float ax = ((s.inv.x >= 0.f ? lo.x : hi.x) - o.x) * s.inv.x;
@@ -99,43 +103,49 @@ __device__ inline bool bvh_begin(const SlotDesc& d, f3 o, f3 k, float tmin, BvhS
 // Points tested per round trip of a point group.
 constexpr int kBvhBatch = 4;
 
-// One step: tests up to kBvhBatch points of the point group, or expands the front-most child
-// of the node group (popping a group when the current one is spent).  Returns true when the
-// ray is done (any-hit: at the first hit, with key = 0).  stk: this lane's stack base, entries
-// stride apart.
+// Point step: tests up to kBvhBatch points of the lane's point group.  Returns true when the
+// ray is done (any-hit: at the first hit, with key = 0).
 template <bool any>
-__device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, int stride) {
-    if (s.pmask) {
-        uint64_t mm = s.pmask;
-        uint32_t p[kBvhBatch];
-        bool ok[kBvhBatch];
+__device__ inline bool bvh_points(BvhState& s) {
+    uint64_t mm = s.pmask;
+    uint32_t p[kBvhBatch];
+    bool ok[kBvhBatch];
 #pragma unroll
-        for (int i = 0; i < kBvhBatch; i++) {
-            ok[i] = mm != 0;
-            p[i] = ok[i] ? s.pbase + (uint32_t)__builtin_ctzll(mm) : p[0];
-            mm &= mm - 1ull;
-        }
-        s.pmask = mm;
-        float4 pa[kBvhBatch], pb[kBvhBatch];
-#pragma unroll
-        for (int i = 0; i < kBvhBatch; i++) {
-            pa[i] = gld(d.wpts + 2 * (uint64_t)p[i]);
-            pb[i] = gld(d.wpts + 2 * (uint64_t)p[i] + 1);
-        }
-#pragma unroll
-        for (int i = 0; i < kBvhBatch; i++) {
-            const float t = disk_t(pa[i], pb[i], s.o, s.k, s.tmin);
-            if (ok[i] && t != FLT_MAX) {
-                if (any) {
-                    s.key = 0;
-                    return true;
-                }
-                const uint64_t c = pack_hit(t, __float_as_uint(pb[i].w));
-                s.key = c < s.key ? c : s.key;
-            }
-        }
-        return s.pmask == 0 && s.ghits == 0 && s.sp == 0;
+    for (int i = 0; i < kBvhBatch; i++) {
+        ok[i] = mm != 0;
+        p[i] = ok[i] ? s.pbase + (uint32_t)__builtin_ctzll(mm) : p[0];
+        mm &= mm - 1ull;
     }
+    s.pmask = mm;
+    // all requests go out before the first test (a slot a lane does not need repeats its
+    // first point's address, and its test result is dropped)
+    float4 pa[kBvhBatch], pb[kBvhBatch];
+#pragma unroll
+    for (int i = 0; i < kBvhBatch; i++) {
+        pa[i] = gld(s.wpts + 2 * (uint64_t)p[i]);
+        pb[i] = gld(s.wpts + 2 * (uint64_t)p[i] + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < kBvhBatch; i++) {
+        const float t = disk_t(pa[i], pb[i], s.o, s.k, s.tmin);
+        if (ok[i] && t != FLT_MAX) {
+            if (any) {
+                s.key = 0;
+                return true;
+            }
+            const uint64_t c = pack_hit(t, __float_as_uint(pb[i].w));
+            s.key = c < s.key ? c : s.key;
+        }
+    }
+    return s.pmask == 0 && s.ghits == 0 && s.sp == 0;
+}
+
+// Node step (for a lane whose point group is empty): expands the front-most child of the node
+// group, popping a group when the current one is spent; the child's hit internal children
+// become the node group and its hit leaf children's points the point group.  Returns true when
+// the ray is done.  stk: this lane's stack base, entries stride apart.
+template <bool any>
+__device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
     if (s.ghits == 0) {
         if (s.sp == 0) return true;
         const uint64_t e = stk[(--s.sp) * stride];
@@ -151,7 +161,7 @@ __device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, i
             (uint64_t)s.gbase | ((uint64_t)s.ghits << 32) | ((uint64_t)s.giocc << 40);
         s.sp++;
     }
-    const uint4* rec = d.wrec + (uint64_t)kWideRec * idx;
+    const uint4* rec = s.wrec + (uint64_t)kWideRec * idx;
     const uint4 q0 = gld(rec), q1 = gld(rec + 1), q2 = gld(rec + 2), q3 = gld(rec + 3),
                 q4 = gld(rec + 4);
     // plane parameter of quantised coordinate q on axis a: (org + q scale - o) / k, as
@@ -166,10 +176,12 @@ __device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, i
     const float tmax = any ? FLT_MAX : key_t(s.key);
     const uint32_t lox[2] = {q2.x, q2.y}, loy[2] = {q2.z, q2.w}, loz[2] = {q3.x, q3.y},
                    hix[2] = {q3.z, q3.w}, hiy[2] = {q4.x, q4.y}, hiz[2] = {q4.z, q4.w};
-    uint32_t nh = 0, off = 0;
-    uint64_t pm = 0;
+    // hit octants, then the internal ones to the node group (rank order) and the leaf ones'
+    // points to the point group; an octant no lane of the wavefront occupies is skipped
+    uint32_t hits = 0;
 #pragma unroll
     for (int o = 0; o < 8; o++) {
+        if (!((occ >> o) & 1u)) continue;
         const int w = o >> 2, sh = 8 * (o & 3);
         const float x0 = fmaf((float)((lox[w] >> sh) & 0xFFu), sx, ax);
         const float x1 = fmaf((float)((hix[w] >> sh) & 0xFFu), sx, ax);
@@ -179,14 +191,19 @@ __device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, i
         const float z1 = fmaf((float)((hiz[w] >> sh) & 0xFFu), sz, az);
         const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fminf(z0, z1));
         const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
-        const bool hit = ((occ >> o) & 1u) && tn <= tf && tf >= s.tmin && tn <= tmax;
+        hits |= (tn <= tf && tf >= s.tmin && tn <= tmax) ? 1u << o : 0u;
+    }
+    const uint32_t ih = hits & iocc;
+    uint32_t nh = 0;
+#pragma unroll
+    for (int o = 0; o < 8; o++) nh |= ((ih >> o) & 1u) << (o ^ s.dmask);
+    // point bits of octant o: cnt_o bits from the sum of the lower octants' counts
+    uint64_t pm = 0;
+    uint32_t lh = hits & ~iocc, off = 0;
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
         const uint32_t cnt = (counts >> (4 * o)) & 0xFu;
-        if (hit) {
-            if ((iocc >> o) & 1u)
-                nh |= 1u << (o ^ s.dmask);
-            else
-                pm |= ((1ull << cnt) - 1ull) << off;
-        }
+        if ((lh >> o) & 1u) pm |= ((1ull << cnt) - 1ull) << off;
         off += cnt;
     }
     s.gbase = q1.x;
@@ -195,6 +212,14 @@ __device__ inline bool bvh_step(const SlotDesc& d, BvhState& s, uint64_t* stk, i
     s.pbase = q1.y;
     s.pmask = pm;
     return nh == 0 && pm == 0 && s.sp == 0;
+}
+
+// One step of a lane: a point step while its point group holds points, else a node step.
+// (Taking one kind of step for the whole wavefront at a time, by a quorum of lanes, was slower:
+// the two kinds then no longer share a memory round trip.)
+template <bool any>
+__device__ inline bool bvh_step(const SlotDesc&, BvhState& s, uint64_t* stk, int stride) {
+    return s.pmask != 0 ? bvh_points<any>(s) : bvh_node<any>(s, stk, stride);
 }
 
 }  // namespace pe

@@ -213,7 +213,7 @@ def test_mixed_batch_vs_exact_oracle(pe, ctx):
 
 def test_admission_8gib_serving_mix(pe, ctx):
     """Serving-mix requests (angle counts capped at 12 to bound the run) on the first pool scenes
-    that fit 1.5 GiB, in a context limited to 8 GiB: the largest requests cannot share the budget
+    that fit 1.25 GiB, in a context limited to 8 GiB: the largest requests cannot share the budget
     with each other, the small ones can; all complete, the context's footprint (polled while they
     run) never exceeds the budget, and three results equal solves in the unconstrained context."""
     import threading
@@ -224,7 +224,7 @@ def test_admission_8gib_serving_mix(pe, ctx):
     for i, n in enumerate(scenes.serving_pool_sizes(64, 5)[:8]):
         sc = scenes.serving_scene(i, n)
         s = pe.Scene.from_scene(c8, sc, view_res=1024)
-        if c8.footprint()[0] > 1.5 * 2**30:
+        if c8.footprint()[0] > 1.25 * 2**30:
             s.close()
             continue
         pool_sc.append(sc)
