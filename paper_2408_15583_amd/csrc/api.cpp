@@ -394,6 +394,11 @@ pe_status pe_scene_create(pe_ctx ctx, const pe_scene_desc* desc, void* hip_strea
         sc->wpts = (float4*)sc->alloc(n * 32);
         launch_wide_emit(sc->bvh, nn, rec, lbase, sc->pa_s, sc->pb_s, sc->wrec, sc->wpts, st);
         HIPCHK(hipGetLastError());
+        float4 root[2];
+        HIPCHK(hipMemcpyAsync(root, sc->bvh, sizeof(root), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const float rb[6] = {root[0].x, root[0].y, root[0].z, root[1].x, root[1].y, root[1].z};
+        std::copy(rb, rb + 6, sc->bvh_root);
     }
 
     // aggregation views

@@ -346,13 +346,21 @@ __global__ __launch_bounds__(256) void k_trace_bvh(const SlotDesc* __restrict__ 
     bvh_persistent<false>(
         ds, *n_live, queue, refill,
         [&](uint64_t j, const SlotDesc*& dp, BvhState& s) {
+            // three rounds of loads: the entry; the slot's fields; the ray state
             const uint32_t entry = list[j];
             dp = ds + entry_slot(entry);
-            if (bounce <= dp->max_b) {
-                const uint64_t g = dp->pix_base + entry_pix(entry);
-                const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
-                if (bvh_begin(*dp, x, leave_dir(kin, nn), dp->eps, s)) return true;
-            }
+            typedef const __attribute__((address_space(1))) SlotDesc& GSlot;
+            GSlot sd = (GSlot)*dp;
+            int max_b = sd.max_b;
+            uint64_t pix_base = sd.pix_base;
+            float eps = sd.eps;
+            BvhScene sc = bvh_scene(dp);
+            bvh_pin(sc, max_b, pix_base, eps);
+            // the ray state is read whatever the bounce guard says (the entry's pixel is
+            // always in range)
+            const uint64_t g = pix_base + entry_pix(entry);
+            const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+            if (bounce <= max_b && bvh_begin(sc, x, leave_dir(kin, nn), eps, s)) return true;
             hitkey[j] = kEmptyKey;
             return false;
         },
@@ -410,30 +418,33 @@ __global__ __launch_bounds__(256) void k_psi_trace(const SlotDesc* __restrict__ 
                                                    int max_obs, RayState rs,
                                                    uint8_t* __restrict__ vis, uint64_t vis_stride,
                                                    uint32_t* __restrict__ queue, int refill) {
-    auto where = [&](uint64_t w, uint64_t& g) {
-        const uint32_t entry = list[w / (uint32_t)max_obs];
-        const SlotDesc* dp = ds + entry_slot(entry);
-        g = dp->pix_base + entry_pix(entry);
-        return dp;
-    };
     bvh_persistent<true>(
         ds, (uint64_t)*n_list * (uint32_t)max_obs, queue, refill,
         [&](uint64_t w, const SlotDesc*& dp, BvhState& s) {
+            // three rounds of loads: the entry; the slot's fields; the facet position and the
+            // observation direction
             const uint32_t o = (uint32_t)(w % (uint32_t)max_obs);
-            uint64_t g;
-            dp = where(w, g);
-            if ((int)o >= dp->n_obs) return false;
-            const ObsDesc& O = obs[dp->obs_base + o];
-            if (bvh_begin(*dp, ld3(rs, RX, g), mk3(O.ks[0], O.ks[1], O.ks[2]), dp->eps, s))
-                return true;
-            vis[o * vis_stride + g] = 1;
+            const uint32_t entry = list[w / (uint32_t)max_obs];
+            dp = ds + entry_slot(entry);
+            typedef const __attribute__((address_space(1))) SlotDesc& GSlot;
+            GSlot sd = (GSlot)*dp;
+            int n_obs = sd.n_obs, obs_base = sd.obs_base;
+            uint64_t pix_base = sd.pix_base;
+            float eps = sd.eps;
+            BvhScene sc = bvh_scene(dp);
+            bvh_pin(sc, n_obs, pix_base, eps);
+            asm volatile("" : "+v"(obs_base));
+            const uint64_t g = pix_base + entry_pix(entry);
+            const bool take = (int)o < n_obs;
+            const ObsDesc& O = obs[take ? obs_base + (int)o : obs_base];
+            const f3 x = ld3(rs, RX, g), ks = mk3(O.ks[0], O.ks[1], O.ks[2]);
+            if (!take) return false;
+            s.out = o * vis_stride + g;
+            if (bvh_begin(sc, x, ks, eps, s)) return true;
+            vis[s.out] = 1;
             return false;
         },
-        [&](uint64_t w, const BvhState& s) {
-            uint64_t g;
-            where(w, g);
-            vis[(w % (uint32_t)max_obs) * vis_stride + g] = s.key == kEmptyKey ? 1 : 0;
-        });
+        [&](uint64_t, const BvhState& s) { vis[s.out] = s.key == kEmptyKey ? 1 : 0; });
 }
 
 void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* list,

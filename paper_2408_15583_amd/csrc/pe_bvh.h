@@ -64,10 +64,46 @@ struct BvhState {
     uint64_t pmask;                //   and the points still to test
     const uint4* wrec;             // the ray's scene (kept per lane: a launch may mix scenes)
     const float4* wpts;
+    uint64_t out;                  // where the pass writes the ray's result
 };
 
+// What a ray needs of its scene to start: the wide records, the leaf-ordered points, the
+// point count of a leaf root, and the root's exact box (kept in the slot descriptor so that a
+// ray starts without a round trip of its own).
+struct BvhScene {
+    const uint4* wrec;
+    const float4* wpts;
+    uint32_t root_pts;
+    float lo[3], hi[3];
+};
+
+// The scene fields of a slot descriptor (read through the global address space; the caller
+// pins them with bvh_pin together with its own fields, so that all are requested in one round).
+__device__ inline BvhScene bvh_scene(const SlotDesc* dp) {
+    typedef const __attribute__((address_space(1))) SlotDesc& GSlot;
+    GSlot sd = (GSlot)*dp;
+    BvhScene b;
+    b.wrec = sd.wrec;
+    b.wpts = sd.wpts;
+    b.root_pts = sd.w_root_pts;
+    for (int a = 0; a < 3; a++) {
+        b.lo[a] = sd.bvh_lo[a];
+        b.hi[a] = sd.bvh_hi[a];
+    }
+    return b;
+}
+
+// Keeps the compiler from sinking the loads of these values into their first uses (which
+// would make each a round trip of its own): they are all requested before any is waited for.
+template <class A, class B, class C>
+__device__ inline void bvh_pin(BvhScene& b, A& x, B& y, C& z) {
+    asm volatile("" : "+v"(b.wrec), "+v"(b.wpts), "+v"(b.root_pts), "+v"(b.lo[0]), "+v"(b.lo[1]),
+                 "+v"(b.lo[2]), "+v"(b.hi[0]), "+v"(b.hi[1]), "+v"(b.hi[2]), "+v"(x), "+v"(y),
+                 "+v"(z));
+}
+
 // Starts a ray; false when it misses the root's box (nothing to trace).
-__device__ inline bool bvh_begin(const SlotDesc& d, f3 o, f3 k, float tmin, BvhState& s) {
+__device__ inline bool bvh_begin(const BvhScene& sc, f3 o, f3 k, float tmin, BvhState& s) {
     s.o = o;
     s.k = k;
     s.inv = mk3(safe_inv(k.x), safe_inv(k.y), safe_inv(k.z));
@@ -75,21 +111,20 @@ __device__ inline bool bvh_begin(const SlotDesc& d, f3 o, f3 k, float tmin, BvhS
     s.dmask = (k.x < 0.f ? 1u : 0u) | (k.y < 0.f ? 2u : 0u) | (k.z < 0.f ? 4u : 0u);
     s.key = kEmptyKey;
     s.sp = 0;
-    s.wrec = d.wrec;
-    s.wpts = d.wpts;
+    s.wrec = sc.wrec;
+    s.wpts = sc.wpts;
     // the root's exact box (slab test with the near and far planes picked by the signs)
-    const float4 lo = gld(d.bvh), hi = gld(d.bvh + 1);
-    const float ax = ((s.inv.x >= 0.f ? lo.x : hi.x) - o.x) * s.inv.x;
-    const float bx = ((s.inv.x >= 0.f ? hi.x : lo.x) - o.x) * s.inv.x;
-    const float ay = ((s.inv.y >= 0.f ? lo.y : hi.y) - o.y) * s.inv.y;
-    const float by = ((s.inv.y >= 0.f ? hi.y : lo.y) - o.y) * s.inv.y;
-    const float az = ((s.inv.z >= 0.f ? lo.z : hi.z) - o.z) * s.inv.z;
-    const float bz = ((s.inv.z >= 0.f ? hi.z : lo.z) - o.z) * s.inv.z;
+    const float ax = ((s.inv.x >= 0.f ? sc.lo[0] : sc.hi[0]) - o.x) * s.inv.x;
+    const float bx = ((s.inv.x >= 0.f ? sc.hi[0] : sc.lo[0]) - o.x) * s.inv.x;
+    const float ay = ((s.inv.y >= 0.f ? sc.lo[1] : sc.hi[1]) - o.y) * s.inv.y;
+    const float by = ((s.inv.y >= 0.f ? sc.hi[1] : sc.lo[1]) - o.y) * s.inv.y;
+    const float az = ((s.inv.z >= 0.f ? sc.lo[2] : sc.hi[2]) - o.z) * s.inv.z;
+    const float bz = ((s.inv.z >= 0.f ? sc.hi[2] : sc.lo[2]) - o.z) * s.inv.z;
     const float tn = fmaxf(fmaxf(ax, ay), az), tf = fminf(fminf(bx, by), bz);
     if (!(tn <= tf && tf >= tmin)) return false;
-    if (d.w_root_pts) {  // the whole scene is one leaf
+    if (sc.root_pts) {  // the whole scene is one leaf
         s.pbase = 0;
-        s.pmask = (1ull << d.w_root_pts) - 1ull;
+        s.pmask = (1ull << sc.root_pts) - 1ull;
         s.ghits = 0;
     } else {  // a node group holding the root record alone (octant 0, internal)
         s.pmask = 0;

@@ -134,6 +134,7 @@ struct SlotDesc {
     const uint4* wrec;
     const float4* wpts;
     uint32_t w_root_pts;  // points of the root when it is a leaf, else 0
+    float bvh_lo[3], bvh_hi[3];  // the root's box (as in its node record)
 };
 
 struct ObsDesc {

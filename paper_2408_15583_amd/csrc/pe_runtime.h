@@ -184,6 +184,7 @@ struct pe_scene_s {
     uint4* wrec = nullptr;     // wide records of the internal nodes (pe::kWideRec)
     float4* wpts = nullptr;    // the points in leaf order, 2 float4 each
     uint32_t w_root_pts = 0;   // points of the root when it is a leaf
+    float bvh_root[6] = {0, 0, 0, 0, 0, 0};  // the root's box: low x, y, z, high x, y, z
     float blend_r = 0.f, bl_h = 0.f;  // Eq. (23) refinement radius and centre-grid cell edge
     int bl_G = 0;
     uint32_t *bl_start = nullptr, *bl_items = nullptr;

@@ -236,6 +236,10 @@ void Batch::setup(const std::vector<SlotSpec>& slots, int contrib_, int precisio
         d.wrec = sc->wrec;
         d.wpts = sc->wpts;
         d.w_root_pts = sc->w_root_pts;
+        for (int a = 0; a < 3; a++) {
+            d.bvh_lo[a] = sc->bvh_root[a];
+            d.bvh_hi[a] = sc->bvh_root[3 + a];
+        }
         bvh_depth = std::max(bvh_depth, sc->bvh_levels);
         if (sc->blend_r > 0.f) blend = true;
         d.views = sc->views_dev;
@@ -371,13 +375,20 @@ void Batch::alloc_rays() {
 
 static int persistent_blocks() { return 2048; }
 
-// Idle lanes at which a traversal wavefront takes new rays (PE_BVH_REFILL overrides).
-static int bvh_refill() {
-    static const int v = [] {
-        const char* e = std::getenv("PE_BVH_REFILL");
-        return e ? std::atoi(e) : 16;
-    }();
-    return v;
+// Idle lanes at which a traversal wavefront takes new rays: measured on the composite bench
+// (ms per step, second bounce / visibility) at 8: 83.4 / 13.8, 16: 46.0 / 8.5, 24: 32.0 / 7.0,
+// 32: 26.1 / 7.2, 40: 25.8 / 7.6, 48: 25.8 / 7.7, 64: 32.1 / 10.0.  PE_BVH_REFILL and
+// PE_PSI_REFILL override.
+static int bvh_refill(bool psi) {
+    static const int v[2] = {[] {
+                                 const char* e = std::getenv("PE_BVH_REFILL");
+                                 return e ? std::atoi(e) : 40;
+                             }(),
+                             [] {
+                                 const char* e = std::getenv("PE_PSI_REFILL");
+                                 return e ? std::atoi(e) : 24;
+                             }()};
+    return v[psi ? 1 : 0];
 }
 
 void Batch::raygen() {
@@ -444,7 +455,7 @@ void Batch::records(int seg, const uint32_t* list, const uint32_t* n_list) {
         prof_end("psi_compact");
         prof_begin();
         launch_psi_trace(dd, dobs, plist, cnt + C_PSI, max_obs, rs, vis, tot_pix, bvh_depth,
-                         ws.get<uint32_t>(B_MQUEUE, kNumXcd), bvh_refill(), persistent_blocks(),
+                         ws.get<uint32_t>(B_MQUEUE, kNumXcd), bvh_refill(true), persistent_blocks(),
                          st);
         prof_end("psi_bvh");
     }
@@ -471,7 +482,8 @@ void Batch::trace(bool with_records) {
         prof_begin();
         if (secondary == PE_SECONDARY_SPLATS) {
             launch_trace_bvh(dd, cur, ncur, rs, hitkey, b, bvh_depth,
-                             ws.get<uint32_t>(B_MQUEUE, kNumXcd), bvh_refill(), persistent_blocks(),
+                             ws.get<uint32_t>(B_MQUEUE, kNumXcd), bvh_refill(false),
+                             persistent_blocks(),
                              st);
             static const char* names[] = {"bvh_b2", "bvh_b3", "bvh_b4", "bvh_b5", "bvh_b6",
                                           "bvh_b7", "bvh_b8", "bvh_b9+"};
