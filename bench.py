@@ -53,13 +53,13 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=20275437.2, write_kib=887990.3, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17581945.3, write_kib=882936.7, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
-             "e08ecdbc431ee1c8fd4c0ae1ded5e49703737b2d84afa9329f32f62033ff9194",
+             "f9c64e1be0316c2905f9fc2d4d421db1eaea628916b727b16f7ddef15bbaa771",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
-             "71f9e0279725ea611dcdbc18a192e61d2662ba203d639825c1a1237fdef37eca",
+             "94bdb094b2580259f38b92e641e4331f62b95113e71ecc41cdcb271edd958bb8",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "893b4a1556de12b39e1d4bce3c3e5729b02b79ccf6637280312394ca4e76c01c",
+             "104fa9974a6456c5f4f2f1a8b0dd31e0ce750cbf8cd7b7c4e1ad2f7eb0511983",
              "paper_2408_15583_amd/csrc/pe_geom.h":
              "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
 
