@@ -80,12 +80,13 @@ void launch_po_tiles(const SlotDesc* d, const uint32_t* seg_cnt, int n_seg, int 
 // well inside the error of the fp32 sine itself.
 // Both branches are evaluated and one is selected (lanes of a wavefront hold different
 // arguments; the small-argument series costs three operations).
+// The hardware sine takes its argument in revolutions, so the reduced r goes to it directly.
 __device__ inline float sinc_f(float x) {
     const float x2 = x * x;
     const float series = 1.f - x2 * (1.f / 6.f) + x2 * x2 * (1.f / 120.f);
     float r = x * 0.15915494309189535f;
     r -= rintf(r);
-    const float full = __sinf(6.283185307179586f * r) * __builtin_amdgcn_rcpf(x);
+    const float full = __builtin_amdgcn_sinf(r) * __builtin_amdgcn_rcpf(x);
     return x2 < 1e-4f ? series : full;
 }
 
@@ -171,8 +172,8 @@ __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, in
                 rf = (float)(ph - floor(ph));
             }
             if (rf >= 0.5f) rf -= 1.f;
-            const float ang = (float)kTwoPi * rf;
-            const float cs = __cosf(ang), sn = __sinf(ang);
+            // cos and sin of 2 pi rf (the hardware takes revolutions)
+            const float cs = __builtin_amdgcn_cosf(rf), sn = __builtin_amdgcn_sinf(rf);
             const float wr = S * cs, wi = -S * sn;  // S exp(-j phase)
 #pragma unroll
             for (int pq = 0; pq < 4; pq++) {
