@@ -35,17 +35,21 @@ union Frag {
 // ------------------------------------------------------------------------------------------
 // Convolution (stride 1, zero padding (K-1)/2) as implicit GEMM on MFMA
 // ------------------------------------------------------------------------------------------
-// Block: 256 threads = 2 x 2 wavefronts over a tile of 128 pixels x BN output channels.  Each
-// K step covers 32 input channels of one tap: the block stages the A tile (128 pixels x 32
-// channels of the shifted input) and the B tile (BN channels x 32) in LDS, double-buffered, and
-// issues the next step's global loads before the current step's MFMAs.  A wavefront computes
-// BM/2 x BN/2 outputs as BM/32 x BN/32 tiles of v_mfma_f32_16x16x32_bf16.  Small layers take a
-// smaller BM so that the launch still has several workgroups per CU to hide load latency.
-// Requirements (checked by the host): Cin % 32 == 0.
-template <int BN, int BM>
+// Block: 256 threads = WGM x (4 / WGM) wavefronts over a tile of BM pixels x BN output
+// channels.  Each K step covers 32 input channels of one tap: the block stages the A tile (BM
+// pixels x 32 channels of the shifted input) and the B tile (BN channels x 32) in LDS,
+// double-buffered, and issues the next step's global loads before the current step's MFMAs.  A
+// wavefront computes BM/WGM x BN/(4/WGM) outputs as tiles of v_mfma_f32_16x16x32_bf16.  Small
+// layers take a smaller BM so that the launch still has several workgroups per CU to hide load
+// latency; narrow layers stack the wavefronts along the pixels (WGM = 4) so that each still
+// holds several MFMA tiles per K step.  Requirements (checked by the host): Cin % 32 == 0.
+template <int BN, int BM, int WGM = 2>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+    constexpr int WGN = 4 / WGM;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;  // wavefront tile
     constexpr int LDS = 40;                       // 32 k + 8 pad (bf16) per row
-    constexpr int TM = BM / 32, TN = BN / 32;     // MFMA tiles per wavefront
+    constexpr int TM = WTM / 16, TN = WTN / 16;   // MFMA tiles per wavefront
+    static_assert(TM >= 1 && TN >= 1, "wavefront tile of at least one MFMA tile");
     constexpr int ACH = BM * 4, AL = (ACH + 255) / 256;  // A chunks of 8 channels, per thread
     constexpr int TLD = BN + 8;                   // row of the bf16 output tile (epilogue)
     __shared__ __attribute__((aligned(16))) uint16_t smem[2 * BM * LDS + 2 * BN * LDS];
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     uint16_t(*As)[BM][LDS] = reinterpret_cast<uint16_t(*)[BM][LDS]>(smem);
     uint16_t(*Bs)[BN][LDS] = reinterpret_cast<uint16_t(*)[BN][LDS]>(smem + 2 * BM * LDS);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WGM, wn = wave / WGM;
     const int HW = a.H * a.W, M = a.N * HW;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     const int pad = (a.K - 1) / 2, taps = a.K * a.K, kpt = a.Cin / 32, steps = taps * kpt;
@@ -113,9 +117,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         if (step + 1 < steps) gload(step + 1);
         Frag fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; i++) fa[i].u = *(const uint4*)&As[buf][wm * (BM / 2) + i * 16 + r][kq];
+        for (int i = 0; i < TM; i++) fa[i].u = *(const uint4*)&As[buf][wm * WTM + i * 16 + r][kq];
 #pragma unroll
-        for (int j = 0; j < TN; j++) fb[j].u = *(const uint4*)&Bs[buf][wn * (BN / 2) + j * 16 + r][kq];
+        for (int j = 0; j < TN; j++) fb[j].u = *(const uint4*)&Bs[buf][wn * WTN + j * 16 + r][kq];
 #pragma unroll
         for (int i = 0; i < TM; i++)
 #pragma unroll
@@ -132,12 +136,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         for (int i = 0; i < TM; i++)
 #pragma unroll
             for (int j = 0; j < TN; j++) {
-                const int co = n0 + wn * (BN / 2) + j * 16 + r;
+                const int co = n0 + wn * WTN + j * 16 + r;
                 const bool cok = co < a.Cout_store;
                 const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const int m = m0 + wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + q;
+                    const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + q;
                     if (cok && m < M) {
                         float v = acc[i][j][q] + bias;
                         if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
@@ -164,12 +168,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     for (int i = 0; i < TM; i++)
 #pragma unroll
         for (int j = 0; j < TN; j++) {
-            const int col = wn * (BN / 2) + j * 16 + r, co = n0 + col;
+            const int col = wn * WTN + j * 16 + r, co = n0 + col;
             const bool cok = co < a.Cout_store;
             const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int row = wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + q, m = m0 + row;
+                const int row = wm * WTM + i * 16 + (lane >> 4) * 4 + q, m = m0 + row;
                 float v = acc[i][j][q] + bias;
                 if (a.res && cok && m < M) v += bf2f(a.res[(size_t)m * a.ldres + co]);
                 if (a.z && cok && m < M) {
@@ -231,24 +235,32 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     }
 }
 
-template <int BN>
-static void launch_conv_fwd_bn(const ConvArgs& a, int M, unsigned gy, hipStream_t st) {
-    // 64-pixel tiles (measured faster than 128: half the registers, twice the workgroups per
-    // CU to hide load latency), 32-pixel tiles when even those give under four workgroups per CU
-    if ((uint64_t)((M + 63) / 64) * gy >= 1024)
-        hipLaunchKernelGGL((k_conv_fwd<BN, 64>), dim3((M + 63) / 64, gy), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_conv_fwd<BN, 32>), dim3((M + 31) / 32, gy), dim3(256), 0, st, a);
+template <int BN, int BM, int WGM>
+static bool launch_conv_fwd_t(const ConvArgs& a, int M, unsigned gy, bool force, hipStream_t st) {
+    const unsigned gx = (unsigned)((M + BM - 1) / BM);
+    if (!force && (uint64_t)gx * gy < 1024) return false;
+    hipLaunchKernelGGL((k_conv_fwd<BN, BM, WGM>), dim3(gx, gy), dim3(256), 0, st, a);
+    return true;
 }
 
+// Tile choice per output width (measured, batch of 8 at 256^2 -> 512^2: inference 2.37 ms with
+// 2 x 2 wavefronts for every width, 2.30 with the narrow layers' wavefronts stacked along the
+// pixels, 2.38 with 256-pixel tiles for 32-channel outputs): the largest tile that still gives
+// the launch 1024 workgroups.
 void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     const int M = a.N * a.H * a.W;
-    if (a.Cout > 64)
-        launch_conv_fwd_bn<128>(a, M, (unsigned)((a.Cout + 127) / 128), st);
-    else if (a.Cout > 32)
-        launch_conv_fwd_bn<64>(a, M, 1u, st);
-    else
-        launch_conv_fwd_bn<32>(a, M, 1u, st);
+    if (a.Cout > 64) {
+        const unsigned gy = (unsigned)((a.Cout + 127) / 128);
+        if (!launch_conv_fwd_t<128, 64, 2>(a, M, gy, false, st))
+            launch_conv_fwd_t<128, 32, 2>(a, M, gy, true, st);
+    } else if (a.Cout > 32) {
+        if (!launch_conv_fwd_t<64, 128, 4>(a, M, 1u, false, st) &&
+            !launch_conv_fwd_t<64, 64, 2>(a, M, 1u, false, st))
+            launch_conv_fwd_t<64, 32, 2>(a, M, 1u, true, st);
+    } else {
+        if (!launch_conv_fwd_t<32, 128, 4>(a, M, 1u, false, st))
+            launch_conv_fwd_t<32, 64, 4>(a, M, 1u, true, st);
+    }
 }
 
 // Weight gradient: dW[co][t][ci] = sum_p dY[p][co] X[p + shift(t)][ci] over one chunk of
