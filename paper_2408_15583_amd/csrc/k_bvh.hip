@@ -289,6 +289,14 @@ void launch_wide_emit(const float4* nodes, uint32_t n_nodes, const uint32_t* rec
                        pb_s, wrec, wpts);
 }
 
+// Launch parameter of the persistent loop: idle lanes at which a wavefront refills (bits 0-7,
+// 1 .. 64) and the quorum of lanes holding points for a point step (bits 8-15, 0 .. 64).
+static int pack_refill(int refill) {
+    const int r = std::min(64, std::max(1, refill & 0xFF));
+    const int q = std::min(64, (refill >> 8) & 0xFF);
+    return r | (q << 8);
+}
+
 // Persistent traversal loop shared by the two passes: every lane holds one ray; a wavefront
 // takes new work items for its idle lanes from a global counter once at least `refill` of its
 // lanes are idle (all from one atomic, so the lanes of a batch are neighbouring items), and
@@ -298,8 +306,8 @@ void launch_wide_emit(const float4* nodes, uint32_t n_nodes, const uint32_t* rec
 // result); finish(j, s): write the result of a finished item.
 template <bool any, class Start, class Finish>
 __device__ inline void bvh_persistent(const SlotDesc* __restrict__ ds, uint64_t n_items,
-                                      uint32_t* __restrict__ queue, int refill, Start start,
-                                      Finish finish) {
+                                      uint32_t* __restrict__ queue, int refill, int quorum,
+                                      Start start, Finish finish) {
     extern __shared__ uint64_t stk[];
     uint64_t* my = stk + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -323,11 +331,27 @@ __device__ inline void bvh_persistent(const SlotDesc* __restrict__ ds, uint64_t 
                 }
             }
         }
-        if (__ballot(active) == 0) {
+        const uint64_t act = __ballot(active);
+        if (act == 0) {
             if (exhausted) break;
             continue;
         }
-        if (active && bvh_step<any>(*dp, s, my, blockDim.x)) {
+        // quorum > 0: one kind of step per iteration for the whole wavefront, point tests once
+        // `quorum` lanes (or all busy lanes) hold points, else node expansions by the lanes
+        // that hold none; quorum 0: each lane takes its own kind of step
+        bool done = false;
+        if (quorum > 0) {
+            const uint64_t want = __ballot(active && s.pmask != 0);
+            const bool points = __popcll(want) >= quorum || want == act;
+            if (points) {
+                if (active && s.pmask != 0) done = bvh_points<any>(s);
+            } else {
+                if (active && s.pmask == 0) done = bvh_node<any>(s, my, blockDim.x);
+            }
+        } else if (active) {
+            done = bvh_step<any>(*dp, s, my, blockDim.x);
+        }
+        if (done) {
             finish(item, s);
             active = false;
         }
@@ -344,7 +368,7 @@ __global__ __launch_bounds__(256) void k_trace_bvh(const SlotDesc* __restrict__ 
                                                    int bounce, uint32_t* __restrict__ queue,
                                                    int refill) {
     bvh_persistent<false>(
-        ds, *n_live, queue, refill,
+        ds, *n_live, queue, refill & 0xFF, refill >> 8,
         [&](uint64_t j, const SlotDesc*& dp, BvhState& s) {
             // three rounds of loads: the entry; the slot's fields; the ray state
             const uint32_t entry = list[j];
@@ -373,7 +397,7 @@ void launch_trace_bvh(const SlotDesc* d, const uint32_t* list, const uint32_t* n
     launch_fill_u32(queue, 0u, 1, st);
     hipLaunchKernelGGL(k_trace_bvh, dim3(n_blocks), dim3(256),
                        (size_t)stack_depth * 256 * sizeof(uint64_t), st, d, list, n_live, rs,
-                       hitkey, bounce, queue, std::min(64, std::max(1, refill)));
+                       hitkey, bounce, queue, pack_refill(refill));
 }
 
 // Visibility, pass 1: which entries need a traced Psi (every facet of a bistatic slot, the
@@ -419,7 +443,7 @@ __global__ __launch_bounds__(256) void k_psi_trace(const SlotDesc* __restrict__ 
                                                    uint8_t* __restrict__ vis, uint64_t vis_stride,
                                                    uint32_t* __restrict__ queue, int refill) {
     bvh_persistent<true>(
-        ds, (uint64_t)*n_list * (uint32_t)max_obs, queue, refill,
+        ds, (uint64_t)*n_list * (uint32_t)max_obs, queue, refill & 0xFF, refill >> 8,
         [&](uint64_t w, const SlotDesc*& dp, BvhState& s) {
             // three rounds of loads: the entry; the slot's fields; the facet position and the
             // observation direction
@@ -454,7 +478,7 @@ void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* lis
     launch_fill_u32(queue, 0u, 1, st);
     hipLaunchKernelGGL(k_psi_trace, dim3(n_blocks), dim3(256),
                        (size_t)stack_depth * 256 * sizeof(uint64_t), st, d, obs, list, n_list,
-                       max_obs, rs, vis, vis_stride, queue, std::min(64, std::max(1, refill)));
+                       max_obs, rs, vis, vis_stride, queue, pack_refill(refill));
 }
 
 }  // namespace pe

@@ -249,9 +249,8 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
     return nh == 0 && pm == 0 && s.sp == 0;
 }
 
-// One step of a lane: a point step while its point group holds points, else a node step.
-// (Taking one kind of step for the whole wavefront at a time, by a quorum of lanes, was slower:
-// the two kinds then no longer share a memory round trip.)
+// One step of a lane: a point step while its point group holds points, else a node step (the
+// persistent loop can instead take one kind of step for the whole wavefront at a time).
 template <bool any>
 __device__ inline bool bvh_step(const SlotDesc&, BvhState& s, uint64_t* stk, int stride) {
     return s.pmask != 0 ? bvh_points<any>(s) : bvh_node<any>(s, stk, stride);

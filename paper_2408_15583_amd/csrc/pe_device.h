@@ -271,7 +271,9 @@ void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* lis
 // above), written to hitkey[entry] (kEmptyKey when none).  stack_depth: the batch's largest
 // octree level count (<= kBvhMaxStack), u64 LDS entries per thread.  Both traversal passes are
 // persistent: queue is one u32 work counter (cleared by the launcher), and a wavefront refills
-// its idle lanes once `refill` (1 .. 64) of them are idle.
+// its idle lanes once `refill & 0xFF` (1 .. 64) of them are idle; with a quorum q = refill >> 8
+// above 0 it takes one kind of step per iteration (point tests once q lanes hold points, else
+// node expansions), with 0 each lane its own.
 void launch_trace_bvh(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
                       RayState rs, uint64_t* hitkey, int bounce, int stack_depth,
                       uint32_t* queue, int refill, int n_blocks, hipStream_t st);

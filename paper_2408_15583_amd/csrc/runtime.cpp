@@ -375,19 +375,20 @@ void Batch::alloc_rays() {
 
 static int persistent_blocks() { return 2048; }
 
-// Idle lanes at which a traversal wavefront takes new rays: measured on the composite bench
-// (ms per step, second bounce / visibility) at 8: 83.4 / 13.8, 16: 46.0 / 8.5, 24: 32.0 / 7.0,
-// 32: 26.1 / 7.2, 40: 25.8 / 7.6, 48: 25.8 / 7.7, 64: 32.1 / 10.0.  PE_BVH_REFILL and
-// PE_PSI_REFILL override.
+// Idle lanes at which a traversal wavefront takes new rays (bits 0-7) and the quorum of lanes
+// holding points at which it runs a point step for the whole wavefront (bits 8-15, 0 = each
+// lane its own kind of step).  Measured on the composite bench (ms per step, second bounce /
+// visibility), refill alone at 8: 83.4 / 13.8, 16: 46.0 / 8.5, 24: 32.0 / 7.0, 32: 26.1 / 7.2,
+// 40: 25.8 / 7.6, 48: 25.8 / 7.7, 64: 32.1 / 10.0; with refill 40, quorum 8: 22.9 / 6.6,
+// 12: 22.4 / 7.0, 16: 22.7 / 7.1 (visibility keeps its own kind of step per lane, 6.6).
+// PE_BVH_REFILL, PE_BVH_QUORUM and PE_PSI_REFILL override.
 static int bvh_refill(bool psi) {
-    static const int v[2] = {[] {
-                                 const char* e = std::getenv("PE_BVH_REFILL");
-                                 return e ? std::atoi(e) : 40;
-                             }(),
-                             [] {
-                                 const char* e = std::getenv("PE_PSI_REFILL");
-                                 return e ? std::atoi(e) : 24;
-                             }()};
+    auto env = [](const char* name, int dflt) {
+        const char* e = std::getenv(name);
+        return e ? std::atoi(e) : dflt;
+    };
+    static const int v[2] = {env("PE_BVH_REFILL", 40) | (env("PE_BVH_QUORUM", 12) << 8),
+                             env("PE_PSI_REFILL", 24)};
     return v[psi ? 1 : 0];
 }
 
