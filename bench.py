@@ -53,13 +53,13 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=17581945.3, write_kib=882936.7, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17954988.0, write_kib=867193.3, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
-             "f9c64e1be0316c2905f9fc2d4d421db1eaea628916b727b16f7ddef15bbaa771",
+             "5c94a756cb27e1a41c9edfca303096dbefa8334d2736a54b602e1dc2f70df6da",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
-             "94bdb094b2580259f38b92e641e4331f62b95113e71ecc41cdcb271edd958bb8",
+             "21e2fd657b43e64aa48818dcfcb33f957065dd8b11dc61628537e90b73284ebf",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "104fa9974a6456c5f4f2f1a8b0dd31e0ce750cbf8cd7b7c4e1ad2f7eb0511983",
+             "ae8bb7c4aa3d4ab250f5c2c5a9949149edb288ecd030c1ae67369d0f81ce0178",
              "paper_2408_15583_amd/csrc/pe_geom.h":
              "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
 
