@@ -4,8 +4,9 @@
 // Layout: activations NHWC in bf16 (uint16 storage), convolution weights OHWI in bf16 with
 // fp32 master copies; every GEMM-shaped convolution runs on MFMA (v_mfma_f32_16x16x32_bf16,
 // fp32 accumulation): forward and data-gradient as implicit GEMM over (pixels x Cout x taps*Cin)
-// with fragments loaded straight from NHWC/OHWI (8 contiguous bf16 per lane), weight-gradient as
-// GEMM over (Cout x Cin x pixels) with tiles transposed through LDS.  Everything that reduces
+// with the tiles copied from NHWC/OHWI straight into LDS (3 x 3 layers over two-dimensional
+// pixel tiles whose input halo serves all nine taps), weight-gradient as GEMM over
+// (Cout x Cin x pixels) with tiles transposed through LDS.  Everything that reduces
 // over pixels writes per-chunk partials summed in a fixed order, so a training step is
 // bit-reproducible.  Depthwise 7x7, LayerNorm, GELU, pooling, losses and AdamW are VALU kernels.
 #include <float.h>
@@ -32,103 +33,22 @@ union Frag {
     v8bf v;
 };
 
-// ------------------------------------------------------------------------------------------
-// Convolution (stride 1, zero padding (K-1)/2) as implicit GEMM on MFMA
-// ------------------------------------------------------------------------------------------
-// Block: 256 threads = WGM x (4 / WGM) wavefronts over a tile of BM pixels x BN output
-// channels.  Each K step covers 32 input channels of one tap: the block stages the A tile (BM
-// pixels x 32 channels of the shifted input) and the B tile (BN channels x 32) in LDS,
-// double-buffered, and issues the next step's global loads before the current step's MFMAs.  A
-// wavefront computes BM/WGM x BN/(4/WGM) outputs as tiles of v_mfma_f32_16x16x32_bf16.  Small
-// layers take a smaller BM so that the launch still has several workgroups per CU to hide load
-// latency; narrow layers stack the wavefronts along the pixels (WGM = 4) so that each still
-// holds several MFMA tiles per K step.  Requirements (checked by the host): Cin % 32 == 0.
-template <int BN, int BM, int WGM = 2>
-__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+// Epilogue of the convolution kernels: bias, residual, GELU, optional pre-activation copy and
+// pixel shuffle, from the accumulator fragments of a BM x BN tile.  The bf16 outputs go through
+// LDS (smem, at least BM x (BN + 8) bf16, free when this is called) for 16-byte row stores.
+// rowm maps a tile row to its output pixel index m (m >= M: past the end, not stored).
+template <int BN, int BM, int WGM, class RowM>
+__device__ inline void conv_epilogue(const ConvArgs& a,
+                                     const v4f (&acc)[BM / WGM / 16][BN / (4 / WGM) / 16],
+                                     uint16_t* smem, RowM rowm, int n0) {
     constexpr int WGN = 4 / WGM;
-    constexpr int WTM = BM / WGM, WTN = BN / WGN;  // wavefront tile
-    constexpr int LDS = 40;                       // 32 k + 8 pad (bf16) per row
-    constexpr int TM = WTM / 16, TN = WTN / 16;   // MFMA tiles per wavefront
-    static_assert(TM >= 1 && TN >= 1, "wavefront tile of at least one MFMA tile");
-    constexpr int ACH = BM * 4, AL = (ACH + 255) / 256;  // A chunks of 8 channels, per thread
-    constexpr int TLD = BN + 8;                   // row of the bf16 output tile (epilogue)
-    __shared__ __attribute__((aligned(16))) uint16_t smem[2 * BM * LDS + 2 * BN * LDS];
-    static_assert(BM * TLD <= 2 * BM * LDS + 2 * BN * LDS, "output tile fits the staging LDS");
-    uint16_t(*As)[BM][LDS] = reinterpret_cast<uint16_t(*)[BM][LDS]>(smem);
-    uint16_t(*Bs)[BN][LDS] = reinterpret_cast<uint16_t(*)[BN][LDS]>(smem + 2 * BM * LDS);
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    constexpr int TLD = BN + 8;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
     const int HW = a.H * a.W, M = a.N * HW;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int pad = (a.K - 1) / 2, taps = a.K * a.K, kpt = a.Cin / 32, steps = taps * kpt;
-    // loader: A chunk c = tid + 256 i (c < ACH): row c >> 2, 8 channels at (c & 3) * 8
-    const int kc = (tid & 3) * 8;
-    int pn[AL], py[AL], px[AL];
-    bool pv[AL];
-    for (int i = 0; i < AL; i++) {
-        const int m = m0 + (tid >> 2) + 64 * i;
-        pv[i] = m < M && tid + 256 * i < ACH;
-        const int mm = pv[i] ? m : 0;
-        pn[i] = mm / HW;
-        py[i] = (mm % HW) / a.W;
-        px[i] = mm % a.W;
-    }
-    constexpr int BCH = BN * 4;                  // B chunks of 8 channels
-    uint4 ra[AL], rb[2];
-    auto gload = [&](int step) {
-        const int t = step / kpt, c0 = (step - t * kpt) * 32;
-        const int dy = t / a.K - pad, dx = t % a.K - pad;
-        for (int i = 0; i < AL; i++) {
-            const int y = py[i] + dy, x = px[i] + dx;
-            const bool ok = pv[i] && y >= 0 && y < a.H && x >= 0 && x < a.W;
-            ra[i] = ok ? *(const uint4*)(a.x + ((size_t)(pn[i] * a.H + y) * a.W + x) * a.ldx +
-                                         a.xoff + c0 + kc)
-                       : make_uint4(0, 0, 0, 0);
-        }
-        for (int i = 0; i < 2; i++) {
-            const int c = tid + 256 * i;
-            rb[i] = make_uint4(0, 0, 0, 0);
-            if (c < BCH) {
-                const int co = n0 + (c >> 2);
-                if (co < a.Cout)
-                    rb[i] = *(const uint4*)(a.w + ((size_t)co * taps + t) * a.Cin + c0 + (c & 3) * 8);
-            }
-        }
-    };
-    auto sstore = [&](int buf) {
-        for (int i = 0; i < AL; i++)
-            if (tid + 256 * i < ACH) *(uint4*)&As[buf][(tid >> 2) + 64 * i][kc] = ra[i];
-        for (int i = 0; i < 2; i++) {
-            const int c = tid + 256 * i;
-            if (c < BCH) *(uint4*)&Bs[buf][c >> 2][(c & 3) * 8] = rb[i];
-        }
-    };
-    v4f acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; i++)
-#pragma unroll
-        for (int j = 0; j < TN; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    const int r = lane & 15, kq = (lane >> 4) * 8;
-    for (int step = 0; step < steps; step++) {
-        const int buf = step & 1;
-        if (step + 1 < steps) gload(step + 1);
-        Frag fa[TM], fb[TN];
-#pragma unroll
-        for (int i = 0; i < TM; i++) fa[i].u = *(const uint4*)&As[buf][wm * WTM + i * 16 + r][kq];
-#pragma unroll
-        for (int j = 0; j < TN; j++) fb[j].u = *(const uint4*)&Bs[buf][wn * WTN + j * 16 + r][kq];
-#pragma unroll
-        for (int i = 0; i < TM; i++)
-#pragma unroll
-            for (int j = 0; j < TN; j++)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
-                                                                   0, 0);
-        if (step + 1 < steps) sstore(buf ^ 1);
-        __syncthreads();
-    }
+    const int r = lane & 15;
     // D fragment: lane holds column (channel) r of rows (pixels) 4 * (lane / 16) + q
     if (a.y32) {
         // fp32 outputs (the heads' last layers, few channels): straight from the fragments
@@ -141,7 +61,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
                 const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + q;
+                    const int m = rowm(wm * WTM + i * 16 + (lane >> 4) * 4 + q);
                     if (cok && m < M) {
                         float v = acc[i][j][q] + bias;
                         if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
@@ -173,7 +93,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
             const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int row = wm * WTM + i * 16 + (lane >> 4) * 4 + q, m = m0 + row;
+                const int row = wm * WTM + i * 16 + (lane >> 4) * 4 + q, m = rowm(row);
                 float v = acc[i][j][q] + bias;
                 if (a.res && cok && m < M) v += bf2f(a.res[(size_t)m * a.ldres + co]);
                 if (a.z && cok && m < M) {
@@ -196,7 +116,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     if (!a.shuffle) {
         constexpr int C8 = BN / 8;
         for (int c = tid; c < BM * C8; c += 256) {
-            const int row = c / C8, c8 = c - row * C8, m = m0 + row, co = n0 + c8 * 8;
+            const int row = c / C8, c8 = c - row * C8, m = rowm(row), co = n0 + c8 * 8;
             if (m >= M || co >= a.Cout_store) continue;
             uint16_t* out = a.y + (size_t)m * a.ldy + a.yoff + co;
             const uint16_t* src = &T[row * TLD + c8 * 8];
@@ -212,7 +132,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         const int oc_end = a.Cout_store >> 2;
         for (int c = tid; c < BM * 4 * O8; c += 256) {
             const int row = c / (4 * O8), rem = c - row * (4 * O8), sub = rem / O8,
-                      c8 = rem - sub * O8, m = m0 + row, oc0 = (n0 >> 2) + c8 * 8;
+                      c8 = rem - sub * O8, m = rowm(row), oc0 = (n0 >> 2) + c8 * 8;
             if (m >= M || oc0 >= oc_end) continue;
             const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
             const int sy = sub >> 1, sx = sub & 1;
@@ -235,31 +155,335 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     }
 }
 
-template <int BN, int BM, int WGM>
-static bool launch_conv_fwd_t(const ConvArgs& a, int M, unsigned gy, bool force, hipStream_t st) {
+// ------------------------------------------------------------------------------------------
+// Convolution (stride 1, zero padding (K-1)/2) as implicit GEMM on MFMA
+// ------------------------------------------------------------------------------------------
+// Block: 256 threads = WGM x (4 / WGM) wavefronts over a tile of BM pixels x BN output
+// channels.  Each K step covers 32 input channels of one tap: the A tile (BM pixels x 32
+// channels of the shifted input) and the B tile (BN channels x 32) are copied from global memory
+// straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the instruction's LDS
+// base + 16 x lane) through NS stages, so that the copies of a K step are issued NS - 1 steps
+// before its MFMAs and cost no registers.  A wavefront computes BM/WGM x BN/(4/WGM) outputs as
+// tiles of v_mfma_f32_16x16x32_bf16.  A stage holds BM + BN rows of 32 bf16 (64 bytes, no
+// padding); a row's four 16-byte chunks are stored at position chunk ^ ((row / 2) % 4), which
+// puts the 8 rows of each phase of a fragment read on distinct banks.  Halo pixels, pixels past
+// the end and weights past Cout are copied from a zero line.  Every wavefront issues the same
+// number of copies per stage (padded with copies of the zero line into a spare slot) so that one
+// vmcnt bound finds a stage complete in each of them.  Small layers take a smaller BM so that
+// the launch still has several workgroups per CU; narrow layers stack the wavefronts along the
+// pixels (WGM = 4) so that each still holds several MFMA tiles per K step.  Requirements
+// (checked by the host): Cin % 32 == 0.
+__device__ __attribute__((aligned(16))) uint4 g_conv_zero[4];
+
+// One 16-byte-per-lane copy from global memory into LDS at byte address lds (wave-uniform).
+// Written as inline assembly so that the compiler's own wait insertion, which treats such a
+// copy as a pending write to every LDS address and would wait for all copies in flight before
+// each LDS read, leaves the stage pipeline alone; the stages are waited for explicitly.  The
+// copy has no register results.
+__device__ inline void copy_to_lds16(const void* src, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src),
+                 "s"(lds)
+                 : "memory", "m0");
+}
+
+template <int N>
+__device__ inline void wait_stage_then_barrier() {
+    // vmcnt(N) and lgkmcnt(0) (this wavefront's LDS accesses done), then the workgroup barrier;
+    // the memory clobber keeps the compiler from moving memory accesses across it
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <int BN, int BM, int WGM, int NS>
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+    constexpr int WGN = 4 / WGM;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    static_assert(TM >= 1 && TN >= 1, "wavefront tile of at least one MFMA tile");
+    constexpr int AI = BM / 16, BI = BN / 16;   // 1 KB copies per stage (16 rows each)
+    constexpr int NI = (AI + BI + 3) / 4;       // copies per wavefront per stage
+    constexpr int SU = (BM + BN) * 4;           // stage size in 16-byte units
+    constexpr int TLD = BN + 8;
+    static_assert(BM * TLD * 2 <= NS * SU * 16, "output tile fits the stage LDS");
+    __shared__ __attribute__((aligned(16))) uint4 lds[NS * SU + 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int HW = a.H * a.W, M = a.N * HW;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int pad = (a.K - 1) / 2, taps = a.K * a.K, kpt = a.Cin / 32, steps = taps * kpt;
+    // this lane's slot in every copy: row q * 16 + lane / 4, position lane % 4, which holds
+    // chunk (lane % 4) ^ ((row / 2) % 4)
+    const int chunk = (lane & 3) ^ ((lane >> 3) & 3);
+    const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_conv_zero);
+    // per copy i of this wavefront: kind (0 A, 1 B, 2 spare), LDS unit offset in a stage, and
+    // the lane's source: pixel (n, y, x) or output channel
+    int kind[NI], uoff[NI], py[NI], px[NI];
+    bool val[NI];
+    size_t base[NI];
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+        const int q = wave + 4 * i;
+        py[i] = px[i] = 0;
+        base[i] = 0;
+        val[i] = false;
+        if (q < AI) {
+            kind[i] = 0;
+            uoff[i] = q * 64;
+            const int m = m0 + q * 16 + (lane >> 2);
+            if (m < M) {
+                const int n = m / HW, y = (m % HW) / a.W, x = m % a.W;
+                val[i] = true;
+                py[i] = y;
+                px[i] = x;
+                base[i] = ((size_t)(n * a.H + y) * a.W + x) * a.ldx + a.xoff + chunk * 8;
+            }
+        } else if (q < AI + BI) {
+            kind[i] = 1;
+            uoff[i] = (q - AI) * 64 + BM * 4;
+            const int co = n0 + (q - AI) * 16 + (lane >> 2);
+            val[i] = co < a.Cout;
+            if (val[i]) base[i] = (size_t)co * taps * a.Cin + chunk * 8;
+        } else {
+            kind[i] = 2;  // the spare slot after the stages
+            uoff[i] = NS * SU;
+        }
+    }
+    // next stage to copy: tap lt (offset ldy, ldx from the centre), channel lc
+    int lt = 0, lc = 0, ldy = -pad, ldx = -pad;
+    auto issue = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NI; i++) {
+            const uint16_t* src = zero;
+            if (kind[i] == 0) {
+                const int y = py[i] + ldy, x = px[i] + ldx;
+                if (val[i] && y >= 0 && y < a.H && x >= 0 && x < a.W)
+                    src = a.x + base[i] + (ptrdiff_t)(ldy * a.W + ldx) * a.ldx + lc;
+            } else if (kind[i] == 1) {
+                if (val[i]) src = a.w + base[i] + (size_t)lt * a.Cin + lc;
+            }
+            const uint4* dst = kind[i] == 2 ? lds + NS * SU : lds + buf * SU + uoff[i];
+            copy_to_lds16(src, __builtin_amdgcn_readfirstlane(
+                                   (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint4*)dst));
+        }
+        lc += 32;
+        if (lc == a.Cin) {
+            lc = 0;
+            lt++;
+            if (++ldx > pad) {
+                ldx = -pad;
+                ldy++;
+            }
+        }
+    };
+    v4f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NS - 1; s++)
+        if (s < steps) issue(s);
+    // fragment reads: row (local) R = tile base + lane % 16 holds chunk c at c ^ ((R / 2) % 4)
+    const int r = lane & 15, pos = (lane >> 4) ^ ((r >> 1) & 3);
+    for (int step = 0; step < steps; step++) {
+        const int buf = step % NS;
+        if (steps - 1 - step >= NS - 2) wait_stage_then_barrier<NI * (NS - 2)>();
+        else wait_stage_then_barrier<0>();
+        if (step + NS - 1 < steps) issue((step + NS - 1) % NS);
+        const uint4* S = lds + buf * SU;
+        Frag fa[TM], fb[TN];
+#pragma unroll
+        for (int i = 0; i < TM; i++) fa[i].u = S[(wm * WTM + i * 16 + r) * 4 + pos];
+#pragma unroll
+        for (int j = 0; j < TN; j++) fb[j].u = S[BM * 4 + (wn * WTN + j * 16 + r) * 4 + pos];
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
+                                                                   0, 0);
+    }
+    // every copy has landed (the last step waited for all); all fragment reads are done
+    // before the epilogue reuses the stages
+    wait_stage_then_barrier<0>();
+    conv_epilogue<BN, BM, WGM>(a, acc, reinterpret_cast<uint16_t*>(lds),
+                               [m0](int row) { return m0 + row; }, n0);
+}
+
+template <int BN, int BM, int WGM, int NS>
+static bool launch_conv_fwd_t(const ConvArgs& a, int M, unsigned gy, bool force,
+                                  hipStream_t st) {
     const unsigned gx = (unsigned)((M + BM - 1) / BM);
     if (!force && (uint64_t)gx * gy < 1024) return false;
-    hipLaunchKernelGGL((k_conv_fwd<BN, BM, WGM>), dim3(gx, gy), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_conv_fwd<BN, BM, WGM, NS>), dim3(gx, gy), dim3(256), 0, st, a);
     return true;
 }
 
-// Tile choice per output width (measured, batch of 8 at 256^2 -> 512^2: inference 2.37 ms with
-// 2 x 2 wavefronts for every width, 2.30 with the narrow layers' wavefronts stacked along the
-// pixels, 2.38 with 256-pixel tiles for 32-channel outputs): the largest tile that still gives
-// the launch 1024 workgroups.
+// 3 x 3 convolutions over two-dimensional pixel tiles (TH rows x 16 columns of one image): the
+// K loop runs over 32-channel slices of the input and, within a slice, over the nine taps.  The
+// slice's input halo ((TH + 2) x 18 pixels x 32 channels) is copied into LDS once and serves all
+// nine taps, so the input is read about (TH + 2) x 18 / (16 TH) times instead of nine times; the
+// weights of one (slice, tap) step go through NS copy stages as in k_conv_fwd.  Halo buffers
+// are double-buffered over slices: the next slice's halo is copied at the first step of the
+// current one.  Requirements (checked by the host): K = 3, W % 16 == 0, H % TH == 0,
+// Cin % 32 == 0.
+template <int BN, int TH, int WGM, int NS>
+__global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
+    constexpr int TW = 16, BM = TH * TW;
+    constexpr int WGN = 4 / WGM;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    static_assert(TM >= 1 && TN >= 1 && WTM % 16 == 0, "wavefront tile of whole MFMA tiles");
+    constexpr int HWD = TW + 2, HT = (TH + 2) * HWD;  // halo pixels
+    constexpr int HJ = (HT + 15) / 16;                 // halo copies (16 pixels each)
+    constexpr int HU = HJ * 64;                        // halo buffer, 16-byte units
+    constexpr int BI = BN / 16;                        // weight copies per step
+    constexpr int NH = (HJ + 3) / 4, NB = (BI + 3) / 4;  // per wavefront
+    constexpr int SU = BN * 4;
+    constexpr int UNITS = 2 * HU + NS * SU + 64;
+    constexpr int TLD = BN + 8;
+    static_assert(BM * TLD * 2 <= UNITS * 16, "output tile fits the LDS");
+    __shared__ __attribute__((aligned(16))) uint4 lds[UNITS];
+    uint4* const hbuf = lds;
+    uint4* const bst = lds + 2 * HU;
+    uint4* const spare = bst + NS * SU;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int tiles_x = a.W / TW, tiles_xy = tiles_x * (a.H / TH);
+    const int n = blockIdx.x / tiles_xy, rem = blockIdx.x - n * tiles_xy;
+    const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+    const int n0 = blockIdx.y * BN;
+    const int nsl = a.Cin / 32, steps = 9 * nsl;
+    const int chunk = (lane & 3) ^ ((lane >> 3) & 3);
+    const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_conv_zero);
+    // this lane's source in each copy of this wavefront: element offset of its 8 channels at
+    // slice 0 (tap 0 for the weights), or the zero line; halo copies of index >= HJ and weight
+    // copies of index >= BI go to the spare slot
+    size_t hsrc[NH], bsrc[NB];
+    bool hval[NH], bval[NB];
+#pragma unroll
+    for (int i = 0; i < NH; i++) {
+        const int hp = (wave + 4 * i) * 16 + (lane >> 2);
+        const int y = y0 - 1 + hp / HWD, x = x0 - 1 + hp % HWD;
+        hval[i] = hp < HT && y >= 0 && y < a.H && x >= 0 && x < a.W;
+        hsrc[i] = hval[i] ? ((size_t)(n * a.H + y) * a.W + x) * a.ldx + a.xoff + chunk * 8 : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        const int q = wave + 4 * i, co = n0 + q * 16 + (lane >> 2);
+        bval[i] = q < BI && co < a.Cout;
+        bsrc[i] = bval[i] ? (size_t)co * 9 * a.Cin + chunk * 8 : 0;
+    }
+    auto lds_addr = [](const uint4* p) {
+        return __builtin_amdgcn_readfirstlane(
+            (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint4*)p);
+    };
+    auto copy_halo = [&](int sl) {
+        uint4* const hb = hbuf + (sl & 1) * HU;
+#pragma unroll
+        for (int i = 0; i < NH; i++) {
+            const int j = wave + 4 * i;
+            copy_to_lds16(hval[i] ? a.x + hsrc[i] + sl * 32 : zero,
+                          lds_addr(j < HJ ? hb + j * 64 : spare));
+        }
+    };
+    int lt = 0, lsl = 0;  // the next weight step to copy: tap lt of slice lsl
+    auto copy_weights = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            const int q = wave + 4 * i;
+            copy_to_lds16(bval[i] ? a.w + bsrc[i] + (size_t)lt * a.Cin + lsl * 32 : zero,
+                          lds_addr(q < BI ? bst + buf * SU + q * 64 : spare));
+        }
+        if (++lt == 9) {
+            lt = 0;
+            lsl++;
+        }
+    };
+    v4f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    copy_halo(0);
+#pragma unroll
+    for (int s = 0; s < NS - 1; s++)
+        if (s < steps) copy_weights(s);
+    const int r = lane & 15, kc = lane >> 4;
+    const int bpos = kc ^ ((r >> 1) & 3);
+    int hp0[TM];  // halo pixel of this lane's row in MFMA tile i, tap (0, 0)
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+        const int p = wm * WTM + i * 16 + r;
+        hp0[i] = (p / TW) * HWD + p % TW;
+    }
+    for (int s = 0; s < steps; s++) {
+        const int sl = s / 9, t = s - 9 * sl;
+        // copies issued after this step's weights: the next NS - 2 weight steps, plus the next
+        // slice's halo when it was issued within the last NS - 1 steps
+        if (steps - 1 - s < NS - 2) wait_stage_then_barrier<0>();
+        else if (t >= 1 && t <= NS - 1 && sl + 1 < nsl) wait_stage_then_barrier<NB * (NS - 2) + NH>();
+        else wait_stage_then_barrier<NB * (NS - 2)>();
+        if (s + NS - 1 < steps) copy_weights((s + NS - 1) % NS);
+        if (t == 0 && sl + 1 < nsl) copy_halo(sl + 1);
+        const int ky = t / 3, kx = t - 3 * ky;
+        const uint4* Hb = hbuf + (sl & 1) * HU;
+        const uint4* Bb = bst + (s % NS) * SU;
+        Frag fa[TM], fb[TN];
+#pragma unroll
+        for (int i = 0; i < TM; i++) {
+            const int hp = hp0[i] + ky * HWD + kx;
+            fa[i].u = Hb[hp * 4 + (kc ^ ((hp >> 1) & 3))];
+        }
+#pragma unroll
+        for (int j = 0; j < TN; j++) fb[j].u = Bb[(wn * WTN + j * 16 + r) * 4 + bpos];
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
+                                                                   0, 0);
+    }
+    wait_stage_then_barrier<0>();
+    const int HWi = a.H * a.W;
+    conv_epilogue<BN, BM, WGM>(
+        a, acc, reinterpret_cast<uint16_t*>(lds),
+        [=](int row) { return n * HWi + (y0 + row / TW) * a.W + x0 + row % TW; }, n0);
+}
+
+template <int BN, int TH, int WGM, int NS>
+static void launch_conv3_halo_t(const ConvArgs& a, hipStream_t st) {
+    const unsigned gx = (unsigned)(a.N * (a.H / TH) * (a.W / 16));
+    const unsigned gy = (unsigned)((a.Cout + BN - 1) / BN);
+    hipLaunchKernelGGL((k_conv3_halo<BN, TH, WGM, NS>), dim3(gx, gy), dim3(256), 0, st, a);
+}
+
+// Tile choice (measured, batch of 8 at 256^2 -> 512^2): 3 x 3 layers whose images split into
+// 16-column tiles go to k_conv3_halo (4-row tiles for outputs wider than 64 channels, 8-row tiles
+// otherwise; three copy stages: four, six and eight stages were slower at every size); the other
+// layers to k_conv_fwd with the largest tile that still gives the launch 1024 workgroups.
 void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
+    constexpr int NS = 3;
+    if (a.K == 3 && a.W % 16 == 0 && a.H % 8 == 0) {
+        if (a.Cout > 64) launch_conv3_halo_t<128, 4, 2, NS>(a, st);
+        else if (a.Cout > 32) launch_conv3_halo_t<64, 8, 2, NS>(a, st);
+        else launch_conv3_halo_t<32, 8, 4, NS>(a, st);
+        return;
+    }
     const int M = a.N * a.H * a.W;
     if (a.Cout > 64) {
         const unsigned gy = (unsigned)((a.Cout + 127) / 128);
-        if (!launch_conv_fwd_t<128, 64, 2>(a, M, gy, false, st))
-            launch_conv_fwd_t<128, 32, 2>(a, M, gy, true, st);
+        if (!launch_conv_fwd_t<128, 64, 2, NS>(a, M, gy, false, st))
+            launch_conv_fwd_t<128, 32, 2, NS>(a, M, gy, true, st);
     } else if (a.Cout > 32) {
-        if (!launch_conv_fwd_t<64, 128, 4>(a, M, 1u, false, st) &&
-            !launch_conv_fwd_t<64, 64, 2>(a, M, 1u, false, st))
-            launch_conv_fwd_t<64, 32, 2>(a, M, 1u, true, st);
+        if (!launch_conv_fwd_t<64, 128, 4, NS>(a, M, 1u, false, st) &&
+            !launch_conv_fwd_t<64, 64, 2, NS>(a, M, 1u, false, st))
+            launch_conv_fwd_t<64, 32, 2, NS>(a, M, 1u, true, st);
     } else {
-        if (!launch_conv_fwd_t<32, 128, 4>(a, M, 1u, false, st))
-            launch_conv_fwd_t<32, 64, 4>(a, M, 1u, true, st);
+        if (!launch_conv_fwd_t<32, 128, 4, NS>(a, M, 1u, false, st))
+            launch_conv_fwd_t<32, 64, 4, NS>(a, M, 1u, true, st);
     }
 }
 
