@@ -318,13 +318,18 @@ struct pe_densifier_s {
         }
         for (int h = 0; h < kHeads; h++) {
             const uint16_t* u = A.sk[3];
+            // a training step keeps each head's concat buffer for its weight gradient; inference
+            // runs the heads one after another through head 0's buffers, whose skip half then
+            // needs copying once
+            const int hc = train ? h : 0;
             for (int l = 3; l >= 1; l--) {
                 const int c = C[l - 1], Hl = H >> l, Wl = W >> l;
-                conv_fwd(up[h][l], u, C[l], 0, N, Hl, Wl, A.cat[h][l - 1], nullptr, 2 * c, 0, 0, 1,
+                conv_fwd(up[h][l], u, C[l], 0, N, Hl, Wl, A.cat[hc][l - 1], nullptr, 2 * c, 0, 0, 1,
                          nullptr, nullptr, st);
-                launch_copy_slice(A.sk[l - 1], c, 0, N * (Hl * 2) * (Wl * 2), c, A.cat[h][l - 1],
-                                  2 * c, c, st);
-                conv_fwd(fuse[h][l], A.cat[h][l - 1], 2 * c, 0, N, 2 * Hl, 2 * Wl, A.u[h][l - 1],
+                if (train || h == 0)
+                    launch_copy_slice(A.sk[l - 1], c, 0, N * (Hl * 2) * (Wl * 2), c,
+                                      A.cat[hc][l - 1], 2 * c, c, st);
+                conv_fwd(fuse[h][l], A.cat[hc][l - 1], 2 * c, 0, N, 2 * Hl, 2 * Wl, A.u[h][l - 1],
                          nullptr, c, 0, 1, 0, train ? A.zf[h][l - 1] : nullptr, nullptr, st);
                 u = A.u[h][l - 1];
             }
