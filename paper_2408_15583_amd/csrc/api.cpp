@@ -184,6 +184,7 @@ pe_status pe_ctx_destroy(pe_ctx ctx) {
     server_shutdown(ctx);
     (void)hipDeviceSynchronize();
     delete ctx->ws;
+    pe::ctx_release_cache(ctx);
     delete ctx;
     return PE_OK;
     API_END

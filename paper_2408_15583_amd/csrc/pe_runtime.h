@@ -29,6 +29,7 @@ void pol_basis(const double s[3], double th[3], double ph[3]);
 
 void* ctx_alloc(pe_ctx ctx, size_t bytes);
 void ctx_free(pe_ctx ctx, void* p, size_t bytes);
+void ctx_release_cache(pe_ctx ctx);
 
 // Growable set of device buffers charged to a context's budget.  In arena mode (arena !=
 // nullptr) nothing is allocated: buffers are carved in request order from a fixed device
@@ -159,6 +160,19 @@ struct pe_ctx_s {
     int device = 0;
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
+    // Device blocks released by ctx_free, kept for reuse by an allocation of the same rounded
+    // size (scenes and their build buffers come and go with the same sizes in steady serving).
+    // `used` counts live blocks only; used + cached stays within the budget and cached within
+    // kCacheCap.  A block freed at generation g is handed out again only after a device
+    // synchronisation (idle_gen > g): its last kernels may still run on any stream.
+    struct CachedBlock {
+        void* p;
+        uint64_t gen;
+    };
+    std::mutex alloc_mu;
+    std::multimap<size_t, CachedBlock> cache;
+    uint64_t cached = 0;
+    uint64_t idle_gen = 0;
     std::mutex mu;  // serialises synchronous calls that use the default workspace
     pe::Workspace* ws = nullptr;
     pe::Server* server = nullptr;

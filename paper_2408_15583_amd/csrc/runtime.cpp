@@ -48,6 +48,30 @@ void hip_check(hipError_t e, const char* what, int line) {
 // Budgeted device memory
 // ------------------------------------------------------------------------------------------
 
+// Largest total of released blocks a context keeps for reuse.
+constexpr uint64_t kCacheCap = 32ull << 30;
+
+// Returns every cached block to HIP (after the device has finished with them).
+void ctx_release_cache(pe_ctx ctx) {
+    std::lock_guard<std::mutex> lk(ctx->alloc_mu);
+    if (ctx->cache.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->cache) (void)hipFree(kv.second.p);
+    ctx->cache.clear();
+    ctx->cached = 0;
+    ctx->idle_gen++;
+}
+
+// Drops cached blocks, largest first, until used + cached <= limit.  Caller holds alloc_mu.
+static void trim_cache_locked(pe_ctx ctx, uint64_t limit) {
+    while (!ctx->cache.empty() && ctx->used.load() + ctx->cached > limit) {
+        auto it = std::prev(ctx->cache.end());
+        (void)hipFree(it->second.p);
+        ctx->cached -= it->first;
+        ctx->cache.erase(it);
+    }
+}
+
 void* ctx_alloc(pe_ctx ctx, size_t bytes) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
@@ -58,12 +82,36 @@ void* ctx_alloc(pe_ctx ctx, size_t bytes) {
                                        " more bytes, " + std::to_string(ctx->budget - cur) +
                                        " left"};
     } while (!ctx->used.compare_exchange_weak(cur, cur + bytes));
+    {
+        std::lock_guard<std::mutex> lk(ctx->alloc_mu);
+        auto it = ctx->cache.find(bytes);
+        if (it != ctx->cache.end()) {
+            if (it->second.gen >= ctx->idle_gen) {
+                (void)hipDeviceSynchronize();
+                ctx->idle_gen++;
+            }
+            void* p = it->second.p;
+            ctx->cached -= bytes;
+            ctx->cache.erase(it);
+            return p;
+        }
+    }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        // the device may be short only because of cached blocks: return them and retry once
+        (void)hipGetLastError();
+        ctx_release_cache(ctx);
+        e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) {
         ctx->used -= bytes;
         (void)hipGetLastError();
         throw Error{PE_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->alloc_mu);
+        trim_cache_locked(ctx, ctx->budget);
     }
     return p;
 }
@@ -72,8 +120,14 @@ void ctx_free(pe_ctx ctx, void* p, size_t bytes) {
     if (!p) return;
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
-    (void)hipFree(p);
     ctx->used -= bytes;
+    std::lock_guard<std::mutex> lk(ctx->alloc_mu);
+    if (ctx->cached + bytes > kCacheCap || ctx->used.load() + ctx->cached + bytes > ctx->budget) {
+        (void)hipFree(p);
+        return;
+    }
+    ctx->cache.insert({bytes, pe_ctx_s::CachedBlock{p, ctx->idle_gen}});
+    ctx->cached += bytes;
 }
 
 void* Workspace::raw(int id, size_t bytes) {
