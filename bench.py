@@ -87,9 +87,9 @@ def po_slots_per_term():
     """Issue slots (fp32 lane-op equivalents) one PO term needs: fp64 ops count twice (half
     rate), transcendentals four times (quarter rate).  The 8 fp64 conversions and adds of the
     accumulators run once per aligned group of four terms."""
-    fp64 = 1 + 2 + 1 + 1 + (8 + 8) / 4  # D*rev, floor+sub, cvt f64->f32, cmp, accumulators
-    fp32 = 2 + 2 * 10 + 2 + 3 + 2 + 8  # k*al, k*be, two sinc (series and full, select),
-    #                                    S and tail mask, half-turn fold, wr/wi, 8 fma
+    fp64 = 1 + 1 + 1 + (8 + 8) / 4  # D*rev, fraction, cvt f64->f32, accumulators
+    fp32 = 2 + 2 * 10 + 2 + 2 + 8  # k*al, k*be, two sinc (series and full, select),
+    #                                S and tail mask, wr/wi, 8 fma
     trans = 4 + 2                          # sin, cos, two sinc sines, two reciprocals
     return 2 * fp64 + fp32 + 4 * trans
 

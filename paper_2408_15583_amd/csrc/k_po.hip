@@ -6,7 +6,7 @@
 // scene-frame phase is shifted back to the global origin by the (k_i - k_s).c factor).
 //
 // Precision (FP64PHASE): the phase k D is formed in fp64 as D * (f / c) revolutions and reduced
-// to [-1/2, 1/2) in fp64 before the fp32 sin/cos; each term (fp32 amplitude x fp32 sinc and
+// to its fraction in [0, 1) in fp64 before the fp32 sin/cos; each term (fp32 amplitude x fp32 sinc and
 // trig) is summed with the other three of its aligned group of four records in fp32, and the
 // group sums are accumulated in fp64.  FP64ACC does the same with every term accumulated in
 // fp64 on its own (no fp32 groups).  FP32 mode does all of it in fp32.  The sum is
@@ -163,15 +163,11 @@ __device__ void po_tile(const SlotDesc& d, uint64_t base, uint32_t rn, int f, in
             // not sink the loads back to their uses)
             const float live = r0 + u < rn ? 1.f : 0.f;
             const float S = sinc_f(kf * cur.al) * sinc_f(kf * cur.be) * live;
+            // phase in revolutions, reduced to [0, 1): fp64 product and fraction, except in the
+            // all-fp32 mode
             float rf;
-            if (MODE == 1) {
-                const float ph = (float)cur.D * revf;
-                rf = ph - floorf(ph);
-            } else {
-                const double ph = cur.D * rev;
-                rf = (float)(ph - floor(ph));
-            }
-            if (rf >= 0.5f) rf -= 1.f;
+            if (MODE == 1) rf = __builtin_amdgcn_fractf((float)cur.D * revf);
+            else rf = (float)__builtin_amdgcn_fract(cur.D * rev);
             // cos and sin of 2 pi rf (the hardware takes revolutions)
             const float cs = __builtin_amdgcn_cosf(rf), sn = __builtin_amdgcn_sinf(rf);
             const float wr = S * cs, wi = -S * sn;  // S exp(-j phase)
