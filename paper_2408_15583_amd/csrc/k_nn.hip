@@ -33,22 +33,47 @@ union Frag {
     v8bf v;
 };
 
+// erf by Abramowitz and Stegun, Handbook of Mathematical Functions, formula 7.1.26: for x >= 0,
+// erf x = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1 / (1 + p x), with
+// absolute error at most 1.5e-7 (three orders below a bf16 step); odd in x.  Branch-free, unlike
+// the library erff, whose two argument ranges diverge within a wavefront.
+__device__ inline float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.f));
+    const float poly =
+        t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
+                                                                          t * 1.061405429f))));
+    return copysignf(1.f - poly * __expf(-ax * ax), x);
+}
+
+// GELU with the exact (erf) Gaussian CDF: 0.5 v (1 + erf(v / sqrt 2)).
+__device__ inline float gelu_f(float v) { return 0.5f * v * (1.f + erf_as(v * 0.70710678118654752f)); }
+
 // Epilogue of the convolution kernels: bias, residual, GELU, optional pre-activation copy and
-// pixel shuffle, from the accumulator fragments of a BM x BN tile.  The bf16 outputs go through
-// LDS (smem, at least BM x (BN + 8) bf16, free when this is called) for 16-byte row stores.
+// pixel shuffle, from the accumulator fragments of a BM x BN tile.  For bf16 outputs the fp32
+// tile plus bias is staged in LDS (smem, at least BM x (BN + 4) floats, free when this is
+// called) and each thread then takes rows of 8 channels: residual (one 16-byte load), the
+// pre-activation copy, GELU and the output as 16-byte stores.  The arithmetic is per element:
+// acc + bias, + residual, then GELU.
 // rowm maps a tile row to its output pixel index m (m >= M: past the end, not stored).
 template <int BN, int BM, int WGM, class RowM>
 __device__ inline void conv_epilogue(const ConvArgs& a,
                                      const v4f (&acc)[BM / WGM / 16][BN / (4 / WGM) / 16],
-                                     uint16_t* smem, RowM rowm, int n0) {
+                                     void* smem, RowM rowm, int n0) {
     constexpr int WGN = 4 / WGM;
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
-    constexpr int TLD = BN + 8;
+    constexpr int TLD = BN + 4;  // floats per staged row (rows 16-byte aligned)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
     const int HW = a.H * a.W, M = a.N * HW;
     const int r = lane & 15;
+    float bj[TN];  // bias of this lane's column in each MFMA tile column
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+        const int co = n0 + wn * WTN + j * 16 + r;
+        bj[j] = (co < a.Cout_store && a.bias) ? a.bias[co] : 0.f;
+    }
     // D fragment: lane holds column (channel) r of rows (pixels) 4 * (lane / 16) + q
     if (a.y32) {
         // fp32 outputs (the heads' last layers, few channels): straight from the fragments
@@ -58,14 +83,13 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
             for (int j = 0; j < TN; j++) {
                 const int co = n0 + wn * WTN + j * 16 + r;
                 const bool cok = co < a.Cout_store;
-                const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int m = rowm(wm * WTM + i * 16 + (lane >> 4) * 4 + q);
                     if (cok && m < M) {
-                        float v = acc[i][j][q] + bias;
+                        float v = acc[i][j][q] + bj[j];
                         if (a.res) v += bf2f(a.res[(size_t)m * a.ldres + co]);
-                        if (a.act == 1) v = 0.5f * v * (1.f + erff(v * 0.70710678118654752f));
+                        if (a.act == 1) v = gelu_f(v);
                         const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
                         size_t o;
                         if (a.shuffle) {
@@ -81,35 +105,16 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
             }
         return;
     }
-    // bf16 outputs: the tile (128 pixels x BN channels) is staged in LDS and written as 16-byte
-    // rows of 8 channels; the pre-activation copy z (training only) goes out per element
-    uint16_t* T = smem;
+    float* T = reinterpret_cast<float*>(smem);
 #pragma unroll
     for (int i = 0; i < TM; i++)
 #pragma unroll
         for (int j = 0; j < TN; j++) {
-            const int col = wn * WTN + j * 16 + r, co = n0 + col;
-            const bool cok = co < a.Cout_store;
-            const float bias = (cok && a.bias) ? a.bias[co] : 0.f;
+            const int col = wn * WTN + j * 16 + r;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int row = wm * WTM + i * 16 + (lane >> 4) * 4 + q, m = rowm(row);
-                float v = acc[i][j][q] + bias;
-                if (a.res && cok && m < M) v += bf2f(a.res[(size_t)m * a.ldres + co]);
-                if (a.z && cok && m < M) {
-                    const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
-                    size_t o;
-                    if (a.shuffle) {
-                        const int oc = co >> 2, sy = (co >> 1) & 1, sx = co & 1;
-                        o = ((size_t)(n * 2 * a.H + 2 * yy + sy) * (2 * a.W) + 2 * xx + sx) * a.ldy +
-                            a.yoff + oc;
-                    } else {
-                        o = (size_t)m * a.ldy + a.yoff + co;
-                    }
-                    a.z[o] = f2bf(v);
-                }
-                if (a.act == 1) v = 0.5f * v * (1.f + erff(v * 0.70710678118654752f));
-                T[row * TLD + col] = f2bf(v);
+                const int row = wm * WTM + i * 16 + (lane >> 4) * 4 + q;
+                T[row * TLD + col] = acc[i][j][q] + bj[j];
             }
         }
     __syncthreads();
@@ -118,12 +123,46 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
         for (int c = tid; c < BM * C8; c += 256) {
             const int row = c / C8, c8 = c - row * C8, m = rowm(row), co = n0 + c8 * 8;
             if (m >= M || co >= a.Cout_store) continue;
-            uint16_t* out = a.y + (size_t)m * a.ldy + a.yoff + co;
-            const uint16_t* src = &T[row * TLD + c8 * 8];
-            if (co + 8 <= a.Cout_store && ((uintptr_t)out & 15) == 0) {
-                *(uint4*)out = *(const uint4*)src;
+            const int ne = min(8, a.Cout_store - co);
+            float v[8];
+            const float4 v0 = *reinterpret_cast<const float4*>(&T[row * TLD + c8 * 8]);
+            const float4 v1 = *reinterpret_cast<const float4*>(&T[row * TLD + c8 * 8 + 4]);
+            v[0] = v0.x, v[1] = v0.y, v[2] = v0.z, v[3] = v0.w;
+            v[4] = v1.x, v[5] = v1.y, v[6] = v1.z, v[7] = v1.w;
+            if (a.res) {
+                const uint16_t* rp = a.res + (size_t)m * a.ldres + co;
+                if (ne == 8 && ((uintptr_t)rp & 15) == 0) {
+                    const uint4 u = *reinterpret_cast<const uint4*>(rp);
+                    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int e = 0; e < 8; e++) v[e] += bf2f((uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+                } else {
+                    for (int e = 0; e < ne; e++) v[e] += bf2f(rp[e]);
+                }
+            }
+            const size_t o = (size_t)m * a.ldy + a.yoff + co;
+            uint16_t h[8];
+            if (a.z) {
+#pragma unroll
+                for (int e = 0; e < 8; e++) h[e] = f2bf(v[e]);
+                uint16_t* zp = a.z + o;
+                if (ne == 8 && ((uintptr_t)zp & 15) == 0) {
+                    *reinterpret_cast<uint4*>(zp) =
+                        make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                                   h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
+                } else {
+                    for (int e = 0; e < ne; e++) zp[e] = h[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; e++) h[e] = f2bf(a.act == 1 ? gelu_f(v[e]) : v[e]);
+            uint16_t* yp = a.y + o;
+            if (ne == 8 && ((uintptr_t)yp & 15) == 0) {
+                *reinterpret_cast<uint4*>(yp) =
+                    make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                               h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
             } else {
-                for (int e = 0; e < 8 && co + e < a.Cout_store; e++) out[e] = src[e];
+                for (int e = 0; e < ne; e++) yp[e] = h[e];
             }
         }
     } else {
@@ -134,22 +173,27 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
             const int row = c / (4 * O8), rem = c - row * (4 * O8), sub = rem / O8,
                       c8 = rem - sub * O8, m = rowm(row), oc0 = (n0 >> 2) + c8 * 8;
             if (m >= M || oc0 >= oc_end) continue;
+            const int ne = min(8, oc_end - oc0);
             const int n = m / HW, yy = (m % HW) / a.W, xx = m % a.W;
             const int sy = sub >> 1, sx = sub & 1;
-            uint16_t* out = a.y + ((size_t)(n * 2 * a.H + 2 * yy + sy) * (2 * a.W) + 2 * xx + sx) *
-                                      a.ldy + a.yoff + oc0;
-            uint16_t v8[8];
+            const size_t o = ((size_t)(n * 2 * a.H + 2 * yy + sy) * (2 * a.W) + 2 * xx + sx) *
+                                 a.ldy + a.yoff + oc0;
+            uint16_t h[8];
 #pragma unroll
-            for (int e = 0; e < 8; e++) v8[e] = T[row * TLD + 4 * (c8 * 8 + e) + sub];
-            if (oc0 + 8 <= oc_end && ((uintptr_t)out & 15) == 0) {
-                uint4 u;
-                u.x = (uint32_t)v8[0] | ((uint32_t)v8[1] << 16);
-                u.y = (uint32_t)v8[2] | ((uint32_t)v8[3] << 16);
-                u.z = (uint32_t)v8[4] | ((uint32_t)v8[5] << 16);
-                u.w = (uint32_t)v8[6] | ((uint32_t)v8[7] << 16);
-                *(uint4*)out = u;
+            for (int e = 0; e < 8; e++) {
+                const int col = 4 * (c8 * 8 + e) + sub;
+                float v = T[row * TLD + col];
+                if (a.res && e < ne) v += bf2f(a.res[(size_t)m * a.ldres + n0 + col]);
+                if (a.z && e < ne) a.z[o + e] = f2bf(v);
+                h[e] = f2bf(a.act == 1 ? gelu_f(v) : v);
+            }
+            uint16_t* yp = a.y + o;
+            if (ne == 8 && ((uintptr_t)yp & 15) == 0) {
+                *reinterpret_cast<uint4*>(yp) =
+                    make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                               h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
             } else {
-                for (int e = 0; e < 8 && oc0 + e < oc_end; e++) out[e] = v8[e];
+                for (int e = 0; e < ne; e++) yp[e] = h[e];
             }
         }
     }
@@ -203,8 +247,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     constexpr int AI = BM / 16, BI = BN / 16;   // 1 KB copies per stage (16 rows each)
     constexpr int NI = (AI + BI + 3) / 4;       // copies per wavefront per stage
     constexpr int SU = (BM + BN) * 4;           // stage size in 16-byte units
-    constexpr int TLD = BN + 8;
-    static_assert(BM * TLD * 2 <= NS * SU * 16, "output tile fits the stage LDS");
+    static_assert(BM * (BN + 4) * 4 <= NS * SU * 16, "fp32 output tile fits the stage LDS");
     __shared__ __attribute__((aligned(16))) uint4 lds[NS * SU + 64];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -307,8 +350,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     // every copy has landed (the last step waited for all); all fragment reads are done
     // before the epilogue reuses the stages
     wait_stage_then_barrier<0>();
-    conv_epilogue<BN, BM, WGM>(a, acc, reinterpret_cast<uint16_t*>(lds),
-                               [m0](int row) { return m0 + row; }, n0);
+    conv_epilogue<BN, BM, WGM>(a, acc, lds, [m0](int row) { return m0 + row; }, n0);
 }
 
 template <int BN, int BM, int WGM, int NS>
@@ -342,8 +384,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
     constexpr int NH = (HJ + 3) / 4, NB = (BI + 3) / 4;  // per wavefront
     constexpr int SU = BN * 4;
     constexpr int UNITS = 2 * HU + NS * SU + 64;
-    constexpr int TLD = BN + 8;
-    static_assert(BM * TLD * 2 <= UNITS * 16, "output tile fits the LDS");
+    static_assert(BM * (BN + 4) * 4 <= UNITS * 16, "fp32 output tile fits the LDS");
     __shared__ __attribute__((aligned(16))) uint4 lds[UNITS];
     uint4* const hbuf = lds;
     uint4* const bst = lds + 2 * HU;
@@ -449,7 +490,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
     wait_stage_then_barrier<0>();
     const int HWi = a.H * a.W;
     conv_epilogue<BN, BM, WGM>(
-        a, acc, reinterpret_cast<uint16_t*>(lds),
+        a, acc, lds,
         [=](int row) { return n * HWi + (y0 + row / TW) * a.W + x0 + row % TW; }, n0);
 }
 
@@ -464,14 +505,8 @@ static void launch_conv3_halo_t(const ConvArgs& a, hipStream_t st) {
 // 16-column tiles go to k_conv3_halo (4-row tiles for outputs wider than 64 channels, 8-row tiles
 // otherwise; three copy stages: four, six and eight stages were slower at every size); the other
 // layers to k_conv_fwd with the largest tile that still gives the launch 1024 workgroups.
-void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
-    constexpr int NS = 3;
-    if (a.K == 3 && a.W % 16 == 0 && a.H % 8 == 0) {
-        if (a.Cout > 64) launch_conv3_halo_t<128, 4, 2, NS>(a, st);
-        else if (a.Cout > 32) launch_conv3_halo_t<64, 8, 2, NS>(a, st);
-        else launch_conv3_halo_t<32, 8, 4, NS>(a, st);
-        return;
-    }
+template <int NS>
+static void launch_conv_fwd_ns(const ConvArgs& a, hipStream_t st) {
     const int M = a.N * a.H * a.W;
     if (a.Cout > 64) {
         const unsigned gy = (unsigned)((a.Cout + 127) / 128);
@@ -485,6 +520,17 @@ void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
         if (!launch_conv_fwd_t<32, 128, 4, NS>(a, M, 1u, false, st))
             launch_conv_fwd_t<32, 64, 4, NS>(a, M, 1u, true, st);
     }
+}
+
+void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
+    constexpr int NS = 3;
+    if (a.K == 3 && a.W % 16 == 0 && a.H % 8 == 0) {
+        if (a.Cout > 64) launch_conv3_halo_t<128, 4, 2, NS>(a, st);
+        else if (a.Cout > 32) launch_conv3_halo_t<64, 8, 2, NS>(a, st);
+        else launch_conv3_halo_t<32, 8, 4, NS>(a, st);
+        return;
+    }
+    launch_conv_fwd_ns<NS>(a, st);
 }
 
 // Weight gradient: dW[co][t][ci] = sum_p dY[p][co] X[p + shift(t)][ci] over one chunk of
@@ -684,13 +730,13 @@ void launch_unshuffle(const uint16_t* g, int N, int H, int W, int C, int ldg, in
     hipLaunchKernelGGL(k_unshuffle, dim3(b), dim3(256), 0, st, g, N, H, W, C, ldg, goff, d, ldd);
 }
 
-// GELU backward: dz = dy * (Phi(z) + z phi(z)) (exact erf form).
+// GELU backward: dz = dy * (Phi(z) + z phi(z)) (erf form, erf_as).
 __global__ void k_gelu_bwd(const uint16_t* __restrict__ z, const uint16_t* __restrict__ dy,
                            size_t n, uint16_t* __restrict__ dz) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const float v = bf2f(z[i]);
-        const float cdf = 0.5f * (1.f + erff(v * 0.70710678118654752f));
+        const float cdf = 0.5f * (1.f + erf_as(v * 0.70710678118654752f));
         const float pdf = 0.3989422804014327f * __expf(-0.5f * v * v);
         dz[i] = f2bf(bf2f(dy[i]) * (cdf + v * pdf));
     }
@@ -763,7 +809,7 @@ __global__ void k_stem_fwd(const float* __restrict__ x, int N, int H, int W, int
             if (y >= 0 && y < H && x2 >= 0 && x2 < W) s += x[(size_t)(bn * H + y) * W + x2] * w[c * 9 + t];
         }
         z[i] = f2bf(s);
-        a[i] = f2bf(0.5f * s * (1.f + erff(s * 0.70710678118654752f)));
+        a[i] = f2bf(gelu_f(s));
     }
 }
 
@@ -797,8 +843,7 @@ __global__ void k_stem_fwd8(const float* __restrict__ x, int N, int H, int W, in
                 v[h] = s;
             }
             zo[e / 2] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-            ao[e / 2] = (uint32_t)f2bf(0.5f * v[0] * (1.f + erff(v[0] * 0.70710678118654752f))) |
-                        ((uint32_t)f2bf(0.5f * v[1] * (1.f + erff(v[1] * 0.70710678118654752f))) << 16);
+            ao[e / 2] = (uint32_t)f2bf(gelu_f(v[0])) | ((uint32_t)f2bf(gelu_f(v[1])) << 16);
         }
         *(uint4*)(z + (size_t)pix * C + g * 8) = make_uint4(zo[0], zo[1], zo[2], zo[3]);
         *(uint4*)(a + (size_t)pix * C + g * 8) = make_uint4(ao[0], ao[1], ao[2], ao[3]);

@@ -365,3 +365,36 @@ def test_tube_topk(pe, ctx, dihedral, K):
     same = both & (idx == idx_o)
     assert same.sum() >= 0.99 * both.sum()
     assert np.abs(dep[same] - dep_o[same]).max() <= 1e-5 * 2 * R
+
+
+def test_released_blocks_reused_within_budget(pe, dihedral):
+    """A context keeps the device blocks it releases for later allocations of the same size,
+    with live plus cached bytes held within its budget.  Under a budget of 2 x what one scene
+    and its solve take, ten rounds of scene creation, solve and close succeed with results
+    bitwise equal to an unconstrained context's, the bytes charged after each close stay the
+    same (no leak in the accounting), and scenes with other view sizes (other block sizes,
+    which the cache must make room for) still fit."""
+    sc, _, _ = dihedral
+    inc = scenes.azimuth_sweep(np.linspace(0.0, 90.0, 8), 0.0)
+    eps = 0.5 * sc.radius
+    probe = pe.Context(0)
+    s = pe.Scene.from_scene(probe, sc, view_res=128)
+    E0 = pe.solve(probe, s, inc, [10e9], 128, max_bounces=2, eps=eps)[0]
+    need = probe.footprint()[0]
+    s.close()
+    probe.close()
+    c = pe.Context(0, budget=int(2 * need))
+    after = []
+    for _ in range(10):
+        s = pe.Scene.from_scene(c, sc, view_res=128)
+        E = pe.solve(c, s, inc, [10e9], 128, max_bounces=2, eps=eps)[0]
+        assert np.array_equal(E, E0)
+        s.close()
+        after.append(c.footprint()[0])
+    assert len(set(after)) == 1 and after[0] < need
+    for res in (64, 96, 128):
+        s = pe.Scene.from_scene(c, sc, view_res=res)
+        pe.solve(c, s, inc, [10e9], 128, max_bounces=2, eps=eps)
+        s.close()
+        assert c.footprint()[0] <= c.footprint()[1]
+    c.close()
