@@ -137,7 +137,9 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
 #pragma unroll
                     for (int e = 0; e < 8; e++) v[e] += bf2f((uint16_t)(w[e >> 1] >> (16 * (e & 1))));
                 } else {
-                    for (int e = 0; e < ne; e++) v[e] += bf2f(rp[e]);
+#pragma unroll
+                    for (int e = 0; e < 8; e++)
+                        if (e < ne) v[e] += bf2f(rp[e]);
                 }
             }
             const size_t o = (size_t)m * a.ldy + a.yoff + co;
@@ -151,7 +153,9 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
                         make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
                                    h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
                 } else {
-                    for (int e = 0; e < ne; e++) zp[e] = h[e];
+#pragma unroll
+                    for (int e = 0; e < 8; e++)
+                        if (e < ne) zp[e] = h[e];
                 }
             }
 #pragma unroll
@@ -162,7 +166,9 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
                     make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
                                h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
             } else {
-                for (int e = 0; e < ne; e++) yp[e] = h[e];
+#pragma unroll
+                for (int e = 0; e < 8; e++)
+                    if (e < ne) yp[e] = h[e];
             }
         }
     } else {
@@ -193,7 +199,9 @@ __device__ inline void conv_epilogue(const ConvArgs& a,
                     make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
                                h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
             } else {
-                for (int e = 0; e < ne; e++) yp[e] = h[e];
+#pragma unroll
+                for (int e = 0; e < 8; e++)
+                    if (e < ne) yp[e] = h[e];
             }
         }
     }
@@ -363,14 +371,15 @@ static bool launch_conv_fwd_t(const ConvArgs& a, int M, unsigned gy, bool force,
 }
 
 // 3 x 3 convolutions over two-dimensional pixel tiles (TH rows x 16 columns of one image): the
-// K loop runs over 32-channel slices of the input and, within a slice, over the nine taps.  The
-// slice's input halo ((TH + 2) x 18 pixels x 32 channels) is copied into LDS once and serves all
-// nine taps, so the input is read about (TH + 2) x 18 / (16 TH) times instead of nine times; the
-// weights of one (slice, tap) step go through NS copy stages as in k_conv_fwd.  Halo buffers
-// are double-buffered over slices: the next slice's halo is copied at the first step of the
-// current one.  Requirements (checked by the host): K = 3, W % 16 == 0, H % TH == 0,
-// Cin % 32 == 0.
-template <int BN, int TH, int WGM, int NS>
+// K loop runs over 32-channel slices of the input and, within a slice, over the nine taps, TPS
+// of them per step.  The slice's input halo ((TH + 2) x 18 pixels x 32 channels) is copied into
+// LDS once and serves all nine taps, so the input is read about (TH + 2) x 18 / (16 TH) times
+// instead of nine times; the weights of one step (TPS taps x BN channels x 32) go through NS
+// copy stages as in k_conv_fwd.  Halo buffers are double-buffered over slices: the next slice's
+// halo is copied at the first step of the current one (after that step's weights, so a step's
+// wait covers it when it was issued within the last NS - 1 steps; NS - 1 < steps per slice).
+// Requirements (checked by the host): K = 3, W % 16 == 0, H % TH == 0, Cin % 32 == 0.
+template <int BN, int TH, int WGM, int NS, int TPS>
 __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
     constexpr int TW = 16, BM = TH * TW;
     constexpr int WGN = 4 / WGM;
@@ -380,9 +389,12 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
     constexpr int HWD = TW + 2, HT = (TH + 2) * HWD;  // halo pixels
     constexpr int HJ = (HT + 15) / 16;                 // halo copies (16 pixels each)
     constexpr int HU = HJ * 64;                        // halo buffer, 16-byte units
-    constexpr int BI = BN / 16;                        // weight copies per step
+    constexpr int SPS = 9 / TPS;                       // steps per slice
+    static_assert(SPS * TPS == 9 && NS >= 2 && NS - 1 < SPS, "taps per step divide the nine");
+    constexpr int RB = BN / 16;                        // 16-row blocks of one tap's weights
+    constexpr int BI = RB * TPS;                       // weight copies per step
     constexpr int NH = (HJ + 3) / 4, NB = (BI + 3) / 4;  // per wavefront
-    constexpr int SU = BN * 4;
+    constexpr int SU = BN * 4 * TPS;
     constexpr int UNITS = 2 * HU + NS * SU + 64;
     static_assert(BM * (BN + 4) * 4 <= UNITS * 16, "fp32 output tile fits the LDS");
     __shared__ __attribute__((aligned(16))) uint4 lds[UNITS];
@@ -396,7 +408,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
     const int n = blockIdx.x / tiles_xy, rem = blockIdx.x - n * tiles_xy;
     const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
     const int n0 = blockIdx.y * BN;
-    const int nsl = a.Cin / 32, steps = 9 * nsl;
+    const int nsl = a.Cin / 32, steps = SPS * nsl;
     const int chunk = (lane & 3) ^ ((lane >> 3) & 3);
     const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_conv_zero);
     // this lane's source in each copy of this wavefront: element offset of its 8 channels at
@@ -413,9 +425,10 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < NB; i++) {
-        const int q = wave + 4 * i, co = n0 + q * 16 + (lane >> 2);
+        // copy q: rows (q % RB) * 16 .. + 15 of tap q / RB of the step
+        const int q = wave + 4 * i, co = n0 + (q % RB) * 16 + (lane >> 2);
         bval[i] = q < BI && co < a.Cout;
-        bsrc[i] = bval[i] ? (size_t)co * 9 * a.Cin + chunk * 8 : 0;
+        bsrc[i] = bval[i] ? ((size_t)co * 9 + q / RB) * a.Cin + chunk * 8 : 0;
     }
     auto lds_addr = [](const uint4* p) {
         return __builtin_amdgcn_readfirstlane(
@@ -430,7 +443,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
                           lds_addr(j < HJ ? hb + j * 64 : spare));
         }
     };
-    int lt = 0, lsl = 0;  // the next weight step to copy: tap lt of slice lsl
+    int lt = 0, lsl = 0;  // the next weight step to copy: taps lt .. lt + TPS - 1 of slice lsl
     auto copy_weights = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < NB; i++) {
@@ -438,7 +451,8 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
             copy_to_lds16(bval[i] ? a.w + bsrc[i] + (size_t)lt * a.Cin + lsl * 32 : zero,
                           lds_addr(q < BI ? bst + buf * SU + q * 64 : spare));
         }
-        if (++lt == 9) {
+        lt += TPS;
+        if (lt == 9) {
             lt = 0;
             lsl++;
         }
@@ -461,7 +475,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
         hp0[i] = (p / TW) * HWD + p % TW;
     }
     for (int s = 0; s < steps; s++) {
-        const int sl = s / 9, t = s - 9 * sl;
+        const int sl = s / SPS, t = s - SPS * sl;
         // copies issued after this step's weights: the next NS - 2 weight steps, plus the next
         // slice's halo when it was issued within the last NS - 1 steps
         if (steps - 1 - s < NS - 2) wait_stage_then_barrier<0>();
@@ -469,23 +483,26 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
         else wait_stage_then_barrier<NB * (NS - 2)>();
         if (s + NS - 1 < steps) copy_weights((s + NS - 1) % NS);
         if (t == 0 && sl + 1 < nsl) copy_halo(sl + 1);
-        const int ky = t / 3, kx = t - 3 * ky;
         const uint4* Hb = hbuf + (sl & 1) * HU;
-        const uint4* Bb = bst + (s % NS) * SU;
-        Frag fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; i++) {
-            const int hp = hp0[i] + ky * HWD + kx;
-            fa[i].u = Hb[hp * 4 + (kc ^ ((hp >> 1) & 3))];
+        for (int tt = 0; tt < TPS; tt++) {
+            const int tap = t * TPS + tt, ky = tap / 3, kx = tap - 3 * ky;
+            const uint4* Bb = bst + (s % NS) * SU + tt * BN * 4;
+            Frag fa[TM], fb[TN];
+#pragma unroll
+            for (int i = 0; i < TM; i++) {
+                const int hp = hp0[i] + ky * HWD + kx;
+                fa[i].u = Hb[hp * 4 + (kc ^ ((hp >> 1) & 3))];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; j++) fb[j].u = Bb[(wn * WTN + j * 16 + r) * 4 + bpos];
+#pragma unroll
+            for (int i = 0; i < TM; i++)
+#pragma unroll
+                for (int j = 0; j < TN; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v,
+                                                                       acc[i][j], 0, 0, 0);
         }
-#pragma unroll
-        for (int j = 0; j < TN; j++) fb[j].u = Bb[(wn * WTN + j * 16 + r) * 4 + bpos];
-#pragma unroll
-        for (int i = 0; i < TM; i++)
-#pragma unroll
-            for (int j = 0; j < TN; j++)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0,
-                                                                   0, 0);
     }
     wait_stage_then_barrier<0>();
     const int HWi = a.H * a.W;
@@ -494,17 +511,19 @@ __global__ __launch_bounds__(256) void k_conv3_halo(ConvArgs a) {
         [=](int row) { return n * HWi + (y0 + row / TW) * a.W + x0 + row % TW; }, n0);
 }
 
-template <int BN, int TH, int WGM, int NS>
+template <int BN, int TH, int WGM, int NS, int TPS = 1>
 static void launch_conv3_halo_t(const ConvArgs& a, hipStream_t st) {
     const unsigned gx = (unsigned)(a.N * (a.H / TH) * (a.W / 16));
     const unsigned gy = (unsigned)((a.Cout + BN - 1) / BN);
-    hipLaunchKernelGGL((k_conv3_halo<BN, TH, WGM, NS>), dim3(gx, gy), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_conv3_halo<BN, TH, WGM, NS, TPS>), dim3(gx, gy), dim3(256), 0, st, a);
 }
 
-// Tile choice (measured, batch of 8 at 256^2 -> 512^2): 3 x 3 layers whose images split into
-// 16-column tiles go to k_conv3_halo (4-row tiles for outputs wider than 64 channels, 8-row tiles
-// otherwise; three copy stages: four, six and eight stages were slower at every size); the other
-// layers to k_conv_fwd with the largest tile that still gives the launch 1024 workgroups.
+// Tile choice (measured, batch of 8 at 256^2 -> 512^2, inference per batch): 3 x 3 layers whose
+// images split into 16-column tiles go to k_conv3_halo with 8-row tiles of 64 (or, for narrow
+// outputs, 32) channels, three taps per K step and two copy stages (1.51 ms; one tap per step
+// with three stages and 4-row 128-channel tiles for wide outputs 1.72 ms, three taps with those
+// tiles 1.59 ms, three taps with three stages 1.83 ms); the other layers to k_conv_fwd with
+// three stages and the largest tile that still gives the launch 1024 workgroups.
 template <int NS>
 static void launch_conv_fwd_ns(const ConvArgs& a, hipStream_t st) {
     const int M = a.N * a.H * a.W;
@@ -525,9 +544,8 @@ static void launch_conv_fwd_ns(const ConvArgs& a, hipStream_t st) {
 void launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     constexpr int NS = 3;
     if (a.K == 3 && a.W % 16 == 0 && a.H % 8 == 0) {
-        if (a.Cout > 64) launch_conv3_halo_t<128, 4, 2, NS>(a, st);
-        else if (a.Cout > 32) launch_conv3_halo_t<64, 8, 2, NS>(a, st);
-        else launch_conv3_halo_t<32, 8, 4, NS>(a, st);
+        if (a.Cout > 32) launch_conv3_halo_t<64, 8, 2, 2, 3>(a, st);
+        else launch_conv3_halo_t<32, 8, 4, 2, 3>(a, st);
         return;
     }
     launch_conv_fwd_ns<NS>(a, st);

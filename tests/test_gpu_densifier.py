@@ -19,8 +19,8 @@ error of s from K runs; measured, the bulk sits at err ~ s (median ratio ~1).
 
 Shapes: 2 images of 16^2 (ragged 32-pixel tiles, flat chunk sums; the 3 x 3 layers of 16-pixel
 images on 16 x 8 halo tiles, the smaller ones on the flat k_conv_fwd tiles), and 256^2 -> 512^2
-(the densifier's configured resolution): every 3 x 3 layer on k_conv3_halo's 4- and 8-row tiles
-with 128-, 64- and 32-channel outputs, the 1 x 1 layers on 64-pixel k_conv_fwd tiles with 128-
+(the densifier's configured resolution): every 3 x 3 layer on k_conv3_halo's 8-row tiles with
+64- and 32-channel outputs (three taps per K step), the 1 x 1 layers on 64-pixel k_conv_fwd tiles with 128-
 and 32-channel outputs, k_conv_wgrad chunks of 576 pixels (18 K steps per block) with the tree
 reduction over 114 chunks; 4 images of 256^2 forward adds the 64 x 64 tile.
 """
