@@ -59,7 +59,7 @@ BVH_TRAFFIC = dict(
              "paper_2408_15583_amd/csrc/pe_bvh.h":
              "21e2fd657b43e64aa48818dcfcb33f957065dd8b11dc61628537e90b73284ebf",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "ae8bb7c4aa3d4ab250f5c2c5a9949149edb288ecd030c1ae67369d0f81ce0178",
+             "8cda6c0a631315b4c81672cf1ca32339f2f25f6b4ec32992dc100794dfdd0baf",
              "paper_2408_15583_amd/csrc/pe_geom.h":
              "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
 

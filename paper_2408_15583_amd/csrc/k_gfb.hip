@@ -216,11 +216,7 @@ __global__ __launch_bounds__(256) void k_gfb_write(const SlotDesc* __restrict__ 
     if (dot(n, K) > 0.f) n = n * -1.f;
     st3(rs, RX, g, U * ou + V * ov + K * (t - d.R));
     st3(rs, RNX, g, n);
-    st3(rs, RKX, g, K);
-    st3(rs, RETX, g, mk3(d.eth[0], d.eth[1], d.eth[2]));
-    st3(rs, REPX, g, mk3(d.eph[0], d.eph[1], d.eph[2]));
-    st3(rs, RUX, g, U * d.pitch);
-    st3(rs, RVX, g, V * d.pitch);
+    st3(rs, RKX, g, K);  // a primary record: incoming fields and tube vectors not stored
     rs.d[g] = (double)t - (double)d.R;
     rs.m[g] = 1;
     rs.hit[g] = (uint32_t)p;

@@ -23,6 +23,15 @@ namespace pe {
 // Ray generation from the first-hit buffer
 // ------------------------------------------------------------------------------------------
 
+// Incoming fields and tube vectors of a primary record, which ray generation does not store
+// (they are the same for every pixel of the slot).
+__device__ inline void primary_fields(const SlotDesc& d, f3& Et, f3& Ep, f3& U, f3& V) {
+    Et = mk3(d.eth[0], d.eth[1], d.eth[2]);
+    Ep = mk3(d.eph[0], d.eph[1], d.eph[2]);
+    U = mk3(d.u[0], d.u[1], d.u[2]) * d.pitch;
+    V = mk3(d.v[0], d.v[1], d.v[2]) * d.pitch;
+}
+
 __device__ inline bool primary_live(const SlotDesc& d, const uint64_t* keys, int p) {
     if (p >= d.W * d.H) return false;
     const uint64_t key = keys[d.pix_base + p];
@@ -91,10 +100,6 @@ __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict
     st3(rs, RX, g, x);
     st3(rs, RNX, g, n);
     st3(rs, RKX, g, K);
-    st3(rs, RETX, g, mk3(d.eth[0], d.eth[1], d.eth[2]));
-    st3(rs, REPX, g, mk3(d.eph[0], d.eph[1], d.eph[2]));
-    st3(rs, RUX, g, U * d.pitch);
-    st3(rs, RVX, g, V * d.pitch);
     rs.d[g] = (double)t - (double)d.R;
     rs.m[g] = 1;
     rs.hit[g] = i;
@@ -405,11 +410,19 @@ __device__ bool apply_bounce(const SlotDesc& d, uint64_t g, const RayState& rs, 
     st3(rs, RX, g, x + k * best_t);
     st3(rs, RNX, g, nn);
     st3(rs, RKX, g, k);
-    const f3 Et = ld3(rs, RETX, g), Ep = ld3(rs, REPX, g);
+    f3 Et, Ep, U, V;
+    if (bounce == 2) {
+        primary_fields(d, Et, Ep, U, V);
+    } else {
+        Et = ld3(rs, RETX, g);
+        Ep = ld3(rs, REPX, g);
+        U = ld3(rs, RUX, g);
+        V = ld3(rs, RVX, g);
+    }
     st3(rs, RETX, g, n * (2.f * dot(n, Et)) - Et);
     st3(rs, REPX, g, n * (2.f * dot(n, Ep)) - Ep);
-    st3(rs, RUX, g, mirror(ld3(rs, RUX, g), n));
-    st3(rs, RVX, g, mirror(ld3(rs, RVX, g), n));
+    st3(rs, RUX, g, mirror(U, n));
+    st3(rs, RVX, g, mirror(V, n));
     rs.d[g] += (double)best_t;
     rs.m[g] = (uint8_t)bounce;
     rs.hit[g] = best_i;
@@ -814,10 +827,17 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
         const SlotDesc& d = ds[entry_slot(entry)];
         const uint64_t g = d.pix_base + entry_pix(entry);
         const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
-        const f3 Et = ld3(rs, RETX, g), Ep = ld3(rs, REPX, g);
-        const f3 u = ld3(rs, RUX, g), v = ld3(rs, RVX, g);
         const double dd = rs.d[g];
         const int m = rs.m[g];
+        f3 Et, Ep, u, v;
+        if (m == 1) {
+            primary_fields(d, Et, Ep, u, v);
+        } else {
+            Et = ld3(rs, RETX, g);
+            Ep = ld3(rs, REPX, g);
+            u = ld3(rs, RUX, g);
+            v = ld3(rs, RVX, g);
+        }
         const float ink = 1.f / dot(nn, kin);
         const f3 up = u - kin * (dot(nn, u) * ink);
         const f3 vp = v - kin * (dot(nn, v) * ink);

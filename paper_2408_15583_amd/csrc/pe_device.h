@@ -145,7 +145,9 @@ struct ObsDesc {
 
 // Ray state, structure of arrays indexed by batch pixel.  The state of a live ray is the
 // record of its last bounce: hit point, oriented normal, incoming direction, incoming fields
-// for both transmit polarisations, incoming tube vectors, image-method path length to x.
+// for both transmit polarisations, incoming tube vectors, image-method path length to x.  A
+// primary record (bounce count 1) does not store the incoming fields and tube vectors: they are
+// its slot's transmit polarisations and screen axes times the pixel pitch.
 enum RayComp { RX = 0, RNX = 3, RKX = 6, RETX = 9, REPX = 12, RUX = 15, RVX = 18, RNCOMP = 21 };
 struct RayState {
     float* f[RNCOMP];
