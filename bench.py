@@ -53,13 +53,13 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=17954988.0, write_kib=867193.3, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17612073.9, write_kib=866625.2, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
-             "5c94a756cb27e1a41c9edfca303096dbefa8334d2736a54b602e1dc2f70df6da",
+             "4055d8ca3bcf69352da6c2914cf121f5eb4ca2e0f3f09383babfd90bb5257414",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
              "21e2fd657b43e64aa48818dcfcb33f957065dd8b11dc61628537e90b73284ebf",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "8cda6c0a631315b4c81672cf1ca32339f2f25f6b4ec32992dc100794dfdd0baf",
+             "0a5d7643741b48c1ff09b29a4d6ef278b11466e099574e662033454f3204352e",
              "paper_2408_15583_amd/csrc/pe_geom.h":
              "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
 

@@ -70,7 +70,8 @@ void launch_blend_grid(const float4* pa, uint64_t n, float R, float h, int G, ui
 // One thread per live ray of the list whose record was written by the current pass.
 __global__ __launch_bounds__(256) void k_blend(const SlotDesc* __restrict__ ds,
                                                const uint32_t* __restrict__ list,
-                                               const uint32_t* __restrict__ n_live, RayState rs) {
+                                               const uint32_t* __restrict__ n_live, RayState rs,
+                                               int primary) {
     const uint32_t n = *n_live;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const uint32_t entry = list[e];
@@ -78,7 +79,9 @@ __global__ __launch_bounds__(256) void k_blend(const SlotDesc* __restrict__ ds,
         if (!(d.blend_r > 0.f)) continue;
         const uint64_t g = d.pix_base + entry_pix(entry);
         const v3f x = mkv(rs.f[RX][g], rs.f[RX + 1][g], rs.f[RX + 2][g]);
-        const v3f k = mkv(rs.f[RKX][g], rs.f[RKX + 1][g], rs.f[RKX + 2][g]);
+        // a primary record does not store its direction (the slot's)
+        const v3f k = primary ? mkv(d.k[0], d.k[1], d.k[2])
+                              : mkv(rs.f[RKX][g], rs.f[RKX + 1][g], rs.f[RKX + 2][g]);
         const float r = d.blend_r, reach = d.blend_r + d.r_max;
         const float tol = 1e-6f * d.R;  // the nearest hit itself lies on P' up to rounding
         int lo[3], hi[3];
@@ -149,8 +152,8 @@ __global__ __launch_bounds__(256) void k_blend(const SlotDesc* __restrict__ ds,
 }
 
 void launch_blend(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_blend, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs);
+                  int primary, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_blend, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs, primary);
 }
 
 }  // namespace pe

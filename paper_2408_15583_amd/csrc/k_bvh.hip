@@ -383,7 +383,9 @@ __global__ __launch_bounds__(256) void k_trace_bvh(const SlotDesc* __restrict__ 
             // the ray state is read whatever the bounce guard says (the entry's pixel is
             // always in range)
             const uint64_t g = pix_base + entry_pix(entry);
-            const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+            const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g);
+            // a primary record (every ray of the second bounce) does not store its direction
+            const f3 kin = bounce == 2 ? mk3(sd.k[0], sd.k[1], sd.k[2]) : ld3(rs, RKX, g);
             if (bounce <= max_b && bvh_begin(sc, x, leave_dir(kin, nn), eps, s)) return true;
             hitkey[j] = kEmptyKey;
             return false;

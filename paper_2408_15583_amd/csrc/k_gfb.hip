@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_gfb_write(const SlotDesc* __restrict__ 
     if (dot(n, K) > 0.f) n = n * -1.f;
     st3(rs, RX, g, U * ou + V * ov + K * (t - d.R));
     st3(rs, RNX, g, n);
-    st3(rs, RKX, g, K);  // a primary record: incoming fields and tube vectors not stored
+    // a primary record: incoming direction, fields and tube vectors not stored
     rs.d[g] = (double)t - (double)d.R;
     rs.m[g] = 1;
     rs.hit[g] = (uint32_t)p;

@@ -23,8 +23,9 @@ namespace pe {
 // Ray generation from the first-hit buffer
 // ------------------------------------------------------------------------------------------
 
-// Incoming fields and tube vectors of a primary record, which ray generation does not store
-// (they are the same for every pixel of the slot).
+// Incoming direction, fields and tube vectors of a primary record, which ray generation does
+// not store (they are the same for every pixel of the slot).
+__device__ inline f3 primary_dir(const SlotDesc& d) { return mk3(d.k[0], d.k[1], d.k[2]); }
 __device__ inline void primary_fields(const SlotDesc& d, f3& Et, f3& Ep, f3& U, f3& V) {
     Et = mk3(d.eth[0], d.eth[1], d.eth[2]);
     Ep = mk3(d.eph[0], d.eph[1], d.eph[2]);
@@ -99,7 +100,6 @@ __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict
     if (dot(n, K) > 0.f) n = n * -1.f;
     st3(rs, RX, g, x);
     st3(rs, RNX, g, n);
-    st3(rs, RKX, g, K);
     rs.d[g] = (double)t - (double)d.R;
     rs.m[g] = 1;
     rs.hit[g] = i;
@@ -535,7 +535,8 @@ __global__ __launch_bounds__(256, 4) void k_march(const SlotDesc* __restrict__ d
                     // always in range), so that it shares a round with the view's descriptor
                     const bool take = (bounce <= max_b) & ((int)v < n_views);
                     const uint64_t g = pix_base + entry_pix(entry);
-                    const f3 xs = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                    const f3 xs = ld3(rs, RX, g), nn = ld3(rs, RNX, g);
+                    const f3 kin = bounce == 2 ? mk3(sd.k[0], sd.k[1], sd.k[2]) : ld3(rs, RKX, g);
                     bt = FLT_MAX;
                     bi = kNone;
                     if (known != kEmptyKey) {
@@ -692,7 +693,8 @@ __global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict
             hitkey[e] = kEmptyKey;
             if (bounce <= d.max_b) {
                 const uint64_t g = d.pix_base + entry_pix(entry);
-                const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+                const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g);
+                const f3 kin = bounce == 2 ? primary_dir(d) : ld3(rs, RKX, g);
                 const f3 k = leave_dir(kin, nn);
                 live = apply_bounce(d, g, rs, x, nn, k, key, bounce);
             }
@@ -826,13 +828,15 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
         const uint32_t entry = list[e];
         const SlotDesc& d = ds[entry_slot(entry)];
         const uint64_t g = d.pix_base + entry_pix(entry);
-        const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g), kin = ld3(rs, RKX, g);
+        const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g);
         const double dd = rs.d[g];
         const int m = rs.m[g];
-        f3 Et, Ep, u, v;
+        f3 kin, Et, Ep, u, v;
         if (m == 1) {
+            kin = primary_dir(d);
             primary_fields(d, Et, Ep, u, v);
         } else {
+            kin = ld3(rs, RKX, g);
             Et = ld3(rs, RETX, g);
             Ep = ld3(rs, REPX, g);
             u = ld3(rs, RUX, g);

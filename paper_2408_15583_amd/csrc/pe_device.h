@@ -146,8 +146,9 @@ struct ObsDesc {
 // Ray state, structure of arrays indexed by batch pixel.  The state of a live ray is the
 // record of its last bounce: hit point, oriented normal, incoming direction, incoming fields
 // for both transmit polarisations, incoming tube vectors, image-method path length to x.  A
-// primary record (bounce count 1) does not store the incoming fields and tube vectors: they are
-// its slot's transmit polarisations and screen axes times the pixel pitch.
+// primary record (bounce count 1) does not store the incoming direction, fields and tube
+// vectors: they are its slot's direction, transmit polarisations and screen axes times the
+// pixel pitch.
 enum RayComp { RX = 0, RNX = 3, RKX = 6, RETX = 9, REPX = 12, RUX = 15, RVX = 18, RNCOMP = 21 };
 struct RayState {
     float* f[RNCOMP];
@@ -287,7 +288,7 @@ void launch_blend_grid(const float4* pa, uint64_t n, float R, float h, int G, ui
                        uint32_t* counts, uint32_t* start, uint32_t* cursor, uint32_t* items,
                        hipStream_t st);
 void launch_blend(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live, RayState rs,
-                  int n_blocks, hipStream_t st);
+                  int primary, int n_blocks, hipStream_t st);
 // PCA normals: bounding box partials (7 doubles per block: lo xyz, hi xyz, non-finite count),
 // grid of G^3 cells of edge h from lo (box-centred frame), k-nearest PCA.
 void launch_nrm_bbox(const void* xyz, int is_f64, uint64_t n, double* partial, int nb,

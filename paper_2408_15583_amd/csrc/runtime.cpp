@@ -463,7 +463,7 @@ void Batch::raygen() {
     prof_end("raygen_write");
     if (blend) {
         prof_begin();
-        launch_blend(dd, lists[0], cnt + C_N0, rs, persistent_blocks(), st);
+        launch_blend(dd, lists[0], cnt + C_N0, rs, 1, persistent_blocks(), st);
         prof_end("blend");
     }
     HIPCHK(hipGetLastError());
@@ -563,7 +563,7 @@ void Batch::trace(bool with_records) {
         prof_end("compact");
         if (blend) {
             prof_begin();
-            launch_blend(dd, out, nout, rs, persistent_blocks(), st);
+            launch_blend(dd, out, nout, rs, 0, persistent_blocks(), st);
             prof_end("blend");
         }
         HIPCHK(hipMemcpyAsync(cnt + C_BOUNCE0 + b, ncur, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
