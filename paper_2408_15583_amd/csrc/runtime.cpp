@@ -434,15 +434,16 @@ static int persistent_blocks() { return 2048; }
 // lane its own kind of step).  Measured on the composite bench (ms per step, second bounce /
 // visibility), refill alone at 8: 83.4 / 13.8, 16: 46.0 / 8.5, 24: 32.0 / 7.0, 32: 26.1 / 7.2,
 // 40: 25.8 / 7.6, 48: 25.8 / 7.7, 64: 32.1 / 10.0; with refill 40, quorum 8: 22.9 / 6.6,
-// 12: 22.4 / 7.0, 16: 22.7 / 7.1 (visibility keeps its own kind of step per lane, 6.6).
-// PE_BVH_REFILL, PE_BVH_QUORUM and PE_PSI_REFILL override.
+// 12: 22.4 / 7.0, 16: 22.7 / 7.1.  Visibility alone, later (ms per step): refill 24 6.85, 40
+// 7.10; refill 40 with quorum 8 6.63, 10 6.75, 12 6.80; refill 24 with quorum 8 6.75.
+// PE_BVH_REFILL, PE_BVH_QUORUM, PE_PSI_REFILL and PE_PSI_QUORUM override.
 static int bvh_refill(bool psi) {
     auto env = [](const char* name, int dflt) {
         const char* e = std::getenv(name);
         return e ? std::atoi(e) : dflt;
     };
     static const int v[2] = {env("PE_BVH_REFILL", 40) | (env("PE_BVH_QUORUM", 12) << 8),
-                             env("PE_PSI_REFILL", 24)};
+                             env("PE_PSI_REFILL", 40) | (env("PE_PSI_QUORUM", 8) << 8)};
     return v[psi ? 1 : 0];
 }
 
