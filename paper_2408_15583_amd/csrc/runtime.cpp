@@ -427,7 +427,17 @@ void Batch::alloc_rays() {
     coff = ws.get<uint32_t>(B_COFF, tot_pix / kWaveChunk + 2);
 }
 
-static int persistent_blocks() { return 2048; }
+// Workgroups of the persistent passes (traversal, apply, compaction, facet records); the
+// traversal holds 6 wavefronts per SIMD, 1536 workgroups of 4 on 256 CUs.  Measured on the
+// composite bench (ms per step): 1024 70.3, 1536 67.1, 2048 66.0, 3072 66.8, 4096 66.2.
+// PE_PERSIST_BLOCKS overrides.
+static int persistent_blocks() {
+    static const int v = [] {
+        const char* e = std::getenv("PE_PERSIST_BLOCKS");
+        return e ? std::max(1, std::atoi(e)) : 2048;
+    }();
+    return v;
+}
 
 // Idle lanes at which a traversal wavefront takes new rays (bits 0-7) and the quorum of lanes
 // holding points at which it runs a point step for the whole wavefront (bits 8-15, 0 = each
