@@ -96,35 +96,34 @@ struct PoRec {
     float al, be, a[4];
 };
 
-// A tile's records: the arrays offset to the tile's first record, so that a record is a
-// 32-bit index from a wave-uniform base (the loads take the base from scalar registers).
+// A tile's records from the tile's first record, so that a record is a 32-bit index from a
+// wave-uniform base (the loads take the base from scalar registers).
 struct PoTileRecs {
-    const double* D;
-    const float *al, *be, *A[4];
+    const ExitRec* rec;
 };
 
 __device__ inline PoTileRecs po_tile_recs(const ExitRecs& er, uint64_t base) {
     PoTileRecs t;
-    t.D = er.D + base;
-    t.al = er.al + base;
-    t.be = er.be + base;
-#pragma unroll
-    for (int pq = 0; pq < 4; pq++) t.A[pq] = er.A[pq] + base;
+    t.rec = er.rec + base;
     return t;
 }
 
-// r < kRT: the byte offsets fit 32 bits, which lets the loads add them to a scalar base.
+// r < kRT: the byte offsets fit 32 bits, which lets the loads add them to a scalar base.  A
+// record is two 16-byte loads.
 __device__ inline PoRec po_rec(const PoTileRecs& t, uint32_t r) {
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
     typedef const __attribute__((address_space(1))) char GC;
-    typedef const __attribute__((address_space(1))) double GD;
-    typedef const __attribute__((address_space(1))) float GF;
-    const uint32_t o4 = r * 4u, o8 = r * 8u;
+    typedef const __attribute__((address_space(1))) u4v GU;
+    const uint32_t o = r * (uint32_t)sizeof(ExitRec);
+    const u4v h0 = *(GU*)((GC*)t.rec + o), h1 = *(GU*)((GC*)t.rec + o + 16);
     PoRec q;
-    q.D = *(GD*)((GC*)t.D + o8);
-    q.al = *(GF*)((GC*)t.al + o4);
-    q.be = *(GF*)((GC*)t.be + o4);
-#pragma unroll
-    for (int pq = 0; pq < 4; pq++) q.a[pq] = *(GF*)((GC*)t.A[pq] + o4);
+    q.D = __hiloint2double((int)h0.y, (int)h0.x);
+    q.al = __uint_as_float(h0.z);
+    q.be = __uint_as_float(h0.w);
+    q.a[0] = __uint_as_float(h1.x);
+    q.a[1] = __uint_as_float(h1.y);
+    q.a[2] = __uint_as_float(h1.z);
+    q.a[3] = __uint_as_float(h1.w);
     return q;
 }
 

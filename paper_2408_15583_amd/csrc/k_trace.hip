@@ -867,13 +867,13 @@ __global__ __launch_bounds__(256) void k_po_prep(const SlotDesc* __restrict__ ds
             const f3 Vt = cross(cross(jt, ks), ks), Vp = cross(cross(jp, ks), ks);
             const f3 rt = mk3(O.eth[0], O.eth[1], O.eth[2]), rp = mk3(O.eph[0], O.eph[1], O.eph[2]);
             const uint64_t r = ((uint64_t)o * n_seg + seg) * rec_stride + e;
-            er.D[r] = dd - ((double)ks.x * x.x + (double)ks.y * x.y + (double)ks.z * x.z);
-            er.al[r] = 0.5f * dot(q, up);
-            er.be[r] = 0.5f * dot(q, vp);
-            er.A[0][r] = w * dot(Vt, rt);
-            er.A[1][r] = w * dot(Vp, rt);
-            er.A[2][r] = w * dot(Vt, rp);
-            er.A[3][r] = w * dot(Vp, rp);
+            const double D = dd - ((double)ks.x * x.x + (double)ks.y * x.y + (double)ks.z * x.z);
+            const uint64_t Db = (uint64_t)__double_as_longlong(D);
+            uint4* out = reinterpret_cast<uint4*>(er.rec + r);
+            out[0] = make_uint4((uint32_t)Db, (uint32_t)(Db >> 32),
+                                __float_as_uint(0.5f * dot(q, up)), __float_as_uint(0.5f * dot(q, vp)));
+            out[1] = make_uint4(__float_as_uint(w * dot(Vt, rt)), __float_as_uint(w * dot(Vp, rt)),
+                                __float_as_uint(w * dot(Vt, rp)), __float_as_uint(w * dot(Vp, rp)));
         }
     }
 }

@@ -157,12 +157,16 @@ struct RayState {
     uint32_t* hit;            // point index of the record's facet
 };
 
-// Exit (facet) records: frequency-independent part of one term of Eq. (14).
+// Exit (facet) record: frequency-independent part of one term of Eq. (14), 32 bytes (written
+// and read as two 16-byte halves).
+struct __attribute__((aligned(16))) ExitRec {
+    double D;                 // d - k_s . x (scene frame)
+    float al;                 // (k_in - k_s) . u' / 2
+    float be;                 // (k_in - k_s) . v' / 2
+    float A[4];               // psi * area * V . e_rx for (rx, tx) = (t,t), (t,p), (p,t), (p,p)
+};
 struct ExitRecs {
-    double* D;                // d - k_s . x (scene frame)
-    float* al;                // (k_in - k_s) . u' / 2
-    float* be;                // (k_in - k_s) . v' / 2
-    float* A[4];              // psi * area * V . e_rx for (rx, tx) = (t,t), (t,p), (p,t), (p,p)
+    ExitRec* rec;
 };
 
 __host__ __device__ inline uint32_t entry_slot(uint32_t e) { return e >> kPixBits; }

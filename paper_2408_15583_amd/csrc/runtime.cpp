@@ -496,11 +496,7 @@ void Batch::raygen_gfb(const float* depth, const float* nrm, const float* prob,
 void Batch::alloc_records() {
     rec_stride = (uint32_t)tot_pix;
     const uint64_t nrec = (uint64_t)max_obs * n_seg * rec_stride;
-    er.D = ws.get<double>(B_RECD, nrec);
-    float* f = ws.get<float>(B_RECF, nrec * 6);
-    er.al = f;
-    er.be = f + nrec;
-    for (int c = 0; c < 4; c++) er.A[c] = f + (2 + c) * nrec;
+    er.rec = ws.get<ExitRec>(B_RECD, nrec);
     seg_beg = ws.get<uint32_t>(B_SEGB, (uint64_t)n_seg * n + 1);
     seg_cnt = ws.get<uint32_t>(B_SEGC, (uint64_t)n_seg * n + 1);
 }
