@@ -349,7 +349,8 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
                                                 const uint32_t* __restrict__ list,
                                                 uint32_t capacity,
                                                 uint64_t* __restrict__ keys, uint32_t n_tiles,
-                                                uint32_t n_slots) {
+                                                uint32_t n_slots, uint32_t* __restrict__ live_count,
+                                                uint32_t live_stride) {
     uint32_t utile, slot;
     if (!xcd_tile_slot(blockIdx.x, n_tiles, n_slots, utile, slot)) return;
     const SlotDesc& d = ds[slot];
@@ -414,22 +415,45 @@ __global__ __launch_bounds__(256) void k_raster(const SlotDesc* __restrict__ ds,
         }
     }
     __syncthreads();
+    // 256 threads over TILE x TILE pixels: a wavefront's lanes cover 64 / TILE whole tile rows
+    static_assert(256 % (TILE * TILE) == 0 || (TILE * TILE) % 256 == 0, "whole iterations");
+    static_assert(64 % TILE == 0, "whole tile rows per wavefront");
     for (int q = threadIdx.x; q < TILE * TILE; q += 256) {
         const int x = px0 + q % TILE, y = py0 + q / TILE;
-        if (x < s.W && y < s.H) keys[d.pix_base + (uint64_t)y * s.W + x] = lk[q];
+        const bool in = x < s.W && y < s.H;
+        const uint64_t key = lk[q];
+        if (in) keys[d.pix_base + (uint64_t)y * s.W + x] = key;
+        if (live_count) {
+            // a ray starts where the first hit is not an absorber (as the ray generation tests)
+            const bool live = in && key != kEmptyKey &&
+                              gld(d.pb + (uint32_t)(key & 0xFFFFFFFFu)).w == 0.f;
+            const uint64_t bal = __ballot(live);
+            const int lane = threadIdx.x & 63;
+            if (lane % TILE == 0 && y < s.H) {
+                const uint64_t run = (bal >> lane) & ((TILE == 64) ? ~0ull : ((1ull << TILE) - 1ull));
+                const uint32_t c = (uint32_t)__popcll(run);
+                if (c) {
+                    const uint32_t blk = (uint32_t)(((uint64_t)y * s.W + px0) / 256);
+                    atomicAdd(&live_count[(uint64_t)slot * live_stride + blk], c);
+                }
+            }
+        }
     }
 }
 
 void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
                    const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
-                   uint64_t* keys, int tile, hipStream_t st) {
+                   uint64_t* keys, int tile, uint32_t* live_count, uint32_t live_stride,
+                   hipStream_t st) {
     const dim3 grid(xcd_tile_grid((uint32_t)max_tiles, (uint32_t)n_slots));
     if (tile == kTileWide)
         hipLaunchKernelGGL(k_raster<kTileWide>, grid, dim3(256), 0, st, d, tile_off, tile_count,
-                           list, capacity, keys, (uint32_t)max_tiles, (uint32_t)n_slots);
+                           list, capacity, keys, (uint32_t)max_tiles, (uint32_t)n_slots,
+                           live_count, live_stride);
     else
         hipLaunchKernelGGL(k_raster<kTile>, grid, dim3(256), 0, st, d, tile_off, tile_count, list,
-                           capacity, keys, (uint32_t)max_tiles, (uint32_t)n_slots);
+                           capacity, keys, (uint32_t)max_tiles, (uint32_t)n_slots, live_count,
+                           live_stride);
 }
 
 // Algorithm 1 with a K-point heap (TUBE slots): per pixel, the K candidates nearest the central

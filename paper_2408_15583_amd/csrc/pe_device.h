@@ -223,9 +223,14 @@ void launch_tile_scatter(const SlotDesc* d, int n_slots, int max_chunks, const i
                          const uint32_t* tile_off, uint32_t* tile_cursor, uint32_t* list,
                          uint32_t capacity, uint32_t* overflow, hipStream_t st);
 // tile: the batch's screen tile edge (every slot's SlotDesc::tile; kTile or kTileWide).
+// live_count (or null): per slot and 256-pixel block of its row-major pixels, the number of
+// pixels whose first hit starts a ray (a hit on a non-absorber), added as the tiles finish
+// (zeroed by the caller; every slot's W a multiple of the tile edge, so a tile row lies in one
+// block); the ray generation's count, at live_stride blocks per slot.
 void launch_raster(const SlotDesc* d, int n_slots, int max_tiles, const uint32_t* tile_off,
                    const uint32_t* tile_count, const uint32_t* list, uint32_t capacity,
-                   uint64_t* keys, int tile, hipStream_t st);
+                   uint64_t* keys, int tile, uint32_t* live_count, uint32_t live_stride,
+                   hipStream_t st);
 void launch_resolve(const SlotDesc* d, const uint64_t* keys, float* depth, float* nrm,
                     uint32_t* idx, uint8_t* mask, int npix, hipStream_t st);
 void launch_view_level0(const SlotDesc* d, int slot, const uint64_t* keys, int W, int H, int P,

@@ -93,6 +93,7 @@ struct Batch {
     int secondary = 0;
     int bvh_depth = 1;  // LDS stack entries per lane of the hierarchy traversals
     bool blend = false;  // some slot's scene refines hits by Eq. (23)
+    bool live_counted = false;  // the raster counted each block's ray-starting pixels
     int max_chunks = 0, max_tiles = 0, max_pix = 0, max_obs = 1, max_freq = 1, tot_out = 0;
     uint64_t tot_pix = 0;
     uint32_t tot_tiles = 0, tot_chunks = 0, tlist_cap = 0, rec_stride = 0;

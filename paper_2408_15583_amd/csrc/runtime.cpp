@@ -403,11 +403,22 @@ void Batch::splat() {
     launch_tile_scatter(dd, n, max_chunks, aabb, toff, tcursor, tlist, tlist_cap,
                         cnt + C_OVERFLOW, st);
     prof_end("tile_scatter");
+    // the nearest-hit raster also counts, per 256-pixel block, the pixels that start rays (the
+    // ray generation's count) when every slot's tile rows lie in single blocks
+    live_counted = topk == 0;
+    for (int s = 0; s < n && live_counted; s++) live_counted = hd[s].W % hd[0].tile == 0;
+    const int gx = (max_pix + 255) / 256;
+    uint32_t* wgc = nullptr;
+    if (live_counted) {
+        wgc = ws.get<uint32_t>(B_WGC, (uint64_t)gx * n + 1);
+        launch_fill_u32(wgc, 0u, (uint64_t)gx * n, st);
+    }
     prof_begin();
     if (topk > 0)
         launch_raster_topk(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, topk, keys, st);
     else
-        launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, hd[0].tile, st);
+        launch_raster(dd, n, max_tiles, toff, tcount, tlist, tlist_cap, keys, hd[0].tile, wgc,
+                      (uint32_t)gx, st);
     prof_end("raster");
     HIPCHK(hipGetLastError());
 }
@@ -462,9 +473,11 @@ void Batch::raygen() {
     const int gx = (max_pix + 255) / 256;
     uint32_t* wgc = ws.get<uint32_t>(B_WGC, (uint64_t)gx * n + 1);
     uint32_t* wgo = ws.get<uint32_t>(B_WGO, (uint64_t)gx * n + 1);
-    prof_begin();
-    launch_raygen_count(dd, n, max_pix, keys, wgc, st);
-    prof_end("raygen_count");
+    if (!live_counted) {
+        prof_begin();
+        launch_raygen_count(dd, n, max_pix, keys, wgc, st);
+        prof_end("raygen_count");
+    }
     prof_begin();
     launch_scan_wide(wgc, wgo, (uint32_t)(gx * n), nullptr, 1, cnt + C_N0,
                      scan_ws, st);
