@@ -42,7 +42,7 @@ FP32_LANE_OPS = 256 * 128 * 2.4e9
 # (FETCH_SIZE reads 524302 KiB for 1 GiB: factor 2.0; WRITE_SIZE 1048576 KiB: factor 1.0).
 # Valid only for the sources they were taken on; any edit of those files reports null.
 MARCH_TRAFFIC = dict(
-    fetch_kib=17602384.3, write_kib=866221.4, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=12002034.8, write_kib=272779.7, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_trace.hip":
              "29d5a3ed46fcc6a9e8e3a31d52ad3cb4dccb09ca086581c56200e5d7259b3adc",
              "paper_2408_15583_amd/csrc/pe_device.h":
@@ -53,13 +53,13 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=17602384.3, write_kib=866221.4, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17605344.4, write_kib=866760.5, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
              "4055d8ca3bcf69352da6c2914cf121f5eb4ca2e0f3f09383babfd90bb5257414",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
              "21e2fd657b43e64aa48818dcfcb33f957065dd8b11dc61628537e90b73284ebf",
              "paper_2408_15583_amd/csrc/pe_device.h":
-             "fa313fcdd5154e3d2c1505232459fabe23b07907b4239dc0b4363b6630822980",
+             "0fc49f89a3ef47b0f58a548b553fdaf736d9d75156e0aa2a339a8359f14eab05",
              "paper_2408_15583_amd/csrc/pe_geom.h":
              "c59a832fb993886519791ad8760ae772576bcca31bb44d5e2b6504e5f4058df1"})
 

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_raygen_write(const SlotDesc* __restrict
     for (int w = 0; w < wave; w++) off += wc[w];
     off += (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
     list[off] = make_entry(slot, (uint32_t)p);
-    hitkey[off] = kEmptyKey;
+    if (hitkey) hitkey[off] = kEmptyKey;  // null: the bounce pass writes every key itself
 
     const uint64_t key = keys[g];
     const float t = __uint_as_float((uint32_t)(key >> 32));
@@ -670,14 +670,16 @@ void launch_march(const SlotDesc* d, const uint32_t* list, const uint32_t* n_liv
 }
 
 // One bounce, pass 2: apply each ray's nearest hit (or stop it), reset its key for the next
-// bounce, and count the survivors of each 64-entry chunk for the order-preserving compaction.
+// bounce when reset_keys (the views' march min-updates keys; the splat traversal writes every
+// key itself), and count the survivors of each 64-entry chunk for the order-preserving
+// compaction.
 __global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict__ ds,
                                                       const uint32_t* __restrict__ list,
                                                       const uint32_t* __restrict__ n_live,
                                                       RayState rs, uint64_t* __restrict__ hitkey,
                                                       uint8_t* __restrict__ alive,
                                                       uint32_t* __restrict__ chunk_count,
-                                                      int bounce) {
+                                                      int bounce, int reset_keys) {
     const uint32_t n = *n_live;
     const uint32_t n_chunks = (n + kWaveChunk - 1) / kWaveChunk;
     const int lane = threadIdx.x & 63;
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict
             const uint32_t entry = list[e];
             const SlotDesc& d = ds[entry_slot(entry)];
             const uint64_t key = hitkey[e];
-            hitkey[e] = kEmptyKey;
+            if (reset_keys) hitkey[e] = kEmptyKey;
             if (bounce <= d.max_b) {
                 const uint64_t g = d.pix_base + entry_pix(entry);
                 const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g);
@@ -707,9 +709,9 @@ __global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict
 
 void launch_bounce_apply(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
                          RayState rs, uint64_t* hitkey, uint8_t* alive, uint32_t* chunk_count,
-                         int bounce, int n_blocks, hipStream_t st) {
+                         int bounce, int reset_keys, int n_blocks, hipStream_t st) {
     hipLaunchKernelGGL(k_bounce_apply, dim3(n_blocks), dim3(256), 0, st, d, list, n_live, rs,
-                       hitkey, alive, chunk_count, bounce);
+                       hitkey, alive, chunk_count, bounce, reset_keys);
 }
 
 // Order-preserving compaction of 64-entry chunks, one wavefront per chunk (grid-stride over

@@ -309,7 +309,7 @@ void launch_nrm_pca(const float4* p, uint64_t n, const float4* ps, const uint32_
                     float lo, float h, int G, int k, float* nrm, hipStream_t st);
 void launch_bounce_apply(const SlotDesc* d, const uint32_t* list, const uint32_t* n_live,
                          RayState rs, uint64_t* hitkey, uint8_t* alive, uint32_t* chunk_count,
-                         int bounce, int n_blocks, hipStream_t st);
+                         int bounce, int reset_keys, int n_blocks, hipStream_t st);
 void launch_compact(const uint32_t* list_in, const uint32_t* n_in, const uint8_t* alive,
                     const uint32_t* chunk_off, uint32_t* list_out, int n_blocks,
                     hipStream_t st);

@@ -483,7 +483,9 @@ void Batch::raygen() {
                      scan_ws, st);
     prof_end("raygen_scan");
     prof_begin();
-    launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs, hitkey, st);
+    // the splat traversal writes every ray's key; the views' march needs them cleared
+    launch_raygen_write(dd, n, max_pix, keys, wgo, lists[0], rs,
+                        secondary == PE_SECONDARY_SPLATS ? nullptr : hitkey, st);
     prof_end("raygen_write");
     if (blend) {
         prof_begin();
@@ -571,7 +573,8 @@ void Batch::trace(bool with_records) {
             prof_end(names[std::min(b - 2, 7)]);
         }
         prof_begin();
-        launch_bounce_apply(dd, cur, ncur, rs, hitkey, alive, ccount, b, persistent_blocks(), st);
+        launch_bounce_apply(dd, cur, ncur, rs, hitkey, alive, ccount, b,
+                            secondary != PE_SECONDARY_SPLATS, persistent_blocks(), st);
         prof_end("bounce_apply");
         prof_begin();
         const uint32_t max_chunks = (uint32_t)((tot_pix + kWaveChunk - 1) / kWaveChunk);
