@@ -693,7 +693,8 @@ __global__ __launch_bounds__(256) void k_bounce_apply(const SlotDesc* __restrict
             const SlotDesc& d = ds[entry_slot(entry)];
             const uint64_t key = hitkey[e];
             if (reset_keys) hitkey[e] = kEmptyKey;
-            if (bounce <= d.max_b) {
+            // a ray without a hit stops: its state is not read (most second-bounce rays)
+            if (bounce <= d.max_b && (uint32_t)(key & 0xFFFFFFFFu) != kNone) {
                 const uint64_t g = d.pix_base + entry_pix(entry);
                 const f3 x = ld3(rs, RX, g), nn = ld3(rs, RNX, g);
                 const f3 kin = bounce == 2 ? primary_dir(d) : ld3(rs, RKX, g);
