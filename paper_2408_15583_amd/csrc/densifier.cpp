@@ -10,6 +10,7 @@
 //   2 C[l-1] -> C[l-1] + GELU; then 3x3 conv C0 -> 4 co + pixel shuffle: outputs at twice
 //   the input resolution.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -297,6 +298,28 @@ struct pe_densifier_s {
         const int c = C[l], M = N * H * W;
         launch_dw_fwd(A.bx[l], N, H, W, c, dwt[l], P(b.dwb), A.dwo[l], st);
         launch_ln_fwd(A.dwo[l], M, c, P(b.lng), P(b.lnb), kLnEps, A.lno[l], A.lst[l], st);
+        static const bool unfused = std::getenv("PE_NN_UNFUSED") != nullptr;
+        if (!train && !unfused) {
+            // inference keeps the hidden activation on chip (the same arithmetic; PE_NN_UNFUSED
+            // selects the two separate convolutions)
+            ConvArgs a{};
+            a.x = A.lno[l];
+            a.ldx = c;
+            a.N = N;
+            a.H = H;
+            a.W = W;
+            a.Cin = 4 * c;
+            a.K = 1;
+            a.w = PB(b.pw2.w);
+            a.Cout = c;
+            a.Cout_store = c;
+            a.bias = P(b.pw2.b);
+            a.res = A.bx[l];
+            a.ldres = c;
+            a.y = A.sk[l];
+            a.ldy = c;
+            if (launch_mlp_fwd(a, PB(b.pw1.w), P(b.pw1.b), st)) return;
+        }
         conv_fwd(b.pw1, A.lno[l], c, 0, N, H, W, A.a1[l], nullptr, 4 * c, 0, 1, 0,
                  train ? A.z1[l] : nullptr, nullptr, st);
         conv_fwd(b.pw2, A.a1[l], 4 * c, 0, N, H, W, A.sk[l], nullptr, c, 0, 0, 0, nullptr, A.bx[l],

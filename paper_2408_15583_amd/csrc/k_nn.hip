@@ -518,6 +518,131 @@ static void launch_conv3_halo_t(const ConvArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_conv3_halo<BN, TH, WGM, NS, TPS>), dim3(gx, gy), dim3(256), 0, st, a);
 }
 
+// ConvNeXt block MLP for inference, fused: y = x2 + W2 GELU(W1 x + b1) + b2 with the 4C-wide
+// hidden activation kept in LDS (the two 1 x 1 convolutions of the block write and read it
+// through HBM otherwise).  A block takes 64 pixels: the x tile (64 x C) is staged once; the
+// hidden channels go in chunks of 64: W1's chunk (64 x C) and W2's (C x 64) staged, GEMM 1
+// into 2 x 2 wavefront tiles, bias + GELU + bf16 into the hidden tile, GEMM 2 accumulating the
+// 64 x C output across chunks (wavefronts 2 x 2 over rows x channels).  The arithmetic is that
+// of the two convolutions: fp32 accumulation in the same K order, the hidden value rounded to
+// bf16, then acc + b2 + residual.  A: the pw2 arguments (output, bias, residual); w1, b1: pw1's.
+template <int C>
+__global__ __launch_bounds__(256) void k_mlp_fwd(ConvArgs a, const uint16_t* __restrict__ w1,
+                                                 const float* __restrict__ b1) {
+    constexpr int BM = 64, HC = 64, H4 = 4 * C;
+    constexpr int XL = C + 8, HL = HC + 8;                   // padded bf16 rows
+    constexpr int TN2 = C / 32;                              // GEMM 2 MFMA tiles per wavefront
+    constexpr int XS = BM * XL, W1S = HC * XL, HS = BM * HL, W2S = C * HL;
+    constexpr int TOT = XS + W1S + HS + W2S;                 // bf16 elements
+    static_assert(BM * (C + 4) * 4 <= TOT * 2, "fp32 output tile fits the LDS");
+    __shared__ __attribute__((aligned(16))) uint16_t lds[TOT];
+    uint16_t* const xs = lds;
+    uint16_t* const ws1 = xs + XS;
+    uint16_t* const hs = ws1 + W1S;
+    uint16_t* const ws2 = hs + HS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int M = a.N * a.H * a.W, m0 = blockIdx.x * BM;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    // x tile: 64 rows x C channels, 16-byte chunks (pixels past the end read as zero)
+    for (int c = tid; c < BM * C / 8; c += 256) {
+        const int row = c / (C / 8), k8 = c - row * (C / 8), m = m0 + row;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (m < M) v = *(const uint4*)(a.x + (size_t)m * a.ldx + a.xoff + k8 * 8);
+        *(uint4*)&xs[row * XL + k8 * 8] = v;
+    }
+    v4f acc2[2][TN2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < TN2; j++) acc2[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int h0 = 0; h0 < H4; h0 += HC) {
+        // the chunk's weights: W1 rows h0 .. h0 + 63 (C each), W2 columns h0 .. h0 + 63
+        for (int c = tid; c < HC * C / 8; c += 256) {
+            const int row = c / (C / 8), k8 = c - row * (C / 8);
+            *(uint4*)&ws1[row * XL + k8 * 8] = *(const uint4*)(w1 + (size_t)(h0 + row) * C + k8 * 8);
+        }
+        for (int c = tid; c < C * HC / 8; c += 256) {
+            const int row = c / (HC / 8), k8 = c - row * (HC / 8);
+            *(uint4*)&ws2[row * HL + k8 * 8] = *(const uint4*)(a.w + (size_t)row * H4 + h0 + k8 * 8);
+        }
+        __syncthreads();
+        // GEMM 1: hidden[64 x 64] = x . W1 chunk^T, wavefront tile 32 x 32
+        v4f acc1[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) acc1[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < C; k0 += 32) {
+            Frag fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++) fa[i].u = *(const uint4*)&xs[(wm * 32 + i * 16 + r) * XL + k0 + kq];
+#pragma unroll
+            for (int j = 0; j < 2; j++) fb[j].u = *(const uint4*)&ws1[(wn * 32 + j * 16 + r) * XL + k0 + kq];
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v,
+                                                                        acc1[i][j], 0, 0, 0);
+        }
+        // bias + GELU, rounded to bf16 as the separate convolution stores it
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int col = wn * 32 + j * 16 + r;
+            const float bias = b1 ? b1[h0 + col] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int row = wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+                    hs[row * HL + col] = f2bf(gelu_f(acc1[i][j][q] + bias));
+                }
+        }
+        __syncthreads();
+        // GEMM 2: out[64 x C] += hidden . W2 chunk^T, wavefront tile 32 x C/2
+#pragma unroll
+        for (int k0 = 0; k0 < HC; k0 += 32) {
+            Frag fa[2], fb[TN2];
+#pragma unroll
+            for (int i = 0; i < 2; i++) fa[i].u = *(const uint4*)&hs[(wm * 32 + i * 16 + r) * HL + k0 + kq];
+#pragma unroll
+            for (int j = 0; j < TN2; j++)
+                fb[j].u = *(const uint4*)&ws2[(wn * (C / 2) + j * 16 + r) * HL + k0 + kq];
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < TN2; j++)
+                    acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v,
+                                                                        acc2[i][j], 0, 0, 0);
+        }
+        __syncthreads();  // the chunk's tiles are free for the next chunk (and the epilogue)
+    }
+    conv_epilogue<C, BM, 2>(a, acc2, lds, [m0](int row) { return m0 + row; }, 0);
+}
+
+template <int C>
+static void launch_mlp_t(const ConvArgs& a, const uint16_t* w1, const float* b1, hipStream_t st) {
+    const int M = a.N * a.H * a.W;
+    hipLaunchKernelGGL(k_mlp_fwd<C>, dim3((M + 63) / 64), dim3(256), 0, st, a, w1, b1);
+}
+
+bool launch_mlp_fwd(const ConvArgs& a, const uint16_t* w1, const float* b1, hipStream_t st) {
+    if (a.K != 1 || a.Cout != a.Cin / 4 || a.Cout_store != a.Cout || a.shuffle || a.y32 || a.z ||
+        a.act || a.xoff % 8 || a.ldx % 8)
+        return false;
+    // Measured (batch 8 at 256^2, us per layer, fused against the two convolutions): C = 32
+    // 55.5 / 91.1, 64 41.7 / 54.5, 128 52.9 / 45.5, 256 108.8 / 40.0 (the deep layers have few
+    // pixels, and the fused tile's registers and LDS leave one or two wavefronts per SIMD), so
+    // only the two wide-image levels take it.
+    switch (a.Cout) {
+        case 32: launch_mlp_t<32>(a, w1, b1, st); return true;
+        case 64: launch_mlp_t<64>(a, w1, b1, st); return true;
+        default: return false;
+    }
+}
+
 // Tile choice (measured, batch of 8 at 256^2 -> 512^2, inference per batch): 3 x 3 layers whose
 // images split into 16-column tiles go to k_conv3_halo with 8-row tiles of 64 (or, for narrow
 // outputs, 32) channels, three taps per K step and two copy stages (1.51 ms; one tap per step

@@ -45,6 +45,11 @@ struct LossArgs {
 };
 
 void launch_conv_fwd(const ConvArgs& a, hipStream_t st);
+// Inference form of a ConvNeXt block's two 1 x 1 convolutions fused (expand x4 with GELU, then
+// project with the residual): a holds the projecting convolution with a.x the block's
+// normalised input and a.Cin the hidden width (4 x a.Cout); w1, b1 the expanding one.  Returns
+// false (nothing launched) for shapes it does not take.
+bool launch_mlp_fwd(const ConvArgs& a, const uint16_t* w1, const float* b1, hipStream_t st);
 void launch_conv_wgrad(const WgradArgs& a, int n_chunks, hipStream_t st);
 void launch_reduce_chunks(const float* part, int n_chunks, size_t stride, size_t n, int inner,
                           int outer, int off, float* out, hipStream_t st);

@@ -175,6 +175,46 @@ def test_forward_batch4_full_size_elementwise(pe, ctx):
     check_elementwise(gpu, nom, s, "4x256^2 forward")
 
 
+_SEPARATE_CONVS = """
+import sys
+import numpy as np
+import torch
+assert torch.cuda.is_available()
+import paper_2408_15583_amd as pe
+ctx = pe.Context(0)
+net = pe.Densifier(ctx, base=32, seed=1)
+g = torch.Generator(device="cpu").manual_seed(0)
+x = (torch.rand((2, 256, 256), generator=g) * (torch.rand((2, 256, 256), generator=g) < 0.7)).cuda()
+np.savez(sys.argv[1], *[o.cpu().numpy() for o in net.infer(x)])
+net.close()
+ctx.close()
+"""
+
+
+def test_fused_block_mlp_matches_separate_convolutions(pe, ctx, tmp_path):
+    """Inference runs each wide-image ConvNeXt block's two 1 x 1 convolutions as one kernel that
+    keeps the hidden activation in LDS; it does the same arithmetic in the same order, so the
+    outputs equal those of the two separate convolutions (selected in a child process by
+    PE_NN_UNFUSED) bit for bit."""
+    import os
+    import subprocess
+    import sys
+    import torch
+    net = pe.Densifier(ctx, base=32, seed=1)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = (torch.rand((2, 256, 256), generator=g) * (torch.rand((2, 256, 256), generator=g) < 0.7)).cuda()
+    fused = [o.cpu().numpy() for o in net.infer(x)]
+    net.close()
+    out = tmp_path / "separate.npz"
+    env = dict(os.environ, PE_NN_UNFUSED="1")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([sys.executable, "-c", _SEPARATE_CONVS, str(out)], env=env, cwd=root,
+                   check=True, timeout=240)
+    sep = np.load(out)
+    for i, a in enumerate(fused):
+        assert np.array_equal(a, sep[f"arr_{i}"]), f"output {i} differs"
+
+
 def test_adamw_step_matches_oracle(pe, ctx):
     net = pe.Densifier(ctx, base=32, seed=4)
     x, dg, ng, mg = batch(6)
