@@ -53,11 +53,11 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=17605344.4, write_kib=866760.5, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17974553.3, write_kib=873897.9, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
              "4055d8ca3bcf69352da6c2914cf121f5eb4ca2e0f3f09383babfd90bb5257414",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
-             "21e2fd657b43e64aa48818dcfcb33f957065dd8b11dc61628537e90b73284ebf",
+             "f135c2a917cc09c6ad31c0644cbe5f93038aefabf3a0d0a777e30079acf1cb03",
              "paper_2408_15583_amd/csrc/pe_device.h":
              "0fc49f89a3ef47b0f58a548b553fdaf736d9d75156e0aa2a339a8359f14eab05",
              "paper_2408_15583_amd/csrc/pe_geom.h":

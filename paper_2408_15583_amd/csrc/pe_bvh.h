@@ -209,8 +209,17 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
     const float az = (__uint_as_float(q0.z) - s.o.z) * s.inv.z;
     const uint32_t occ = q0.w >> 24, iocc = q1.z, counts = q1.w;
     const float tmax = any ? FLT_MAX : key_t(s.key);
-    const uint32_t lox[2] = {q2.x, q2.y}, loy[2] = {q2.z, q2.w}, loz[2] = {q3.x, q3.y},
-                   hix[2] = {q3.z, q3.w}, hiy[2] = {q4.x, q4.y}, hiz[2] = {q4.z, q4.w};
+    // the near plane of an axis is the low one where the ray runs toward +axis (reciprocal
+    // > 0), else the high one: picked once per record.  The plane parameter q (scale / k) +
+    // (org - o) / k is monotonic in q (a correctly rounded fma of a monotonic map), so the
+    // picked planes give exactly the minimum and maximum of each child's two.
+    const bool bx = s.inv.x < 0.f, by = s.inv.y < 0.f, bz = s.inv.z < 0.f;
+    const uint32_t nx[2] = {bx ? q3.z : q2.x, bx ? q3.w : q2.y},
+                   fx[2] = {bx ? q2.x : q3.z, bx ? q2.y : q3.w},
+                   ny[2] = {by ? q4.x : q2.z, by ? q4.y : q2.w},
+                   fy[2] = {by ? q2.z : q4.x, by ? q2.w : q4.y},
+                   nz[2] = {bz ? q4.z : q3.x, bz ? q4.w : q3.y},
+                   fz[2] = {bz ? q3.x : q4.z, bz ? q3.y : q4.w};
     // hit octants, then the internal ones to the node group (rank order) and the leaf ones'
     // points to the point group; an octant no lane of the wavefront occupies is skipped
     uint32_t hits = 0;
@@ -218,28 +227,39 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
     for (int o = 0; o < 8; o++) {
         if (!((occ >> o) & 1u)) continue;
         const int w = o >> 2, sh = 8 * (o & 3);
-        const float x0 = fmaf((float)((lox[w] >> sh) & 0xFFu), sx, ax);
-        const float x1 = fmaf((float)((hix[w] >> sh) & 0xFFu), sx, ax);
-        const float y0 = fmaf((float)((loy[w] >> sh) & 0xFFu), sy, ay);
-        const float y1 = fmaf((float)((hiy[w] >> sh) & 0xFFu), sy, ay);
-        const float z0 = fmaf((float)((loz[w] >> sh) & 0xFFu), sz, az);
-        const float z1 = fmaf((float)((hiz[w] >> sh) & 0xFFu), sz, az);
-        const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fminf(z0, z1));
-        const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
+        const float tn = fmaxf(fmaxf(fmaf((float)((nx[w] >> sh) & 0xFFu), sx, ax),
+                                     fmaf((float)((ny[w] >> sh) & 0xFFu), sy, ay)),
+                               fmaf((float)((nz[w] >> sh) & 0xFFu), sz, az));
+        const float tf = fminf(fminf(fmaf((float)((fx[w] >> sh) & 0xFFu), sx, ax),
+                                     fmaf((float)((fy[w] >> sh) & 0xFFu), sy, ay)),
+                               fmaf((float)((fz[w] >> sh) & 0xFFu), sz, az));
         hits |= (tn <= tf && tf >= s.tmin && tn <= tmax) ? 1u << o : 0u;
     }
-    const uint32_t ih = hits & iocc;
-    uint32_t nh = 0;
-#pragma unroll
-    for (int o = 0; o < 8; o++) nh |= ((ih >> o) & 1u) << (o ^ s.dmask);
-    // point bits of octant o: cnt_o bits from the sum of the lower octants' counts
+    // the hit internal octants in rank order (octant XOR sign mask): XOR with each set bit of
+    // the sign mask swaps neighbouring bits, pairs of bits or nibbles
+    uint32_t nh = hits & iocc;
+    if (s.dmask & 1u) nh = ((nh & 0x55u) << 1) | ((nh >> 1) & 0x55u);
+    if (s.dmask & 2u) nh = ((nh & 0x33u) << 2) | ((nh >> 2) & 0x33u);
+    if (s.dmask & 4u) nh = ((nh & 0x0Fu) << 4) | (nh >> 4);
+    // point bits of octant o: cnt_o bits from S_o, the sum of the lower octants' counts (at
+    // most 64 in all).  The S_o come as bytes: the counts summed in pairs, the pairs of the
+    // lower bytes added by shifts (no byte carries over) for the even octants' starts, plus
+    // the even octant's count for the odd ones'.  Counts of leaf octants not hit are cleared
+    // (a nibble mask spread from the hit bits) after the offsets are taken.
+    const uint32_t ce = counts & 0x0F0F0F0Fu, co = (counts >> 4) & 0x0F0F0F0Fu;
+    const uint32_t pr = ce + co;
+    const uint32_t s_even = (pr << 8) + (pr << 16) + (pr << 24), s_odd = s_even + ce;
+    uint32_t lm = hits & ~iocc;
+    lm = (lm | (lm << 12)) & 0x000F000Fu;
+    lm = (lm | (lm << 6)) & 0x03030303u;
+    lm = (lm | (lm << 3)) & 0x11111111u;
+    const uint32_t hc = counts & ((lm << 4) - lm);
     uint64_t pm = 0;
-    uint32_t lh = hits & ~iocc, off = 0;
 #pragma unroll
     for (int o = 0; o < 8; o++) {
-        const uint32_t cnt = (counts >> (4 * o)) & 0xFu;
-        if ((lh >> o) & 1u) pm |= ((1ull << cnt) - 1ull) << off;
-        off += cnt;
+        const uint32_t cnt = (hc >> (4 * o)) & 0xFu;
+        const uint32_t st = (((o & 1) ? s_odd : s_even) >> (8 * (o >> 1))) & 63u;
+        pm |= (uint64_t)((1u << cnt) - 1u) << st;
     }
     s.gbase = q1.x;
     s.giocc = iocc;
