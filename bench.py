@@ -53,11 +53,11 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=17974553.3, write_kib=873897.9, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17488079.2, write_kib=854796.6, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
-             "4055d8ca3bcf69352da6c2914cf121f5eb4ca2e0f3f09383babfd90bb5257414",
+             "2f00419cfdb57f5d932923cde7392aa7fade7dd46970408766a0a4a1c5ef215e",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
-             "f135c2a917cc09c6ad31c0644cbe5f93038aefabf3a0d0a777e30079acf1cb03",
+             "6844ff519786c3cfce6079d496ff3109e4a655a75ebd61b1fb071abafd4fb929",
              "paper_2408_15583_amd/csrc/pe_device.h":
              "0fc49f89a3ef47b0f58a548b553fdaf736d9d75156e0aa2a339a8359f14eab05",
              "paper_2408_15583_amd/csrc/pe_geom.h":

@@ -289,6 +289,10 @@ void launch_wide_emit(const float4* nodes, uint32_t n_nodes, const uint32_t* rec
                        pb_s, wrec, wpts);
 }
 
+// Threads per workgroup of the traversal kernels; a lane's stack entries lie this many apart
+// in LDS (a constant, so an entry's address is a shift, not a multiply).
+constexpr int kBvhBlock = 256;
+
 // Launch parameter of the persistent loop: idle lanes at which a wavefront refills (bits 0-7,
 // 1 .. 64) and the quorum of lanes holding points for a point step (bits 8-15, 0 .. 64).
 static int pack_refill(int refill) {
@@ -346,10 +350,10 @@ __device__ inline void bvh_persistent(const SlotDesc* __restrict__ ds, uint64_t 
             if (points) {
                 if (active && s.pmask != 0) done = bvh_points<any>(s);
             } else {
-                if (active && s.pmask == 0) done = bvh_node<any>(s, my, blockDim.x);
+                if (active && s.pmask == 0) done = bvh_node<any>(s, my, kBvhBlock);
             }
         } else if (active) {
-            done = bvh_step<any>(*dp, s, my, blockDim.x);
+            done = bvh_step<any>(*dp, s, my, kBvhBlock);
         }
         if (done) {
             finish(item, s);
@@ -361,7 +365,7 @@ __device__ inline void bvh_persistent(const SlotDesc* __restrict__ ds, uint64_t 
 // One bounce, pass 1 with every splat as bounce geometry: each live ray leaves its facet along
 // the Eq. (4) reflection and takes the nearest disk hit beyond eps over the whole scene; the
 // packed (t, index) key goes to hitkey[entry] for the apply pass.
-__global__ __launch_bounds__(256) void k_trace_bvh(const SlotDesc* __restrict__ ds,
+__global__ __launch_bounds__(kBvhBlock) void k_trace_bvh(const SlotDesc* __restrict__ ds,
                                                    const uint32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ n_live,
                                                    RayState rs, uint64_t* __restrict__ hitkey,
@@ -397,8 +401,8 @@ void launch_trace_bvh(const SlotDesc* d, const uint32_t* list, const uint32_t* n
                       RayState rs, uint64_t* hitkey, int bounce, int stack_depth,
                       uint32_t* queue, int refill, int n_blocks, hipStream_t st) {
     launch_fill_u32(queue, 0u, 1, st);
-    hipLaunchKernelGGL(k_trace_bvh, dim3(n_blocks), dim3(256),
-                       (size_t)stack_depth * 256 * sizeof(uint64_t), st, d, list, n_live, rs,
+    hipLaunchKernelGGL(k_trace_bvh, dim3(n_blocks), dim3(kBvhBlock),
+                       (size_t)stack_depth * kBvhBlock * sizeof(uint64_t), st, d, list, n_live, rs,
                        hitkey, bounce, queue, pack_refill(refill));
 }
 
@@ -437,7 +441,7 @@ void launch_psi_mark(const SlotDesc* d, const uint32_t* list, const uint32_t* n_
 
 // Visibility, pass 2: one lane per (compacted facet, observation direction): any hit toward
 // k_s beyond eps.
-__global__ __launch_bounds__(256) void k_psi_trace(const SlotDesc* __restrict__ ds,
+__global__ __launch_bounds__(kBvhBlock) void k_psi_trace(const SlotDesc* __restrict__ ds,
                                                    const ObsDesc* __restrict__ obs,
                                                    const uint32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ n_list,
@@ -478,8 +482,8 @@ void launch_psi_trace(const SlotDesc* d, const ObsDesc* obs, const uint32_t* lis
                       uint64_t vis_stride, int stack_depth, uint32_t* queue, int refill,
                       int n_blocks, hipStream_t st) {
     launch_fill_u32(queue, 0u, 1, st);
-    hipLaunchKernelGGL(k_psi_trace, dim3(n_blocks), dim3(256),
-                       (size_t)stack_depth * 256 * sizeof(uint64_t), st, d, obs, list, n_list,
+    hipLaunchKernelGGL(k_psi_trace, dim3(n_blocks), dim3(kBvhBlock),
+                       (size_t)stack_depth * kBvhBlock * sizeof(uint64_t), st, d, obs, list, n_list,
                        max_obs, rs, vis, vis_stride, queue, pack_refill(refill));
 }
 

@@ -242,18 +242,21 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
     if (s.dmask & 2u) nh = ((nh & 0x33u) << 2) | ((nh >> 2) & 0x33u);
     if (s.dmask & 4u) nh = ((nh & 0x0Fu) << 4) | (nh >> 4);
     // point bits of octant o: cnt_o bits from S_o, the sum of the lower octants' counts (at
-    // most 64 in all).  The S_o come as bytes: the counts summed in pairs, the pairs of the
-    // lower bytes added by shifts (no byte carries over) for the even octants' starts, plus
-    // the even octant's count for the odd ones'.  Counts of leaf octants not hit are cleared
-    // (a nibble mask spread from the hit bits) after the offsets are taken.
+    // most 64 in all).  The S_o come as bytes: the counts summed in pairs, each byte then the
+    // sum of the pairs below it (a 24-bit multiply by 0x010101 shifted up a byte; no byte
+    // carries over) for the even octants' starts, plus the even octant's count for the odd
+    // ones'.  Counts of leaf octants not hit are cleared (a nibble mask spread from the hit
+    // bits) after the offsets are taken.
     const uint32_t ce = counts & 0x0F0F0F0Fu, co = (counts >> 4) & 0x0F0F0F0Fu;
     const uint32_t pr = ce + co;
-    const uint32_t s_even = (pr << 8) + (pr << 16) + (pr << 24), s_odd = s_even + ce;
+    const uint32_t s_even = __umul24(pr & 0xFFFFFFu, 0x010101u) << 8, s_odd = s_even + ce;
     uint32_t lm = hits & ~iocc;
     lm = (lm | (lm << 12)) & 0x000F000Fu;
     lm = (lm | (lm << 6)) & 0x03030303u;
     lm = (lm | (lm << 3)) & 0x11111111u;
-    const uint32_t hc = counts & ((lm << 4) - lm);
+    lm |= lm << 1;
+    lm |= lm << 2;
+    const uint32_t hc = counts & lm;
     uint64_t pm = 0;
 #pragma unroll
     for (int o = 0; o < 8; o++) {

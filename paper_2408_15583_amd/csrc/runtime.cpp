@@ -456,14 +456,17 @@ static int persistent_blocks() {
 // visibility), refill alone at 8: 83.4 / 13.8, 16: 46.0 / 8.5, 24: 32.0 / 7.0, 32: 26.1 / 7.2,
 // 40: 25.8 / 7.6, 48: 25.8 / 7.7, 64: 32.1 / 10.0; with refill 40, quorum 8: 22.9 / 6.6,
 // 12: 22.4 / 7.0, 16: 22.7 / 7.1.  Visibility alone, later (ms per step): refill 24 6.85, 40
-// 7.10; refill 40 with quorum 8 6.63, 10 6.75, 12 6.80; refill 24 with quorum 8 6.75.
-// PE_BVH_REFILL, PE_BVH_QUORUM, PE_PSI_REFILL and PE_PSI_QUORUM override.
+// 7.10; refill 40 with quorum 8 6.63, 10 6.75, 12 6.80; refill 24 with quorum 8 6.75.  Once
+// node steps took fewer instructions (near and far planes picked per record), the second
+// bounce at quorum 12 moved to refill 32: 25.4, 40: 21.4-21.5, 44: 20.4, 48: 20.1-20.2, 52:
+// 20.9, 56: 23.8 ms (48 with quorum 8: 20.4, 16: 21.0); visibility at refill 32, 40 and 48:
+// 5.9-6.1 ms.  PE_BVH_REFILL, PE_BVH_QUORUM, PE_PSI_REFILL and PE_PSI_QUORUM override.
 static int bvh_refill(bool psi) {
     auto env = [](const char* name, int dflt) {
         const char* e = std::getenv(name);
         return e ? std::atoi(e) : dflt;
     };
-    static const int v[2] = {env("PE_BVH_REFILL", 40) | (env("PE_BVH_QUORUM", 12) << 8),
+    static const int v[2] = {env("PE_BVH_REFILL", 48) | (env("PE_BVH_QUORUM", 12) << 8),
                              env("PE_PSI_REFILL", 40) | (env("PE_PSI_QUORUM", 8) << 8)};
     return v[psi ? 1 : 0];
 }
