@@ -53,11 +53,11 @@ MARCH_TRAFFIC = dict(
 # per dispatch over its three bounces), scaled by the same copy calibration; null once any of
 # the traversal's sources changes.
 BVH_TRAFFIC = dict(
-    fetch_kib=17488079.2, write_kib=854796.6, fetch_factor=2.0, write_factor=1.0,
+    fetch_kib=17450870.3, write_kib=842965.5, fetch_factor=2.0, write_factor=1.0,
     sources={"paper_2408_15583_amd/csrc/k_bvh.hip":
              "2f00419cfdb57f5d932923cde7392aa7fade7dd46970408766a0a4a1c5ef215e",
              "paper_2408_15583_amd/csrc/pe_bvh.h":
-             "6844ff519786c3cfce6079d496ff3109e4a655a75ebd61b1fb071abafd4fb929",
+             "16d20123701aff881396c50d0cef005bd6dc8b60e7ed4c0845356475ff60e2d1",
              "paper_2408_15583_amd/csrc/pe_device.h":
              "0fc49f89a3ef47b0f58a548b553fdaf736d9d75156e0aa2a339a8359f14eab05",
              "paper_2408_15583_amd/csrc/pe_geom.h":

@@ -221,11 +221,13 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
                    nz[2] = {bz ? q4.z : q3.x, bz ? q4.w : q3.y},
                    fz[2] = {bz ? q3.x : q4.z, bz ? q3.y : q4.w};
     // hit octants, then the internal ones to the node group (rank order) and the leaf ones'
-    // points to the point group; an octant no lane of the wavefront occupies is skipped
+    // points to the point group.  Any-hit skips an octant no lane of the wavefront occupies;
+    // nearest-hit tests all eight (fewer instructions than the skip's branches) and keeps the
+    // occupied ones.
     uint32_t hits = 0;
 #pragma unroll
     for (int o = 0; o < 8; o++) {
-        if (!((occ >> o) & 1u)) continue;
+        if (any && !((occ >> o) & 1u)) continue;
         const int w = o >> 2, sh = 8 * (o & 3);
         const float tn = fmaxf(fmaxf(fmaf((float)((nx[w] >> sh) & 0xFFu), sx, ax),
                                      fmaf((float)((ny[w] >> sh) & 0xFFu), sy, ay)),
@@ -235,6 +237,7 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
                                fmaf((float)((fz[w] >> sh) & 0xFFu), sz, az));
         hits |= (tn <= tf && tf >= s.tmin && tn <= tmax) ? 1u << o : 0u;
     }
+    hits &= occ;
     // the hit internal octants in rank order (octant XOR sign mask): XOR with each set bit of
     // the sign mask swaps neighbouring bits, pairs of bits or nibbles
     uint32_t nh = hits & iocc;
@@ -243,19 +246,21 @@ __device__ inline bool bvh_node(BvhState& s, uint64_t* stk, int stride) {
     if (s.dmask & 4u) nh = ((nh & 0x0Fu) << 4) | (nh >> 4);
     // point bits of octant o: cnt_o bits from S_o, the sum of the lower octants' counts (at
     // most 64 in all).  The S_o come as bytes: the counts summed in pairs, each byte then the
-    // sum of the pairs below it (a 24-bit multiply by 0x010101 shifted up a byte; no byte
-    // carries over) for the even octants' starts, plus the even octant's count for the odd
-    // ones'.  Counts of leaf octants not hit are cleared (a nibble mask spread from the hit
-    // bits) after the offsets are taken.
+    // sum of the pairs below it (a 24-bit multiply by 0x010101, which ignores the top pair,
+    // shifted up a byte; no byte carries over) for the even octants' starts, plus the even
+    // octant's count for the odd ones'.  Counts of leaf octants not hit are cleared (a nibble
+    // mask spread from the hit bits; its last two steps written as shift-or instructions,
+    // which the compiler would otherwise fold into a full 32-bit multiply by 15) after the
+    // offsets are taken.
     const uint32_t ce = counts & 0x0F0F0F0Fu, co = (counts >> 4) & 0x0F0F0F0Fu;
     const uint32_t pr = ce + co;
-    const uint32_t s_even = __umul24(pr & 0xFFFFFFu, 0x010101u) << 8, s_odd = s_even + ce;
+    const uint32_t s_even = __umul24(pr, 0x010101u) << 8, s_odd = s_even + ce;
     uint32_t lm = hits & ~iocc;
     lm = (lm | (lm << 12)) & 0x000F000Fu;
     lm = (lm | (lm << 6)) & 0x03030303u;
     lm = (lm | (lm << 3)) & 0x11111111u;
-    lm |= lm << 1;
-    lm |= lm << 2;
+    asm("v_lshl_or_b32 %0, %1, 1, %1" : "=v"(lm) : "v"(lm));
+    asm("v_lshl_or_b32 %0, %1, 2, %1" : "=v"(lm) : "v"(lm));
     const uint32_t hc = counts & lm;
     uint64_t pm = 0;
 #pragma unroll
