@@ -618,7 +618,7 @@ def main():
     if name in ("march", "bvh"):
         # algorithmic bytes of one bounce (the secondary-hit pass and its apply) per live ray:
         # the ray state, 76 B (18 fp32 + fp64 path + u32 pixel id), read once and written once
-        # for the rays that continue; the SoA state this build keeps is 97 B (21 fp32: the
+        # for the rays that continue; the SoA state the library keeps is 97 B (21 fp32: the
         # incoming direction and the two incident polarisations kept whole, + fp64 path + u8
         # bounce count + u32 facet index), reported beside.  Scene data and view pyramids are
         # not counted.
