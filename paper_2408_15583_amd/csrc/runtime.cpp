@@ -460,7 +460,10 @@ static int persistent_blocks() {
 // node steps took fewer instructions (near and far planes picked per record), the second
 // bounce at quorum 12 moved to refill 32: 25.4, 40: 21.4-21.5, 44: 20.4, 48: 20.1-20.2, 52:
 // 20.9, 56: 23.8 ms (48 with quorum 8: 20.4, 16: 21.0); visibility at refill 32, 40 and 48:
-// 5.9-6.1 ms.  PE_BVH_REFILL, PE_BVH_QUORUM, PE_PSI_REFILL and PE_PSI_QUORUM override.
+// 5.9-6.1 ms.  With every child slot tested in nearest-hit: second bounce at refill 48 and
+// quorum 10 20.1, 12 19.9-20.1, 14 20.3 ms; visibility at refill 24 6.41, 32 5.92-5.98, 40
+// 5.93-6.10 ms (quorum 8).  PE_BVH_REFILL, PE_BVH_QUORUM, PE_PSI_REFILL and PE_PSI_QUORUM
+// override.
 static int bvh_refill(bool psi) {
     auto env = [](const char* name, int dflt) {
         const char* e = std::getenv(name);
